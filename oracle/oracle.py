@@ -1,0 +1,250 @@
+"""Python wrapper of the plain FP64 CPU oracle (``alp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this module; the product package
+``paper_2609_39443_amd`` never does.  The oracle shares no code with the GPU
+path; both sides only share the seeded input generators.
+
+The oracle follows Section 3.2 of Taran et al. (arXiv 2609.39443): point
+location (eq. 16, 18), upstream sampling (eq. 17), drag (eq. 19 / eq. 6) with
+relaxation (eq. 20), nearest-segment projection with the truncated Gaussian
+(eq. 21-22), nodal normalisation (Sec. 3.2.4) and the momentum source (eq. 23).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "alp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BRUTE, GRID = 0, 1
+FULLMAG, COMPONENTWISE = 0, 1
+F_OUTSIDE, F_FALLBACK, F_DEGENERATE = 1, 2, 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: FP64, -O2, no FMA contraction, no fast-math."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Beams(ct.Structure):
+    _fields_ = [("n_beams", ct.c_int32), ("pad_", ct.c_int32), ("n_points", ct.c_int64),
+                ("offsets", ct.c_void_p), ("P", ct.c_void_p), ("P_spread", ct.c_void_p),
+                ("e_t", ct.c_void_p), ("Pdot", ct.c_void_p), ("d", ct.c_void_p),
+                ("L", ct.c_void_p), ("eps", ct.c_void_p), ("Cdn", ct.c_void_p),
+                ("Cdt", ct.c_void_p), ("ls", ct.c_void_p), ("n_p", ct.c_void_p),
+                ("e_up", ct.c_void_p)]
+
+
+class _Params(ct.Structure):
+    _fields_ = [("rho", ct.c_double), ("alpha_f", ct.c_double), ("tau", ct.c_double),
+                ("drag_form", ct.c_int32), ("pad_", ct.c_int32)]
+
+
+class _Diag(ct.Structure):
+    _fields_ = [("n_outside", ct.c_int64), ("n_fallback", ct.c_int64),
+                ("n_fallback_degenerate", ct.c_int64), ("n_zero_weight", ct.c_int64),
+                ("n_band_cells", ct.c_int64), ("n_pairs", ct.c_int64),
+                ("F_beam", ct.c_double * 3), ("F_fluid", ct.c_double * 3),
+                ("cons_rel_err", ct.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"n_outside": self.n_outside, "n_fallback": self.n_fallback,
+                "n_fallback_degenerate": self.n_fallback_degenerate,
+                "n_zero_weight": self.n_zero_weight, "n_band_cells": self.n_band_cells,
+                "n_pairs": self.n_pairs, "F_beam": np.array(self.F_beam[:]),
+                "F_fluid": np.array(self.F_fluid[:]), "cons_rel_err": self.cons_rel_err}
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ct.CDLL(_LIB)
+        vp = ct.c_void_p
+        lib.orc_mesh_create.argtypes = [ct.c_int64, vp, vp, vp, ct.c_int, ct.POINTER(vp)]
+        lib.orc_mesh_destroy.argtypes = [vp]
+        lib.orc_mesh_box.argtypes = [vp]
+        lib.orc_mesh_box.restype = ct.POINTER(ct.c_double)
+        lib.orc_locate_many.argtypes = [vp, ct.c_int64, vp, vp]
+        lib.orc_sample.argtypes = [vp, vp, ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp,
+                                   vp, ct.POINTER(_Diag)]
+        lib.orc_drag.argtypes = [ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp]
+        lib.orc_spread.argtypes = [vp, ct.POINTER(_Beams), vp, vp, vp, vp, ct.POINTER(_Diag)]
+        lib.orc_step.argtypes = [vp, vp, ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp,
+                                 vp, vp, vp, vp, vp, ct.POINTER(_Diag)]
+        lib.orc_nearest_segment.argtypes = [ct.c_int64, vp, vp, ct.POINTER(ct.c_double),
+                                            ct.POINTER(ct.c_double)]
+        lib.orc_nearest_segment.restype = ct.c_int64
+        _lib = lib
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Mesh:
+    """Cell centres C [n,3], volumes V [n], optional domain box [lo(3), hi(3)]."""
+
+    def __init__(self, C, V, box=None, mode: int = GRID):
+        lib = _load()
+        self.C = _f64(C, (-1, 3))
+        self.V = _f64(V, (-1,))
+        self.n = self.C.shape[0]
+        box_a = None if box is None else _f64(box, (6,))
+        h = ct.c_void_p()
+        rc = lib.orc_mesh_create(self.n, _ptr(self.C), _ptr(self.V), _ptr(box_a), mode, ct.byref(h))
+        if rc != 0:
+            raise ValueError(f"orc_mesh_create failed ({rc})")
+        self._h = h
+        self.mode = mode
+        self.box = np.array(lib.orc_mesh_box(h)[:6])
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_mesh_destroy(self._h)
+            self._h = None
+
+    def locate(self, X):
+        X = _f64(X, (-1, 3))
+        out = np.empty(X.shape[0], dtype=np.int64)
+        rc = _load().orc_locate_many(self._h, X.shape[0], _ptr(X), _ptr(out))
+        if rc != 0:
+            raise ValueError("orc_locate_many failed")
+        return out
+
+
+class _BeamArgs:
+    """Holds contiguous copies of a beam-set dict and the ctypes struct."""
+
+    def __init__(self, beams: dict):
+        self.offsets = np.ascontiguousarray(beams["offsets"], dtype=np.int64)
+        nb = self.offsets.shape[0] - 1
+        self.P = _f64(beams["P"], (-1, 3))
+        npnt = self.P.shape[0]
+        ps = beams.get("P_spread")
+        self.P_spread = None if ps is None else _f64(ps, (-1, 3))
+        self.e_t = _f64(beams["e_t"], (-1, 3))
+        self.Pdot = _f64(beams["Pdot"], (-1, 3))
+        self.d = _f64(beams["d"], (-1,))
+        self.L = _f64(beams["L"], (-1,))
+        self.eps = _f64(beams["eps"], (-1,))
+        self.Cdn = _f64(beams["Cdn"], (-1,))
+        self.Cdt = _f64(beams["Cdt"], (-1,))
+        self.ls = _f64(beams["ls"], (-1,))
+        self.n_p = _f64(beams["n_p"], (-1, 3))
+        self.e_up = _f64(beams["e_up"], (-1, 3))
+        for name, arr, n in (("e_t", self.e_t, npnt), ("Pdot", self.Pdot, npnt), ("d", self.d, npnt),
+                             ("L", self.L, npnt), ("eps", self.eps, npnt), ("Cdn", self.Cdn, nb),
+                             ("Cdt", self.Cdt, nb), ("ls", self.ls, nb), ("n_p", self.n_p, nb),
+                             ("e_up", self.e_up, nb)):
+            if arr.shape[0] != n:
+                raise ValueError(f"beams[{name!r}] has {arr.shape[0]} rows, expected {n}")
+        self.s = _Beams(nb, 0, npnt, _ptr(self.offsets), _ptr(self.P), _ptr(self.P_spread),
+                        _ptr(self.e_t), _ptr(self.Pdot), _ptr(self.d), _ptr(self.L), _ptr(self.eps),
+                        _ptr(self.Cdn), _ptr(self.Cdt), _ptr(self.ls), _ptr(self.n_p), _ptr(self.e_up))
+        self.n_points = npnt
+
+
+def _params(params: dict) -> _Params:
+    form = params.get("drag_form", FULLMAG)
+    if isinstance(form, str):
+        form = {"fullmag": FULLMAG, "componentwise": COMPONENTWISE}[form]
+    return _Params(float(params["rho"]), float(params.get("alpha_f", 1.0)),
+                   float(params.get("tau", 1e-6)), int(form), 0)
+
+
+def sample(mesh: Mesh, U, beams: dict, params: dict) -> dict:
+    lib = _load()
+    U = _f64(U, (-1, 3))
+    b = _BeamArgs(beams)
+    n = b.n_points
+    out = {"U_s": np.zeros((n, 3)), "P_s": np.zeros((n, 3)), "cell_a": np.zeros(n, np.int64),
+           "cell_s": np.zeros(n, np.int64), "flags": np.zeros(n, np.int32)}
+    d = _Diag()
+    rc = lib.orc_sample(mesh._h, _ptr(U), ct.byref(b.s), ct.byref(_params(params)), _ptr(out["U_s"]),
+                        _ptr(out["P_s"]), _ptr(out["cell_a"]), _ptr(out["cell_s"]), _ptr(out["flags"]),
+                        ct.byref(d))
+    if rc != 0:
+        raise ValueError(f"orc_sample failed ({rc})")
+    out["diag"] = d.as_dict()
+    return out
+
+
+def drag(beams: dict, params: dict, U_s, cell_s=None, f_prev=None):
+    lib = _load()
+    b = _BeamArgs(beams)
+    U_s = _f64(U_s, (-1, 3))
+    cs = None if cell_s is None else np.ascontiguousarray(cell_s, dtype=np.int64)
+    fp = None if f_prev is None else _f64(f_prev, (-1, 3))
+    f = np.zeros((b.n_points, 3))
+    rc = lib.orc_drag(ct.byref(b.s), ct.byref(_params(params)), _ptr(U_s), _ptr(cs), _ptr(fp), _ptr(f))
+    if rc != 0:
+        raise ValueError(f"orc_drag failed ({rc})")
+    return f
+
+
+def spread(mesh: Mesh, beams: dict, f) -> dict:
+    lib = _load()
+    b = _BeamArgs(beams)
+    f = _f64(f, (-1, 3))
+    out = {"S": np.zeros((mesh.n, 3)), "w": np.zeros(b.n_points), "fhat": np.zeros((b.n_points, 3))}
+    d = _Diag()
+    rc = lib.orc_spread(mesh._h, ct.byref(b.s), _ptr(f), _ptr(out["S"]), _ptr(out["w"]),
+                        _ptr(out["fhat"]), ct.byref(d))
+    if rc != 0:
+        raise ValueError(f"orc_spread failed ({rc})")
+    out["diag"] = d.as_dict()
+    return out
+
+
+def step(mesh: Mesh, U, beams: dict, params: dict, f_prev=None) -> dict:
+    """One coupling step (Algorithm 1, steps 2-5 and 7-8)."""
+    lib = _load()
+    b = _BeamArgs(beams)
+    U = _f64(U, (-1, 3))
+    n = b.n_points
+    fp = None if f_prev is None else _f64(f_prev, (-1, 3))
+    out = {"U_s": np.zeros((n, 3)), "P_s": np.zeros((n, 3)), "cell_a": np.zeros(n, np.int64),
+           "cell_s": np.zeros(n, np.int64), "f": np.zeros((n, 3)), "S": np.zeros((mesh.n, 3)),
+           "w": np.zeros(n), "fhat": np.zeros((n, 3))}
+    d = _Diag()
+    rc = lib.orc_step(mesh._h, _ptr(U), ct.byref(b.s), ct.byref(_params(params)), _ptr(fp),
+                      _ptr(out["U_s"]), _ptr(out["P_s"]), _ptr(out["cell_a"]), _ptr(out["cell_s"]),
+                      _ptr(out["f"]), _ptr(out["S"]), _ptr(out["w"]), _ptr(out["fhat"]), ct.byref(d))
+    if rc != 0:
+        raise ValueError(f"orc_step failed ({rc})")
+    out["diag"] = d.as_dict()
+    return out
+
+
+def nearest_segment(X, c):
+    """Closest segment of polyline X [n,3] to point c (eq. 21): (index, s, r^2)."""
+    X = _f64(X, (-1, 3))
+    c = _f64(c, (3,))
+    s = ct.c_double()
+    r2 = ct.c_double()
+    i = _load().orc_nearest_segment(X.shape[0], _ptr(X), _ptr(c), ct.byref(s), ct.byref(r2))
+    return int(i), s.value, r2.value
