@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the actuator-line coupling step on one MI355X.
+
+A step is one pass of the whole operator (segment binning, upstream sampling,
+drag and relaxation, nodal weights, normalisation, spreading, conservation
+check) over the canopy workload: 256^3 uniform cells (h = 4 mm, 16.8M cells),
+2000 straight stems of 20..200 CVs (about 220k actuator points) with
+overlapping kernels, all stems in one persistent launch per stage, the step
+captured in a hipGraph and replayed.  Inputs are seeded synthetic arrays,
+resident in HBM before timing starts.
+
+Prints one JSON line: actuator points/s of the FP32-split batched step (the
+headline), plus cell-updates/s, the algorithmic HBM rate, the all-FP64 and the
+plain (unbatched, uncaptured) FP64 timings, live per-stage timings, the
+roofline of the dominant kernel and the oracle's CPU baseline on a bounded
+sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0       # MI355X HBM3E
+VALU_PEAK_TOPS = 39.32       # 256 CU x 64 lanes x 2.4 GHz (non-packed FP32 / FP64 lane-ops)
+BYTES_PER_BAND_CELL = 92     # 2 x (FP64 centre 24 B + volume 8 B) + source 24 B + cell index 4 B
+BYTES_PER_POINT = 272        # P, e_t, Pdot (72) + d, L, eps (24) + 2 velocity gathers (48)
+                             # + f, U_s, P_s, w (80) + f_hat written and read (48)
+BYTES_WEIGHTS_PER_BAND_CELL = 32   # weights pass: FP64 centre + volume
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256, help="cells per mesh edge (default 256)")
+    ap.add_argument("--stems", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stems", type=int, default=1000,
+                    help="stems in the oracle's timed sample (about 10-30 s of CPU work)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison runs")
+    return ap.parse_args()
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2609_39443_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, fn), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, n_cells, n_stems):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current sources and this workload."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except Exception:
+        return None
+    if t.get("source_hash") != source_hash() or t.get("n_cells") != n_cells or t.get("stems") != n_stems:
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "single-GPU build: the coupling operator runs on one MI355X; "
+                                   "--gpus must be 1 (the multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2609_39443_amd import alp
+    from paper_2609_39443_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    alp.load()
+    t0 = time.time()
+    wl = W.canopy(n=args.n, n_stems=args.stems)
+    log(f"workload {wl['name']}: {wl['C'].shape[0]} cells, {wl['beams']['P'].shape[0]} points "
+        f"({time.time() - t0:.1f} s to generate)")
+    dev = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    C, V, U = dev(wl["C"]), dev(wl["V"]), dev(wl["U"])
+    n_cells = C.shape[0]
+    ctx = alp.Context(0)
+    mesh = ctx.bin_cells(C, V)
+    beams = alp.DeviceBeams(wl["beams"])
+    npnt = beams.n_points
+    z = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")
+    out = {k: z(npnt, 3) for k in ("f", "U_s", "P_s")}
+    out["w"] = z(npnt)
+    S = z(n_cells, 3)
+    cell_s = torch.zeros(npnt, dtype=torch.int64, device="cuda")
+
+    def case(prec):
+        return alp.alp_case(mesh, U.data_ptr(), beams.struct, alp.make_params(wl["params"], prec), None,
+                            out["f"].data_ptr(), S.data_ptr(), out["U_s"].data_ptr(),
+                            out["w"].data_ptr(), out["P_s"].data_ptr(), None, None)
+
+    def timed_graph(prec, steps, warmup):
+        cs = [case(prec)]
+        alp.alp_step_batched(ctx.h, cs, alp.USE_GRAPH)   # sizes, runs and captures
+        for _ in range(warmup):
+            alp.alp_step_batched(ctx.h, cs, alp.USE_GRAPH)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            alp.alp_step_batched(ctx.h, cs, alp.USE_GRAPH)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        alp.alp_invalidate(ctx.h)
+        return dt, ctx.diag(0)
+
+    def timed_plain(prec, steps, warmup):
+        p = alp.make_params(wl["params"], prec)
+
+        def one():
+            alp.alp_sample(ctx.h, mesh, U, beams.struct, p, out["U_s"], out["P_s"], None, cell_s)
+            alp.alp_drag(ctx.h, beams.struct, p, out["U_s"], cell_s, None, out["f"])
+            alp.alp_spread(ctx.h, mesh, beams.struct, p, out["f"], S, out["w"], None)
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    # headline: FP32-split, batched persistent launches, graph replay
+    log("timing the FP32-split graph step")
+    t_split, diag = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup)
+    log(f"split: {t_split * 1e3:.3f} ms/step, diag {diag}")
+    # live per-stage timings (HIP events on the stream the kernels run on)
+    stage_runs = [alp.alp_step_profile(ctx.h, [case(alp.PREC_FP32_SPLIT)]) for _ in range(5)]
+    stages = {k: float(np.median([r[k] for r in stage_runs])) for k in stage_runs[0]}
+    log(f"stages (ms): {stages}")
+    res = {}
+    if not args.no_fp64:
+        t64, d64 = timed_graph(alp.PREC_FP64, max(3, args.steps // 2), 1)
+        res["fp64_graph_ms_per_step"] = t64 * 1e3
+        res["fp64_cons_rel_err"] = d64["cons_rel_err"]
+        stage64 = [alp.alp_step_profile(ctx.h, [case(alp.PREC_FP64)]) for _ in range(3)]
+        res["fp64_stages_ms"] = {k: float(np.median([r[k] for r in stage64])) for k in stage64[0]}
+        tp = timed_plain(alp.PREC_FP64, max(3, args.steps // 4), 1)
+        res["plain_fp64_unbatched_ms_per_step"] = tp * 1e3
+        res["speedup_split_vs_fp64_graph"] = t64 / t_split
+        res["speedup_vs_plain_fp64"] = tp / t_split
+        log(f"fp64 graph {t64 * 1e3:.3f} ms, plain fp64 {tp * 1e3:.3f} ms")
+
+    n_band, n_pairs = int(diag["n_band_cells"]), int(diag["n_pairs"])
+    bytes_step = n_band * BYTES_PER_BAND_CELL + npnt * BYTES_PER_POINT
+    gbps = bytes_step / t_split / 1e9
+    # dominant kernel: the weights pass (closest segment per pair, eq. 21-22)
+    t_w = stages["weights"] * 1e-3
+    bytes_w = n_band * BYTES_WEIGHTS_PER_BAND_CELL
+    ach_w = bytes_w / t_w / 1e9
+    traffic = traffic_from_profiles("k_weights", n_cells, args.stems)
+    roofline = {"kernel": "k_weights", "bound": "hbm", "achieved": ach_w, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": ach_w / HBM_PEAK_GBPS, "traffic": traffic,
+                "alg_bytes_per_launch": bytes_w, "avg_ms": stages["weights"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        rng = np.random.default_rng(7)
+        pick = sorted(rng.choice(args.stems, size=min(args.cpu_stems, args.stems), replace=False).tolist())
+        sub = W.subset_beams(wl["beams"], pick)
+        log(f"oracle CPU baseline on {len(pick)} stems ({sub['P'].shape[0]} points)")
+        om = oracle.Mesh(wl["C"], wl["V"], None, oracle.GRID)
+        t = time.perf_counter()
+        r = oracle.step(om, wl["U"], sub, wl["params"])
+        dt = time.perf_counter() - t
+        cpu = {"value": sub["P"].shape[0] / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(pick)} of {args.stems} stems ({sub['P'].shape[0]} points) on the full "
+                         f"{n_cells}-cell mesh, one FP64 step (sample, drag, project), grid mode, "
+                         f"{dt:.1f} s", "seconds": dt, "pairs": int(r["diag"]["n_pairs"])}
+        log(f"oracle: {dt:.2f} s")
+
+    line = {
+        "metric": "actuator points/s per coupling step", "value": npnt / t_split, "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_split * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32-split",
+        "data": "synthetic",
+        "config": {"workload": f"canopy: {args.n}^3 uniform cells (h = 4 mm), {args.stems} stems of "
+                               f"20-200 CVs, FP32-split, all stems in one persistent launch per stage, "
+                               f"hipGraph replay", "n_cells": n_cells, "n_points": npnt,
+                   "n_band_cells": n_band, "n_pairs": n_pairs, "parallelism": "single GPU"},
+        "cell_updates_per_s": n_pairs / t_split, "band_cells_per_s": n_band / t_split,
+        "mesh_cells_per_s": n_cells / t_split, "alg_hbm_gbps": gbps, "alg_hbm_frac": gbps / HBM_PEAK_GBPS,
+        "cons_rel_err": diag["cons_rel_err"], "stages_ms": stages, "roofline": roofline,
+        "cpu_baseline": cpu, **res,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

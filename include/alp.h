@@ -1,0 +1,233 @@
+/*
+ * alp.h -- C ABI of libalp, an MI355X (gfx950) implementation of the
+ * actuator-line coupling operator of Taran, Bali, Tukovic, Pakrashi and
+ * Cardiff, "Two-way actuator-line coupling of a geometrically exact
+ * finite-volume beam with incompressible and free-surface flow"
+ * (arXiv 2609.39443), Section 3.2.
+ *
+ * Per coupling step the operator
+ *   1. samples the Eulerian velocity upstream of every actuator point
+ *      (eq. 16-18, Sec. 3.2.2),
+ *   2. evaluates the quasi-steady Morison drag on the relative velocity and
+ *      relaxes it (eq. 19-20, Sec. 3.2.3),
+ *   3. projects the equal and opposite force onto the mesh through the
+ *      truncated Gaussian of eq. (22), normalised per actuator node so that the
+ *      transferred resultant force is conserved exactly (eq. 21-23, Sec. 3.2.4).
+ *
+ * Conventions (all entry points)
+ *   - Every array argument is DEVICE memory unless marked HOST, contiguous,
+ *     row-major, little-endian, owned by the caller.  [n][3] means n rows of
+ *     (x, y, z) doubles.  Indices are 0-based.
+ *   - The library owns contexts, meshes and workspace.  It keeps no pointer to
+ *     caller arrays beyond a call, except where a captured graph replays
+ *     (alp_step_batched with ALP_USE_GRAPH): then the arrays named in the cases
+ *     must stay valid until alp_invalidate or alp_destroy.
+ *   - All calls are asynchronous on the context's stream except alp_create,
+ *     alp_bin_cells, alp_get_diag, alp_destroy and alp_mesh_destroy, which
+ *     synchronise it.  Calls on one context must not overlap.
+ *   - Errors the host can detect return a negative alp_status and launch
+ *     nothing; alp_last_error() then describes the problem.  Conditions for
+ *     which the method defines a behaviour are not errors: a point outside the
+ *     fluid domain carries no load (Sec. 3.2.5), an ill-conditioned upstream
+ *     direction falls back to the prescribed one (Sec. 3.2.2), a node that
+ *     catches no cell gets no load (Sec. 3.2.4).  They are counted in alp_diag.
+ *   - Units are SI.  S is a force per unit volume on the fluid (N/m^3) that
+ *     integrates as sum_j S_j V_j; f is the force per unit length on the beam.
+ *   - Readings of the paper used throughout: f = +1/2 rho d |U_r| (Cdn U_n +
+ *     Cdt U_t) acts on the beam (the printed minus sign of eq. 19 contradicts
+ *     eq. 6, eq. 23 and the conservation statement of Sec. 3.2.4); Delta s_k is
+ *     the CV length L_k; c(x) is the nearest cell centre (ties: smaller
+ *     (x, y, z), then smaller index); the cutoff is inclusive; eps is given per
+ *     actuator point and interpolated with the linear weights of Sec. 3.2.4;
+ *     beams are normalised independently and their sources add.
+ */
+#ifndef ALP_H
+#define ALP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct alp_context alp_context; /* opaque: stream, workspace, graphs, diagnostics */
+typedef struct alp_mesh alp_mesh;       /* opaque: binned copy of a static mesh */
+
+typedef enum {
+  ALP_OK = 0,
+  ALP_ERR_INVALID_ARG = -1, /* NULL required pointer, bad size, bad enum, eps <= 0, ... */
+  ALP_ERR_HIP = -2,         /* HIP runtime failure (details in alp_last_error) */
+  ALP_ERR_OOM = -3,         /* device allocation failed */
+  ALP_ERR_CAPTURE = -4,     /* call not allowed while the stream is capturing */
+  ALP_ERR_SHAPE = -5,       /* shapes changed after graph capture without alp_invalidate */
+  ALP_ERR_CAPACITY = -6     /* a per-step work list overflowed; results of that step are invalid */
+} alp_status;
+
+typedef enum {
+  ALP_PREC_FP64 = 0,      /* everything in FP64 */
+  ALP_PREC_FP32_SPLIT = 1 /* kernel weights eta and linear weights omega in FP32; every
+                             geometric decision, sum and normalisation in FP64 */
+} alp_precision;
+
+typedef enum {
+  ALP_DRAG_FULLMAG = 0,      /* eq. (19): 1/2 rho d |U_r| (Cdn U_n + Cdt U_t) */
+  ALP_DRAG_COMPONENTWISE = 1 /* eq. (6):  1/2 rho d (Cdn |U_n| U_n + Cdt |U_t| U_t) */
+} alp_drag_form;
+
+/* The beam set (Sec. 3.2.2): one actuator point per beam control volume.
+   Beams are a CSR over points: beam b owns points offsets[b] .. offsets[b+1]-1,
+   ordered along the centreline.  All pointers are DEVICE pointers. */
+typedef struct {
+  int32_t n_beams;
+  int32_t reserved0;
+  int64_t n_points;
+  const int64_t *offsets; /* [n_beams+1], offsets[0] = 0, non-decreasing, last = n_points */
+  const double *P;        /* [n_points][3] actuator points P_a (eq. 15) used for sampling */
+  const double *P_spread; /* [n_points][3] positions for the projection (Algorithm 1, the
+                             projection step uses the updated positions), or NULL = P */
+  const double *e_t;      /* [n_points][3] centreline tangents, normalised internally; a zero
+                             tangent is an error */
+  const double *Pdot;     /* [n_points][3] actuator-point velocities (eq. 13) */
+  const double *d;        /* [n_points] drag reference length (diameter) */
+  const double *L;        /* [n_points] CV length L_k = Delta s_k */
+  const double *eps;      /* [n_points] kernel width eps > 0 (eq. 22) */
+  const double *Cdn;      /* [n_beams] normal drag coefficient */
+  const double *Cdt;      /* [n_beams] tangential drag coefficient */
+  const double *ls;       /* [n_beams] sampling distance l_s (eq. 17) */
+  const double *n_p;      /* [n_beams][3] plane normal of eq. (17), unit, or zero = none */
+  const double *e_up;     /* [n_beams][3] fallback upstream direction (Sec. 3.2.2) */
+} alp_beams;
+
+typedef struct {
+  double rho;      /* fluid density > 0 */
+  double alpha_f;  /* relaxation factor of eq. (20) in (0, 1]; used only when f_prev != NULL */
+  double tau;      /* fallback threshold on |u0_n| [m/s] (Sec. 3.2.2); 0 disables */
+  int32_t prec;    /* alp_precision */
+  int32_t drag_form; /* alp_drag_form */
+} alp_params;
+
+/* Diagnostics of the last step of a case (written on the device, read by
+   alp_get_diag). */
+typedef struct {
+  int64_t n_outside;             /* points whose actuator or sampling point left the domain */
+  int64_t n_fallback;            /* points that used the fallback direction */
+  int64_t n_fallback_degenerate; /* fallback direction parallel to the tangent: e_s = 0 */
+  int64_t n_zero_weight;         /* nodes with w_k = 0 (no load transferred) */
+  int64_t n_band_cells;          /* cells that received a source */
+  int64_t n_pairs;               /* (cell, beam) pairs inside the 3 eps cutoff */
+  int64_t n_overflow;            /* work-list overflow flags (non-zero: results invalid) */
+  int64_t n_invalid;             /* points with eps <= 0, a zero tangent or non-finite data */
+  double F_beam[3];   /* sum_k f_k L_k  (force on the beam, eq. 14) */
+  double F_fluid[3];  /* sum_j S_j V_j  (force on the fluid, eq. 14) */
+  double cons_rel_err; /* |F_fluid + F_beam| / sum_k |f_k L_k| */
+} alp_diag;
+
+/* Create a context on HIP device `device` that launches on `hip_stream`
+   (a hipStream_t, or NULL for the null stream).  Synchronous. */
+alp_status alp_create(int device, void *hip_stream, alp_context **out);
+/* Free the context, its workspace and captured graphs.  Synchronous. */
+alp_status alp_destroy(alp_context *ctx);
+/* Text of the last error on this context ("" if none).  Valid until the next call. */
+const char *alp_last_error(const alp_context *ctx);
+
+/* Bin a static mesh once (the paper builds its search structure once at the
+   start of the run, Sec. 3.2.5): a uniform spatial hash of the cell centres,
+   the cells sorted by (tile, bin) with a counting sort, bin CSR, sorted FP64
+   centres and volumes, and the permutation back to the caller's order.
+     n_cells     >= 1, < 2^31
+     C           DEVICE [n_cells][3] cell centres
+     V           DEVICE [n_cells] cell volumes (> 0)
+     domain_box  HOST [6] (lo x,y,z, hi x,y,z) or NULL = AABB of the centres
+                 inflated by half the largest V^(1/3); points outside it carry no load
+     bin_size    > 0, or <= 0 for the cube root of the mean cell volume
+     tile_bins   bins per tile edge (1..8), or 0 for the default (4)
+   The mesh keeps its own copies; C and V may be freed afterwards.  Synchronous. */
+alp_status alp_bin_cells(alp_context *ctx, int64_t n_cells, const double *C, const double *V,
+                         const double *domain_box, double bin_size, int32_t tile_bins,
+                         alp_mesh **out);
+alp_status alp_mesh_destroy(alp_mesh *mesh);
+
+/* Eq. (16)-(18): locate each actuator point, build the upstream sampling point,
+   locate it and sample the velocity of that single cell.
+     U       DEVICE [n_cells][3] velocity in the caller's cell order
+     U_s     DEVICE out [n_points][3] sampled velocity (0 for points outside)
+     P_s     DEVICE out [n_points][3] sampling points, or NULL
+     cell_a  DEVICE out [n_points] cell of P_a (caller's order, -1 outside), or NULL
+     cell_s  DEVICE out [n_points] cell of P_s (-1 outside), or NULL  */
+alp_status alp_sample(alp_context *ctx, const alp_mesh *mesh, const double *U,
+                      const alp_beams *beams, const alp_params *params, double *U_s,
+                      double *P_s, int64_t *cell_a, int64_t *cell_s);
+
+/* Eq. (19) (or eq. 6) and eq. (20): line force on the beam from the sampled
+   velocity.  cell_s (nullable) marks points without a sample (< 0): they carry
+   no load.  f_prev (nullable) enables relaxation with params->alpha_f.
+     f  DEVICE out [n_points][3]  */
+alp_status alp_drag(alp_context *ctx, const alp_beams *beams, const alp_params *params,
+                    const double *U_s, const int64_t *cell_s, const double *f_prev, double *f);
+
+/* Eq. (21)-(23) and Sec. 3.2.4: nodal weights, normalised forces and the
+   momentum source, using beams->P_spread (or P).
+     f     DEVICE [n_points][3] line force on the beam
+     S     DEVICE out [n_cells][3] source in the caller's order; every cell is
+           written (zero outside the 3 eps band)
+     w     DEVICE out [n_points] nodal weights w_k, or NULL
+     fhat  DEVICE out [n_points][3] normalised nodal forces f_k L_k / w_k, or NULL  */
+alp_status alp_spread(alp_context *ctx, const alp_mesh *mesh, const alp_beams *beams,
+                      const alp_params *params, const double *f, double *S, double *w,
+                      double *fhat);
+
+/* One independent coupling case of a batch.  Outputs other than f and S are
+   nullable. */
+typedef struct {
+  const alp_mesh *mesh;
+  const double *U;      /* DEVICE [n_cells][3] */
+  alp_beams beams;
+  alp_params params;
+  const double *f_prev; /* DEVICE [n_points][3] or NULL (no relaxation) */
+  double *f;            /* DEVICE out [n_points][3] */
+  double *S;            /* DEVICE out [n_cells][3] */
+  double *U_s;          /* DEVICE out [n_points][3] or NULL */
+  double *w;            /* DEVICE out [n_points] or NULL */
+  double *P_s;          /* DEVICE out [n_points][3] or NULL */
+  int64_t *cell_a;      /* DEVICE out [n_points] cell of P_a (-1 outside) or NULL */
+  int64_t *cell_s;      /* DEVICE out [n_points] cell of P_s (-1 outside) or NULL */
+} alp_case;
+
+#define ALP_USE_GRAPH 1u /* capture the step on the first call, replay it afterwards */
+#define ALP_CHECKED 2u   /* synchronise at the end and grow the work lists on overflow */
+
+/* A whole coupling step (sample -> drag -> project) for n_cases independent
+   cases in one set of launches: every stage runs once over the concatenated
+   work of all cases.  cases is a HOST array.  With ALP_USE_GRAPH the first call
+   for a given set of cases captures the launch sequence in a hipGraph and later
+   calls with identical case descriptors replay it; the arrays in the cases may
+   be updated in place between replays.  A mesh may appear in at most one case
+   of a batch. */
+alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *cases,
+                            uint32_t flags);
+
+/* Diagnostics of case `case_index` of the last step (or of the last
+   alp_sample / alp_spread pair, index 0).  Synchronous. */
+alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out);
+
+/* Drop captured graphs and work-list sizing (call after shape changes). */
+alp_status alp_invalidate(alp_context *ctx);
+
+/* Run one un-captured step of alp_step_batched (same arguments, flags
+   ignored) with HIP events recorded on the context stream between its stages,
+   synchronise, and return the duration of each stage in milliseconds:
+     stage_ms   HOST out [max_stages]; stage i is named by alp_stage_name(i)
+     n_stages   HOST out, number of stages written
+   The step's outputs are produced as by alp_step_batched.  For measurement. */
+alp_status alp_step_profile(alp_context *ctx, int32_t n_cases, const alp_case *cases,
+                            double *stage_ms, int32_t max_stages, int32_t *n_stages);
+/* Name of profiling stage i ("" when out of range). */
+const char *alp_stage_name(int32_t i);
+
+/* Library version string. */
+const char *alp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ALP_H */

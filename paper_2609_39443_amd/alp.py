@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libalp (include/alp.h).
+
+Argument marshalling only: every step of the coupling operator runs in the HIP
+kernels of libalp.so.  PyTorch supplies device memory (tensors on ``cuda``,
+i.e. HIP) and the stream.  The functions carry the C names; ``Context`` is a
+small convenience wrapper around them.  Importing this module does not need a
+GPU; loading the library does need libalp.so, and using it needs a GPU.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libalp.so")
+
+ALP_OK = 0
+STATUS = {0: "ALP_OK", -1: "ALP_ERR_INVALID_ARG", -2: "ALP_ERR_HIP", -3: "ALP_ERR_OOM",
+          -4: "ALP_ERR_CAPTURE", -5: "ALP_ERR_SHAPE", -6: "ALP_ERR_CAPACITY"}
+PREC_FP64, PREC_FP32_SPLIT = 0, 1
+DRAG_FULLMAG, DRAG_COMPONENTWISE = 0, 1
+USE_GRAPH, CHECKED = 1, 2
+
+# every symbol include/alp.h declares
+EXPORTS = ("alp_create", "alp_destroy", "alp_last_error", "alp_bin_cells", "alp_mesh_destroy",
+           "alp_sample", "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag",
+           "alp_invalidate", "alp_version", "alp_step_profile", "alp_stage_name")
+
+
+class AlpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class alp_beams(ct.Structure):
+    _fields_ = [("n_beams", ct.c_int32), ("reserved0", ct.c_int32), ("n_points", ct.c_int64),
+                ("offsets", ct.c_void_p), ("P", ct.c_void_p), ("P_spread", ct.c_void_p),
+                ("e_t", ct.c_void_p), ("Pdot", ct.c_void_p), ("d", ct.c_void_p), ("L", ct.c_void_p),
+                ("eps", ct.c_void_p), ("Cdn", ct.c_void_p), ("Cdt", ct.c_void_p), ("ls", ct.c_void_p),
+                ("n_p", ct.c_void_p), ("e_up", ct.c_void_p)]
+
+
+class alp_params(ct.Structure):
+    _fields_ = [("rho", ct.c_double), ("alpha_f", ct.c_double), ("tau", ct.c_double),
+                ("prec", ct.c_int32), ("drag_form", ct.c_int32)]
+
+
+class alp_diag(ct.Structure):
+    _fields_ = [("n_outside", ct.c_int64), ("n_fallback", ct.c_int64),
+                ("n_fallback_degenerate", ct.c_int64), ("n_zero_weight", ct.c_int64),
+                ("n_band_cells", ct.c_int64), ("n_pairs", ct.c_int64), ("n_overflow", ct.c_int64),
+                ("n_invalid", ct.c_int64), ("F_beam", ct.c_double * 3), ("F_fluid", ct.c_double * 3),
+                ("cons_rel_err", ct.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("F_beam", "F_fluid")}
+        d["F_beam"] = list(self.F_beam)
+        d["F_fluid"] = list(self.F_fluid)
+        return d
+
+
+class alp_case(ct.Structure):
+    _fields_ = [("mesh", ct.c_void_p), ("U", ct.c_void_p), ("beams", alp_beams),
+                ("params", alp_params), ("f_prev", ct.c_void_p), ("f", ct.c_void_p),
+                ("S", ct.c_void_p), ("U_s", ct.c_void_p), ("w", ct.c_void_p), ("P_s", ct.c_void_p),
+                ("cell_a", ct.c_void_p), ("cell_s", ct.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load libalp.so; raises if it was not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python -m paper_2609_39443_amd.build")
+    lib = ct.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_uint32
+    lib.alp_create.argtypes = [ct.c_int, vp, ct.POINTER(vp)]
+    lib.alp_destroy.argtypes = [vp]
+    lib.alp_last_error.argtypes = [vp]
+    lib.alp_last_error.restype = ct.c_char_p
+    lib.alp_bin_cells.argtypes = [vp, i64, vp, vp, vp, ct.c_double, i32, ct.POINTER(vp)]
+    lib.alp_mesh_destroy.argtypes = [vp]
+    lib.alp_sample.argtypes = [vp, vp, vp, ct.POINTER(alp_beams), ct.POINTER(alp_params), vp, vp, vp, vp]
+    lib.alp_drag.argtypes = [vp, ct.POINTER(alp_beams), ct.POINTER(alp_params), vp, vp, vp, vp]
+    lib.alp_spread.argtypes = [vp, vp, ct.POINTER(alp_beams), ct.POINTER(alp_params), vp, vp, vp, vp]
+    lib.alp_step_batched.argtypes = [vp, i32, ct.POINTER(alp_case), u32]
+    lib.alp_get_diag.argtypes = [vp, i32, ct.POINTER(alp_diag)]
+    lib.alp_invalidate.argtypes = [vp]
+    lib.alp_version.restype = ct.c_char_p
+    lib.alp_step_profile.argtypes = [vp, i32, ct.POINTER(alp_case), ct.POINTER(ct.c_double), i32,
+                                     ct.POINTER(i32)]
+    lib.alp_step_profile.restype = ct.c_int
+    lib.alp_stage_name.argtypes = [i32]
+    lib.alp_stage_name.restype = ct.c_char_p
+    for name in ("alp_create", "alp_destroy", "alp_bin_cells", "alp_mesh_destroy", "alp_sample",
+                 "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag", "alp_invalidate"):
+        getattr(lib, name).restype = ct.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libalp takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libalp takes contiguous tensors")
+    return t.data_ptr()
+
+
+def _check(ctx_handle, status):
+    if status != ALP_OK:
+        msg = load().alp_last_error(ctx_handle).decode(errors="replace")
+        raise AlpError(status, msg)
+
+
+# ------------------------------------------------------------ C-named calls --
+def alp_create(device=0, stream=None):
+    h = ct.c_void_p()
+    st = ct.c_void_p(stream) if stream else None
+    s = load().alp_create(int(device), st, ct.byref(h))
+    if s != ALP_OK:
+        raise AlpError(s, "alp_create failed")
+    return h
+
+
+def alp_destroy(ctx):
+    _check(None, load().alp_destroy(ctx))
+
+
+def alp_bin_cells(ctx, C, V, domain_box=None, bin_size=0.0, tile_bins=0):
+    h = ct.c_void_p()
+    box = None if domain_box is None else (ct.c_double * 6)(*[float(x) for x in domain_box])
+    _check(ctx, load().alp_bin_cells(ctx, C.shape[0], _ptr(C), _ptr(V), box, float(bin_size),
+                                     int(tile_bins), ct.byref(h)))
+    return h
+
+
+def alp_mesh_destroy(mesh):
+    load().alp_mesh_destroy(mesh)
+
+
+def alp_sample(ctx, mesh, U, beams: alp_beams, params: alp_params, U_s, P_s=None, cell_a=None,
+               cell_s=None):
+    _check(ctx, load().alp_sample(ctx, mesh, _ptr(U), ct.byref(beams), ct.byref(params), _ptr(U_s),
+                                  _ptr(P_s), _ptr(cell_a), _ptr(cell_s)))
+
+
+def alp_drag(ctx, beams: alp_beams, params: alp_params, U_s, cell_s, f_prev, f):
+    _check(ctx, load().alp_drag(ctx, ct.byref(beams), ct.byref(params), _ptr(U_s), _ptr(cell_s),
+                                _ptr(f_prev), _ptr(f)))
+
+
+def alp_spread(ctx, mesh, beams: alp_beams, params: alp_params, f, S, w=None, fhat=None):
+    _check(ctx, load().alp_spread(ctx, mesh, ct.byref(beams), ct.byref(params), _ptr(f), _ptr(S),
+                                  _ptr(w), _ptr(fhat)))
+
+
+def alp_step_batched(ctx, cases, flags=0):
+    arr = (alp_case * len(cases))(*cases)
+    _check(ctx, load().alp_step_batched(ctx, len(cases), arr, int(flags)))
+
+
+def alp_get_diag(ctx, case_index=0):
+    d = alp_diag()
+    _check(ctx, load().alp_get_diag(ctx, int(case_index), ct.byref(d)))
+    return d.as_dict()
+
+
+def alp_invalidate(ctx):
+    _check(ctx, load().alp_invalidate(ctx))
+
+
+def alp_version():
+    return load().alp_version().decode()
+
+
+def alp_step_profile(ctx, cases, max_stages=16):
+    arr = (alp_case * len(cases))(*cases)
+    ms = (ct.c_double * max_stages)()
+    n = ct.c_int32()
+    _check(ctx, load().alp_step_profile(ctx, len(cases), arr, ms, max_stages, ct.byref(n)))
+    return {load().alp_stage_name(i).decode(): ms[i] for i in range(n.value)}
+
+
+# ---------------------------------------------------------------- helpers --
+class DeviceBeams:
+    """Device copy of a beam-set dict (see workloads.py) and its alp_beams view."""
+
+    KEYS3 = ("P", "e_t", "Pdot")
+
+    def __init__(self, beams: dict, device="cuda"):
+        import numpy as np
+        import torch
+
+        def f64(a):
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+        self.offsets = torch.as_tensor(np.ascontiguousarray(beams["offsets"], dtype=np.int64), device=device)
+        self.t = {k: f64(beams[k]) for k in ("P", "e_t", "Pdot", "d", "L", "eps", "Cdn", "Cdt", "ls",
+                                               "n_p", "e_up")}
+        ps = beams.get("P_spread")
+        self.t["P_spread"] = None if ps is None else f64(ps)
+        self.n_beams = int(self.offsets.shape[0] - 1)
+        self.n_points = int(self.t["P"].shape[0])
+        self.struct = self.make_struct()
+
+    def make_struct(self):
+        t = self.t
+        return alp_beams(self.n_beams, 0, self.n_points, _ptr(self.offsets), _ptr(t["P"]),
+                         _ptr(t["P_spread"]), _ptr(t["e_t"]), _ptr(t["Pdot"]), _ptr(t["d"]),
+                         _ptr(t["L"]), _ptr(t["eps"]), _ptr(t["Cdn"]), _ptr(t["Cdt"]), _ptr(t["ls"]),
+                         _ptr(t["n_p"]), _ptr(t["e_up"]))
+
+
+def make_params(params: dict, prec=PREC_FP64):
+    form = params.get("drag_form", DRAG_FULLMAG)
+    if isinstance(form, str):
+        form = {"fullmag": DRAG_FULLMAG, "componentwise": DRAG_COMPONENTWISE}[form]
+    return alp_params(float(params["rho"]), float(params.get("alpha_f", 1.0)),
+                      float(params.get("tau", 1e-6)), int(prec), int(form))
+
+
+class Context:
+    """One libalp context on the current torch stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.h = alp_create(device, stream)
+        self.meshes = []
+
+    def close(self):
+        if self.h is not None:
+            for m in self.meshes:
+                alp_mesh_destroy(m)
+            self.meshes = []
+            alp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bin_cells(self, C, V, domain_box=None, bin_size=0.0, tile_bins=0):
+        m = alp_bin_cells(self.h, C, V, domain_box, bin_size, tile_bins)
+        self.meshes.append(m)
+        return m
+
+    def diag(self, case_index=0):
+        return alp_get_diag(self.h, case_index)

@@ -1,0 +1,906 @@
+// alp_api.hip -- host side of libalp: contexts, mesh binning, argument
+// validation, workspace sizing, the launch sequence of a coupling step,
+// hipGraph capture and replay, and diagnostics read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "alp_internal.h"
+
+using namespace alp;
+
+struct alp_mesh {
+  int device = 0;
+  MeshDev d{};
+  uint32_t *bin_start = nullptr;
+  double *cx = nullptr, *cy = nullptr, *cz = nullptr, *vs = nullptr;
+  uint32_t *perm = nullptr;
+  uint8_t *tile_prev = nullptr;
+  const double *last_S = nullptr;  // output array the band state refers to
+};
+
+struct alp_context {
+  int device = 0;
+  hipStream_t user = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::string err;
+  int n_cu = 256;
+  // workspace
+  Work w{};
+  std::vector<void *> wallocs;
+  int64_t have_points = -1, have_beams = -1, have_tiles = -1, have_cases = -1, have_pblocks = -1;
+  int64_t have_emit = -1, have_item = -1, have_rec = -1, have_chunk = -1;
+  uint32_t *scan_tmp = nullptr;
+  int64_t have_scan = -1;
+  // case tables
+  CaseDev *d_cases = nullptr;
+  int64_t *d_bases = nullptr;  // [3][cap_cases+1]: points, beams, tiles
+  int cap_cases = 0;
+  std::vector<CaseDev> h_cases;
+  std::vector<int64_t> h_bases;
+  std::vector<int32_t> h_pbcase;
+  std::vector<int64_t> h_pbrange;
+  // graph
+  hipGraphExec_t gexec = nullptr;
+  std::vector<alp_case> gkey;
+  uint32_t gflags = 0;
+  int last_cases = 0;
+};
+
+namespace {
+
+alp_status fail(alp_context *ctx, alp_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? ALP_ERR_OOM : ALP_ERR_HIP, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                           \
+  } while (0)
+
+template <typename T>
+alp_status dalloc(alp_context *ctx, T **p, int64_t n) {
+  *p = nullptr;
+  size_t bytes = (size_t)(n > 0 ? n : 1) * sizeof(T);
+  HIPCHK(ctx, hipMalloc((void **)p, bytes));
+  return ALP_OK;
+}
+
+void free_work(alp_context *ctx) {
+  for (void *p : ctx->wallocs) (void)hipFree(p);
+  ctx->wallocs.clear();
+  std::memset(&ctx->w, 0, sizeof(ctx->w));
+  ctx->have_points = ctx->have_beams = ctx->have_tiles = ctx->have_cases = ctx->have_pblocks = -1;
+  ctx->have_emit = ctx->have_item = ctx->have_rec = ctx->have_chunk = -1;
+  if (ctx->scan_tmp) (void)hipFree(ctx->scan_tmp);
+  ctx->scan_tmp = nullptr;
+  ctx->have_scan = -1;
+}
+
+void drop_graph(alp_context *ctx) {
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  ctx->gexec = nullptr;
+  ctx->gkey.clear();
+}
+
+bool is_capturing(alp_context *ctx) {
+  hipStreamCaptureStatus s = hipStreamCaptureStatusNone;
+  if (ctx->user && hipStreamIsCapturing(ctx->user, &s) == hipSuccess &&
+      s != hipStreamCaptureStatusNone)
+    return true;
+  return false;
+}
+
+// event ordering between the caller's stream and the internal stream
+alp_status enter(alp_context *ctx) {
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->st, ctx->ev_in, 0));
+  return ALP_OK;
+}
+alp_status leave(alp_context *ctx) {
+  HIPCHK(ctx, hipEventRecord(ctx->ev_out, ctx->st));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
+  return ALP_OK;
+}
+
+
+// Work-list capacities and per-case sizes for one step.
+struct StepShape {
+  int n_cases = 0;
+  int64_t n_points = 0, n_beams = 0, n_tiles = 0, n_cells = 0;
+  int64_t cap_chunk = 0, cap_item = 0;
+  int n_pblocks = 0;
+};
+
+alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit, int64_t want_rec) {
+  Work &w = ctx->w;
+  bool grow = sh.n_points > ctx->have_points || sh.n_beams > ctx->have_beams ||
+              sh.n_tiles > ctx->have_tiles || sh.n_cases > ctx->have_cases ||
+              sh.n_pblocks > ctx->have_pblocks || want_emit > ctx->have_emit ||
+              sh.cap_item > ctx->have_item || want_rec > ctx->have_rec ||
+              sh.cap_chunk > ctx->have_chunk;
+  if (!grow) {
+    w.n_points = sh.n_points;
+    w.n_beams = sh.n_beams;
+    w.n_tiles = sh.n_tiles;
+    w.n_cases = sh.n_cases;
+    w.n_pblocks = sh.n_pblocks;
+    return ALP_OK;
+  }
+  drop_graph(ctx);
+  (void)hipStreamSynchronize(ctx->st);
+  // keep every dimension at least as large as before
+  int64_t P = std::max(sh.n_points, ctx->have_points), B = std::max(sh.n_beams, ctx->have_beams);
+  int64_t T = std::max(sh.n_tiles, ctx->have_tiles);
+  int64_t NC = std::max<int64_t>(sh.n_cases, ctx->have_cases);
+  int64_t PB = std::max<int64_t>(sh.n_pblocks, ctx->have_pblocks);
+  int64_t EM = std::max(want_emit, ctx->have_emit), IT = std::max(sh.cap_item, ctx->have_item);
+  int64_t RC = std::max(want_rec, ctx->have_rec), CH = std::max(sh.cap_chunk, ctx->have_chunk);
+  free_work(ctx);
+  std::vector<void *> &A = ctx->wallocs;
+  alp_status rc;
+#define WALLOC(field, n)                                  \
+  do {                                                    \
+    if ((rc = dalloc(ctx, &w.field, (n))) != ALP_OK) return rc; \
+    A.push_back((void *)w.field);                         \
+  } while (0)
+  WALLOC(pbeam, P);
+  WALLOC(pflags, P);
+  WALLOC(wexp, P);
+  WALLOC(w_hi, P);
+  WALLOC(w_lo, P);
+  WALLOC(fhat, 3 * P);
+  WALLOC(Us, 3 * P);
+  WALLOC(f, 3 * P);
+  WALLOC(bcase, B);
+  WALLOC(beps_max, B);
+  WALLOC(bchunks, B + 1);
+  WALLOC(chunk_beam, CH);
+  WALLOC(chunk_s0, CH);
+  WALLOC(chunk_s1, CH);
+  WALLOC(tile_cnt, T + 1);
+  WALLOC(tile_off, T + 1);
+  WALLOC(tile_fill, T + 1);
+  WALLOC(tile_nent, T + 1);
+  WALLOC(tile_items, T + 1);
+  WALLOC(tile_itoff, T + 1);
+  WALLOC(emit, EM);
+  WALLOC(entry, EM);
+  WALLOC(item, IT);
+  WALLOC(rec_base, IT);
+  WALLOC(rec_cnt, IT);
+  WALLOC(rec, RC);
+  w.item_F = nullptr;
+  WALLOC(F_hi, 3 * NC);
+  WALLOC(F_lo, 3 * NC);
+  WALLOC(F_exp, NC);
+  WALLOC(beam_part, 4 * PB);
+  WALLOC(pblock_case, PB);
+  WALLOC(pblock_range, 2 * PB);
+  WALLOC(cnt, 8 * NC);
+  WALLOC(diag_out, 16 * NC);
+  WALLOC(counters, 16);
+#undef WALLOC
+  int64_t sc = scan_tmp_words(std::max({B + 1, T + 1, (int64_t)1}));
+  if ((rc = dalloc(ctx, &ctx->scan_tmp, sc)) != ALP_OK) return rc;
+  ctx->have_scan = sc;
+  HIPCHK(ctx, hipMemsetAsync(w.counters, 0, 16 * sizeof(uint32_t), ctx->st));
+  HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, 8 * NC * sizeof(long long), ctx->st));
+  HIPCHK(ctx, hipMemsetAsync(w.diag_out, 0, 16 * NC * sizeof(double), ctx->st));
+  w.cap_emit = EM;
+  w.cap_item = IT;
+  w.cap_rec = RC;
+  w.cap_chunk = CH;
+  ctx->have_points = P;
+  ctx->have_beams = B;
+  ctx->have_tiles = T;
+  ctx->have_cases = NC;
+  ctx->have_pblocks = PB;
+  ctx->have_emit = EM;
+  ctx->have_item = IT;
+  ctx->have_rec = RC;
+  ctx->have_chunk = CH;
+  w.n_points = sh.n_points;
+  w.n_beams = sh.n_beams;
+  w.n_tiles = sh.n_tiles;
+  w.n_cases = sh.n_cases;
+  w.n_pblocks = sh.n_pblocks;
+  return ALP_OK;
+}
+
+alp_status ensure_cases(alp_context *ctx, int n) {
+  if (n <= ctx->cap_cases) return ALP_OK;
+  drop_graph(ctx);
+  (void)hipStreamSynchronize(ctx->st);
+  if (ctx->d_cases) (void)hipFree(ctx->d_cases);
+  if (ctx->d_bases) (void)hipFree(ctx->d_bases);
+  ctx->d_cases = nullptr;
+  ctx->d_bases = nullptr;
+  int cap = std::max(n, 8);
+  alp_status rc;
+  if ((rc = dalloc(ctx, &ctx->d_cases, cap)) != ALP_OK) return rc;
+  if ((rc = dalloc(ctx, &ctx->d_bases, 3 * (cap + 1))) != ALP_OK) return rc;
+  ctx->cap_cases = cap;
+  return ALP_OK;
+}
+
+alp_status check_beams(alp_context *ctx, const alp_beams *b, bool need_spread_fields,
+                       bool need_sample_fields, bool copy_offsets) {
+  if (!b) return fail(ctx, ALP_ERR_INVALID_ARG, "beams is NULL");
+  if (b->n_beams < 0 || b->n_points < 0 || b->n_points >= (int64_t)INT32_MAX)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "bad beam counts (n_beams=%d, n_points=%lld)",
+                b->n_beams, (long long)b->n_points);
+  if (b->n_beams > 0 && !b->offsets) return fail(ctx, ALP_ERR_INVALID_ARG, "beams.offsets is NULL");
+  if (b->n_points > 0) {
+    if (!b->P || !b->e_t || !b->Pdot || !b->d || !b->L || !b->eps)
+      return fail(ctx, ALP_ERR_INVALID_ARG, "a per-point beam array is NULL");
+  }
+  if (b->n_beams > 0 && (!b->Cdn || !b->Cdt || !b->ls || !b->n_p || !b->e_up))
+    return fail(ctx, ALP_ERR_INVALID_ARG, "a per-beam array is NULL");
+  (void)need_spread_fields;
+  (void)need_sample_fields;
+  if (copy_offsets && b->n_beams > 0) {
+    // read on the caller's stream, which produced the array
+    std::vector<int64_t> off((size_t)b->n_beams + 1);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipMemcpyAsync(off.data(), b->offsets, off.size() * sizeof(int64_t),
+                               hipMemcpyDeviceToHost, ctx->user));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->user));
+    if (off[0] != 0 || off[b->n_beams] != b->n_points)
+      return fail(ctx, ALP_ERR_INVALID_ARG, "beams.offsets must start at 0 and end at n_points");
+    for (int32_t i = 0; i < b->n_beams; ++i)
+      if (off[i + 1] < off[i]) return fail(ctx, ALP_ERR_INVALID_ARG, "beams.offsets decreases at %d", i);
+  }
+  if (b->n_beams == 0 && b->n_points != 0)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "points without beams");
+  return ALP_OK;
+}
+
+alp_status check_params(alp_context *ctx, const alp_params *p, bool relax) {
+  if (!p) return fail(ctx, ALP_ERR_INVALID_ARG, "params is NULL");
+  if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return fail(ctx, ALP_ERR_INVALID_ARG, "rho must be > 0");
+  if (relax && !(p->alpha_f > 0.0 && p->alpha_f <= 1.0))
+    return fail(ctx, ALP_ERR_INVALID_ARG, "alpha_f must be in (0, 1]");
+  if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(ctx, ALP_ERR_INVALID_ARG, "tau must be >= 0");
+  if (p->prec != ALP_PREC_FP64 && p->prec != ALP_PREC_FP32_SPLIT)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "unknown precision %d", p->prec);
+  if (p->drag_form != ALP_DRAG_FULLMAG && p->drag_form != ALP_DRAG_COMPONENTWISE)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "unknown drag form %d", p->drag_form);
+  return ALP_OK;
+}
+
+void fill_case(CaseDev &c, const alp_mesh *m, const alp_beams *b, const alp_params *p) {
+  std::memset(&c, 0, sizeof(c));
+  if (m) c.m = m->d;
+  c.n_points = b->n_points;
+  c.n_beams = b->n_beams;
+  c.prec = p->prec;
+  c.drag_form = p->drag_form;
+  c.rho = p->rho;
+  c.alpha_f = p->alpha_f;
+  c.tau = p->tau;
+  c.offsets = b->offsets;
+  c.P = b->P;
+  c.Psp = b->P_spread ? b->P_spread : b->P;
+  c.e_t = b->e_t;
+  c.Pdot = b->Pdot;
+  c.d = b->d;
+  c.L = b->L;
+  c.eps = b->eps;
+  c.Cdn = b->Cdn;
+  c.Cdt = b->Cdt;
+  c.ls = b->ls;
+  c.n_p = b->n_p;
+  c.e_up = b->e_up;
+  if (m) c.tile_prev = m->tile_prev;
+}
+
+// global bases, point blocks for the beam-side sums, capacities
+StepShape shape_cases(alp_context *ctx, std::vector<CaseDev> &cs) {
+  StepShape sh;
+  sh.n_cases = (int)cs.size();
+  ctx->h_bases.assign(3 * (cs.size() + 1), 0);
+  ctx->h_pbcase.clear();
+  ctx->h_pbrange.clear();
+  int64_t P = 0, B = 0, T = 0, NC = 0, CH = 0, IT = 0;
+  for (size_t i = 0; i < cs.size(); ++i) {
+    CaseDev &c = cs[i];
+    c.point_base = P;
+    c.beam_base = B;
+    c.tile_base = T;
+    ctx->h_bases[i] = P;
+    ctx->h_bases[(cs.size() + 1) + i] = B;
+    ctx->h_bases[2 * (cs.size() + 1) + i] = T;
+    for (int64_t k0 = 0; k0 < c.n_points; k0 += 1024) {
+      ctx->h_pbcase.push_back((int32_t)i);
+      ctx->h_pbrange.push_back(k0);
+      ctx->h_pbrange.push_back(std::min<int64_t>(k0 + 1024, c.n_points));
+    }
+    P += c.n_points;
+    B += c.n_beams;
+    T += c.m.n_tiles;
+    NC += c.m.n_cells;
+    CH += c.n_beams + (c.n_points + kChunkSegs - 1) / kChunkSegs + 1;
+    IT += c.m.n_tiles + (c.m.n_cells + 63) / 64;
+  }
+  ctx->h_bases[cs.size()] = P;
+  ctx->h_bases[2 * cs.size() + 1] = B;
+  ctx->h_bases[3 * cs.size() + 2] = T;
+  sh.n_points = P;
+  sh.n_beams = B;
+  sh.n_tiles = T;
+  sh.n_cells = NC;
+  sh.cap_chunk = CH;
+  sh.cap_item = IT;
+  sh.n_pblocks = (int)ctx->h_pbcase.size();
+  return sh;
+}
+
+alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const StepShape &sh) {
+  alp_status rc;
+  if ((rc = ensure_cases(ctx, (int)cs.size())) != ALP_OK) return rc;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_cases, cs.data(), cs.size() * sizeof(CaseDev),
+                             hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_bases, ctx->h_bases.data(), ctx->h_bases.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, ctx->st));
+  if (sh.n_pblocks > 0) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->w.pblock_case, ctx->h_pbcase.data(),
+                               ctx->h_pbcase.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->w.pblock_range, ctx->h_pbrange.data(),
+                               ctx->h_pbrange.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->st));
+  }
+  // the host copies must outlive the asynchronous transfer
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return ALP_OK;
+}
+
+StepLaunch make_launch(alp_context *ctx, int n_cases) {
+  StepLaunch L;
+  L.cases = ctx->d_cases;
+  L.pbase = ctx->d_bases;
+  L.bbase = ctx->d_bases + (n_cases + 1);
+  L.tbase = ctx->d_bases + 2 * (n_cases + 1);
+  L.w = ctx->w;
+  L.n_cases = n_cases;
+  L.grid_persistent = ctx->n_cu * 16;
+  return L;
+}
+
+enum { ST_SAMPLE = 1, ST_DRAG = 2, ST_PROJECT = 4, ST_ALL = 7 };
+
+const char *const kStageNames[] = {"prep", "sample", "drag", "segment_binning", "weights",
+                                   "normalise", "spread", "finalise"};
+constexpr int kNumStages = 8;
+
+// the launch sequence of one step (no host synchronisation inside); when ev is
+// given, ev[i+1] is recorded after stage i (ev[0] before the first)
+void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent_t *ev = nullptr) {
+  hipStream_t st = ctx->st;
+  const Work &w = L.w;
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], st);
+  };
+  mark(0);
+  if ((stages & ST_PROJECT) && (stages & ST_SAMPLE)) launch_step_reset(L, st);
+  else if (stages & ST_PROJECT) launch_step_reset_project(L, st);
+  else if (stages & ST_SAMPLE) launch_step_reset_sample(L, st);
+  launch_points_prep(L, st);
+  mark(1);
+  if (stages & ST_SAMPLE) launch_sample(L, st);
+  mark(2);
+  if (stages & ST_DRAG) launch_drag(L, st);
+  mark(3);
+  if (!(stages & ST_PROJECT)) return;
+  launch_beams_prep(L, st);
+  launch_scan_u32(w.bchunks, w.bchunks, w.n_beams, ctx->scan_tmp, st);
+  launch_chunks(L, st);
+  launch_chunk_tiles(L, 0, st);
+  launch_scan_u32(w.tile_cnt, w.tile_off, w.n_tiles, ctx->scan_tmp, st);
+  launch_chunk_tiles(L, 1, st);
+  launch_tile_merge(L, st);
+  launch_scan_u32(w.tile_items, w.tile_itoff, w.n_tiles, ctx->scan_tmp, st);
+  launch_items(L, st);
+  mark(4);
+  launch_weights(L, st);
+  mark(5);
+  launch_norm(L, st);
+  launch_beam_sums(L, st);
+  mark(6);
+  launch_spread(L, st);
+  mark(7);
+  launch_zero_dirty(L, st);
+  launch_finalize(L, st);
+  mark(8);
+}
+
+// Clear S and the band state when an output array is used with a mesh for
+// the first time (the incremental zeroing assumes S held the last source).
+alp_status prepare_outputs(alp_context *ctx, const std::vector<alp_mesh *> &meshes,
+                           const std::vector<double *> &S) {
+  for (size_t i = 0; i < meshes.size(); ++i) {
+    alp_mesh *m = meshes[i];
+    if (!m || !S[i]) continue;
+    if (m->last_S != S[i]) {
+      launch_fill_f64(S[i], 0.0, 3 * (int64_t)m->d.n_cells, ctx->st);
+      launch_fill_u8(m->tile_prev, 0, m->d.n_tiles, ctx->st);
+      m->last_S = S[i];
+    }
+  }
+  HIPCHK(ctx, hipGetLastError());
+  return ALP_OK;
+}
+
+// read the overflow word and the sizes the lists needed (synchronises)
+alp_status read_needs(alp_context *ctx, uint32_t &ovf, int64_t &need_emit, int64_t &need_rec) {
+  uint32_t cnt[16];
+  uint32_t em = 0;
+  HIPCHK(ctx, hipMemcpyAsync(cnt, ctx->w.counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->st));
+  if (ctx->w.n_tiles > 0)
+    HIPCHK(ctx, hipMemcpyAsync(&em, ctx->w.tile_off + ctx->w.n_tiles, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  ovf = cnt[3];
+  need_emit = em;
+  need_rec = cnt[2];
+  return ALP_OK;
+}
+
+alp_status run_checked(alp_context *ctx, std::vector<CaseDev> &cs, int stages,
+                       const std::vector<alp_mesh *> &meshes, const std::vector<double *> &S) {
+  StepShape sh = shape_cases(ctx, cs);
+  int64_t want_emit = std::max<int64_t>(ctx->have_emit, 16 * sh.n_points + 4096);
+  int64_t want_rec = std::max<int64_t>(ctx->have_rec, 4 * sh.n_cells + (1 << 20));
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    alp_status rc = ensure_work(ctx, sh, want_emit, want_rec);
+    if (rc != ALP_OK) return rc;
+    if ((rc = upload_cases(ctx, cs, sh)) != ALP_OK) return rc;
+    if ((rc = prepare_outputs(ctx, meshes, S)) != ALP_OK) return rc;
+    StepLaunch L = make_launch(ctx, (int)cs.size());
+    launch_sequence(ctx, L, stages);
+    HIPCHK(ctx, hipGetLastError());
+    if (!(stages & ST_PROJECT)) return ALP_OK;
+    uint32_t ovf;
+    int64_t ne, nr;
+    if ((rc = read_needs(ctx, ovf, ne, nr)) != ALP_OK) return rc;
+    if (ovf == 0) return ALP_OK;
+    if (ovf & (4u | 8u | 16u))
+      return fail(ctx, ALP_ERR_CAPACITY,
+                  "per-tile limits exceeded (flags 0x%x): more than %d beams or %d emissions in one "
+                  "tile, or a segment window longer than 65535",
+                  ovf, kMaxEntries, kMaxEmit);
+    want_emit = std::max(want_emit, ne + ne / 2 + 1024);
+    want_rec = std::max(want_rec, nr + nr / 2 + 1024);
+    // the band state was updated by the failed attempt: force a full clear
+    for (alp_mesh *m : meshes)
+      if (m) m->last_S = nullptr;
+  }
+  return fail(ctx, ALP_ERR_CAPACITY, "work lists kept overflowing");
+}
+
+}  // namespace
+
+// ================================================================= C ABI ==
+extern "C" {
+
+const char *alp_version(void) { return "libalp 0.1 (gfx950)"; }
+
+alp_status alp_create(int device, void *hip_stream, alp_context **out) {
+  if (!out) return ALP_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return ALP_ERR_HIP;
+  if (device < 0 || device >= ndev) return ALP_ERR_INVALID_ARG;
+  alp_context *ctx = new alp_context();
+  ctx->device = device;
+  ctx->user = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess) {
+    delete ctx;
+    return ALP_ERR_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->n_cu = prop.multiProcessorCount;
+  *out = ctx;
+  return ALP_OK;
+}
+
+alp_status alp_destroy(alp_context *ctx) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->st);
+  drop_graph(ctx);
+  free_work(ctx);
+  if (ctx->d_cases) (void)hipFree(ctx->d_cases);
+  if (ctx->d_bases) (void)hipFree(ctx->d_bases);
+  (void)hipEventDestroy(ctx->ev_in);
+  (void)hipEventDestroy(ctx->ev_out);
+  (void)hipStreamDestroy(ctx->st);
+  delete ctx;
+  return ALP_OK;
+}
+
+const char *alp_last_error(const alp_context *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+alp_status alp_bin_cells(alp_context *ctx, int64_t n_cells, const double *C, const double *V,
+                         const double *domain_box, double bin_size, int32_t tile_bins,
+                         alp_mesh **out) {
+  if (!ctx || !out) return fail(ctx, ALP_ERR_INVALID_ARG, "NULL context or output");
+  *out = nullptr;
+  if (n_cells < 1 || n_cells >= (int64_t)INT32_MAX)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "n_cells must be in [1, 2^31)");
+  if (!C || !V) return fail(ctx, ALP_ERR_INVALID_ARG, "C or V is NULL");
+  if (tile_bins == 0) tile_bins = 4;
+  if (tile_bins < 1 || tile_bins > 8) return fail(ctx, ALP_ERR_INVALID_ARG, "tile_bins must be in 1..8");
+  if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "alp_bin_cells cannot run under capture");
+  if (domain_box) {
+    for (int a = 0; a < 3; ++a)
+      if (!(domain_box[a] <= domain_box[3 + a]) || !std::isfinite(domain_box[a]) ||
+          !std::isfinite(domain_box[3 + a]))
+        return fail(ctx, ALP_ERR_INVALID_ARG, "domain_box must satisfy lo <= hi and be finite");
+  }
+  alp_status rc = enter(ctx);
+  if (rc != ALP_OK) return rc;
+  hipStream_t st = ctx->st;
+  // bounds of the centres and the largest volume
+  int nblk = mesh_bounds_blocks(n_cells);
+  double *part = nullptr;
+  if ((rc = dalloc(ctx, &part, 7 * nblk)) != ALP_OK) return rc;
+  launch_mesh_bounds(C, V, n_cells, part, nblk, st);
+  std::vector<double> hp(7 * (size_t)nblk);
+  HIPCHK(ctx, hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  (void)hipFree(part);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, vmax = 0;
+  for (int b = 0; b < nblk; ++b) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::fmin(lo[a], hp[7 * b + a]);
+      hi[a] = std::fmax(hi[a], hp[7 * b + 3 + a]);
+    }
+    vmax = std::fmax(vmax, hp[7 * b + 6]);
+  }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]))
+      return fail(ctx, ALP_ERR_INVALID_ARG, "cell centres must be finite");
+  if (!(vmax > 0.0) || !std::isfinite(vmax))
+    return fail(ctx, ALP_ERR_INVALID_ARG, "cell volumes must be positive and finite");
+  alp_mesh *m = new alp_mesh();
+  m->device = ctx->device;
+  MeshDev &d = m->d;
+  d.n_cells = (int32_t)n_cells;
+  d.T = tile_bins;
+  d.vmax = vmax;
+  double pad = 0.5 * std::cbrt(vmax);
+  for (int a = 0; a < 3; ++a) {
+    d.box[a] = domain_box ? domain_box[a] : lo[a] - pad;
+    d.box[3 + a] = domain_box ? domain_box[3 + a] : hi[a] + pad;
+  }
+  double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
+  double b = bin_size;
+  if (!(b > 0.0) || !std::isfinite(b)) {
+    // cube root of the mean cell volume of the AABB (the cell size for a uniform mesh)
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) vol *= std::max(hi[a] - lo[a] + 2 * pad, 1e-3 * (ext + 2 * pad));
+    b = std::cbrt(vol / (double)n_cells);
+  }
+  if (!(b > 0.0)) b = 1.0;
+  // keep the number of bins bounded (<= 4 n + 512 before tiling)
+  for (;;) {
+    double nbins = 1;
+    for (int a = 0; a < 3; ++a) nbins *= std::floor((hi[a] - lo[a]) / b) + 1;
+    if (nbins <= 4.0 * (double)n_cells + 512.0) break;
+    b *= 1.25;
+  }
+  d.bin = b;
+  d.inv_bin = 1.0 / b;
+  d.tile_len = b * tile_bins;
+  int64_t nbins = 1, ntiles = 1;
+  for (int a = 0; a < 3; ++a) {
+    d.lo[a] = lo[a];
+    int64_t n = (int64_t)std::floor((hi[a] - lo[a]) / b) + 1;
+    int64_t t = (n + tile_bins - 1) / tile_bins;
+    d.nt[a] = (int32_t)t;
+    d.nb[a] = (int32_t)(t * tile_bins);
+    nbins *= d.nb[a];
+    ntiles *= t;
+  }
+  if (nbins >= (int64_t)UINT32_MAX - 1) {
+    delete m;
+    return fail(ctx, ALP_ERR_INVALID_ARG, "mesh needs too many bins (%lld)", (long long)nbins);
+  }
+  d.n_bins = nbins;
+  d.n_tiles = ntiles;
+  uint32_t *key = nullptr, *count = nullptr, *fillc = nullptr, *tmp = nullptr;
+#define MALLOC_OR_FAIL(p, n)                      \
+  if ((rc = dalloc(ctx, &(p), (n))) != ALP_OK) { \
+    alp_mesh_destroy(m);                          \
+    return rc;                                    \
+  }
+  MALLOC_OR_FAIL(m->bin_start, nbins + 1);
+  MALLOC_OR_FAIL(m->cx, n_cells);
+  MALLOC_OR_FAIL(m->cy, n_cells);
+  MALLOC_OR_FAIL(m->cz, n_cells);
+  MALLOC_OR_FAIL(m->vs, n_cells);
+  MALLOC_OR_FAIL(m->perm, n_cells);
+  MALLOC_OR_FAIL(m->tile_prev, ntiles);
+  MALLOC_OR_FAIL(key, n_cells);
+  MALLOC_OR_FAIL(count, nbins + 1);
+  MALLOC_OR_FAIL(fillc, nbins + 1);
+  MALLOC_OR_FAIL(tmp, scan_tmp_words(nbins + 1));
+#undef MALLOC_OR_FAIL
+  launch_fill_u32(count, 0u, nbins + 1, st);
+  launch_fill_u32(fillc, 0u, nbins + 1, st);
+  launch_fill_u8(m->tile_prev, 0, ntiles, st);
+  launch_bin_keys(d, C, n_cells, key, count, st);
+  launch_scan_u32(count, m->bin_start, nbins, tmp, st);
+  launch_bin_scatter(key, n_cells, m->bin_start, fillc, m->perm, st);
+  launch_bin_sort(m->bin_start, nbins, m->perm, st);
+  launch_bin_reorder(C, V, m->perm, n_cells, m->cx, m->cy, m->cz, m->vs, st);
+  hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(key);
+  (void)hipFree(count);
+  (void)hipFree(fillc);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    alp_mesh_destroy(m);
+    return fail(ctx, ALP_ERR_HIP, "binning failed: %s", hipGetErrorString(e));
+  }
+  d.bin_start = m->bin_start;
+  d.cx = m->cx;
+  d.cy = m->cy;
+  d.cz = m->cz;
+  d.vs = m->vs;
+  d.perm = m->perm;
+  *out = m;
+  return leave(ctx);
+}
+
+alp_status alp_mesh_destroy(alp_mesh *m) {
+  if (!m) return ALP_ERR_INVALID_ARG;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  void *ps[] = {m->bin_start, m->cx, m->cy, m->cz, m->vs, m->perm, m->tile_prev};
+  for (void *p : ps)
+    if (p) (void)hipFree(p);
+  delete m;
+  return ALP_OK;
+}
+
+alp_status alp_sample(alp_context *ctx, const alp_mesh *mesh, const double *U,
+                      const alp_beams *beams, const alp_params *params, double *U_s, double *P_s,
+                      int64_t *cell_a, int64_t *cell_s) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!mesh || !U || !U_s) return fail(ctx, ALP_ERR_INVALID_ARG, "mesh, U or U_s is NULL");
+  alp_status rc;
+  if ((rc = check_beams(ctx, beams, false, true, true)) != ALP_OK) return rc;
+  if ((rc = check_params(ctx, params, false)) != ALP_OK) return rc;
+  if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "use alp_step_batched under capture");
+  if (beams->n_points == 0) return ALP_OK;
+  if ((rc = enter(ctx)) != ALP_OK) return rc;
+  std::vector<CaseDev> cs(1);
+  fill_case(cs[0], mesh, beams, params);
+  cs[0].U = U;
+  cs[0].U_s = U_s;
+  cs[0].P_s = P_s;
+  cs[0].cell_a = cell_a;
+  cs[0].cell_s = cell_s;
+  cs[0].tile_prev = nullptr;
+  if ((rc = run_checked(ctx, cs, ST_SAMPLE, {}, {})) != ALP_OK) return rc;
+  ctx->last_cases = 1;
+  return leave(ctx);
+}
+
+alp_status alp_drag(alp_context *ctx, const alp_beams *beams, const alp_params *params,
+                    const double *U_s, const int64_t *cell_s, const double *f_prev, double *f) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!U_s || !f) return fail(ctx, ALP_ERR_INVALID_ARG, "U_s or f is NULL");
+  alp_status rc;
+  if ((rc = check_beams(ctx, beams, false, true, true)) != ALP_OK) return rc;
+  if ((rc = check_params(ctx, params, f_prev != nullptr)) != ALP_OK) return rc;
+  if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "use alp_step_batched under capture");
+  if (beams->n_points == 0) return ALP_OK;
+  if ((rc = enter(ctx)) != ALP_OK) return rc;
+  std::vector<CaseDev> cs(1);
+  fill_case(cs[0], nullptr, beams, params);
+  cs[0].U_s = const_cast<double *>(U_s);
+  cs[0].cell_s = const_cast<int64_t *>(cell_s);
+  cs[0].f_prev = f_prev;
+  cs[0].has_fprev = f_prev != nullptr;
+  cs[0].f = f;
+  StepShape sh = shape_cases(ctx, cs);
+  if ((rc = ensure_work(ctx, sh, std::max<int64_t>(ctx->have_emit, 1), std::max<int64_t>(ctx->have_rec, 1))) != ALP_OK)
+    return rc;
+  if ((rc = upload_cases(ctx, cs, sh)) != ALP_OK) return rc;
+  StepLaunch L = make_launch(ctx, 1);
+  launch_points_prep(L, ctx->st);
+  launch_drag_mode(L, 1, ctx->st);
+  HIPCHK(ctx, hipGetLastError());
+  return leave(ctx);
+}
+
+alp_status alp_spread(alp_context *ctx, const alp_mesh *mesh, const alp_beams *beams,
+                      const alp_params *params, const double *f, double *S, double *w,
+                      double *fhat) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!mesh || !f || !S) return fail(ctx, ALP_ERR_INVALID_ARG, "mesh, f or S is NULL");
+  alp_status rc;
+  if ((rc = check_beams(ctx, beams, true, false, true)) != ALP_OK) return rc;
+  if ((rc = check_params(ctx, params, false)) != ALP_OK) return rc;
+  if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "use alp_step_batched under capture");
+  if ((rc = enter(ctx)) != ALP_OK) return rc;
+  std::vector<CaseDev> cs(1);
+  alp_mesh *m = const_cast<alp_mesh *>(mesh);
+  fill_case(cs[0], m, beams, params);
+  cs[0].f = const_cast<double *>(f);
+  cs[0].S = S;
+  cs[0].w = w;
+  cs[0].fhat = fhat;
+  cs[0].write_S = 1;
+  if ((rc = run_checked(ctx, cs, ST_PROJECT, {m}, {S})) != ALP_OK) return rc;
+  ctx->last_cases = 1;
+  return leave(ctx);
+}
+
+alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *cases,
+                            uint32_t flags) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (n_cases < 1 || !cases) return fail(ctx, ALP_ERR_INVALID_ARG, "need n_cases >= 1 and cases");
+  if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "the stream is capturing");
+  bool use_graph = (flags & ALP_USE_GRAPH) != 0;
+  alp_status rc;
+  // replay an existing graph for identical case descriptors
+  if (use_graph && ctx->gexec && (int)ctx->gkey.size() == n_cases && ctx->gflags == flags &&
+      std::memcmp(ctx->gkey.data(), cases, sizeof(alp_case) * (size_t)n_cases) == 0) {
+    if ((rc = enter(ctx)) != ALP_OK) return rc;
+    HIPCHK(ctx, hipGraphLaunch(ctx->gexec, ctx->st));
+    if (flags & ALP_CHECKED) {
+      uint32_t ovf;
+      int64_t ne, nr;
+      if ((rc = read_needs(ctx, ovf, ne, nr)) != ALP_OK) return rc;
+      if (ovf) return fail(ctx, ALP_ERR_CAPACITY, "work list overflow in graph replay (0x%x); call alp_invalidate", ovf);
+    }
+    ctx->last_cases = n_cases;
+    return leave(ctx);
+  }
+  std::vector<CaseDev> cs((size_t)n_cases);
+  std::vector<alp_mesh *> meshes((size_t)n_cases);
+  std::vector<double *> S((size_t)n_cases);
+  for (int i = 0; i < n_cases; ++i) {
+    const alp_case &c = cases[i];
+    if (!c.mesh || !c.U || !c.f || !c.S)
+      return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: mesh, U, f and S are required", i);
+    for (int j = 0; j < i; ++j)
+      if (cases[j].mesh == c.mesh)
+        return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: a mesh may appear in one case per batch", i);
+    if ((rc = check_beams(ctx, &c.beams, true, true, true)) != ALP_OK) return rc;
+    if ((rc = check_params(ctx, &c.params, c.f_prev != nullptr)) != ALP_OK) return rc;
+    alp_mesh *m = const_cast<alp_mesh *>(c.mesh);
+    fill_case(cs[i], m, &c.beams, &c.params);
+    cs[i].U = c.U;
+    cs[i].f_prev = c.f_prev;
+    cs[i].has_fprev = c.f_prev != nullptr;
+    cs[i].f = c.f;
+    cs[i].S = c.S;
+    cs[i].U_s = c.U_s;
+    cs[i].w = c.w;
+    cs[i].P_s = c.P_s;
+    cs[i].cell_a = c.cell_a;
+    cs[i].cell_s = c.cell_s;
+    cs[i].write_S = 1;
+    meshes[i] = m;
+    S[i] = c.S;
+  }
+  if ((rc = enter(ctx)) != ALP_OK) return rc;
+  // size the work lists with a checked run (this also produces this step's result)
+  if ((rc = run_checked(ctx, cs, ST_ALL, meshes, S)) != ALP_OK) return rc;
+  ctx->last_cases = n_cases;
+  if (use_graph) {
+    drop_graph(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+    StepLaunch L = make_launch(ctx, n_cases);
+    hipGraph_t g = nullptr;
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->st, hipStreamCaptureModeThreadLocal));
+    launch_sequence(ctx, L, ST_ALL);
+    hipError_t e = hipStreamEndCapture(ctx->st, &g);
+    if (e != hipSuccess) return fail(ctx, ALP_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      ctx->gexec = nullptr;
+      return fail(ctx, ALP_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    ctx->gkey.assign(cases, cases + n_cases);
+    ctx->gflags = flags;
+  }
+  return leave(ctx);
+}
+
+const char *alp_stage_name(int32_t i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : ""; }
+
+alp_status alp_step_profile(alp_context *ctx, int32_t n_cases, const alp_case *cases,
+                            double *stage_ms, int32_t max_stages, int32_t *n_stages) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  if (!stage_ms || !n_stages || max_stages < 1)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "stage_ms, n_stages and max_stages >= 1 are required");
+  // validate, size and warm the work lists exactly like an uncaptured batched step
+  alp_status rc = alp_step_batched(ctx, n_cases, cases, 0);
+  if (rc != ALP_OK) return rc;
+  hipEvent_t ev[kNumStages + 1];
+  for (int i = 0; i <= kNumStages; ++i) HIPCHK(ctx, hipEventCreate(&ev[i]));
+  StepLaunch L = make_launch(ctx, n_cases);
+  if ((rc = enter(ctx)) != ALP_OK) return rc;
+  launch_sequence(ctx, L, ST_ALL, ev);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipEventSynchronize(ev[kNumStages]));
+  int n = std::min<int>(max_stages, kNumStages);
+  for (int i = 0; i < n; ++i) {
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    stage_ms[i] = ms;
+  }
+  for (int i = 0; i <= kNumStages; ++i) (void)hipEventDestroy(ev[i]);
+  *n_stages = n;
+  return leave(ctx);
+}
+
+alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out) {
+  if (!ctx || !out) return fail(ctx, ALP_ERR_INVALID_ARG, "NULL argument");
+  if (case_index < 0 || case_index >= ctx->last_cases || !ctx->w.cnt)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "no diagnostics for case %d", case_index);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  long long cnt[8];
+  double d[16];
+  uint32_t counters[16];
+  HIPCHK(ctx, hipMemcpyAsync(cnt, ctx->w.cnt + 8 * case_index, sizeof(cnt), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(d, ctx->w.diag_out + 16 * case_index, sizeof(d), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(counters, ctx->w.counters, sizeof(counters), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  std::memset(out, 0, sizeof(*out));
+  out->n_outside = cnt[0];
+  out->n_fallback = cnt[1];
+  out->n_fallback_degenerate = cnt[2];
+  out->n_zero_weight = cnt[3];
+  out->n_band_cells = cnt[4];
+  out->n_pairs = cnt[5];
+  out->n_invalid = cnt[6];
+  out->n_overflow = counters[3];
+  for (int a = 0; a < 3; ++a) {
+    out->F_beam[a] = d[a];
+    out->F_fluid[a] = d[4 + a];
+  }
+  out->cons_rel_err = d[7];
+  return ALP_OK;
+}
+
+alp_status alp_invalidate(alp_context *ctx) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->st);
+  drop_graph(ctx);
+  return ALP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+// alp_internal.h -- device-side data layout and helpers shared by the libalp
+// kernels (gfx950).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "alp.h"
+
+namespace alp {
+
+constexpr int kWave = 64;
+constexpr int kChunkSegs = 8;       // segments per emission chunk (segment binning)
+constexpr int kMaxEntries = 256;    // (tile, beam) entries per tile handled by one wave
+constexpr int kMaxEmit = 1024;      // emissions per tile the merge can sort
+constexpr int kNodeSlots = 512;     // per-wave LDS node accumulators (w_k partials)
+constexpr int kHiShift = 46;        // fixed-point: hi word holds v * 2^(46-E)
+constexpr int kLoBits = 40;         // lo word holds the next 40 bits
+constexpr int kSampleLanes = 1;     // threads per actuator point in the sampler
+
+// Binned mesh, device view (built by alp_bin_cells).
+struct MeshDev {
+  int32_t n_cells;
+  int32_t T;        // bins per tile edge
+  int32_t nb[3];    // bins per axis (multiple of T)
+  int32_t nt[3];    // tiles per axis
+  int64_t n_bins, n_tiles;
+  double lo[3];     // grid origin
+  double bin, inv_bin, tile_len;
+  double box[6];    // domain box (outside -> no load)
+  double vmax;      // largest cell volume
+  const uint32_t *bin_start;  // [n_bins+1] sorted-cell ranges, bins in tile-major order
+  const double *cx, *cy, *cz; // [n] sorted centres (FP64, absolute)
+  const double *vs;           // [n] sorted volumes
+  const uint32_t *perm;       // [n] sorted -> caller index
+};
+
+// One case of a step, device view.  Points, beams and tiles of all cases are
+// concatenated into global index spaces (the *_base fields).
+struct CaseDev {
+  MeshDev m;
+  int64_t point_base, beam_base, tile_base;
+  int64_t n_points;
+  int32_t n_beams;
+  int32_t prec, drag_form;
+  int32_t has_fprev;
+  double rho, alpha_f, tau;
+  const int64_t *offsets;
+  const double *P, *Psp, *e_t, *Pdot, *d, *L, *eps, *Cdn, *Cdt, *ls, *n_p, *e_up;
+  const double *U;
+  const double *f_prev;
+  double *S, *f, *U_s, *P_s, *w, *fhat;
+  int64_t *cell_a, *cell_s;
+  uint8_t *tile_prev;   // [n_tiles] tiles written at the previous step of this mesh
+  int32_t write_S;      // spread writes S (0 for sample/drag-only calls)
+  int32_t pad_;
+};
+
+// A (tile, beam) entry: the beam's candidate segment window for the tile and
+// a screening capsule in tile-local FP32 coordinates.
+struct Entry {
+  int32_t kp;   // global point index of the beam's first point
+  int32_t nb;   // points of the beam
+  int32_t i0, i1;  // candidate segments i0..i1 (nb == 1: 0..0, the point kernel)
+  float ax, ay, az, bx, by, bz;  // screening chord, tile-local
+  float r2;     // screening radius^2 (conservative)
+  int32_t beam; // global beam index
+};
+
+struct Emit {
+  int32_t beam, lo, hi, pad;
+};
+
+struct Item {
+  int32_t tile;   // global tile index
+  int32_t c0, c1; // sorted cell range
+  int32_t cs;     // case index
+};
+
+// Per-step workspace (device pointers), sized by the host.
+struct Work {
+  // points (global index)
+  int32_t *pbeam;       // point -> global beam
+  int32_t *pflags;      // sampling flags
+  int32_t *wexp;        // per-node fixed-point exponent
+  long long *w_hi;      // per-node fixed-point accumulators
+  unsigned long long *w_lo;
+  double *fhat;         // [N_P][3]
+  double *Us;           // [N_P][3] internal sampled velocity
+  double *f;            // [N_P][3] internal force (when the case has none)
+  // beams (global)
+  int32_t *bcase;       // beam -> case
+  double *beps_max;     // beam max eps
+  uint32_t *bchunks;    // chunks per beam, then exclusive scan ([N_B+1])
+  // chunks
+  int32_t *chunk_beam, *chunk_s0, *chunk_s1;
+  // tiles (global)
+  uint32_t *tile_cnt;   // emissions per tile, scanned into tile_off ([N_T+1])
+  uint32_t *tile_off;
+  uint32_t *tile_fill;
+  uint32_t *tile_nent;  // merged entries per tile
+  uint32_t *tile_items; // work items per tile, scanned ([N_T+1])
+  uint32_t *tile_itoff;
+  // lists
+  Emit *emit;           // [cap_emit]
+  Entry *entry;         // [cap_emit] (same offsets as emit)
+  Item *item;           // [cap_item]
+  uint32_t *rec_base, *rec_cnt;  // per item
+  uint32_t *rec;        // [cap_rec]
+  double *item_F;       // [cap_item][3] (unused slots ignored)
+  // per-case reductions
+  long long *F_hi;      // [n_cases][3]
+  unsigned long long *F_lo;
+  int32_t *F_exp;       // [n_cases]
+  double *beam_part;    // [n_pblocks][4] (F_beam xyz, sum |f L|)
+  int32_t *pblock_case; // [n_pblocks]
+  int64_t *pblock_range;// [n_pblocks][2]
+  long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, spare
+  double *diag_out;     // [n_cases][16] finalised diagnostics
+  // scalars
+  uint32_t *counters;   // [16]: 0 items counter (weights), 1 items counter (spread), 2 record alloc,
+                        // 3 overflow flag, 4 n_items total, 5 n_emit total, 6 chunks total
+  int64_t cap_emit, cap_item, cap_rec, cap_chunk;
+  int64_t n_points, n_beams, n_tiles;
+  int32_t n_cases, n_pblocks;
+};
+
+// ----------------------------------------------------------------- helpers --
+// Decision arithmetic (nearest cell, nearest segment, cutoff): the one
+// evaluation order dot(a,b) = (ax bx + ay by) + az bz, IEEE operations, no
+// contraction into fused multiply-adds, so that every decision is bitwise
+// reproducible on any IEEE FP64 machine.
+__device__ __forceinline__ double dot3_exact(double ax, double ay, double az, double bx, double by,
+                                             double bz) {
+#pragma clang fp contract(off)
+  return (ax * bx + ay * by) + az * bz;
+}
+
+// Closest point of segment [A, B] to C (eq. 21): foot parameter s in [0, 1]
+// (0 for a zero-length segment) and squared distance r2.
+__device__ __forceinline__ void seg_foot(double cx, double cy, double cz, double ax, double ay,
+                                         double az, double bx, double by, double bz, double &s,
+                                         double &r2) {
+#pragma clang fp contract(off)
+  double ex = bx - ax, ey = by - ay, ez = bz - az;
+  double qx = cx - ax, qy = cy - ay, qz = cz - az;
+  double t = (qx * ex + qy * ey) + qz * ez;
+  double ee = (ex * ex + ey * ey) + ez * ez;
+  double u = 0.0;
+  if (ee > 0.0) {
+    u = t / ee;
+    if (u < 0.0) u = 0.0;
+    if (u > 1.0) u = 1.0;
+  }
+  double px = qx - u * ex, py = qy - u * ey, pz = qz - u * ez;
+  r2 = (px * px + py * py) + pz * pz;
+  s = u;
+}
+
+__device__ __forceinline__ double sqdist_exact(double cx, double cy, double cz, double ax, double ay,
+                                               double az) {
+#pragma clang fp contract(off)
+  double qx = cx - ax, qy = cy - ay, qz = cz - az;
+  return (qx * qx + qy * qy) + qz * qz;
+}
+
+// Kernel width at the foot point (per-point eps interpolated with the linear
+// weights) and the inclusive 3 eps cutoff, evaluated in FP64.
+__device__ __forceinline__ double eps_at(double s, double e0, double e1) {
+#pragma clang fp contract(off)
+  return (1.0 - s) * e0 + s * e1;
+}
+__device__ __forceinline__ bool inside_cutoff(double r2, double ej) {
+#pragma clang fp contract(off)
+  return r2 <= 9.0 * (ej * ej);
+}
+
+// Truncated 2D Gaussian of eq. (22) times the linear weights of Sec. 3.2.4:
+// a0 = (1 - s) eta, a1 = s eta.  In the split precision eta and the weights
+// are FP32 (the values are then widened to FP64 for every product and sum).
+// Both projection passes call this with identical arguments, so the weights
+// that build w_k and the ones that build S are bit-identical.
+__device__ __forceinline__ void pair_weights(int prec, double s, double r2, double ej, double &a0,
+                                             double &a1) {
+  if (prec == ALP_PREC_FP32_SPLIT) {
+    float e2 = (float)(ej * ej);
+    float x = (float)r2 / e2;
+    float eta = expf(-x) / (3.14159265358979323846f * e2);
+    float sf = (float)s;
+    a0 = (double)((1.0f - sf) * eta);
+    a1 = (double)(sf * eta);
+  } else {
+    double e2 = ej * ej;
+    double eta = exp(-(r2 / e2)) / (3.14159265358979323846 * e2);
+    a0 = (1.0 - s) * eta;
+    a1 = s * eta;
+  }
+}
+
+// Exact fixed-point accumulation (order independent, so deterministic under
+// any work distribution or atomic order).  A non-negative or signed value v
+// with |v| < 2^E is split into hi = floor(v 2^(46-E)) and
+// lo = floor(frac * 2^40); both are summed as 64-bit integers.
+__device__ __forceinline__ void fx_encode(double v, int E, long long &hi, unsigned long long &lo) {
+  double t = ldexp(v, kHiShift - E);
+  double th = floor(t);
+  double r = t - th;  // exact, in [0, 1)
+  double tl = floor(ldexp(r, kLoBits));
+  hi = (long long)th;
+  lo = (unsigned long long)tl;
+}
+__device__ __host__ inline double fx_decode(long long hi, unsigned long long lo, int E) {
+  hi += (long long)(lo >> kLoBits);
+  lo &= ((1ull << kLoBits) - 1ull);
+  return ldexp((double)hi, E - kHiShift) + ldexp((double)lo, E - kHiShift - kLoBits);
+}
+
+// bin key: tiles in x-fastest order, then bins inside the tile x-fastest
+__device__ __host__ inline uint32_t bin_key(const MeshDev &m, int ix, int iy, int iz) {
+  int T = m.T;
+  int tx = ix / T, ty = iy / T, tz = iz / T;
+  int lx = ix - tx * T, ly = iy - ty * T, lz = iz - tz * T;
+  uint32_t tile = (uint32_t)((tz * m.nt[1] + ty) * m.nt[0] + tx);
+  return tile * (uint32_t)(T * T * T) + (uint32_t)((lz * T + ly) * T + lx);
+}
+
+__device__ __forceinline__ int case_of(const int64_t *bases, int n, int64_t idx) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (bases[mid] <= idx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------- launchers --
+// (defined in the kernel translation units)
+void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t st);
+int64_t scan_tmp_words(int64_t n);
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t st);
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t st);
+void launch_fill_i64(long long *p, long long v, int64_t n, hipStream_t st);
+
+// mesh binning
+void launch_mesh_bounds(const double *C, const double *V, int64_t n, double *part, int nblk,
+                        hipStream_t st);
+int mesh_bounds_blocks(int64_t n);
+void launch_bin_keys(const MeshDev &m, const double *C, int64_t n, uint32_t *key, uint32_t *count,
+                     hipStream_t st);
+void launch_bin_scatter(const uint32_t *key, int64_t n, const uint32_t *start, uint32_t *fill,
+                        uint32_t *sorted, hipStream_t st);
+void launch_bin_sort(const uint32_t *start, int64_t n_bins, uint32_t *sorted, hipStream_t st);
+void launch_bin_reorder(const double *C, const double *V, const uint32_t *sorted, int64_t n,
+                        double *cx, double *cy, double *cz, double *vs, hipStream_t st);
+
+// step
+struct StepLaunch {
+  const CaseDev *cases;    // device
+  const int64_t *pbase;    // device [n_cases+1] point bases
+  const int64_t *bbase;    // device [n_cases+1] beam bases
+  const int64_t *tbase;    // device [n_cases+1] tile bases
+  Work w;
+  int n_cases;
+  int grid_persistent;     // blocks for persistent wave kernels
+};
+void launch_step_reset(const StepLaunch &L, hipStream_t st);
+void launch_step_reset_sample(const StepLaunch &L, hipStream_t st);
+void launch_step_reset_project(const StepLaunch &L, hipStream_t st);
+void launch_drag_mode(const StepLaunch &L, int use_cell_s, hipStream_t st);
+void launch_points_prep(const StepLaunch &L, hipStream_t st);
+void launch_beams_prep(const StepLaunch &L, hipStream_t st);
+void launch_chunks(const StepLaunch &L, hipStream_t st);
+void launch_chunk_tiles(const StepLaunch &L, int emit, hipStream_t st);
+void launch_tile_merge(const StepLaunch &L, hipStream_t st);
+void launch_items(const StepLaunch &L, hipStream_t st);
+void launch_sample(const StepLaunch &L, hipStream_t st);
+void launch_drag(const StepLaunch &L, hipStream_t st);
+void launch_weights(const StepLaunch &L, hipStream_t st);
+void launch_norm(const StepLaunch &L, hipStream_t st);
+void launch_beam_sums(const StepLaunch &L, hipStream_t st);
+void launch_spread(const StepLaunch &L, hipStream_t st);
+void launch_zero_dirty(const StepLaunch &L, hipStream_t st);
+void launch_finalize(const StepLaunch &L, hipStream_t st);
+
+}  // namespace alp

@@ -1,0 +1,252 @@
+"""GPU parity: libalp (HIP, through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (from the arithmetic, stated per precision):
+  - integer work (cell indices, pair/band/zero-weight counts): exact;
+  - the sampled velocity is a copy of one cell's value: exact;
+  - ALP_PREC_FP64: every geometric decision is taken in FP64 with the same
+    expressions and order as the oracle, so only summation order and the
+    last-ulp differences of exp differ: w, f, S <= 1e-12 relative (normwise);
+  - ALP_PREC_FP32_SPLIT: eta and the linear weights are FP32 (relative error a
+    few 1e-7 through exp of an argument up to 9); S and w <= 1e-5;
+  - conservation |F_fluid + F_beam| / sum |f L| <= 1e-12 in both modes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2609_39443_amd import alp  # noqa: E402
+from paper_2609_39443_amd import workloads as W  # noqa: E402
+
+TOL = {alp.PREC_FP64: (1e-12, 1e-12), alp.PREC_FP32_SPLIT: (1e-5, 1e-5)}
+
+
+@pytest.fixture(scope="module")
+def gu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import gpu_util
+    return gpu_util
+
+
+@pytest.fixture(scope="module")
+def ctx(gu):
+    alp.load()
+    c = alp.Context(0)
+    yield c
+    c.close()
+
+
+def random_scene(seed, nx=26, ny=22, nz=18, h=0.01, n_beams=6, jitter=True, outside=False,
+                 single=True):
+    rng = np.random.default_rng(seed)
+    C, _ = W.uniform_mesh(nx, ny, nz, h)
+    if jitter:
+        C = C + rng.uniform(-0.3 * h, 0.3 * h, size=C.shape)
+        V = h ** 3 * np.exp(0.3 * rng.normal(size=C.shape[0]))
+        perm = rng.permutation(C.shape[0])
+        C, V = C[perm], V[perm]
+    else:
+        V = np.full(C.shape[0], h ** 3)
+    pts, tan, pd, dd, LL, ee = [], [], [], [], [], []
+    for b in range(n_beams):
+        n = 1 if (single and b == 0) else int(rng.integers(2, 40))
+        start = rng.uniform([0.04, 0.04, 0.01], [nx * h - 0.04, ny * h - 0.04, 0.04])
+        d0 = rng.normal(size=3) * 0.4 + np.array([0, 0, 1.0])
+        d0 /= np.linalg.norm(d0)
+        steps = (d0[None, :] + 0.15 * rng.normal(size=(n, 3))) * rng.uniform(0.4, 1.2) * h
+        P = start + np.cumsum(steps, axis=0)
+        t = np.gradient(P, axis=0) if n > 1 else d0[None, :]
+        pts.append(P)
+        tan.append(t / np.linalg.norm(t, axis=1, keepdims=True))
+        pd.append(0.02 * rng.normal(size=(n, 3)))
+        dd.append(np.full(n, rng.uniform(0.001, 0.005)))
+        LL.append(np.full(n, 0.8 * h))
+        ee.append(rng.uniform(1.0, 3.0, size=n) * h)
+    if outside:
+        pts[-1][-1] = [-0.05, 0.1, 0.1]
+    beams = W._beamset(pts, tan, pd, dd, LL, ee, rng.uniform(1, 3, n_beams), np.full(n_beams, 0.05),
+                       rng.uniform(0.02, 0.06, n_beams), np.zeros((n_beams, 3)),
+                       np.tile([-1.0, 0, 0], (n_beams, 1)))
+    U = np.tile([0.3, 0.0, 0.0], (C.shape[0], 1)) + 0.05 * rng.normal(size=C.shape)
+    return {"name": f"random-{seed}", "C": C, "V": V, "U": U, "box": None, "h": h, "beams": beams,
+            "params": {"rho": 1000.0, "alpha_f": 1.0, "tau": 1e-6, "drag_form": 0}}
+
+
+def run_and_compare(gu, ctx, wl, prec, batched=True, tile_bins=0, bin_size=0.0, f_prev=None,
+                    check_sample=True):
+    gu.log(f"[parity] {wl['name']} prec={prec} batched={batched} tile_bins={tile_bins}")
+    case = gu.GpuCase(ctx, wl, prec, tile_bins=tile_bins, bin_size=bin_size, f_prev=f_prev)
+    if batched:
+        gu.step_batched(ctx, [case])
+    else:
+        case.step_unbatched()
+    res = case.results()
+    diag = ctx.diag(0)
+    ref = gu.oracle_step(wl, f_prev=f_prev)
+    tS, tw = TOL[prec]
+    err = gu.compare(res, ref, diag, ref["diag"], tS, tw, check_sample=check_sample)
+    gu.log(f"[parity]   errors {err}")
+    return case, res, ref, diag
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+@pytest.mark.parametrize("noise", [False, True])
+def test_channel(gu, ctx, prec, noise):
+    wl = W.channel(noise=noise)
+    case, res, ref, diag = run_and_compare(gu, ctx, wl, prec)
+    if not noise:
+        assert np.allclose(res["f"], [0.3, 0, 0], rtol=1e-15, atol=0)
+        assert np.allclose(diag["F_fluid"], [-0.06, 0, 0], rtol=1e-12, atol=1e-16)
+
+
+def test_channel_unbatched_sequence(gu, ctx):
+    run_and_compare(gu, ctx, W.channel(noise=True), alp.PREC_FP64, batched=False)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_random_scenes(gu, ctx, seed, prec):
+    wl = random_scene(seed, outside=(seed % 2 == 0))
+    run_and_compare(gu, ctx, wl, prec, tile_bins=[0, 2, 3, 4, 5][seed - 1])
+
+
+def test_relaxation_and_componentwise(gu, ctx):
+    wl = random_scene(11)
+    wl["params"]["alpha_f"] = 0.35
+    wl["params"]["drag_form"] = 1
+    fp = np.random.default_rng(3).normal(size=wl["beams"]["P"].shape)
+    run_and_compare(gu, ctx, wl, alp.PREC_FP64, f_prev=fp)
+
+
+def test_small_canopy(gu, ctx):
+    wl = W.canopy(n=48, n_stems=40, cv_range=(5, 40), inset=0.05)
+    for prec in (alp.PREC_FP64, alp.PREC_FP32_SPLIT):
+        run_and_compare(gu, ctx, wl, prec)
+
+
+def test_small_wave_flume(gu, ctx):
+    for snap in (0, 1):
+        wl = W.wave_flume(snapshot=snap, nx=120, ny=30, nz=60, q=1.0236, n_cv=60, stem_len=0.18)
+        wl["beams"]["P"][:, 0] -= 0.6013 - 0.3013
+        wl["beams"]["ls"][:] = 0.2
+        run_and_compare(gu, ctx, wl, alp.PREC_FP64)
+
+
+def test_small_jittered_net(gu, ctx):
+    wl = W.jittered_net(nx=60, ny=60, nz=16, h=0.005, n_strands=12, n_cv=40, net_lo=0.03,
+                        net_hi=0.27, z0=0.05, sag=0.015)
+    for prec in (alp.PREC_FP64, alp.PREC_FP32_SPLIT):
+        run_and_compare(gu, ctx, wl, prec)
+
+
+def test_edge_cases(gu, ctx):
+    # zero weight: eps << h, beam on a cell-corner line
+    C, V = W.uniform_mesh(12, 12, 12, 0.01)
+    n = 8
+    P = np.stack([np.full(n, 0.06), np.full(n, 0.06), 0.02 + np.arange(n) * 0.01], axis=1)
+    P[3] = [0.0551, 0.0549, 0.0551]
+    P[5] = P[4]  # zero-length segment
+    beams = W._beamset([P], [np.tile([0, 0, 1.0], (n, 1))], [np.zeros((n, 3))], [np.full(n, 0.002)],
+                       [np.full(n, 0.01)], [np.full(n, 0.001)], [1.2], [0.0], [0.03], [[0, 0, 0]],
+                       [[-1.0, 0, 0]])
+    wl = {"name": "zero-weight", "C": C, "V": V, "U": np.tile([0.3, 0.1, 0.0], (C.shape[0], 1)),
+          "box": None, "beams": beams, "params": {"rho": 1000.0, "tau": 1e-6}}
+    _, _, ref, diag = run_and_compare(gu, ctx, wl, alp.PREC_FP64)
+    assert diag["n_zero_weight"] > 0
+    # single-cell mesh and a two-point beam
+    wl = {"name": "single-cell", "C": np.array([[0.5, 0.5, 0.5]]), "V": np.array([1e-3]),
+          "U": np.array([[1.0, 0.0, 0.0]]), "box": None,
+          "beams": W._beamset([np.array([[0.5, 0.5, 0.45], [0.5, 0.5, 0.55]])],
+                              [np.tile([0, 0, 1.0], (2, 1))], [np.zeros((2, 3))], [np.full(2, 0.01)],
+                              [np.full(2, 0.05)], [np.full(2, 0.05)], [1.0], [0.0], [0.0], [[0, 0, 0]],
+                              [[-1.0, 0, 0]]),
+          "params": {"rho": 1000.0, "tau": 1e-6}}
+    run_and_compare(gu, ctx, wl, alp.PREC_FP64)
+
+
+def test_batch_equals_single_cases(gu, ctx):
+    wls = [random_scene(20 + i, nx=18 + 3 * i, ny=16, nz=14, n_beams=2 + i) for i in range(4)]
+    cases = [gu.GpuCase(ctx, wl, alp.PREC_FP64) for wl in wls]
+    gu.step_batched(ctx, cases)
+    for i, (wl, case) in enumerate(zip(wls, cases)):
+        ref = gu.oracle_step(wl)
+        gu.compare(case.results(), ref, ctx.diag(i), ref["diag"], 1e-12, 1e-12)
+
+
+def test_graph_replay_bitwise_and_updates(gu, ctx):
+    wl = random_scene(31)
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP64)
+    flags = alp.USE_GRAPH
+    gu.step_batched(ctx, [case], flags)
+    first = case.results()
+    for rep in range(5):
+        gu.step_batched(ctx, [case], flags)
+        again = case.results()
+        for k in first:
+            assert np.array_equal(first[k], again[k]), (rep, k)
+    # update the velocity and beam positions in place: the replay follows them
+    wl2 = dict(wl)
+    wl2["U"] = wl["U"] * 1.3 + 0.01
+    b2 = dict(wl["beams"])
+    b2["P"] = wl["beams"]["P"] + np.array([0.004, -0.002, 0.001])
+    wl2["beams"] = b2
+    case.U.copy_(gu.dev(wl2["U"]))
+    case.beams.t["P"].copy_(gu.dev(b2["P"]))
+    gu.step_batched(ctx, [case], flags)
+    ref = gu.oracle_step(wl2)
+    gu.compare(case.results(), ref, ctx.diag(0), ref["diag"], 1e-12, 1e-12)
+    alp.alp_invalidate(ctx.h)
+
+
+def test_determinism_repeated_steps(gu, ctx):
+    wl = W.canopy(n=40, n_stems=30, cv_range=(5, 30), inset=0.04)
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP32_SPLIT)
+    gu.step_batched(ctx, [case])
+    first = case.results()
+    for _ in range(10):
+        gu.step_batched(ctx, [case])
+        r = case.results()
+        for k in first:
+            assert np.array_equal(first[k], r[k]), k
+
+
+def test_moving_band_zeroes_old_cells(gu, ctx):
+    """A beam that moves leaves no stale source behind (incremental zeroing)."""
+    wl = random_scene(41, n_beams=2, single=False)
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP64)
+    gu.step_batched(ctx, [case])
+    P = wl["beams"]["P"].copy()
+    for shift in ([0.05, 0.0, 0.0], [0.05, 0.06, 0.0], [-0.03, 0.02, 0.0]):
+        wl2 = dict(wl)
+        b2 = dict(wl["beams"])
+        b2["P"] = P + np.array(shift)
+        wl2["beams"] = b2
+        case.beams.t["P"].copy_(gu.dev(b2["P"]))
+        gu.step_batched(ctx, [case])
+        ref = gu.oracle_step(wl2)
+        gu.compare(case.results(), ref, ctx.diag(0), ref["diag"], 1e-12, 1e-12)
+
+
+def test_invalid_arguments_launch_nothing(gu, ctx):
+    wl = W.channel(noise=False)
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP64)
+    bad = alp.make_params(wl["params"])
+    bad.rho = -1.0
+    with pytest.raises(alp.AlpError) as ei:
+        alp.alp_spread(ctx.h, case.mesh, case.beams.struct, bad, case.f, case.S)
+    assert ei.value.status == -1
+    bad = alp.make_params(wl["params"])
+    bad.prec = 7
+    with pytest.raises(alp.AlpError):
+        alp.alp_sample(ctx.h, case.mesh, case.U, case.beams.struct, bad, case.U_s)
+    b = alp.DeviceBeams(wl["beams"])
+    b.offsets[-1] = 3  # last offset != n_points
+    with pytest.raises(alp.AlpError):
+        alp.alp_spread(ctx.h, case.mesh, b.make_struct(), case.params, case.f, case.S)
+    with pytest.raises(alp.AlpError):
+        alp.alp_step_batched(ctx.h, [case.case_struct(), case.case_struct()], 0)  # mesh twice
