@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-stems", type=int, default=1000,
                     help="stems in the oracle's timed sample (about 10-30 s of CPU work)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison runs")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -98,6 +100,14 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     alp.load()
+    if args.copy_probe_mb > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the HBM counters
+        nel = args.copy_probe_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     wl = W.canopy(n=args.n, n_stems=args.stems)
     log(f"workload {wl['name']}: {wl['C'].shape[0]} cells, {wl['beams']['P'].shape[0]} points "

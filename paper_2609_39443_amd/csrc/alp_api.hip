@@ -175,19 +175,19 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(chunk_beam, CH);
   WALLOC(chunk_s0, CH);
   WALLOC(chunk_s1, CH);
+  WALLOC(chunk_box, CH + 1);
   WALLOC(tile_cnt, T + 1);
   WALLOC(tile_off, T + 1);
   WALLOC(tile_fill, T + 1);
-  WALLOC(tile_nent, T + 1);
   WALLOC(tile_items, T + 1);
   WALLOC(tile_itoff, T + 1);
+  WALLOC(emit_raw, EM);
   WALLOC(emit, EM);
-  WALLOC(entry, EM);
   WALLOC(item, IT);
   WALLOC(rec_base, IT);
   WALLOC(rec_cnt, IT);
   WALLOC(rec, RC);
-  w.item_F = nullptr;
+  WALLOC(rec_alloc, 1);
   WALLOC(F_hi, 3 * NC);
   WALLOC(F_lo, 3 * NC);
   WALLOC(F_exp, NC);
@@ -198,7 +198,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(diag_out, 16 * NC);
   WALLOC(counters, 16);
 #undef WALLOC
-  int64_t sc = scan_tmp_words(std::max({B + 1, T + 1, (int64_t)1}));
+  int64_t sc = scan_tmp_words(std::max({B + 1, T + 1, CH + 1, (int64_t)1}));
   if ((rc = dalloc(ctx, &ctx->scan_tmp, sc)) != ALP_OK) return rc;
   ctx->have_scan = sc;
   HIPCHK(ctx, hipMemsetAsync(w.counters, 0, 16 * sizeof(uint32_t), ctx->st));
@@ -379,7 +379,7 @@ StepLaunch make_launch(alp_context *ctx, int n_cases) {
   L.tbase = ctx->d_bases + 2 * (n_cases + 1);
   L.w = ctx->w;
   L.n_cases = n_cases;
-  L.grid_persistent = ctx->n_cu * 16;
+  L.grid_persistent = ctx->n_cu * 8;
   return L;
 }
 
@@ -411,10 +411,12 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   launch_beams_prep(L, st);
   launch_scan_u32(w.bchunks, w.bchunks, w.n_beams, ctx->scan_tmp, st);
   launch_chunks(L, st);
-  launch_chunk_tiles(L, 0, st);
+  launch_chunk_boxes(L, st);
+  launch_scan_u32(w.chunk_box, w.chunk_box, w.cap_chunk, ctx->scan_tmp, st);
+  launch_chunk_tiles(L, st);
   launch_scan_u32(w.tile_cnt, w.tile_off, w.n_tiles, ctx->scan_tmp, st);
-  launch_chunk_tiles(L, 1, st);
-  launch_tile_merge(L, st);
+  launch_emit_scatter(L, st);
+  launch_tile_items(L, st);
   launch_scan_u32(w.tile_items, w.tile_itoff, w.n_tiles, ctx->scan_tmp, st);
   launch_items(L, st);
   mark(4);
@@ -450,15 +452,17 @@ alp_status prepare_outputs(alp_context *ctx, const std::vector<alp_mesh *> &mesh
 // read the overflow word and the sizes the lists needed (synchronises)
 alp_status read_needs(alp_context *ctx, uint32_t &ovf, int64_t &need_emit, int64_t &need_rec) {
   uint32_t cnt[16];
+  unsigned long long rb = 0;
   uint32_t em = 0;
   HIPCHK(ctx, hipMemcpyAsync(cnt, ctx->w.counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->st));
-  if (ctx->w.n_tiles > 0)
-    HIPCHK(ctx, hipMemcpyAsync(&em, ctx->w.tile_off + ctx->w.n_tiles, sizeof(uint32_t),
+  HIPCHK(ctx, hipMemcpyAsync(&rb, ctx->w.rec_alloc, sizeof(rb), hipMemcpyDeviceToHost, ctx->st));
+  if (ctx->w.cap_chunk > 0)
+    HIPCHK(ctx, hipMemcpyAsync(&em, ctx->w.chunk_box + ctx->w.cap_chunk, sizeof(em),
                                hipMemcpyDeviceToHost, ctx->st));
   HIPCHK(ctx, hipStreamSynchronize(ctx->st));
   ovf = cnt[3];
   need_emit = em;
-  need_rec = cnt[2];
+  need_rec = (int64_t)rb;
   return ALP_OK;
 }
 
@@ -466,7 +470,8 @@ alp_status run_checked(alp_context *ctx, std::vector<CaseDev> &cs, int stages,
                        const std::vector<alp_mesh *> &meshes, const std::vector<double *> &S) {
   StepShape sh = shape_cases(ctx, cs);
   int64_t want_emit = std::max<int64_t>(ctx->have_emit, 16 * sh.n_points + 4096);
-  int64_t want_rec = std::max<int64_t>(ctx->have_rec, 4 * sh.n_cells + (1 << 20));
+  int64_t want_rec = std::max<int64_t>(ctx->have_rec, 24 * (3 * sh.n_cells + (1 << 16)) +
+                                                        (int64_t)ctx->n_cu * 8 * (int64_t)kRecBlock);
   for (int attempt = 0; attempt < 4; ++attempt) {
     alp_status rc = ensure_work(ctx, sh, want_emit, want_rec);
     if (rc != ALP_OK) return rc;
@@ -482,11 +487,11 @@ alp_status run_checked(alp_context *ctx, std::vector<CaseDev> &cs, int stages,
     if (ovf == 0) return ALP_OK;
     if (ovf & (4u | 8u | 16u))
       return fail(ctx, ALP_ERR_CAPACITY,
-                  "per-tile limits exceeded (flags 0x%x): more than %d beams or %d emissions in one "
-                  "tile, or a segment window longer than 65535",
-                  ovf, kMaxEntries, kMaxEmit);
+                  "per-tile limits exceeded (flags 0x%x): more than %d beams or %d segment windows "
+                  "in one tile",
+                  ovf, kMaxEntries, kMaxEmitTile);
     want_emit = std::max(want_emit, ne + ne / 2 + 1024);
-    want_rec = std::max(want_rec, nr + nr / 2 + 1024);
+    want_rec = std::max(want_rec, nr + nr / 2 + (int64_t)ctx->n_cu * 8 * (int64_t)kRecBlock);
     // the band state was updated by the failed attempt: force a full clear
     for (alp_mesh *m : meshes)
       if (m) m->last_S = nullptr;

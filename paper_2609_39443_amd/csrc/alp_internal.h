@@ -9,13 +9,15 @@
 namespace alp {
 
 constexpr int kWave = 64;
-constexpr int kChunkSegs = 8;       // segments per emission chunk (segment binning)
-constexpr int kMaxEntries = 256;    // (tile, beam) entries per tile handled by one wave
-constexpr int kMaxEmit = 1024;      // emissions per tile the merge can sort
-constexpr int kNodeSlots = 512;     // per-wave LDS node accumulators (w_k partials)
+constexpr int kChunkSegs = 16;      // segments per chunk in the segment binning
+constexpr int kMaxEmitTile = 256;   // (chunk, tile) windows of one tile a wave can merge
+constexpr int kMaxEntries = 128;    // merged (tile, beam) entries a wave can screen
+constexpr int kMaskWords = kMaxEntries / 32;
+constexpr int kStagePts = 192;      // window points (and node accumulators) staged in LDS
 constexpr int kHiShift = 46;        // fixed-point: hi word holds v * 2^(46-E)
 constexpr int kLoBits = 40;         // lo word holds the next 40 bits
-constexpr int kSampleLanes = 1;     // threads per actuator point in the sampler
+constexpr int kSampleLanes = 16;    // lanes per actuator point in the sampler
+constexpr unsigned long long kRecBlock = 64ull << 10;  // pair-record bytes a wave reserves at once
 
 // Binned mesh, device view (built by alp_bin_cells).
 struct MeshDev {
@@ -55,20 +57,20 @@ struct CaseDev {
   int32_t pad_;
 };
 
-// A (tile, beam) entry: the beam's candidate segment window for the tile and
-// a screening capsule in tile-local FP32 coordinates.
-struct Entry {
-  int32_t kp;   // global point index of the beam's first point
-  int32_t nb;   // points of the beam
-  int32_t i0, i1;  // candidate segments i0..i1 (nb == 1: 0..0, the point kernel)
-  float ax, ay, az, bx, by, bz;  // screening chord, tile-local
-  float r2;     // screening radius^2 (conservative)
-  int32_t beam; // global beam index
+// A (chunk, tile) window: the candidate segments lo..hi of one chunk of a
+// beam for one tile (segment binning output, grouped by tile).
+struct Emit {
+  int32_t beam;   // global beam index
+  int32_t lo, hi; // candidate segments (beam-local); 0..0 for a single-point beam
+  int32_t tile;   // global tile index
 };
 
-struct Emit {
-  int32_t beam, lo, hi, pad;
-};
+// Pair record written by the weights pass and read by the spread pass:
+// meta = cell lane in the work item (bits 0-5) | 0x80 for a single-point beam,
+// node = global index of the first node, then a0, a1 as float (split) or
+// double (FP64).  16 or 24 bytes.
+constexpr uint32_t kRecSingle = 0x80u;
+__host__ __device__ inline int rec_size(int prec) { return prec == ALP_PREC_FP32_SPLIT ? 16 : 24; }
 
 struct Item {
   int32_t tile;   // global tile index
@@ -93,20 +95,21 @@ struct Work {
   uint32_t *bchunks;    // chunks per beam, then exclusive scan ([N_B+1])
   // chunks
   int32_t *chunk_beam, *chunk_s0, *chunk_s1;
+  uint32_t *chunk_box;  // tiles in each chunk's box, scanned into slot offsets ([cap_chunk+1])
   // tiles (global)
-  uint32_t *tile_cnt;   // emissions per tile, scanned into tile_off ([N_T+1])
-  uint32_t *tile_off;
+  uint32_t *tile_cnt;   // windows per tile ([N_T+1])
+  uint32_t *tile_off;   // exclusive scan of tile_cnt ([N_T+1])
   uint32_t *tile_fill;
-  uint32_t *tile_nent;  // merged entries per tile
-  uint32_t *tile_items; // work items per tile, scanned ([N_T+1])
-  uint32_t *tile_itoff;
+  uint32_t *tile_items; // work items per tile ([N_T+1])
+  uint32_t *tile_itoff; // exclusive scan of tile_items ([N_T+1])
   // lists
-  Emit *emit;           // [cap_emit]
-  Entry *entry;         // [cap_emit] (same offsets as emit)
+  Emit *emit_raw;       // [cap_emit] one slot per (chunk, box tile); beam < 0 = empty
+  Emit *emit;           // [cap_emit] windows grouped by tile
   Item *item;           // [cap_item]
-  uint32_t *rec_base, *rec_cnt;  // per item
-  uint32_t *rec;        // [cap_rec]
-  double *item_F;       // [cap_item][3] (unused slots ignored)
+  unsigned long long *rec_base;  // per item, byte offset into rec
+  uint32_t *rec_cnt;    // per item
+  unsigned char *rec;   // [cap_rec bytes] pair records
+  unsigned long long *rec_alloc; // byte allocator
   // per-case reductions
   long long *F_hi;      // [n_cases][3]
   unsigned long long *F_lo;
@@ -117,8 +120,7 @@ struct Work {
   long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, spare
   double *diag_out;     // [n_cases][16] finalised diagnostics
   // scalars
-  uint32_t *counters;   // [16]: 0 items counter (weights), 1 items counter (spread), 2 record alloc,
-                        // 3 overflow flag, 4 n_items total, 5 n_emit total, 6 chunks total
+  uint32_t *counters;   // [16]: 3 overflow flags
   int64_t cap_emit, cap_item, cap_rec, cap_chunk;
   int64_t n_points, n_beams, n_tiles;
   int32_t n_cases, n_pblocks;
@@ -271,8 +273,10 @@ void launch_drag_mode(const StepLaunch &L, int use_cell_s, hipStream_t st);
 void launch_points_prep(const StepLaunch &L, hipStream_t st);
 void launch_beams_prep(const StepLaunch &L, hipStream_t st);
 void launch_chunks(const StepLaunch &L, hipStream_t st);
-void launch_chunk_tiles(const StepLaunch &L, int emit, hipStream_t st);
-void launch_tile_merge(const StepLaunch &L, hipStream_t st);
+void launch_chunk_boxes(const StepLaunch &L, hipStream_t st);
+void launch_chunk_tiles(const StepLaunch &L, hipStream_t st);
+void launch_emit_scatter(const StepLaunch &L, hipStream_t st);
+void launch_tile_items(const StepLaunch &L, hipStream_t st);
 void launch_items(const StepLaunch &L, hipStream_t st);
 void launch_sample(const StepLaunch &L, hipStream_t st);
 void launch_drag(const StepLaunch &L, hipStream_t st);

@@ -1,11 +1,11 @@
 // alp_step.hip -- the per-step kernels of the coupling operator (gfx950).
 //
 // One step of a batch runs, over the concatenated work of every case:
-//   reset -> points_prep / beams_prep -> chunks -> chunk_tiles (count) -> scan
-//   -> chunk_tiles (emit) -> tile_merge -> items     [segment binning]
-//   sample -> drag                                    [eq. 16-20]
-//   weights -> norm -> beam_sums -> finalize_beam      [eq. 21-22, nodal weights]
-//   spread -> zero_dirty -> finalize                   [eq. 23, eq. 14 check]
+//   reset, points_prep, beams_prep, chunks, chunk_tiles, scan, emit_scatter,
+//   tile_items, scan, items                       [segment binning]
+//   sample, drag                                    [eq. 16-20]
+//   weights, norm, beam_sums                        [eq. 21-22, nodal weights]
+//   spread, zero_dirty, finalize                    [eq. 23, eq. 14 check]
 //
 // Work lists live on the device; the kernels that walk them are persistent
 // (fixed grids that loop), so a step can be captured in a hipGraph once and
@@ -54,11 +54,11 @@ __device__ __forceinline__ void wave_count_add(long long *dst, bool pred) {
 __device__ __forceinline__ void set_overflow(Work &W, uint32_t bit) { atomicOr(&W.counters[3], bit); }
 
 __device__ __forceinline__ void tile_origin(const MeshDev &m, int64_t tl, double &ox, double &oy,
-                                            double &oz, int &tx, int &ty, int &tz) {
-  tx = (int)(tl % m.nt[0]);
+                                            double &oz) {
+  int tx = (int)(tl % m.nt[0]);
   int64_t r = tl / m.nt[0];
-  ty = (int)(r % m.nt[1]);
-  tz = (int)(r / m.nt[1]);
+  int ty = (int)(r % m.nt[1]);
+  int tz = (int)(r / m.nt[1]);
   ox = m.lo[0] + (double)tx * m.tile_len;
   oy = m.lo[1] + (double)ty * m.tile_len;
   oz = m.lo[2] + (double)tz * m.tile_len;
@@ -69,7 +69,6 @@ __device__ __forceinline__ uint32_t tile_cell_start(const MeshDev &m, int64_t tl
 }
 
 // ------------------------------------------------------------------ reset --
-// stage masks for the reset
 enum { RESET_SAMPLE = 1, RESET_PROJECT = 2 };
 
 __global__ void k_step_reset(StepLaunch L, int what) {
@@ -77,6 +76,7 @@ __global__ void k_step_reset(StepLaunch L, int what) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (tid < 16 && (what & RESET_PROJECT)) W.counters[tid] = 0;
+  if (tid == 0 && (what & RESET_PROJECT)) *W.rec_alloc = 0;
   for (int64_t c = tid; c < (int64_t)L.n_cases * 8; c += stride) {
     int k = (int)(c & 7);
     bool samp = k < 3;
@@ -98,13 +98,13 @@ __global__ void k_step_reset(StepLaunch L, int what) {
 }
 
 void launch_step_reset(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_step_reset, dim3(2048), dim3(256), 0, st, L, (int)(RESET_SAMPLE | RESET_PROJECT));
+  hipLaunchKernelGGL(k_step_reset, dim3(1024), dim3(256), 0, st, L, (int)(RESET_SAMPLE | RESET_PROJECT));
 }
 void launch_step_reset_sample(const StepLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(256), 0, st, L, (int)RESET_SAMPLE);
 }
 void launch_step_reset_project(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_step_reset, dim3(2048), dim3(256), 0, st, L, (int)RESET_PROJECT);
+  hipLaunchKernelGGL(k_step_reset, dim3(1024), dim3(256), 0, st, L, (int)RESET_PROJECT);
 }
 
 // ------------------------------------------------------------ points prep --
@@ -198,273 +198,223 @@ void launch_chunks(const StepLaunch &L, hipStream_t st) {
 // segments can be the closest segment of the beam for some point of the tile
 // and lies within 3 eps_max of it:
 //   (a) the segment's AABB inflated by 3 eps_max(beam) overlaps the tile, and
-//   (b) slab rule: a segment i is never the (lowest-index) closest segment of a
-//       point X that lies behind its start plane (the previous segment ends at
-//       the same vertex) or beyond its end plane while in front of the next
-//       segment's start plane (the next segment is strictly closer).
-// The chunk's window for a tile is [first, last] candidate segment.
-__device__ __forceinline__ bool seg_candidate(const double *A, const double *B, const double *An,
-                                              bool first, bool last, double R, const double *tlo,
-                                              double tl, double m) {
-  // (a) inflated AABB against the tile box
-  for (int a = 0; a < 3; ++a) {
-    double lo = fmin(A[a], B[a]) - R, hi = fmax(A[a], B[a]) + R;
-    if (hi < tlo[a] - m || lo > tlo[a] + tl + m) return false;
-  }
-  double e[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
-  double len = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-  if (!(len > 0.0)) return true;
-  double half = 0.5 * tl + m;
-  double ac = 0.0, hw = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    double u = e[a] / len;
-    ac += (tlo[a] + 0.5 * tl - A[a]) * u;
-    hw += half * fabs(u);
-  }
-  double amin = ac - hw, amax = ac + hw;
-  if (!first && !(amax > -m)) return false;
-  if (!last && !(amin < len + m)) {
-    // the point could still sit in the wedge behind the next segment's start
-    if (!An) return false;
-    double en[3] = {An[0] - B[0], An[1] - B[1], An[2] - B[2]};
-    double ln = sqrt(en[0] * en[0] + en[1] * en[1] + en[2] * en[2]);
-    if (!(ln > 0.0)) return true;
-    double acn = 0.0, hwn = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      double u = en[a] / ln;
-      acn += (tlo[a] + 0.5 * tl - B[a]) * u;
-      hwn += half * fabs(u);
-    }
-    if (!(acn - hwn < m)) return false;
-  }
-  return true;
-}
+//   (b) slab rule: segment i is never the (lowest-index) closest segment of a
+//       point behind its start plane (the previous segment ends at the same
+//       vertex) or beyond its end plane while in front of the next segment's
+//       start plane (the next segment is strictly closer).
+// The window [first, last] candidate segment of the chunk is appended for
+// every such tile, and counted per tile for the grouping scatter.
+struct SegInfo {
+  double lo[3], hi[3];  // inflated AABB
+  double a[3];          // start point
+  double u[3];          // unit direction (0 for a zero-length segment)
+  double len, su;       // length, |ux| + |uy| + |uz|
+};
 
-__global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L, int emit) {
-  Work W = L.w;
-  int64_t ch = blockIdx.x;
-  uint32_t n_chunks = W.bchunks[W.n_beams];
-  if (ch >= (int64_t)n_chunks || ch >= W.cap_chunk) return;
-  int lane = threadIdx.x;
-  int gb = W.chunk_beam[ch];
+// tile box of a chunk: tiles overlapped by the union of its segments' AABBs
+// inflated by 3 eps_max; returns false when the box misses the tile grid
+__device__ bool chunk_box(const StepLaunch &L, int64_t ch, int32_t *box, double *Rout) {
+  const Work &W = L.w;
+  const int gb = W.chunk_beam[ch];
   const CaseDev &cs = L.cases[W.bcase[gb]];
   const MeshDev &m = cs.m;
-  int64_t b = gb - cs.beam_base;
-  int64_t k0 = cs.offsets[b];
-  int64_t nb = cs.offsets[b + 1] - k0;
-  int s0 = W.chunk_s0[ch], s1 = W.chunk_s1[ch];
-  int nseg = nb >= 2 ? (int)nb - 1 : 1;
+  const int64_t b = gb - cs.beam_base;
+  const int64_t k0 = cs.offsets[b];
+  const int nb = (int)(cs.offsets[b + 1] - k0);
+  const int s0 = W.chunk_s0[ch], s1 = W.chunk_s1[ch];
   const double *X = cs.Psp + 3 * k0;
+  const double tl = m.tile_len;
   double R = 3.0 * W.beps_max[gb];
-  double tl = m.tile_len;
-  double mrg = 1e-7 * (tl + R);
-  R += mrg;
-  // chunk AABB
+  R += 1e-7 * (tl + R);
+  *Rout = R;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  int plast = nb >= 2 ? s1 + 1 : 0;
-  for (int p = s0; p <= plast; ++p)
+  const int plast = nb >= 2 ? s1 + 1 : 0;
+  for (int p = (nb >= 2 ? s0 : 0); p <= plast; ++p)
     for (int a = 0; a < 3; ++a) {
       lo[a] = fmin(lo[a], X[3 * p + a]);
       hi[a] = fmax(hi[a], X[3 * p + a]);
     }
-  int t0[3], t1[3];
-  int64_t ntile = 1;
+  bool ok = true;
   for (int a = 0; a < 3; ++a) {
     double f0 = floor((lo[a] - R - m.lo[a]) / tl), f1 = floor((hi[a] + R - m.lo[a]) / tl);
-    if (!(f1 >= 0.0) || !(f0 <= (double)(m.nt[a] - 1))) return;  // also rejects NaN
-    t0[a] = !(f0 > 0.0) ? 0 : (int)f0;
-    t1[a] = f1 > (double)(m.nt[a] - 1) ? m.nt[a] - 1 : (int)f1;
-    ntile *= (t1[a] - t0[a] + 1);
+    if (!(f1 >= 0.0) || !(f0 <= (double)(m.nt[a] - 1))) ok = false;  // also rejects NaN
+    box[a] = !(f0 > 0.0) ? 0 : (int)f0;
+    box[3 + a] = f1 > (double)(m.nt[a] - 1) ? m.nt[a] - 1 : (f1 > 0.0 ? (int)f1 : 0);
   }
-  int nx = t1[0] - t0[0] + 1, ny = t1[1] - t0[1] + 1;
-  for (int64_t q = lane; q < ntile; q += 64) {
-    int tx = t0[0] + (int)(q % nx), ty = t0[1] + (int)((q / nx) % ny), tz = t0[2] + (int)(q / ((int64_t)nx * ny));
-    double tlo[3] = {m.lo[0] + tx * tl, m.lo[1] + ty * tl, m.lo[2] + tz * tl};
-    int wlo = -1, whi = -1;
-    if (nb == 1) {
-      if (seg_candidate(X, X, nullptr, true, true, R, tlo, tl, mrg)) wlo = whi = 0;
-    } else {
-      for (int i = s0; i <= s1; ++i) {
-        const double *A = X + 3 * i, *B = X + 3 * (i + 1);
-        const double *An = (i + 2 < nb) ? X + 3 * (i + 2) : nullptr;
-        if (seg_candidate(A, B, An, i == 0, i == nseg - 1, R, tlo, tl, mrg)) {
-          if (wlo < 0) wlo = i;
-          whi = i;
-        }
-      }
-    }
-    if (wlo < 0) continue;
-    int64_t tg = cs.tile_base + ((int64_t)tz * m.nt[1] + ty) * m.nt[0] + tx;
-    if (!emit) {
-      atomicAdd(&W.tile_cnt[tg], 1u);
-    } else {
-      uint32_t slot = W.tile_off[tg] + atomicAdd(&W.tile_fill[tg], 1u);
-      if ((int64_t)slot < W.cap_emit) {
-        Emit e;
-        e.beam = gb;
-        e.lo = wlo;
-        e.hi = whi;
-        e.pad = 0;
-        W.emit[slot] = e;
-      } else {
-        set_overflow(W, 1u);
-      }
-    }
-  }
+  return ok;
 }
 
-void launch_chunk_tiles(const StepLaunch &L, int emit, hipStream_t st) {
+__global__ void k_chunk_boxes(StepLaunch L) {
+  const Work &W = L.w;
+  const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= W.cap_chunk) return;
+  uint32_t n = 0;
+  if (ch < (int64_t)W.bchunks[W.n_beams]) {
+    int32_t box[6];
+    double R;
+    if (chunk_box(L, ch, box, &R))
+      n = (uint32_t)((box[3] - box[0] + 1) * (box[4] - box[1] + 1) * (box[5] - box[2] + 1));
+  }
+  W.chunk_box[ch] = n;
+}
+
+void launch_chunk_boxes(const StepLaunch &L, hipStream_t st) {
   if (L.w.cap_chunk == 0) return;
-  hipLaunchKernelGGL(k_chunk_tiles, dim3((unsigned)L.w.cap_chunk), dim3(64), 0, st, L, emit);
+  hipLaunchKernelGGL(k_chunk_boxes, dim3((unsigned)((L.w.cap_chunk + 255) / 256)), dim3(256), 0, st, L);
 }
 
-// ------------------------------------------------------------- tile merge --
-// Per tile: sort the emissions by (beam, first segment), merge those of one
-// beam into a single window, and build the screening capsule of each entry:
-// the chord from the window's first to last point, inflated by the largest
-// distance of a window point from it plus 3 eps_max of the window.
-__global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
+__global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
   Work W = L.w;
-  __shared__ unsigned long long s_key[kMaxEmit];
-  __shared__ int32_t s_hi[kMaxEmit];
-  __shared__ int32_t s_cnt;
-  int lane = threadIdx.x;
-  int64_t nw = (int64_t)gridDim.x;
-  for (int64_t tg = blockIdx.x; tg < W.n_tiles; tg += nw) {
-    uint32_t off = W.tile_off[tg];
-    uint32_t n = W.tile_off[tg + 1] - off;
-    if (n == 0) {
-      if (lane == 0) {
-        W.tile_nent[tg] = 0;
-        W.tile_items[tg] = 0;
-      }
-      continue;
-    }
-    int c = case_of(L.tbase, L.n_cases, tg);
-    const CaseDev &cs = L.cases[c];
+  __shared__ SegInfo sg[kChunkSegs + 1];
+  const int lane = threadIdx.x;
+  const uint32_t n_chunks = W.bchunks[W.n_beams];
+  const uint32_t *box_off = W.chunk_box;  // exclusive scan of the box sizes
+  for (int64_t ch = blockIdx.x; ch < (int64_t)n_chunks && ch < W.cap_chunk; ch += gridDim.x) {
+    const uint32_t slot0 = box_off[ch];
+    const int64_t ntile = (int64_t)box_off[ch + 1] - slot0;
+    if (ntile == 0) continue;
+    int32_t box[6];
+    double R;
+    chunk_box(L, ch, box, &R);
+    const int gb = W.chunk_beam[ch];
+    const CaseDev &cs = L.cases[W.bcase[gb]];
     const MeshDev &m = cs.m;
-    int64_t tl = tg - cs.tile_base;
-    if (n > (uint32_t)kMaxEmit || (int64_t)off + n > W.cap_emit) {
-      if (lane == 0) {
-        W.tile_nent[tg] = 0;
-        W.tile_items[tg] = 0;
-        set_overflow(W, n > (uint32_t)kMaxEmit ? 4u : 1u);
-      }
-      continue;
-    }
-    uint32_t np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    for (uint32_t i = lane; i < np2; i += 64) {
-      if (i < n) {
-        Emit e = W.emit[off + i];
-        s_key[i] = ((unsigned long long)(uint32_t)e.beam << 32) | (uint32_t)e.lo;
-        s_hi[i] = e.hi;
+    const int64_t b = gb - cs.beam_base;
+    const int64_t k0 = cs.offsets[b];
+    const int nb = (int)(cs.offsets[b + 1] - k0);
+    const int s0 = W.chunk_s0[ch], s1 = W.chunk_s1[ch];
+    const int nseg = nb >= 2 ? nb - 1 : 1;
+    const int nsg = s1 - s0 + 1;
+    const double *X = cs.Psp + 3 * k0;
+    const double tl = m.tile_len;
+    const double mrg = 1e-7 * (tl + R);
+    // segment data: the chunk's segments and the one after it (wedge test)
+    for (int j = lane; j <= nsg; j += 64) {
+      int i = s0 + j;
+      SegInfo q;
+      bool exists = (nb == 1) ? (j == 0) : (i <= nb - 2);
+      if (exists) {
+        const double *A = X + 3 * (nb == 1 ? 0 : i), *B = X + 3 * (nb == 1 ? 0 : i + 1);
+        double e[3];
+        for (int a = 0; a < 3; ++a) {
+          q.lo[a] = fmin(A[a], B[a]) - R;
+          q.hi[a] = fmax(A[a], B[a]) + R;
+          q.a[a] = A[a];
+          e[a] = B[a] - A[a];
+        }
+        q.len = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        q.su = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          q.u[a] = q.len > 0.0 ? e[a] / q.len : 0.0;
+          q.su += fabs(q.u[a]);
+        }
       } else {
-        s_key[i] = ~0ull;
-        s_hi[i] = 0;
+        for (int a = 0; a < 3; ++a) {
+          q.lo[a] = INFINITY;
+          q.hi[a] = -INFINITY;
+          q.a[a] = 0.0;
+          q.u[a] = 0.0;
+        }
+        q.len = 0.0;
+        q.su = 0.0;
       }
+      sg[j] = q;
     }
     __syncthreads();
-    // bitonic sort of (key, hi) pairs in LDS
-    for (uint32_t k = 2; k <= np2; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = lane; i < np2; i += 64) {
-          uint32_t p = i ^ j;
-          if (p > i) {
-            bool up = (i & k) == 0;
-            unsigned long long a = s_key[i], bk = s_key[p];
-            if ((a > bk) == up) {
-              s_key[i] = bk;
-              s_key[p] = a;
-              int32_t t = s_hi[i];
-              s_hi[i] = s_hi[p];
-              s_hi[p] = t;
+    const int nx = box[3] - box[0] + 1, ny = box[4] - box[1] + 1;
+    for (int64_t q = lane; q < ntile; q += 64) {
+      int wlo = -1, whi = -1;
+      int tx = box[0] + (int)(q % nx), ty = box[1] + (int)((q / nx) % ny),
+          tz = box[2] + (int)(q / ((int64_t)nx * ny));
+      double tlo[3] = {m.lo[0] + tx * tl, m.lo[1] + ty * tl, m.lo[2] + tz * tl};
+      double tc[3] = {tlo[0] + 0.5 * tl, tlo[1] + 0.5 * tl, tlo[2] + 0.5 * tl};
+      double half = 0.5 * tl + mrg;
+      for (int j = 0; j < nsg; ++j) {
+        const SegInfo &g = sg[j];
+        bool ov = true;
+        for (int a = 0; a < 3; ++a)
+          ov = ov && !(g.hi[a] < tlo[a] - mrg || g.lo[a] > tlo[a] + tl + mrg);
+        if (!ov) continue;
+        const int i = s0 + j;
+        if (nb >= 2 && g.len > 0.0) {
+          double ac = (tc[0] - g.a[0]) * g.u[0] + (tc[1] - g.a[1]) * g.u[1] + (tc[2] - g.a[2]) * g.u[2];
+          double hw = half * g.su;
+          if (i > 0 && !(ac + hw > -mrg)) continue;
+          if (i < nseg - 1 && !(ac - hw < g.len + mrg)) {
+            const SegInfo &gn = sg[j + 1];
+            if (gn.len > 0.0) {
+              double acn = (tc[0] - gn.a[0]) * gn.u[0] + (tc[1] - gn.a[1]) * gn.u[1] +
+                           (tc[2] - gn.a[2]) * gn.u[2];
+              if (!(acn - half * gn.su < mrg)) continue;
             }
           }
         }
-        __syncthreads();
+        if (wlo < 0) wlo = i;
+        whi = i;
       }
-    }
-    // merge windows of the same beam (lane 0; tiles hold a few dozen emissions)
-    if (lane == 0) {
-      int ne = 0;
-      for (uint32_t i = 0; i < n; ++i) {
-        uint32_t beam = (uint32_t)(s_key[i] >> 32);
-        int32_t lo = (int32_t)(s_key[i] & 0xffffffffu);
-        if (ne > 0 && (uint32_t)(s_key[ne - 1] >> 32) == beam) {
-          if (s_hi[i] > s_hi[ne - 1]) s_hi[ne - 1] = s_hi[i];
-        } else {
-          s_key[ne] = ((unsigned long long)beam << 32) | (uint32_t)lo;
-          s_hi[ne] = s_hi[i];
-          ++ne;
-        }
+      const int64_t slot = (int64_t)slot0 + q;
+      if (slot >= W.cap_emit) {
+        set_overflow(W, 1u);
+        continue;
       }
-      s_cnt = ne;
-    }
-    __syncthreads();
-    int ne = s_cnt;
-    double ox, oy, oz;
-    int tx, ty, tz;
-    tile_origin(m, tl, ox, oy, oz, tx, ty, tz);
-    for (int e = lane; e < ne; e += 64) {
-      int gb = (int)(s_key[e] >> 32);
-      int i0 = (int)(s_key[e] & 0xffffffffu), i1 = s_hi[e];
-      int64_t b = gb - cs.beam_base;
-      int64_t k0 = cs.offsets[b];
-      int nb = (int)(cs.offsets[b + 1] - k0);
-      const double *X = cs.Psp + 3 * k0;
-      int plast = nb >= 2 ? i1 + 1 : 0;
-      const double *A = X + 3 * i0, *B = X + 3 * plast;
-      double ab[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
-      double ll = ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2];
-      double dev = 0.0, em = 0.0;
-      for (int p = i0; p <= plast; ++p) {
-        const double *Q = X + 3 * p;
-        double q[3] = {Q[0] - A[0], Q[1] - A[1], Q[2] - A[2]};
-        double t = ll > 0.0 ? (q[0] * ab[0] + q[1] * ab[1] + q[2] * ab[2]) / ll : 0.0;
-        t = fmin(fmax(t, 0.0), 1.0);
-        double r[3] = {q[0] - t * ab[0], q[1] - t * ab[1], q[2] - t * ab[2]};
-        dev = fmax(dev, sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
-        em = fmax(em, cs.eps[k0 + p]);
-      }
-      double R = (3.0 * em + dev) * (1.0 + 1e-5) + 1e-6 * (m.tile_len + 3.0 * em + dev);
-      if (nb >= 2 && i1 - i0 + 1 > 0xffff) set_overflow(W, 4u);  // record field width
-      Entry en;
-      en.kp = (int32_t)k0;
-      en.nb = nb;
-      en.i0 = i0;
-      en.i1 = nb >= 2 ? i1 : 0;
-      en.ax = (float)(A[0] - ox);
-      en.ay = (float)(A[1] - oy);
-      en.az = (float)(A[2] - oz);
-      en.bx = (float)(B[0] - ox);
-      en.by = (float)(B[1] - oy);
-      en.bz = (float)(B[2] - oz);
-      float Rf = (float)R;
-      en.r2 = Rf * Rf * (1.0f + 1e-5f);
-      en.beam = (int32_t)b;
-      W.entry[off + e] = en;
-    }
-    if (lane == 0) {
-      if (ne > kMaxEntries) {
-        set_overflow(W, 4u);
-        ne = 0;
-      }
-      W.tile_nent[tg] = (uint32_t)ne;
-      uint32_t ncell = tile_cell_start(m, tl + 1) - tile_cell_start(m, tl);
-      W.tile_items[tg] = ne > 0 ? (ncell + 63u) / 64u : 0u;
+      Emit e;
+      e.beam = wlo >= 0 ? gb : -1;
+      e.lo = nb == 1 ? 0 : wlo;
+      e.hi = nb == 1 ? 0 : whi;
+      e.tile = (int32_t)(cs.tile_base + ((int64_t)tz * m.nt[1] + ty) * m.nt[0] + tx);
+      W.emit_raw[slot] = e;
+      if (wlo >= 0) atomicAdd(&W.tile_cnt[e.tile], 1u);
     }
     __syncthreads();
   }
 }
 
-void launch_tile_merge(const StepLaunch &L, hipStream_t st) {
-  if (L.w.n_tiles == 0) return;
-  int64_t g = L.w.n_tiles < 16384 ? L.w.n_tiles : 16384;
-  hipLaunchKernelGGL(k_tile_merge, dim3((unsigned)g), dim3(64), 0, st, L);
+void launch_chunk_tiles(const StepLaunch &L, hipStream_t st) {
+  if (L.w.cap_chunk == 0) return;
+  int64_t g = L.w.cap_chunk < 65536 ? L.w.cap_chunk : 65536;
+  hipLaunchKernelGGL(k_chunk_tiles, dim3((unsigned)g), dim3(64), 0, st, L);
 }
 
-// ------------------------------------------------------------------ items --
+// windows -> grouped by tile (counting sort; order inside a tile is fixed by
+// the weights pass, which sorts each tile's windows by beam)
+__global__ void k_emit_scatter(StepLaunch L) {
+  Work W = L.w;
+  int64_t n = W.chunk_box[W.cap_chunk];
+  if (n > W.cap_emit) n = W.cap_emit;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    Emit e = W.emit_raw[i];
+    if (e.beam < 0) continue;
+    uint32_t slot = W.tile_off[e.tile] + atomicAdd(&W.tile_fill[e.tile], 1u);
+    W.emit[slot] = e;
+  }
+}
+
+void launch_emit_scatter(const StepLaunch &L, hipStream_t st) {
+  hipLaunchKernelGGL(k_emit_scatter, dim3(L.grid_persistent), dim3(256), 0, st, L);
+}
+
+// work items per tile: tiles with at least one window, 64 cells per item
+__global__ void k_tile_items(StepLaunch L) {
+  Work W = L.w;
+  int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tg >= W.n_tiles) return;
+  uint32_t ni = 0;
+  if (W.tile_cnt[tg] > 0) {
+    int c = case_of(L.tbase, L.n_cases, tg);
+    const CaseDev &cs = L.cases[c];
+    int64_t tl = tg - cs.tile_base;
+    uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
+    ni = (ncell + 63u) / 64u;
+  }
+  W.tile_items[tg] = ni;
+}
+
+void launch_tile_items(const StepLaunch &L, hipStream_t st) {
+  if (L.w.n_tiles == 0) return;
+  hipLaunchKernelGGL(k_tile_items, dim3((unsigned)((L.w.n_tiles + 255) / 256)), dim3(256), 0, st, L);
+}
+
 __global__ void k_items(StepLaunch L) {
   Work W = L.w;
   int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -499,10 +449,12 @@ void launch_items(const StepLaunch &L, hipStream_t st) {
 // ----------------------------------------------------------------- sample --
 // c(x): nearest cell centre (ties: smaller (x, y, z), then smaller caller
 // index), searched over Chebyshev shells of bins until no unvisited bin can
-// hold a centre as close as the best found.  Returns the sorted index or -1
-// when x is outside the domain box.
-__device__ __forceinline__ bool closer_cell(const MeshDev &m, double D, uint32_t j, double bD,
+// hold a centre as close as the best found.  A group of kSampleLanes lanes
+// searches each shell together.  Returns the sorted index (the same on every
+// lane of the group) or -1 when x is outside the domain box.
+__device__ __forceinline__ bool closer_cell(const MeshDev &m, double D, int64_t j, double bD,
                                             int64_t best) {
+  if (j < 0) return false;
   if (best < 0) return true;
   if (D < bD) return true;
   if (D > bD) return false;
@@ -515,43 +467,49 @@ __device__ __forceinline__ bool closer_cell(const MeshDev &m, double D, uint32_t
   return m.perm[j] < m.perm[best];
 }
 
-__device__ int64_t locate_cell(const MeshDev &m, double x, double y, double z) {
+__device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, int sub) {
   if (!(x >= m.box[0] && x <= m.box[3] && y >= m.box[1] && y <= m.box[4] && z >= m.box[2] &&
         z <= m.box[5]))
     return -1;
-  double q[3] = {x, y, z};
+  const double q[3] = {x, y, z};
   int qi[3];
   for (int a = 0; a < 3; ++a) {
     double f = floor((q[a] - m.lo[a]) / m.bin);
     qi[a] = !(f > 0.0) ? 0 : (f > (double)(m.nb[a] - 1) ? m.nb[a] - 1 : (int)f);
   }
-  double slack = 1e-9 * (m.bin * (double)(m.nb[0] + m.nb[1] + m.nb[2]) + fabs(m.lo[0]) +
-                         fabs(m.lo[1]) + fabs(m.lo[2]));
+  const double slack = 1e-9 * (m.bin * (double)(m.nb[0] + m.nb[1] + m.nb[2]) + fabs(m.lo[0]) +
+                               fabs(m.lo[1]) + fabs(m.lo[2]));
   int64_t best = -1;
   double bD = INFINITY;
   for (int r = 0;; ++r) {
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = qi[a] - r < 0 ? 0 : qi[a] - r;
-      hi[a] = qi[a] + r > m.nb[a] - 1 ? m.nb[a] - 1 : qi[a] + r;
-    }
-    for (int iz = lo[2]; iz <= hi[2]; ++iz)
-      for (int iy = lo[1]; iy <= hi[1]; ++iy)
-        for (int ix = lo[0]; ix <= hi[0]; ++ix) {
-          int ch = abs(ix - qi[0]);
-          ch = max(ch, abs(iy - qi[1]));
-          ch = max(ch, abs(iz - qi[2]));
-          if (ch != r) continue;
-          uint32_t k = bin_key(m, ix, iy, iz);
-          uint32_t e = m.bin_start[k + 1];
-          for (uint32_t j = m.bin_start[k]; j < e; ++j) {
-            double D = sqdist_exact(x, y, z, m.cx[j], m.cy[j], m.cz[j]);
-            if (closer_cell(m, D, j, bD, best)) {
-              best = j;
-              bD = D;
-            }
-          }
+    const int side = 2 * r + 1;
+    const int ncube = side * side * side;
+    for (int c = sub; c < ncube; c += kSampleLanes) {
+      int dz = c / (side * side), dy = (c / side) % side, dx = c % side;
+      int ix = qi[0] - r + dx, iy = qi[1] - r + dy, iz = qi[2] - r + dz;
+      int ch = max(abs(dx - r), max(abs(dy - r), abs(dz - r)));
+      if (ch != r || ix < 0 || iy < 0 || iz < 0 || ix >= m.nb[0] || iy >= m.nb[1] || iz >= m.nb[2])
+        continue;
+      uint32_t k = bin_key(m, ix, iy, iz);
+      uint32_t e = m.bin_start[k + 1];
+      for (uint32_t j = m.bin_start[k]; j < e; ++j) {
+        double D = sqdist_exact(x, y, z, m.cx[j], m.cy[j], m.cz[j]);
+        if (closer_cell(m, D, j, bD, best)) {
+          best = j;
+          bD = D;
         }
+      }
+    }
+    // group reduction (all lanes of the group end with the same best)
+#pragma unroll
+    for (int o = kSampleLanes / 2; o > 0; o >>= 1) {
+      double oD = __shfl_xor(bD, o, 64);
+      long long ob = __shfl_xor((long long)best, o, 64);
+      if (closer_cell(m, oD, ob, bD, best)) {
+        best = ob;
+        bD = oD;
+      }
+    }
     bool all = true;
     double bound = INFINITY;
     for (int a = 0; a < 3; ++a) {
@@ -571,25 +529,27 @@ __device__ int64_t locate_cell(const MeshDev &m, double x, double y, double z) {
   return best;
 }
 
-// Eq. (16)-(18) per actuator point, in the paper's order.
-__global__ void k_sample(StepLaunch L) {
+// Eq. (16)-(18) per actuator point, in the paper's order.  Every lane of a
+// group computes the same values; lane 0 of the group writes them.
+__global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
 #pragma clang fp contract(off)
   Work W = L.w;
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool act = g < W.n_points;
+  const int sub = threadIdx.x % kSampleLanes;
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSampleLanes;
+  const bool act = g < W.n_points;
   bool out = false, fb = false, dg = false;
   int c = 0;
   if (act) {
     c = case_of(L.pbase, L.n_cases, g);
     const CaseDev &cs = L.cases[c];
     const MeshDev &m = cs.m;
-    int64_t k = g - cs.point_base;
-    int64_t b = W.pbeam[g] - cs.beam_base;
+    const int64_t k = g - cs.point_base;
+    const int64_t b = W.pbeam[g] - cs.beam_base;
     const double *Pa = cs.P + 3 * k, *Pd = cs.Pdot + 3 * k, *et = cs.e_t + 3 * k;
     double nrm = sqrt(dot3_exact(et[0], et[1], et[2], et[0], et[1], et[2]));
     double e[3] = {et[0] / nrm, et[1] / nrm, et[2] / nrm};
     double ps[3] = {Pa[0], Pa[1], Pa[2]}, us[3] = {0.0, 0.0, 0.0};
-    int64_t ca = locate_cell(m, Pa[0], Pa[1], Pa[2]), cs_ = -1;
+    int64_t ca = locate_group(m, Pa[0], Pa[1], Pa[2], sub), cs_ = -1;
     if (ca < 0) {
       out = true;
     } else {
@@ -622,7 +582,7 @@ __global__ void k_sample(StepLaunch L) {
       double dn = dot3_exact(np[0], np[1], np[2], es[0], es[1], es[2]);
       double ls = cs.ls[b];
       for (int a = 0; a < 3; ++a) ps[a] = Pa[a] + ls * (es[a] - dn * np[a]);
-      cs_ = locate_cell(m, ps[0], ps[1], ps[2]);
+      cs_ = locate_group(m, ps[0], ps[1], ps[2], sub);
       if (cs_ < 0) {
         out = true;
       } else {
@@ -632,30 +592,29 @@ __global__ void k_sample(StepLaunch L) {
         us[2] = Us[2];
       }
     }
-    double *Uout = cs.U_s ? cs.U_s + 3 * k : W.Us + 3 * g;
-    Uout[0] = us[0];
-    Uout[1] = us[1];
-    Uout[2] = us[2];
-    if (cs.U_s) {
+    if (sub == 0) {
       W.Us[3 * g] = us[0];
       W.Us[3 * g + 1] = us[1];
       W.Us[3 * g + 2] = us[2];
+      if (cs.U_s)
+        for (int a = 0; a < 3; ++a) cs.U_s[3 * k + a] = us[a];
+      if (cs.P_s)
+        for (int a = 0; a < 3; ++a) cs.P_s[3 * k + a] = ps[a];
+      if (cs.cell_a) cs.cell_a[k] = ca < 0 ? -1 : (int64_t)m.perm[ca];
+      if (cs.cell_s) cs.cell_s[k] = cs_ < 0 ? -1 : (int64_t)m.perm[cs_];
+      W.pflags[g] = (out ? 1 : 0) | (fb ? 2 : 0) | (dg ? 4 : 0);
     }
-    if (cs.P_s)
-      for (int a = 0; a < 3; ++a) cs.P_s[3 * k + a] = ps[a];
-    if (cs.cell_a) cs.cell_a[k] = ca < 0 ? -1 : (int64_t)m.perm[ca];
-    if (cs.cell_s) cs.cell_s[k] = cs_ < 0 ? -1 : (int64_t)m.perm[cs_];
-    W.pflags[g] = (out ? 1 : 0) | (fb ? 2 : 0) | (dg ? 4 : 0);
   }
-  // counters (one atomic per wave and case; a wave may straddle two cases)
+  // counters: group leaders only (a wave may straddle two cases)
+  const bool lead = act && sub == 0;
   int c0 = __shfl(c, 0, 64);
   bool same = __all(!act || c == c0);
   if (same) {
     long long *cnt = W.cnt + 8 * c0;
-    wave_count_add(cnt + 0, act && out);
-    wave_count_add(cnt + 1, act && fb);
-    wave_count_add(cnt + 2, act && dg);
-  } else if (act) {
+    wave_count_add(cnt + 0, lead && out);
+    wave_count_add(cnt + 1, lead && fb);
+    wave_count_add(cnt + 2, lead && dg);
+  } else if (lead) {
     long long *cnt = W.cnt + 8 * c;
     if (out) atomicAdd((unsigned long long *)(cnt + 0), 1ull);
     if (fb) atomicAdd((unsigned long long *)(cnt + 1), 1ull);
@@ -665,7 +624,8 @@ __global__ void k_sample(StepLaunch L) {
 
 void launch_sample(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_points == 0) return;
-  hipLaunchKernelGGL(k_sample, dim3((unsigned)((L.w.n_points + 63) / 64)), dim3(64), 0, st, L);
+  int64_t threads = L.w.n_points * kSampleLanes;
+  hipLaunchKernelGGL(k_sample, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------------- drag --
@@ -716,99 +676,234 @@ void launch_drag(const StepLaunch &L, hipStream_t st) { launch_drag_mode(L, 0, s
 // ---------------------------------------------------------------- weights --
 // Eq. (21)-(22) and the nodal weights of Sec. 3.2.4.  One wave per work item
 // (up to 64 cells of one tile):
-//   1. screen every (cell, entry) combination against the entry's capsule and
-//      list the candidate pairs in (cell, entry) order;
-//   2. for each candidate pair (64 at a time, full lanes) find the closest
-//      segment of the entry's window exactly in FP64, apply the inclusive 3 eps
-//      cutoff and compute the weights a0, a1;
-//   3. add a V into per-node fixed-point accumulators (LDS integer atomics,
-//      then one global integer atomic per touched node);
-//   4. store the surviving pairs as 32-bit records (cell, entry, segment) for
-//      the spread pass.
-constexpr int kMaskWords = kMaxEntries / 32;
-
-struct WaveScratch {
-  double cx[64], cy[64], cz[64], v[64];
-  float lx[64], ly[64], lz[64];
+//   1. sort the tile's windows by (beam, first segment) and merge those of one
+//      beam into entries (beam order);
+//   2. stage each entry's window points, kernel widths and node accumulators
+//      in LDS and build a screening box (window AABB inflated by 3 eps_max);
+//   3. screen every (cell, entry) combination and list the candidate pairs in
+//      (cell, entry) order;
+//   4. for each candidate (64 at a time, full lanes) find the closest segment
+//      of the window exactly in FP64, apply the inclusive 3 eps cutoff and
+//      compute the weights a0, a1;
+//   5. add a V into the node accumulators (exact fixed point: LDS integer
+//      atomics, then one global integer atomic per touched node);
+//   6. write one record per surviving pair (cell, node, a0, a1) for the
+//      spread pass.
+struct WeightsScratch {
+  union {
+    struct {
+      unsigned long long key[kMaxEmitTile];  // (beam << 32) | first segment
+      int32_t hi[kMaxEmitTile];
+    } srt;
+    struct {
+      double px[kStagePts], py[kStagePts], pz[kStagePts], pe[kStagePts];
+      long long ahi[kStagePts];
+      unsigned long long alo[kStagePts];
+    } stg;
+  } u;
+  int32_t e_kp[kMaxEntries], e_nb[kMaxEntries], e_i0[kMaxEntries], e_i1[kMaxEntries];
+  float e_box[6][kMaxEntries];
+  int32_t e_pt0[kMaxEntries + 1];
   uint32_t mask[64 * kMaskWords];
   uint32_t off[65];
-  uint32_t slot0[kMaxEntries + 1];
-  long long acc_hi[kNodeSlots];
-  unsigned long long acc_lo[kNodeSlots];
-  uint32_t item;
+  int32_t n_ent, n_staged, n_pts;
 };
 
-__device__ __forceinline__ float seg_dist2_f32(float px, float py, float pz, float ax, float ay,
-                                               float az, float bx, float by, float bz) {
-  float ex = bx - ax, ey = by - ay, ez = bz - az;
-  float qx = px - ax, qy = py - ay, qz = pz - az;
-  float ee = ex * ex + ey * ey + ez * ez;
-  float t = qx * ex + qy * ey + qz * ez;
-  float u = ee > 0.0f ? fminf(fmaxf(t / ee, 0.0f), 1.0f) : 0.0f;
-  float rx = qx - u * ex, ry = qy - u * ey, rz = qz - u * ez;
-  return rx * rx + ry * ry + rz * rz;
-}
-
-// closest segment of the entry's window to C (FP64, lowest index on ties)
-__device__ __forceinline__ void window_argmin(const double *X, const Entry &en, double cx, double cy,
-                                              double cz, int &bi, double &bs, double &br2) {
-  if (en.nb == 1) {
-    bi = 0;
-    bs = 0.0;
-    br2 = sqdist_exact(cx, cy, cz, X[0], X[1], X[2]);
-    return;
-  }
-  br2 = INFINITY;
-  bi = en.i0;
-  bs = 0.0;
-  double ax = X[3 * en.i0], ay = X[3 * en.i0 + 1], az = X[3 * en.i0 + 2];
-  for (int i = en.i0; i <= en.i1; ++i) {
-    double bx = X[3 * i + 3], by = X[3 * i + 4], bz = X[3 * i + 5];
-    double s, r2;
-    seg_foot(cx, cy, cz, ax, ay, az, bx, by, bz, s, r2);
-    if (r2 < br2) {
-      br2 = r2;
-      bi = i;
-      bs = s;
+// window point j of entry e (staged in LDS, or read from the beam array)
+struct WinPts {
+  const WeightsScratch &sh;
+  const double *X;
+  const double *eps;
+  __device__ __forceinline__ void get(int e, int pt0, int p, double &x, double &y, double &z) const {
+    if (pt0 >= 0) {
+      x = sh.u.stg.px[pt0 + p];
+      y = sh.u.stg.py[pt0 + p];
+      z = sh.u.stg.pz[pt0 + p];
+    } else {
+      const double *P = X + 3 * (int64_t)(sh.e_kp[e] + (sh.e_nb[e] == 1 ? 0 : sh.e_i0[e]) + p);
+      x = P[0];
+      y = P[1];
+      z = P[2];
     }
-    ax = bx;
-    ay = by;
-    az = bz;
   }
-}
-
-__device__ __forceinline__ void acc_add(WaveScratch &sh, bool lds, Work &W, uint32_t slot,
-                                        int64_t node, double v) {
-  long long h;
-  unsigned long long l;
-  fx_encode(v, W.wexp[node], h, l);
-  if (lds) {
-    atomicAdd((unsigned long long *)&sh.acc_hi[slot], (unsigned long long)h);
-    atomicAdd(&sh.acc_lo[slot], l);
-  } else {
-    atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h);
-    atomicAdd(&W.w_lo[node], l);
+  __device__ __forceinline__ double geteps(int e, int pt0, int p) const {
+    return pt0 >= 0 ? sh.u.stg.pe[pt0 + p]
+                    : eps[sh.e_kp[e] + (sh.e_nb[e] == 1 ? 0 : sh.e_i0[e]) + p];
   }
-}
+};
 
 __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
   Work W = L.w;
-  __shared__ WaveScratch sh;
+  __shared__ WeightsScratch sh;
   const int lane = threadIdx.x;
   const uint32_t n_items = W.tile_itoff[W.n_tiles];
-  for (;;) {
-    if (lane == 0) sh.item = atomicAdd(&W.counters[0], 1u);
-    __syncthreads();
-    const uint32_t item = sh.item;
-    __syncthreads();
-    if (item >= n_items || (int64_t)item >= W.cap_item) break;
+  // record space is reserved in blocks per wave; pair counts are flushed per case
+  unsigned long long blk_cur = 0, blk_end = 0;
+  int acc_case = -1;
+  unsigned long long acc_pairs = 0;
+  for (uint32_t item = blockIdx.x; item < n_items && (int64_t)item < W.cap_item; item += gridDim.x) {
     const Item it = W.item[item];
+    if (it.cs != acc_case) {
+      if (lane == 0 && acc_case >= 0 && acc_pairs)
+        atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
+      acc_case = it.cs;
+      acc_pairs = 0;
+    }
     const CaseDev &cs = L.cases[it.cs];
     const MeshDev &m = cs.m;
     const int64_t tl = it.tile - cs.tile_base;
+    const uint32_t eoff = W.tile_off[it.tile];
+    const uint32_t n_emit = W.tile_off[it.tile + 1] - eoff;
+    const int rsz = rec_size(cs.prec);
+    if (n_emit > (uint32_t)kMaxEmitTile) {
+      if (lane == 0) {
+        set_overflow(W, 4u);
+        W.rec_cnt[item] = 0;
+        W.rec_base[item] = 0;
+      }
+      continue;
+    }
+    // 1. sort windows by (beam, lo) and merge per beam
+    uint32_t np2 = 1;
+    while (np2 < n_emit) np2 <<= 1;
+    for (uint32_t i = lane; i < np2; i += 64) {
+      if (i < n_emit) {
+        Emit e = W.emit[eoff + i];
+        sh.u.srt.key[i] = ((unsigned long long)(uint32_t)(e.beam - (int32_t)cs.beam_base) << 32) |
+                          (uint32_t)e.lo;
+        sh.u.srt.hi[i] = e.hi;
+      } else {
+        sh.u.srt.key[i] = ~0ull;
+        sh.u.srt.hi[i] = 0;
+      }
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= np2; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = lane; i < np2; i += 64) {
+          uint32_t p = i ^ j;
+          if (p > i) {
+            bool up = (i & k) == 0;
+            unsigned long long a = sh.u.srt.key[i], bk = sh.u.srt.key[p];
+            if ((a > bk) == up) {
+              sh.u.srt.key[i] = bk;
+              sh.u.srt.key[p] = a;
+              int32_t t = sh.u.srt.hi[i];
+              sh.u.srt.hi[i] = sh.u.srt.hi[p];
+              sh.u.srt.hi[p] = t;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    uint32_t ne = 0;
+    for (uint32_t r0 = 0; r0 < n_emit; r0 += 64) {
+      const uint32_t i = r0 + lane;
+      bool head = false;
+      uint32_t beam = 0;
+      if (i < n_emit) {
+        beam = (uint32_t)(sh.u.srt.key[i] >> 32);
+        head = (i == 0) || ((uint32_t)(sh.u.srt.key[i - 1] >> 32) != beam);
+      }
+      const uint64_t bal = ballot64(head);
+      if (head) {
+        const uint32_t idx = ne + lanemask_lt_popc(bal);
+        int32_t hi = sh.u.srt.hi[i];
+        for (uint32_t j = i + 1; j < n_emit && (uint32_t)(sh.u.srt.key[j] >> 32) == beam; ++j)
+          hi = max(hi, sh.u.srt.hi[j]);
+        if (idx < (uint32_t)kMaxEntries) {
+          int64_t k0 = cs.offsets[beam];
+          sh.e_kp[idx] = (int32_t)k0;
+          sh.e_nb[idx] = (int32_t)(cs.offsets[beam + 1] - k0);
+          sh.e_i0[idx] = (int32_t)(sh.u.srt.key[i] & 0xffffffffu);
+          sh.e_i1[idx] = hi;
+        }
+      }
+      ne += (uint32_t)__popcll(bal);
+    }
+    if (ne > (uint32_t)kMaxEntries) {
+      if (lane == 0) {
+        set_overflow(W, 4u);
+        W.rec_cnt[item] = 0;
+        W.rec_base[item] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    __syncthreads();
+    // 2. staging: the leading entries whose windows fit in LDS
+    {
+      uint32_t carry = 0;
+      int nst = 0;
+      for (uint32_t e0 = 0; e0 < ne; e0 += 64) {
+        const uint32_t e = e0 + lane;
+        uint32_t cntp = 0;
+        if (e < ne) cntp = sh.e_nb[e] == 1 ? 1u : (uint32_t)(sh.e_i1[e] - sh.e_i0[e] + 2);
+        uint32_t tot;
+        uint32_t ex = wave_excl_scan_u32(cntp, tot) + carry;
+        const bool fits = e < ne && ex + cntp <= (uint32_t)kStagePts;
+        if (e < ne) sh.e_pt0[e] = fits ? (int32_t)ex : -1;
+        nst += __popcll(ballot64(fits));
+        carry += tot;
+      }
+      if (lane == 0) sh.n_staged = nst;
+      __syncthreads();
+      int npts = 0;
+      if (nst > 0) {
+        const int last = nst - 1;
+        npts = sh.e_pt0[last] + (sh.e_nb[last] == 1 ? 1 : sh.e_i1[last] - sh.e_i0[last] + 2);
+      }
+      for (int q = lane; q < npts; q += 64) {
+        int lo = 0, hi = nst - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (sh.e_pt0[mid] <= q) lo = mid;
+          else hi = mid - 1;
+        }
+        const int64_t pk = sh.e_kp[lo] + (sh.e_nb[lo] == 1 ? 0 : sh.e_i0[lo]) + (q - sh.e_pt0[lo]);
+        const double *P = cs.Psp + 3 * pk;
+        sh.u.stg.px[q] = P[0];
+        sh.u.stg.py[q] = P[1];
+        sh.u.stg.pz[q] = P[2];
+        sh.u.stg.pe[q] = cs.eps[pk];
+        sh.u.stg.ahi[q] = 0;
+        sh.u.stg.alo[q] = 0;
+      }
+      if (lane == 0) sh.n_pts = npts;
+      __syncthreads();
+    }
+    const int n_staged = sh.n_staged;
+    const WinPts wp{sh, cs.Psp, cs.eps};
     double ox, oy, oz;
-    int tx, ty, tz;
-    tile_origin(m, tl, ox, oy, oz, tx, ty, tz);
+    tile_origin(m, tl, ox, oy, oz);
+    // screening boxes: window AABB inflated by 3 eps_max of the window
+    for (uint32_t e = lane; e < ne; e += 64) {
+      const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
+      const int np = sh.e_nb[e] == 1 ? 1 : sh.e_i1[e] - sh.e_i0[e] + 2;
+      double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, em = 0;
+      for (int p = 0; p < np; ++p) {
+        double x, y, z;
+        wp.get(e, pt0, p, x, y, z);
+        lo[0] = fmin(lo[0], x);
+        lo[1] = fmin(lo[1], y);
+        lo[2] = fmin(lo[2], z);
+        hi[0] = fmax(hi[0], x);
+        hi[1] = fmax(hi[1], y);
+        hi[2] = fmax(hi[2], z);
+        em = fmax(em, wp.geteps(e, pt0, p));
+      }
+      const double R = 3.0 * em * (1.0 + 1e-6) + 1e-6 * m.tile_len;
+      sh.e_box[0][e] = (float)(lo[0] - R - ox) - 1e-6f * (float)m.tile_len;
+      sh.e_box[1][e] = (float)(lo[1] - R - oy) - 1e-6f * (float)m.tile_len;
+      sh.e_box[2][e] = (float)(lo[2] - R - oz) - 1e-6f * (float)m.tile_len;
+      sh.e_box[3][e] = (float)(hi[0] + R - ox) + 1e-6f * (float)m.tile_len;
+      sh.e_box[4][e] = (float)(hi[1] + R - oy) + 1e-6f * (float)m.tile_len;
+      sh.e_box[5][e] = (float)(hi[2] + R - oz) + 1e-6f * (float)m.tile_len;
+      if ((int)e >= n_staged) sh.e_pt0[e] = -1;
+    }
+    __syncthreads();
+    // 3. cells and screening
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
     double cx = 0, cy = 0, cz = 0, v = 0;
@@ -822,42 +917,11 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
       ly = (float)(cy - oy);
       lz = (float)(cz - oz);
     }
-    sh.cx[lane] = cx;
-    sh.cy[lane] = cy;
-    sh.cz[lane] = cz;
-    sh.v[lane] = v;
-    const uint32_t ent0 = W.tile_off[it.tile];
-    const int ne = (int)W.tile_nent[it.tile];
-    const Entry *E = W.entry + ent0;
-    const double *X = cs.Psp;
-    // node-slot bases per entry
-    uint32_t carry = 0;
-    for (int e0 = 0; e0 < ne; e0 += 64) {
-      int e = e0 + lane;
-      uint32_t ns = 0;
-      if (e < ne) {
-        Entry en = E[e];
-        ns = en.nb == 1 ? 1u : (uint32_t)(en.i1 - en.i0 + 2);
-      }
-      uint32_t tot;
-      uint32_t ex = wave_excl_scan_u32(ns, tot);
-      if (e < ne) sh.slot0[e] = carry + ex;
-      carry += tot;
-    }
-    if (lane == 0) sh.slot0[ne] = carry;
-    const uint32_t nslot = carry;
-    const bool lds = nslot <= (uint32_t)kNodeSlots;
-    if (lds)
-      for (uint32_t s = lane; s < nslot; s += 64) {
-        sh.acc_hi[s] = 0;
-        sh.acc_lo[s] = 0;
-      }
-    // 1. screening
     uint32_t word = 0, cnt = 0;
-    for (int e = 0; e < ne; ++e) {
-      const Entry en = E[e];
-      float d2 = seg_dist2_f32(lx, ly, lz, en.ax, en.ay, en.az, en.bx, en.by, en.bz);
-      if (valid && d2 <= en.r2) word |= 1u << (e & 31);
+    for (uint32_t e = 0; e < ne; ++e) {
+      const bool hit = valid && lx >= sh.e_box[0][e] && lx <= sh.e_box[3][e] && ly >= sh.e_box[1][e] &&
+                       ly <= sh.e_box[4][e] && lz >= sh.e_box[2][e] && lz <= sh.e_box[5][e];
+      if (hit) word |= 1u << (e & 31);
       if ((e & 31) == 31 || e == ne - 1) {
         sh.mask[lane * kMaskWords + (e >> 5)] = word;
         cnt += __popc(word);
@@ -865,24 +929,30 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
       }
     }
     uint32_t total;
-    uint32_t myoff = wave_excl_scan_u32(cnt, total);
+    const uint32_t myoff = wave_excl_scan_u32(cnt, total);
     sh.off[lane] = myoff;
     if (lane == 63) sh.off[64] = myoff + cnt;
     __syncthreads();
-    // record space for up to `total` pairs
-    uint32_t rbase = 0;
-    if (lane == 0) rbase = atomicAdd(&W.counters[2], total);
-    rbase = __shfl(rbase, 0, 64);
-    const bool rec_ok = (int64_t)rbase + total <= W.cap_rec;
+    // record space for up to `total` pairs, carved from the wave's block
+    const unsigned long long need = ((unsigned long long)total * rsz + 15ull) & ~15ull;
+    if (blk_cur + need > blk_end) {
+      const unsigned long long take = need > kRecBlock ? need : kRecBlock;
+      unsigned long long got = 0;
+      if (lane == 0) got = atomicAdd(W.rec_alloc, take);
+      blk_cur = __shfl(got, 0, 64);
+      blk_end = blk_cur + take;
+    }
+    const unsigned long long rbase = blk_cur;
+    blk_cur += need;
+    const bool rec_ok = (int64_t)(rbase + need) <= W.cap_rec;
     if (!rec_ok && lane == 0) set_overflow(W, 2u);
     uint32_t nreal = 0;
-    const int nwords = (ne + 31) >> 5;
-    // 2.-4. candidate pairs, 64 per round
+    const int nwords = (int)((ne + 31) >> 5);
+    // 4.-6. candidate pairs, 64 per round
     for (uint32_t p0 = 0; p0 < total; p0 += 64) {
       const uint32_t p = p0 + lane;
       const bool act = p < total;
-      bool in = false;
-      int L_ = 0, e = 0, bi = 0;
+      int Lc = lane, e = 0;
       if (act) {
         int lo = 0, hi = 63;
         while (lo < hi) {
@@ -890,10 +960,10 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
           if (sh.off[mid] <= p) lo = mid;
           else hi = mid - 1;
         }
-        L_ = lo;
-        uint32_t r = p - sh.off[L_];
+        Lc = lo;
+        uint32_t r = p - sh.off[Lc];
         for (int wd = 0; wd < nwords; ++wd) {
-          uint32_t mw = sh.mask[L_ * kMaskWords + wd];
+          uint32_t mw = sh.mask[Lc * kMaskWords + wd];
           uint32_t pc = __popc(mw);
           if (r < pc) {
             for (uint32_t q = 0; q < r; ++q) mw &= mw - 1u;
@@ -902,61 +972,121 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
           }
           r -= pc;
         }
-        const Entry en = E[e];
-        const double *Xb = X + 3 * (int64_t)en.kp;
-        const double pcx = sh.cx[L_], pcy = sh.cy[L_], pcz = sh.cz[L_];
-        double bs, br2;
-        window_argmin(Xb, en, pcx, pcy, pcz, bi, bs, br2);
-        const double *epsb = cs.eps + en.kp;
-        double ej = en.nb == 1 ? epsb[0] : eps_at(bs, epsb[bi], epsb[bi + 1]);
+      }
+      const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
+      const double pv = __shfl(v, Lc, 64);
+      bool in = false;
+      int bi = 0, single = 0;
+      double a0 = 0.0, a1 = 0.0;
+      if (act) {
+        const int pt0 = sh.e_pt0[e];
+        const int nb = sh.e_nb[e], i0 = sh.e_i0[e], i1 = sh.e_i1[e];
+        double bs = 0.0, br2;
+        double ej;
+        if (nb == 1) {
+          single = 1;
+          double x, y, z;
+          wp.get(e, pt0, 0, x, y, z);
+          br2 = sqdist_exact(pcx, pcy, pcz, x, y, z);
+          ej = wp.geteps(e, pt0, 0);
+        } else {
+          br2 = INFINITY;
+          bi = i0;
+          double ax, ay, az;
+          wp.get(e, pt0, 0, ax, ay, az);
+          for (int i = i0; i <= i1; ++i) {
+            double bx, by, bz, s, r2;
+            wp.get(e, pt0, i - i0 + 1, bx, by, bz);
+            seg_foot(pcx, pcy, pcz, ax, ay, az, bx, by, bz, s, r2);
+            if (r2 < br2) {
+              br2 = r2;
+              bi = i;
+              bs = s;
+            }
+            ax = bx;
+            ay = by;
+            az = bz;
+          }
+          ej = eps_at(bs, wp.geteps(e, pt0, bi - i0), wp.geteps(e, pt0, bi - i0 + 1));
+        }
         in = inside_cutoff(br2, ej);
         if (in) {
-          double a0, a1;
           pair_weights(cs.prec, bs, br2, ej, a0, a1);
-          const double vv = sh.v[L_];
-          const int64_t node = cs.point_base + en.kp + bi;
-          const uint32_t slot = sh.slot0[e] + (uint32_t)(en.nb == 1 ? 0 : bi - en.i0);
-          acc_add(sh, lds, W, slot, node, a0 * vv);
-          if (en.nb > 1) acc_add(sh, lds, W, slot + 1, node + 1, a1 * vv);
+          const int jl = nb == 1 ? 0 : bi - i0;
+          const int64_t node = cs.point_base + sh.e_kp[e] + (nb == 1 ? 0 : bi);
+          long long h0, h1 = 0;
+          unsigned long long l0, l1 = 0;
+          fx_encode(a0 * pv, W.wexp[node], h0, l0);
+          if (nb > 1) fx_encode(a1 * pv, W.wexp[node + 1], h1, l1);
+          if (pt0 >= 0) {
+            atomicAdd((unsigned long long *)&sh.u.stg.ahi[pt0 + jl], (unsigned long long)h0);
+            atomicAdd(&sh.u.stg.alo[pt0 + jl], l0);
+            if (nb > 1) {
+              atomicAdd((unsigned long long *)&sh.u.stg.ahi[pt0 + jl + 1], (unsigned long long)h1);
+              atomicAdd(&sh.u.stg.alo[pt0 + jl + 1], l1);
+            }
+          } else {
+            atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h0);
+            atomicAdd(&W.w_lo[node], l0);
+            if (nb > 1) {
+              atomicAdd((unsigned long long *)&W.w_hi[node + 1], (unsigned long long)h1);
+              atomicAdd(&W.w_lo[node + 1], l1);
+            }
+          }
+          bi = (int)node;  // reuse: global node index for the record
         }
       }
       const uint64_t bal = ballot64(act && in);
       if (act && in && rec_ok) {
-        uint32_t rank = lanemask_lt_popc(bal);
-        const Entry en = E[e];
-        uint32_t seg = (uint32_t)(en.nb == 1 ? 0 : bi - en.i0);
-        W.rec[rbase + nreal + rank] = ((uint32_t)L_ << 26) | ((uint32_t)e << 16) | seg;
+        const unsigned long long at = rbase + (unsigned long long)(nreal + lanemask_lt_popc(bal)) * rsz;
+        unsigned char *r = W.rec + at;
+        const uint32_t meta = (uint32_t)Lc | (single ? kRecSingle : 0u);
+        if (rsz == 16) {
+          uint4 q;
+          q.x = meta;
+          q.y = (uint32_t)bi;
+          q.z = __float_as_uint((float)a0);
+          q.w = __float_as_uint((float)a1);
+          *(uint4 *)r = q;
+        } else {
+          uint2 q;
+          q.x = meta;
+          q.y = (uint32_t)bi;
+          *(uint2 *)r = q;
+          *(double2 *)(r + 8) = make_double2(a0, a1);
+        }
       }
       nreal += (uint32_t)__popcll(bal);
     }
     __syncthreads();
-    // flush node accumulators
-    if (lds) {
-      for (uint32_t s = lane; s < nslot; s += 64) {
-        long long h = sh.acc_hi[s];
-        unsigned long long l = sh.acc_lo[s];
-        if (h == 0 && l == 0) continue;
-        int lo = 0, hi = ne - 1;
-        while (lo < hi) {
-          int mid = (lo + hi + 1) >> 1;
-          if (sh.slot0[mid] <= s) lo = mid;
-          else hi = mid - 1;
-        }
-        const Entry en = E[lo];
-        int64_t node = cs.point_base + en.kp + (en.nb == 1 ? 0 : en.i0) + (s - sh.slot0[lo]);
-        h += (long long)(l >> kLoBits);
-        l &= (1ull << kLoBits) - 1ull;
-        atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h);
-        atomicAdd(&W.w_lo[node], l);
+    // flush the staged node accumulators
+    const int npts = sh.n_pts;
+    for (int q = lane; q < npts; q += 64) {
+      long long h = sh.u.stg.ahi[q];
+      unsigned long long l = sh.u.stg.alo[q];
+      if (h == 0 && l == 0) continue;
+      int lo = 0, hi = n_staged - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sh.e_pt0[mid] <= q) lo = mid;
+        else hi = mid - 1;
       }
+      const int64_t node = cs.point_base + sh.e_kp[lo] + (sh.e_nb[lo] == 1 ? 0 : sh.e_i0[lo]) +
+                           (q - sh.e_pt0[lo]);
+      h += (long long)(l >> kLoBits);
+      l &= (1ull << kLoBits) - 1ull;
+      atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h);
+      atomicAdd(&W.w_lo[node], l);
     }
     if (lane == 0) {
       W.rec_base[item] = rbase;
       W.rec_cnt[item] = rec_ok ? nreal : 0u;
-      atomicAdd((unsigned long long *)(W.cnt + 8 * it.cs + 5), (unsigned long long)nreal);
     }
+    acc_pairs += nreal;
     __syncthreads();
   }
+  if (lane == 0 && acc_case >= 0 && acc_pairs)
+    atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
 }
 
 void launch_weights(const StepLaunch &L, hipStream_t st) {
@@ -1029,7 +1159,8 @@ __global__ __launch_bounds__(kSumBlock) void k_beam_sums(StepLaunch L) {
     for (int q = 0; q < 4; ++q) W.beam_part[4 * pb + q] = s[q][0];
 }
 
-// per case: F_beam, sum |f L| and the fixed-point exponent of the fluid-side sum
+// per case: F_beam, sum |f L| and the fixed-point exponent of the fluid-side
+// sum (every partial of sum_j S_j V_j is bounded by sum_k |f_k L_k|)
 __global__ void k_finalize_beam(StepLaunch L) {
   Work W = L.w;
   int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1054,15 +1185,14 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 
 // ----------------------------------------------------------------- spread --
 // Eq. (23): S_j = -sum over the cell's pairs (beam order) of
-// a0 f_hat_i + a1 f_hat_i+1, with a0, a1 recomputed bit-identically from the
-// stored pair records.  Each cell is summed by one lane in record order, so
-// the source needs no atomics; every cell of an active tile is written.
+// a0 f_hat_i + a1 f_hat_i+1, from the records of the weights pass (the same
+// a0, a1 that built w_k, so the transferred force balances exactly).  Each
+// cell is summed by one lane in record order; every cell of an active tile is
+// written.
 struct SpreadScratch {
-  double cx[64], cy[64], cz[64];
   double cc[3][64];
   uint32_t cnt[64];
   uint32_t off[65];
-  uint32_t item;
 };
 
 __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
@@ -1070,33 +1200,43 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
   __shared__ SpreadScratch sh;
   const int lane = threadIdx.x;
   const uint32_t n_items = W.tile_itoff[W.n_tiles];
-  for (;;) {
-    if (lane == 0) sh.item = atomicAdd(&W.counters[1], 1u);
-    __syncthreads();
-    const uint32_t item = sh.item;
-    __syncthreads();
-    if (item >= n_items || (int64_t)item >= W.cap_item) break;
+  // per-wave accumulation (exact fixed point, flushed when the case changes)
+  int acc_case = -1;
+  unsigned long long acc_band = 0;
+  long long fh = 0;          // lanes 0..2 hold x, y, z
+  unsigned long long fl = 0;
+  for (uint32_t item = blockIdx.x; item < n_items && (int64_t)item < W.cap_item; item += gridDim.x) {
     const Item it = W.item[item];
+    if (it.cs != acc_case) {
+      if (acc_case >= 0) {
+        if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
+        if (lane < 3 && (fh || fl)) {
+          fh += (long long)(fl >> kLoBits);
+          fl &= (1ull << kLoBits) - 1ull;
+          atomicAdd((unsigned long long *)&W.F_hi[3 * acc_case + lane], (unsigned long long)fh);
+          atomicAdd(&W.F_lo[3 * acc_case + lane], fl);
+        }
+      }
+      acc_case = it.cs;
+      acc_band = 0;
+      fh = 0;
+      fl = 0;
+    }
     const CaseDev &cs = L.cases[it.cs];
     const MeshDev &m = cs.m;
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
-    double v = 0.0;
-    if (valid) {
-      sh.cx[lane] = m.cx[c];
-      sh.cy[lane] = m.cy[c];
-      sh.cz[lane] = m.cz[c];
-      v = m.vs[c];
-    }
+    const double v = valid ? m.vs[c] : 0.0;
+    const uint32_t rn = W.rec_cnt[item];
+    const unsigned char *rec = W.rec + W.rec_base[item];
+    const int rsz = rec_size(cs.prec);
     sh.cnt[lane] = 0;
     __syncthreads();
-    const uint32_t rb = W.rec_base[item], rn = W.rec_cnt[item];
-    const uint32_t ent0 = W.tile_off[it.tile];
-    const Entry *E = W.entry + ent0;
-    for (uint32_t j = lane; j < rn; j += 64) atomicAdd(&sh.cnt[W.rec[rb + j] >> 26], 1u);
+    for (uint32_t j = lane; j < rn; j += 64)
+      atomicAdd(&sh.cnt[*(const uint32_t *)(rec + (size_t)j * rsz) & 63u], 1u);
     __syncthreads();
     uint32_t tot;
-    uint32_t myoff = wave_excl_scan_u32(sh.cnt[lane], tot);
+    const uint32_t myoff = wave_excl_scan_u32(sh.cnt[lane], tot);
     sh.off[lane] = myoff;
     if (lane == 63) sh.off[64] = tot;
     __syncthreads();
@@ -1104,30 +1244,26 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
     for (uint32_t p0 = 0; p0 < rn; p0 += 64) {
       const uint32_t p = p0 + lane;
       if (p < rn) {
-        const uint32_t r = W.rec[rb + p];
-        const int L_ = (int)(r >> 26), e = (int)((r >> 16) & 1023u), seg = (int)(r & 0xffffu);
-        const Entry en = E[e];
-        const double *Xb = cs.Psp + 3 * (int64_t)en.kp;
-        const double *epsb = cs.eps + en.kp;
-        const double pcx = sh.cx[L_], pcy = sh.cy[L_], pcz = sh.cz[L_];
-        double s, r2, ej;
-        int i;
-        if (en.nb == 1) {
-          i = 0;
-          s = 0.0;
-          r2 = sqdist_exact(pcx, pcy, pcz, Xb[0], Xb[1], Xb[2]);
-          ej = epsb[0];
-        } else {
-          i = en.i0 + seg;
-          seg_foot(pcx, pcy, pcz, Xb[3 * i], Xb[3 * i + 1], Xb[3 * i + 2], Xb[3 * i + 3],
-                   Xb[3 * i + 4], Xb[3 * i + 5], s, r2);
-          ej = eps_at(s, epsb[i], epsb[i + 1]);
-        }
+        const unsigned char *r = rec + (size_t)p * rsz;
+        uint32_t meta, node;
         double a0, a1;
-        pair_weights(cs.prec, s, r2, ej, a0, a1);
-        const double *fh = W.fhat + 3 * (cs.point_base + en.kp + i);
+        if (rsz == 16) {
+          const uint4 q = *(const uint4 *)r;
+          meta = q.x;
+          node = q.y;
+          a0 = (double)__uint_as_float(q.z);
+          a1 = (double)__uint_as_float(q.w);
+        } else {
+          const uint2 q = *(const uint2 *)r;
+          meta = q.x;
+          node = q.y;
+          const double2 a = *(const double2 *)(r + 8);
+          a0 = a.x;
+          a1 = a.y;
+        }
+        const double *fh = W.fhat + 3 * (int64_t)node;
         double q0 = a0 * fh[0], q1 = a0 * fh[1], q2 = a0 * fh[2];
-        if (en.nb > 1) {
+        if (!(meta & kRecSingle)) {
           q0 += a1 * fh[3];
           q1 += a1 * fh[4];
           q2 += a1 * fh[5];
@@ -1152,20 +1288,29 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
       S[1] = S1;
       S[2] = S2;
     }
-    wave_count_add(W.cnt + 8 * it.cs + 4, valid && sh.cnt[lane] > 0);
+    acc_band += (unsigned long long)__popcll(ballot64(valid && sh.cnt[lane] > 0));
     // force on the fluid: deterministic wave sum, then exact accumulation
-    double fx = wave_sum_f64(S0 * v), fy = wave_sum_f64(S1 * v), fz = wave_sum_f64(S2 * v);
+    const double fx = wave_sum_f64(S0 * v), fy = wave_sum_f64(S1 * v), fz = wave_sum_f64(S2 * v);
     if (lane < 3) {
-      double val = lane == 0 ? fx : (lane == 1 ? fy : fz);
+      const double val = lane == 0 ? fx : (lane == 1 ? fy : fz);
       if (val != 0.0) {
         long long h;
         unsigned long long l;
         fx_encode(val, W.F_exp[it.cs], h, l);
-        atomicAdd((unsigned long long *)&W.F_hi[3 * it.cs + lane], (unsigned long long)h);
-        atomicAdd(&W.F_lo[3 * it.cs + lane], l);
+        fh += h;
+        fl += l;
       }
     }
     __syncthreads();
+  }
+  if (acc_case >= 0) {
+    if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
+    if (lane < 3 && (fh || fl)) {
+      fh += (long long)(fl >> kLoBits);
+      fl &= (1ull << kLoBits) - 1ull;
+      atomicAdd((unsigned long long *)&W.F_hi[3 * acc_case + lane], (unsigned long long)fh);
+      atomicAdd(&W.F_lo[3 * acc_case + lane], fl);
+    }
   }
 }
 
@@ -1184,7 +1329,7 @@ __global__ void k_zero_dirty(StepLaunch L) {
   const CaseDev &cs = L.cases[c];
   if (!cs.write_S || !cs.tile_prev) return;
   int64_t tl = tg - cs.tile_base;
-  uint8_t now = W.tile_nent[tg] > 0 ? 1 : 0;
+  uint8_t now = W.tile_items[tg] > 0 ? 1 : 0;
   if (cs.tile_prev[tl] && !now) {
     uint32_t c0 = tile_cell_start(cs.m, tl), c1 = tile_cell_start(cs.m, tl + 1);
     for (uint32_t j = c0; j < c1; ++j) {
