@@ -102,8 +102,9 @@ def compare(res, ref, diag, ref_diag, tol_S, tol_w, tol_f=1e-12, check_sample=Tr
         assert err["P_s"] <= 1e-15 and err["U_s"] == 0.0, err
     err["f"] = normwise(res["f"], ref["f"])
     assert err["f"] <= tol_f, err
-    err["w"] = float(np.max(np.abs(res["w"] - ref["w"]) / np.maximum(np.abs(ref["w"]), 1e-300))) \
-        if ref["w"].size else 0.0
+    zw = ref["w"] == 0
+    assert np.all(res["w"][zw] == 0), "weight on a node that catches no cell"
+    err["w"] = float(np.max(np.abs(res["w"][~zw] - ref["w"][~zw]) / ref["w"][~zw])) if np.any(~zw) else 0.0
     assert err["w"] <= tol_w, err
     err["S"] = normwise(res["S"], ref["S"])
     assert err["S"] <= tol_S, err
