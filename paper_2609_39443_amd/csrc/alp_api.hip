@@ -29,7 +29,8 @@ struct alp_context {
   int device = 0;
   hipStream_t user = nullptr;
   hipStream_t st = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t st2 = nullptr;  // second stream: sampling and drag run beside the projection
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   int n_cu = 256;
   // workspace
@@ -403,10 +404,21 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   else if (stages & ST_SAMPLE) launch_step_reset_sample(L, st);
   launch_points_prep(L, st);
   mark(1);
-  if (stages & ST_SAMPLE) launch_sample(L, st);
+  // Sampling and drag (eq. 16-20) do not depend on the segment binning or the
+  // weights pass (eq. 21-22): in a full step they run on the second stream and
+  // join before the normalisation, which needs f.  The profiled step keeps
+  // everything on one stream so that each stage is timed on its own.
+  const bool fork = (stages == ST_ALL) && !ev;
+  hipStream_t sd = fork ? ctx->st2 : st;
+  if (fork) {
+    (void)hipEventRecord(ctx->ev_fork, st);
+    (void)hipStreamWaitEvent(sd, ctx->ev_fork, 0);
+  }
+  if (stages & ST_SAMPLE) launch_sample(L, sd);
   mark(2);
-  if (stages & ST_DRAG) launch_drag(L, st);
+  if (stages & ST_DRAG) launch_drag(L, sd);
   mark(3);
+  if (fork) (void)hipEventRecord(ctx->ev_join, sd);
   if (!(stages & ST_PROJECT)) return;
   launch_beams_prep(L, st);
   launch_scan_u32(w.bchunks, w.bchunks, w.n_beams, ctx->scan_tmp, st);
@@ -422,6 +434,7 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   mark(4);
   launch_weights(L, st);
   mark(5);
+  if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
   launch_norm(L, st);
   launch_beam_sums(L, st);
   mark(6);
@@ -518,7 +531,10 @@ alp_status alp_create(int device, void *hip_stream, alp_context **out) {
   if (hipSetDevice(device) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->st, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
     delete ctx;
     return ALP_ERR_HIP;
   }
@@ -539,6 +555,9 @@ alp_status alp_destroy(alp_context *ctx) {
   if (ctx->d_bases) (void)hipFree(ctx->d_bases);
   (void)hipEventDestroy(ctx->ev_in);
   (void)hipEventDestroy(ctx->ev_out);
+  (void)hipEventDestroy(ctx->ev_fork);
+  (void)hipEventDestroy(ctx->ev_join);
+  (void)hipStreamDestroy(ctx->st2);
   (void)hipStreamDestroy(ctx->st);
   delete ctx;
   return ALP_OK;

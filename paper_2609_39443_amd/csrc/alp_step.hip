@@ -95,6 +95,7 @@ __global__ void k_step_reset(StepLaunch L, int what) {
     W.tile_cnt[i] = 0;
     W.tile_fill[i] = 0;
   }
+  for (int64_t i = tid; i < W.n_beams; i += stride) W.beps_max[i] = 0.0;
 }
 
 void launch_step_reset(const StepLaunch &L, hipStream_t st) {
@@ -125,6 +126,12 @@ __global__ void k_points_prep(StepLaunch L) {
     else hi = mid - 1;
   }
   W.pbeam[g] = (int32_t)(cs.beam_base + lo);
+  // largest kernel width of the beam: for non-negative doubles the bit
+  // patterns order like the values, so an integer max is exact and
+  // independent of the order of the atomics
+  if (cs.eps[k] > 0.0)
+    atomicMax((unsigned long long *)&W.beps_max[cs.beam_base + lo],
+              (unsigned long long)__double_as_longlong(cs.eps[k]));
   int64_t k0 = cs.offsets[lo], k1 = cs.offsets[lo + 1];
   double em = cs.eps[k];
   if (k > k0) em = fmin(em, cs.eps[k - 1]);
@@ -150,12 +157,8 @@ __global__ void k_beams_prep(StepLaunch L) {
   int c = case_of(L.bbase, L.n_cases, gb);
   const CaseDev &cs = L.cases[c];
   int64_t b = gb - cs.beam_base;
-  int64_t k0 = cs.offsets[b], k1 = cs.offsets[b + 1];
-  int64_t n = k1 - k0;
-  double em = 0.0;
-  for (int64_t k = k0; k < k1; ++k) em = fmax(em, cs.eps[k]);
+  int64_t n = cs.offsets[b + 1] - cs.offsets[b];
   W.bcase[gb] = c;
-  W.beps_max[gb] = em;
   int64_t nseg = n >= 2 ? n - 1 : n;
   W.bchunks[gb] = (uint32_t)((nseg + kChunkSegs - 1) / kChunkSegs);
 }
@@ -1160,27 +1163,35 @@ __global__ __launch_bounds__(kSumBlock) void k_beam_sums(StepLaunch L) {
 }
 
 // per case: F_beam, sum |f L| and the fixed-point exponent of the fluid-side
-// sum (every partial of sum_j S_j V_j is bounded by sum_k |f_k L_k|)
-__global__ void k_finalize_beam(StepLaunch L) {
+// sum (every partial of sum_j S_j V_j is bounded by sum_k |f_k L_k|); one
+// block per case, each thread sums a fixed stride of the case's point blocks,
+// then a fixed tree
+__global__ __launch_bounds__(kSumBlock) void k_finalize_beam(StepLaunch L) {
   Work W = L.w;
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= L.n_cases) return;
+  __shared__ double s[4][kSumBlock];
+  const int c = blockIdx.x;
   double r[4] = {0, 0, 0, 0};
-  for (int pb = 0; pb < W.n_pblocks; ++pb)
+  for (int pb = threadIdx.x; pb < W.n_pblocks; pb += kSumBlock)
     if (W.pblock_case[pb] == c)
       for (int q = 0; q < 4; ++q) r[q] += W.beam_part[4 * pb + q];
-  double *d = W.diag_out + 16 * c;
-  d[0] = r[0];
-  d[1] = r[1];
-  d[2] = r[2];
-  d[3] = r[3];
-  W.F_exp[c] = r[3] > 0.0 ? ilogb(r[3]) + 2 : 0;
+  for (int q = 0; q < 4; ++q) s[q][threadIdx.x] = r[q];
+  __syncthreads();
+  for (int w = kSumBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double *d = W.diag_out + 16 * c;
+    for (int q = 0; q < 4; ++q) d[q] = s[q][0];
+    W.F_exp[c] = s[3][0] > 0.0 ? ilogb(s[3][0]) + 2 : 0;
+  }
 }
 
 void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_pblocks > 0)
     hipLaunchKernelGGL(k_beam_sums, dim3(L.w.n_pblocks), dim3(kSumBlock), 0, st, L);
-  hipLaunchKernelGGL(k_finalize_beam, dim3((L.n_cases + 63) / 64), dim3(64), 0, st, L);
+  hipLaunchKernelGGL(k_finalize_beam, dim3(L.n_cases), dim3(kSumBlock), 0, st, L);
 }
 
 // ----------------------------------------------------------------- spread --
@@ -1315,7 +1326,7 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
 }
 
 void launch_spread(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_spread, dim3(L.grid_persistent), dim3(64), 0, st, L);
+  hipLaunchKernelGGL(k_spread, dim3(L.grid_persistent * 3), dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------- zero dirty --
