@@ -9,7 +9,7 @@ the seeds listed per workload.
 The shapes stand in for the paper's workloads (Taran et al., arXiv 2609.39443):
 the confined channel of Sec. 5 (kernel width about twice the cell size, 20 beam
 CVs, sampling offset about five kernel widths) and the wave-flume stem of
-Sec. 7.2 (stem diameter, drag coefficients, 0.375 m sampling offset projected
+Sec. 7.2-7.4 (stem diameter, drag coefficients, 0.375 m sampling offset projected
 onto the vertical plane through the stem).  The canopy, net and batched-scenario
 workloads scale these shapes up; no item of any external dataset is used.
 
