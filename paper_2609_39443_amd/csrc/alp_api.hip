@@ -180,10 +180,12 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(tile_cnt, T + 1);
   WALLOC(tile_off, T + 1);
   WALLOC(tile_fill, T + 1);
+  WALLOC(tile_nent, T + 1);
   WALLOC(tile_items, T + 1);
   WALLOC(tile_itoff, T + 1);
   WALLOC(emit_raw, EM);
   WALLOC(emit, EM);
+  WALLOC(entry, EM);
   WALLOC(item, IT);
   WALLOC(rec_base, IT);
   WALLOC(rec_cnt, IT);
@@ -428,7 +430,7 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   launch_chunk_tiles(L, st);
   launch_scan_u32(w.tile_cnt, w.tile_off, w.n_tiles, ctx->scan_tmp, st);
   launch_emit_scatter(L, st);
-  launch_tile_items(L, st);
+  launch_tile_merge(L, st);
   launch_scan_u32(w.tile_items, w.tile_itoff, w.n_tiles, ctx->scan_tmp, st);
   launch_items(L, st);
   mark(4);

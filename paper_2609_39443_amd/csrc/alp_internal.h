@@ -13,7 +13,7 @@ constexpr int kChunkSegs = 16;      // segments per chunk in the segment binning
 constexpr int kMaxEmitTile = 256;   // (chunk, tile) windows of one tile a wave can merge
 constexpr int kMaxEntries = 128;    // merged (tile, beam) entries a wave can screen
 constexpr int kMaskWords = kMaxEntries / 32;
-constexpr int kStagePts = 192;      // window points (and node accumulators) staged in LDS
+constexpr int kStagePts = 160;      // window points (and node accumulators) staged in LDS
 constexpr int kHiShift = 46;        // fixed-point: hi word holds v * 2^(46-E)
 constexpr int kLoBits = 40;         // lo word holds the next 40 bits
 constexpr int kSampleLanes = 16;    // lanes per actuator point in the sampler
@@ -72,10 +72,20 @@ struct Emit {
 constexpr uint32_t kRecSingle = 0x80u;
 __host__ __device__ inline int rec_size(int prec) { return prec == ALP_PREC_FP32_SPLIT ? 16 : 24; }
 
+// A merged window: the candidate segments i0..i1 of one beam for one tile
+// (every window of that beam in the tile joined), written by the tile merge.
+struct Entry {
+  int32_t k0;      // first point of the beam (case-local point index)
+  int32_t i0, i1;  // beam-local segment range
+  int32_t single;  // 1: single-point beam (point kernel about its only node)
+};
+
 struct Item {
   int32_t tile;   // global tile index
   int32_t c0, c1; // sorted cell range
   int32_t cs;     // case index
+  uint32_t eoff;  // first entry of the tile
+  uint32_t nent;  // entries of the tile (beam order)
 };
 
 // Per-step workspace (device pointers), sized by the host.
@@ -100,11 +110,13 @@ struct Work {
   uint32_t *tile_cnt;   // windows per tile ([N_T+1])
   uint32_t *tile_off;   // exclusive scan of tile_cnt ([N_T+1])
   uint32_t *tile_fill;
+  uint32_t *tile_nent;  // merged entries per tile ([N_T+1])
   uint32_t *tile_items; // work items per tile ([N_T+1])
   uint32_t *tile_itoff; // exclusive scan of tile_items ([N_T+1])
   // lists
   Emit *emit_raw;       // [cap_emit] one slot per (chunk, box tile); beam < 0 = empty
   Emit *emit;           // [cap_emit] windows grouped by tile
+  Entry *entry;         // [cap_emit] merged windows, at the tile's window offset
   Item *item;           // [cap_item]
   unsigned long long *rec_base;  // per item, byte offset into rec
   uint32_t *rec_cnt;    // per item
@@ -276,7 +288,7 @@ void launch_chunks(const StepLaunch &L, hipStream_t st);
 void launch_chunk_boxes(const StepLaunch &L, hipStream_t st);
 void launch_chunk_tiles(const StepLaunch &L, hipStream_t st);
 void launch_emit_scatter(const StepLaunch &L, hipStream_t st);
-void launch_tile_items(const StepLaunch &L, hipStream_t st);
+void launch_tile_merge(const StepLaunch &L, hipStream_t st);
 void launch_items(const StepLaunch &L, hipStream_t st);
 void launch_sample(const StepLaunch &L, hipStream_t st);
 void launch_drag(const StepLaunch &L, hipStream_t st);

@@ -2,7 +2,7 @@
 //
 // One step of a batch runs, over the concatenated work of every case:
 //   reset, points_prep, beams_prep, chunks, chunk_tiles, scan, emit_scatter,
-//   tile_items, scan, items                       [segment binning]
+//   tile_merge, scan, items                       [segment binning]
 //   sample, drag                                    [eq. 16-20]
 //   weights, norm, beam_sums                        [eq. 21-22, nodal weights]
 //   spread, zero_dirty, finalize                    [eq. 23, eq. 14 check]
@@ -95,7 +95,6 @@ __global__ void k_step_reset(StepLaunch L, int what) {
     W.tile_cnt[i] = 0;
     W.tile_fill[i] = 0;
   }
-  for (int64_t i = tid; i < W.n_beams; i += stride) W.beps_max[i] = 0.0;
 }
 
 void launch_step_reset(const StepLaunch &L, hipStream_t st) {
@@ -126,12 +125,6 @@ __global__ void k_points_prep(StepLaunch L) {
     else hi = mid - 1;
   }
   W.pbeam[g] = (int32_t)(cs.beam_base + lo);
-  // largest kernel width of the beam: for non-negative doubles the bit
-  // patterns order like the values, so an integer max is exact and
-  // independent of the order of the atomics
-  if (cs.eps[k] > 0.0)
-    atomicMax((unsigned long long *)&W.beps_max[cs.beam_base + lo],
-              (unsigned long long)__double_as_longlong(cs.eps[k]));
   int64_t k0 = cs.offsets[lo], k1 = cs.offsets[lo + 1];
   double em = cs.eps[k];
   if (k > k0) em = fmin(em, cs.eps[k - 1]);
@@ -150,22 +143,33 @@ void launch_points_prep(const StepLaunch &L, hipStream_t st) {
 }
 
 // ------------------------------------------------------------- beams prep --
-__global__ void k_beams_prep(StepLaunch L) {
+// One wave per beam: case index, chunk count and the largest kernel width of
+// the beam (a max is exact in any order).
+__global__ __launch_bounds__(256) void k_beams_prep(StepLaunch L) {
   Work W = L.w;
-  int64_t gb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gb >= W.n_beams) return;
-  int c = case_of(L.bbase, L.n_cases, gb);
+  const int lane = lane_id();
+  const int64_t gb = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (gb >= W.n_beams) return;  // uniform per wave
+  const int c = case_of(L.bbase, L.n_cases, gb);
   const CaseDev &cs = L.cases[c];
-  int64_t b = gb - cs.beam_base;
-  int64_t n = cs.offsets[b + 1] - cs.offsets[b];
-  W.bcase[gb] = c;
-  int64_t nseg = n >= 2 ? n - 1 : n;
-  W.bchunks[gb] = (uint32_t)((nseg + kChunkSegs - 1) / kChunkSegs);
+  const int64_t b = gb - cs.beam_base;
+  const int64_t k0 = cs.offsets[b], k1 = cs.offsets[b + 1];
+  double em = 0.0;
+  for (int64_t k = k0 + lane; k < k1; k += 64) em = fmax(em, cs.eps[k]);
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) em = fmax(em, __shfl_xor(em, d, 64));
+  if (lane == 0) {
+    const int64_t n = k1 - k0;
+    const int64_t nseg = n >= 2 ? n - 1 : n;
+    W.bcase[gb] = c;
+    W.beps_max[gb] = em;
+    W.bchunks[gb] = (uint32_t)((nseg + kChunkSegs - 1) / kChunkSegs);
+  }
 }
 
 void launch_beams_prep(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_beams == 0) return;
-  hipLaunchKernelGGL(k_beams_prep, dim3((unsigned)((L.w.n_beams + 255) / 256)), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(k_beams_prep, dim3((unsigned)((L.w.n_beams + 3) / 4)), dim3(256), 0, st, L);
 }
 
 // ----------------------------------------------------------------- chunks --
@@ -397,25 +401,108 @@ void launch_emit_scatter(const StepLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL(k_emit_scatter, dim3(L.grid_persistent), dim3(256), 0, st, L);
 }
 
-// work items per tile: tiles with at least one window, 64 cells per item
-__global__ void k_tile_items(StepLaunch L) {
+// Tile merge, one wave per tile: sort the tile's windows by (beam, first
+// segment), join the windows of one beam into one entry (beam order), and
+// count the work items of the tile (64 cells each; none without entries).
+struct MergeScratch {
+  unsigned long long key[kMaxEmitTile];  // (beam << 32) | first segment
+  int32_t hi[kMaxEmitTile];
+};
+
+__global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
   Work W = L.w;
-  int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ MergeScratch sh;
+  const int lane = threadIdx.x;
+  const int64_t tg = blockIdx.x;
   if (tg >= W.n_tiles) return;
-  uint32_t ni = 0;
-  if (W.tile_cnt[tg] > 0) {
-    int c = case_of(L.tbase, L.n_cases, tg);
-    const CaseDev &cs = L.cases[c];
-    int64_t tl = tg - cs.tile_base;
-    uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
-    ni = (ncell + 63u) / 64u;
+  const uint32_t eoff = W.tile_off[tg];
+  const uint32_t n_emit = W.tile_off[tg + 1] - eoff;
+  if (n_emit == 0 || n_emit > (uint32_t)kMaxEmitTile) {
+    if (lane == 0) {
+      if (n_emit) set_overflow(W, 4u);
+      W.tile_nent[tg] = 0;
+      W.tile_items[tg] = 0;
+    }
+    return;
   }
-  W.tile_items[tg] = ni;
+  const int c = case_of(L.tbase, L.n_cases, tg);
+  const CaseDev &cs = L.cases[c];
+  uint32_t np2 = 1;
+  while (np2 < n_emit) np2 <<= 1;
+  for (uint32_t i = lane; i < np2; i += 64) {
+    if (i < n_emit) {
+      const Emit e = W.emit[eoff + i];
+      sh.key[i] = ((unsigned long long)(uint32_t)(e.beam - (int32_t)cs.beam_base) << 32) | (uint32_t)e.lo;
+      sh.hi[i] = e.hi;
+    } else {
+      sh.key[i] = ~0ull;
+      sh.hi[i] = 0;
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= np2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = lane; i < np2; i += 64) {
+        const uint32_t p = i ^ j;
+        if (p > i) {
+          const bool up = (i & k) == 0;
+          const unsigned long long a = sh.key[i], bk = sh.key[p];
+          if ((a > bk) == up) {
+            sh.key[i] = bk;
+            sh.key[p] = a;
+            const int32_t t = sh.hi[i];
+            sh.hi[i] = sh.hi[p];
+            sh.hi[p] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  uint32_t ne = 0;
+  for (uint32_t r0 = 0; r0 < n_emit; r0 += 64) {
+    const uint32_t i = r0 + lane;
+    bool head = false;
+    uint32_t beam = 0;
+    if (i < n_emit) {
+      beam = (uint32_t)(sh.key[i] >> 32);
+      head = (i == 0) || ((uint32_t)(sh.key[i - 1] >> 32) != beam);
+    }
+    const uint64_t bal = ballot64(head);
+    if (head) {
+      const uint32_t idx = ne + lanemask_lt_popc(bal);
+      int32_t hi = sh.hi[i];
+      for (uint32_t j = i + 1; j < n_emit && (uint32_t)(sh.key[j] >> 32) == beam; ++j)
+        hi = max(hi, sh.hi[j]);
+      if (idx < (uint32_t)kMaxEntries) {
+        const int64_t k0 = cs.offsets[beam];
+        Entry en;
+        en.k0 = (int32_t)k0;
+        en.i0 = (int32_t)(sh.key[i] & 0xffffffffu);
+        en.i1 = hi;
+        en.single = (cs.offsets[beam + 1] - k0) == 1 ? 1 : 0;
+        W.entry[eoff + idx] = en;
+      }
+    }
+    ne += (uint32_t)__popcll(bal);
+  }
+  if (lane == 0) {
+    uint32_t ni = 0;
+    if (ne > (uint32_t)kMaxEntries) {
+      set_overflow(W, 4u);
+    } else {
+      const int64_t tl = tg - cs.tile_base;
+      const uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
+      ni = (ncell + 63u) / 64u;
+    }
+    W.tile_nent[tg] = ni ? ne : 0u;
+    W.tile_items[tg] = ni;
+  }
 }
 
-void launch_tile_items(const StepLaunch &L, hipStream_t st) {
+void launch_tile_merge(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_tiles == 0) return;
-  hipLaunchKernelGGL(k_tile_items, dim3((unsigned)((L.w.n_tiles + 255) / 256)), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(k_tile_merge, dim3((unsigned)L.w.n_tiles), dim3(64), 0, st, L);
 }
 
 __global__ void k_items(StepLaunch L) {
@@ -440,6 +527,8 @@ __global__ void k_items(StepLaunch L) {
     it.c0 = (int32_t)(c0 + 64u * j);
     it.c1 = (int32_t)(c0 + 64u * (j + 1) < c1 ? c0 + 64u * (j + 1) : c1);
     it.cs = c;
+    it.eoff = W.tile_off[tg];
+    it.nent = W.tile_nent[tg];
     W.item[id] = it;
   }
 }
@@ -678,64 +767,76 @@ void launch_drag(const StepLaunch &L, hipStream_t st) { launch_drag_mode(L, 0, s
 
 // ---------------------------------------------------------------- weights --
 // Eq. (21)-(22) and the nodal weights of Sec. 3.2.4.  One wave per work item
-// (up to 64 cells of one tile):
-//   1. sort the tile's windows by (beam, first segment) and merge those of one
-//      beam into entries (beam order);
-//   2. stage each entry's window points, kernel widths and node accumulators
-//      in LDS and build a screening box (window AABB inflated by 3 eps_max);
-//   3. screen every (cell, entry) combination and list the candidate pairs in
+// (up to 64 cells of one tile, with the tile's merged entries in beam order):
+//   1. stage each entry's window in LDS as FP32 points relative to the tile
+//      centre, with the node exponents and node accumulators, and build a
+//      screening box (window AABB inflated by 3 eps_max, in registers);
+//   2. screen every (cell, entry) combination and list the candidate pairs in
 //      (cell, entry) order;
-//   4. for each candidate (64 at a time, full lanes) find the closest segment
-//      of the window exactly in FP64, apply the inclusive 3 eps cutoff and
-//      compute the weights a0, a1;
-//   5. add a V into the node accumulators (exact fixed point: LDS integer
+//   3. for each candidate (64 at a time) find the closest segment of the
+//      window: an FP32 pass ranks the segments, and every segment whose FP32
+//      distance lies within a proven error band of the best one is evaluated
+//      again exactly in FP64 (from the beam arrays) with the same expressions
+//      as a plain scan, so the chosen segment, s and r^2 are exactly those of a
+//      full FP64 scan; then the inclusive 3 eps cutoff and the weights a0, a1;
+//   4. add a V into the node accumulators (exact fixed point: LDS integer
 //      atomics, then one global integer atomic per touched node);
-//   6. write one record per surviving pair (cell, node, a0, a1) for the
+//   5. write one record per surviving pair (cell, node, a0, a1) for the
 //      spread pass.
+// Entries whose windows do not fit the staging area are scanned exactly from
+// the beam arrays.
+constexpr uint32_t kSegIdxMask = 0xffu;  // segment index packed below the FP32 distance
+static_assert(kStagePts <= 256, "segment index must fit the key");
+
 struct WeightsScratch {
-  union {
-    struct {
-      unsigned long long key[kMaxEmitTile];  // (beam << 32) | first segment
-      int32_t hi[kMaxEmitTile];
-    } srt;
-    struct {
-      double px[kStagePts], py[kStagePts], pz[kStagePts], pe[kStagePts];
-      long long ahi[kStagePts];
-      unsigned long long alo[kStagePts];
-    } stg;
-  } u;
-  int32_t e_kp[kMaxEntries], e_nb[kMaxEntries], e_i0[kMaxEntries], e_i1[kMaxEntries];
-  float e_box[6][kMaxEntries];
+  float4 sa[kStagePts];  // window point relative to the tile centre; w: 1/|e|^2 of the segment it starts
+  long long ahi[kStagePts];
+  unsigned long long alo[kStagePts];
+  int32_t wx[kStagePts];  // fixed-point exponent of the node
+  int32_t e_k0[kMaxEntries], e_i0[kMaxEntries], e_i1[kMaxEntries];  // e_i1 < 0: single point
   int32_t e_pt0[kMaxEntries + 1];
+  uint32_t e_em[kMaxEntries];  // bits of the window's largest eps (FP32, rounded up)
+  float e_dabs[kMaxEntries];   // absolute error allowance of the FP32 ranking
   uint32_t mask[64 * kMaskWords];
   uint32_t off[65];
-  int32_t n_ent, n_staged, n_pts;
 };
 
-// window point j of entry e (staged in LDS, or read from the beam array)
-struct WinPts {
-  const WeightsScratch &sh;
-  const double *X;
-  const double *eps;
-  __device__ __forceinline__ void get(int e, int pt0, int p, double &x, double &y, double &z) const {
-    if (pt0 >= 0) {
-      x = sh.u.stg.px[pt0 + p];
-      y = sh.u.stg.py[pt0 + p];
-      z = sh.u.stg.pz[pt0 + p];
-    } else {
-      const double *P = X + 3 * (int64_t)(sh.e_kp[e] + (sh.e_nb[e] == 1 ? 0 : sh.e_i0[e]) + p);
-      x = P[0];
-      y = P[1];
-      z = P[2];
+// exact FP64 scan of window segments j0..j1 (local indices; points read from
+// the beam array at X), strict '<' so the lowest index wins a tie
+__device__ __forceinline__ void exact_scan(const double *X, int j0, int j1, double cx, double cy,
+                                           double cz, int &bj, double &bs, double &br2) {
+  double ax = X[3 * j0], ay = X[3 * j0 + 1], az = X[3 * j0 + 2];
+  for (int j = j0; j <= j1; ++j) {
+    const double bx = X[3 * j + 3], by = X[3 * j + 4], bz = X[3 * j + 5];
+    double s, r2;
+    seg_foot(cx, cy, cz, ax, ay, az, bx, by, bz, s, r2);
+    if (r2 < br2) {
+      br2 = r2;
+      bj = j;
+      bs = s;
     }
+    ax = bx;
+    ay = by;
+    az = bz;
   }
-  __device__ __forceinline__ double geteps(int e, int pt0, int p) const {
-    return pt0 >= 0 ? sh.u.stg.pe[pt0 + p]
-                    : eps[sh.e_kp[e] + (sh.e_nb[e] == 1 ? 0 : sh.e_i0[e]) + p];
-  }
-};
+}
 
-__global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
+__device__ __forceinline__ int entry_of_point(const WeightsScratch &sh, int n_staged, int q) {
+  int lo = 0, hi = n_staged - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sh.e_pt0[mid] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
+void k_weights(StepLaunch L) {
   Work W = L.w;
   __shared__ WeightsScratch sh;
   const int lane = threadIdx.x;
@@ -744,8 +845,14 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
   unsigned long long blk_cur = 0, blk_end = 0;
   int acc_case = -1;
   unsigned long long acc_pairs = 0;
-  for (uint32_t item = blockIdx.x; item < n_items && (int64_t)item < W.cap_item; item += gridDim.x) {
-    const Item it = W.item[item];
+  const uint32_t stride = gridDim.x;
+  uint32_t item = blockIdx.x;
+  Item nxt;
+  if (item < n_items && (int64_t)item < W.cap_item) nxt = W.item[item];
+  for (; item < n_items && (int64_t)item < W.cap_item; item += stride) {
+    const Item it = nxt;
+    // the next item's descriptor is fetched while this one runs
+    if (item + stride < n_items && (int64_t)(item + stride) < W.cap_item) nxt = W.item[item + stride];
     if (it.cs != acc_case) {
       if (lane == 0 && acc_case >= 0 && acc_pairs)
         atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
@@ -755,175 +862,158 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
     const CaseDev &cs = L.cases[it.cs];
     const MeshDev &m = cs.m;
     const int64_t tl = it.tile - cs.tile_base;
-    const uint32_t eoff = W.tile_off[it.tile];
-    const uint32_t n_emit = W.tile_off[it.tile + 1] - eoff;
     const int rsz = rec_size(cs.prec);
-    if (n_emit > (uint32_t)kMaxEmitTile) {
-      if (lane == 0) {
-        set_overflow(W, 4u);
-        W.rec_cnt[item] = 0;
-        W.rec_base[item] = 0;
-      }
-      continue;
-    }
-    // 1. sort windows by (beam, lo) and merge per beam
-    uint32_t np2 = 1;
-    while (np2 < n_emit) np2 <<= 1;
-    for (uint32_t i = lane; i < np2; i += 64) {
-      if (i < n_emit) {
-        Emit e = W.emit[eoff + i];
-        sh.u.srt.key[i] = ((unsigned long long)(uint32_t)(e.beam - (int32_t)cs.beam_base) << 32) |
-                          (uint32_t)e.lo;
-        sh.u.srt.hi[i] = e.hi;
-      } else {
-        sh.u.srt.key[i] = ~0ull;
-        sh.u.srt.hi[i] = 0;
-      }
-    }
-    __syncthreads();
-    for (uint32_t k = 2; k <= np2; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = lane; i < np2; i += 64) {
-          uint32_t p = i ^ j;
-          if (p > i) {
-            bool up = (i & k) == 0;
-            unsigned long long a = sh.u.srt.key[i], bk = sh.u.srt.key[p];
-            if ((a > bk) == up) {
-              sh.u.srt.key[i] = bk;
-              sh.u.srt.key[p] = a;
-              int32_t t = sh.u.srt.hi[i];
-              sh.u.srt.hi[i] = sh.u.srt.hi[p];
-              sh.u.srt.hi[p] = t;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-    uint32_t ne = 0;
-    for (uint32_t r0 = 0; r0 < n_emit; r0 += 64) {
-      const uint32_t i = r0 + lane;
-      bool head = false;
-      uint32_t beam = 0;
-      if (i < n_emit) {
-        beam = (uint32_t)(sh.u.srt.key[i] >> 32);
-        head = (i == 0) || ((uint32_t)(sh.u.srt.key[i - 1] >> 32) != beam);
-      }
-      const uint64_t bal = ballot64(head);
-      if (head) {
-        const uint32_t idx = ne + lanemask_lt_popc(bal);
-        int32_t hi = sh.u.srt.hi[i];
-        for (uint32_t j = i + 1; j < n_emit && (uint32_t)(sh.u.srt.key[j] >> 32) == beam; ++j)
-          hi = max(hi, sh.u.srt.hi[j]);
-        if (idx < (uint32_t)kMaxEntries) {
-          int64_t k0 = cs.offsets[beam];
-          sh.e_kp[idx] = (int32_t)k0;
-          sh.e_nb[idx] = (int32_t)(cs.offsets[beam + 1] - k0);
-          sh.e_i0[idx] = (int32_t)(sh.u.srt.key[i] & 0xffffffffu);
-          sh.e_i1[idx] = hi;
-        }
-      }
-      ne += (uint32_t)__popcll(bal);
-    }
-    if (ne > (uint32_t)kMaxEntries) {
-      if (lane == 0) {
-        set_overflow(W, 4u);
-        W.rec_cnt[item] = 0;
-        W.rec_base[item] = 0;
-      }
-      __syncthreads();
-      continue;
-    }
-    __syncthreads();
-    // 2. staging: the leading entries whose windows fit in LDS
-    {
-      uint32_t carry = 0;
-      int nst = 0;
-      for (uint32_t e0 = 0; e0 < ne; e0 += 64) {
-        const uint32_t e = e0 + lane;
-        uint32_t cntp = 0;
-        if (e < ne) cntp = sh.e_nb[e] == 1 ? 1u : (uint32_t)(sh.e_i1[e] - sh.e_i0[e] + 2);
-        uint32_t tot;
-        uint32_t ex = wave_excl_scan_u32(cntp, tot) + carry;
-        const bool fits = e < ne && ex + cntp <= (uint32_t)kStagePts;
-        if (e < ne) sh.e_pt0[e] = fits ? (int32_t)ex : -1;
-        nst += __popcll(ballot64(fits));
-        carry += tot;
-      }
-      if (lane == 0) sh.n_staged = nst;
-      __syncthreads();
-      int npts = 0;
-      if (nst > 0) {
-        const int last = nst - 1;
-        npts = sh.e_pt0[last] + (sh.e_nb[last] == 1 ? 1 : sh.e_i1[last] - sh.e_i0[last] + 2);
-      }
-      for (int q = lane; q < npts; q += 64) {
-        int lo = 0, hi = nst - 1;
-        while (lo < hi) {
-          int mid = (lo + hi + 1) >> 1;
-          if (sh.e_pt0[mid] <= q) lo = mid;
-          else hi = mid - 1;
-        }
-        const int64_t pk = sh.e_kp[lo] + (sh.e_nb[lo] == 1 ? 0 : sh.e_i0[lo]) + (q - sh.e_pt0[lo]);
-        const double *P = cs.Psp + 3 * pk;
-        sh.u.stg.px[q] = P[0];
-        sh.u.stg.py[q] = P[1];
-        sh.u.stg.pz[q] = P[2];
-        sh.u.stg.pe[q] = cs.eps[pk];
-        sh.u.stg.ahi[q] = 0;
-        sh.u.stg.alo[q] = 0;
-      }
-      if (lane == 0) sh.n_pts = npts;
-      __syncthreads();
-    }
-    const int n_staged = sh.n_staged;
-    const WinPts wp{sh, cs.Psp, cs.eps};
-    double ox, oy, oz;
-    tile_origin(m, tl, ox, oy, oz);
-    // screening boxes: window AABB inflated by 3 eps_max of the window
-    for (uint32_t e = lane; e < ne; e += 64) {
-      const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
-      const int np = sh.e_nb[e] == 1 ? 1 : sh.e_i1[e] - sh.e_i0[e] + 2;
-      double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, em = 0;
-      for (int p = 0; p < np; ++p) {
-        double x, y, z;
-        wp.get(e, pt0, p, x, y, z);
-        lo[0] = fmin(lo[0], x);
-        lo[1] = fmin(lo[1], y);
-        lo[2] = fmin(lo[2], z);
-        hi[0] = fmax(hi[0], x);
-        hi[1] = fmax(hi[1], y);
-        hi[2] = fmax(hi[2], z);
-        em = fmax(em, wp.geteps(e, pt0, p));
-      }
-      const double R = 3.0 * em * (1.0 + 1e-6) + 1e-6 * m.tile_len;
-      sh.e_box[0][e] = (float)(lo[0] - R - ox) - 1e-6f * (float)m.tile_len;
-      sh.e_box[1][e] = (float)(lo[1] - R - oy) - 1e-6f * (float)m.tile_len;
-      sh.e_box[2][e] = (float)(lo[2] - R - oz) - 1e-6f * (float)m.tile_len;
-      sh.e_box[3][e] = (float)(hi[0] + R - ox) + 1e-6f * (float)m.tile_len;
-      sh.e_box[4][e] = (float)(hi[1] + R - oy) + 1e-6f * (float)m.tile_len;
-      sh.e_box[5][e] = (float)(hi[2] + R - oz) + 1e-6f * (float)m.tile_len;
-      if ((int)e >= n_staged) sh.e_pt0[e] = -1;
-    }
-    __syncthreads();
-    // 3. cells and screening
+    const uint32_t ne = it.nent;  // <= kMaxEntries (the tile merge drops larger tiles)
+    // cells of the item
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
     double cx = 0, cy = 0, cz = 0, v = 0;
-    float lx = 3e30f, ly = 3e30f, lz = 3e30f;
     if (valid) {
       cx = m.cx[c];
       cy = m.cy[c];
       cz = m.cz[c];
       v = m.vs[c];
-      lx = (float)(cx - ox);
-      ly = (float)(cy - oy);
-      lz = (float)(cz - oz);
     }
+    // 1. entries and the staging plan: the leading entries whose windows fit
+    uint32_t carry = 0;
+    int nst = 0;
+    for (uint32_t e0 = 0; e0 < ne; e0 += 64) {
+      const uint32_t e = e0 + lane;
+      uint32_t cntp = 0;
+      if (e < ne) {
+        const Entry en = W.entry[it.eoff + e];
+        sh.e_k0[e] = en.k0;
+        sh.e_i0[e] = en.i0;
+        sh.e_i1[e] = en.single ? -1 : en.i1;
+        sh.e_em[e] = 0u;
+        cntp = en.single ? 1u : (uint32_t)(en.i1 - en.i0 + 2);
+      }
+      uint32_t tot;
+      const uint32_t ex = wave_excl_scan_u32(cntp, tot) + carry;
+      const bool fits = e < ne && ex + cntp <= (uint32_t)kStagePts;
+      if (e < ne) sh.e_pt0[e] = fits ? (int32_t)ex : -1;
+      nst += __popcll(ballot64(fits));
+      carry += tot;
+    }
+    __syncthreads();
+    const int n_staged = nst;
+    int npts = 0;
+    if (nst > 0) {
+      const int last = nst - 1;
+      npts = sh.e_pt0[last] + (sh.e_i1[last] < 0 ? 1 : sh.e_i1[last] - sh.e_i0[last] + 2);
+    }
+    double ox, oy, oz;
+    tile_origin(m, tl, ox, oy, oz);
+    const double hl = 0.5 * m.tile_len;
+    const double ctx = ox + hl, cty = oy + hl, ctz = oz + hl;
+    for (int q = lane; q < npts; q += 64) {
+      const int e = entry_of_point(sh, n_staged, q);
+      const int64_t k = sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
+      const double *P = cs.Psp + 3 * k;
+      sh.sa[q] = make_float4((float)(P[0] - ctx), (float)(P[1] - cty), (float)(P[2] - ctz), 0.f);
+      sh.ahi[q] = 0;
+      sh.alo[q] = 0;
+      sh.wx[q] = W.wexp[cs.point_base + k];
+      // eps rounded up to FP32 (positive floats order like their bits)
+      const double ep = cs.eps[k];
+      float ef = (float)ep;
+      if ((double)ef < ep) ef = nextafterf(ef, INFINITY);
+      if (ef > 0.f) atomicMax(&sh.e_em[e], __float_as_uint(ef));
+    }
+    __syncthreads();
+    for (int q = lane; q < npts; q += 64) {
+      const int e = entry_of_point(sh, n_staged, q);
+      const int np = sh.e_i1[e] < 0 ? 1 : sh.e_i1[e] - sh.e_i0[e] + 2;
+      if (q - sh.e_pt0[e] < np - 1) {
+        const float4 A = sh.sa[q], B = sh.sa[q + 1];
+        const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
+        const float ee = ex * ex + ey * ey + ez * ez;
+        sh.sa[q].w = ee > 0.f ? 1.0f / ee : 0.f;
+      }
+    }
+    // screening boxes (window AABB inflated by 3 eps_max, relative to the
+    // tile centre) in registers: lane l holds entry 64 b + l
+    float bl[2][3], bh[2][3];
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const uint32_t e = 64u * bb + lane;
+      bl[bb][0] = bl[bb][1] = bl[bb][2] = INFINITY;
+      bh[bb][0] = bh[bb][1] = bh[bb][2] = -INFINITY;
+      if (e < ne) {
+        const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
+        const bool sgl = sh.e_i1[e] < 0;
+        const int np = sgl ? 1 : sh.e_i1[e] - sh.e_i0[e] + 2;
+        float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY,
+              hi2 = -INFINITY, rr = 0.f, em;
+        if (pt0 >= 0) {
+          for (int p = 0; p < np; ++p) {
+            const float4 A = sh.sa[pt0 + p];
+            lo0 = fminf(lo0, A.x);
+            lo1 = fminf(lo1, A.y);
+            lo2 = fminf(lo2, A.z);
+            hi0 = fmaxf(hi0, A.x);
+            hi1 = fmaxf(hi1, A.y);
+            hi2 = fmaxf(hi2, A.z);
+            rr = fmaxf(rr, A.x * A.x + A.y * A.y + A.z * A.z);
+          }
+          em = __uint_as_float(sh.e_em[e]);
+        } else {
+          const int64_t k = sh.e_k0[e] + (sgl ? 0 : sh.e_i0[e]);
+          double dem = 0.0;
+          for (int p = 0; p < np; ++p) {
+            const double *P = cs.Psp + 3 * (k + p);
+            const float ax = (float)(P[0] - ctx), ay = (float)(P[1] - cty), az = (float)(P[2] - ctz);
+            lo0 = fminf(lo0, ax);
+            lo1 = fminf(lo1, ay);
+            lo2 = fminf(lo2, az);
+            hi0 = fmaxf(hi0, ax);
+            hi1 = fmaxf(hi1, ay);
+            hi2 = fmaxf(hi2, az);
+            rr = fmaxf(rr, ax * ax + ay * ay + az * az);
+            dem = fmax(dem, cs.eps[k + p]);
+          }
+          em = (float)(dem * (1.0 + 1e-6));
+        }
+        // margin for the FP32 rounding of the points and the cells
+        const float Rf = 3.0f * em * (1.0f + 1e-5f) + 1e-5f * sqrtf(rr) + 1e-5f * (float)m.tile_len;
+        bl[bb][0] = lo0 - Rf;
+        bl[bb][1] = lo1 - Rf;
+        bl[bb][2] = lo2 - Rf;
+        bh[bb][0] = hi0 + Rf;
+        bh[bb][1] = hi1 + Rf;
+        bh[bb][2] = hi2 + Rf;
+        // |FP32 distance^2 - exact distance^2| stays below ~80 u Rmax^2
+        // (u = 2^-24) for coordinates within Rmax of the tile centre: rounding
+        // of the inputs moves the distance by at most 2 sqrt(3) u Rmax, and the
+        // clamped projection adds at most ~64 u Rmax^2.  The allowance takes
+        // 2^-14 Rmax^2 (256 u Rmax^2).
+        const float r2max = fmaxf(rr, (float)(3.0 * hl * hl));
+        sh.e_dabs[e] = ldexpf(r2max, -14) * (1.0f + 1e-5f);
+      }
+    }
+    __syncthreads();
+    // 2. screening
+    const float lx = (float)(cx - ctx), ly = (float)(cy - cty), lz = (float)(cz - ctz);
     uint32_t word = 0, cnt = 0;
     for (uint32_t e = 0; e < ne; ++e) {
-      const bool hit = valid && lx >= sh.e_box[0][e] && lx <= sh.e_box[3][e] && ly >= sh.e_box[1][e] &&
-                       ly <= sh.e_box[4][e] && lz >= sh.e_box[2][e] && lz <= sh.e_box[5][e];
+      const int bb = (int)(e >> 6), l = (int)(e & 63);
+      float x0, y0, z0, x1, y1, z1;
+      if (bb == 0) {
+        x0 = rdlane(bl[0][0], l);
+        y0 = rdlane(bl[0][1], l);
+        z0 = rdlane(bl[0][2], l);
+        x1 = rdlane(bh[0][0], l);
+        y1 = rdlane(bh[0][1], l);
+        z1 = rdlane(bh[0][2], l);
+      } else {
+        x0 = rdlane(bl[1][0], l);
+        y0 = rdlane(bl[1][1], l);
+        z0 = rdlane(bl[1][2], l);
+        x1 = rdlane(bh[1][0], l);
+        y1 = rdlane(bh[1][1], l);
+        z1 = rdlane(bh[1][2], l);
+      }
+      const bool hit = valid && lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1 && lz >= z0 && lz <= z1;
       if (hit) word |= 1u << (e & 31);
       if ((e & 31) == 31 || e == ne - 1) {
         sh.mask[lane * kMaskWords + (e >> 5)] = word;
@@ -951,7 +1041,7 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
     if (!rec_ok && lane == 0) set_overflow(W, 2u);
     uint32_t nreal = 0;
     const int nwords = (int)((ne + 31) >> 5);
-    // 4.-6. candidate pairs, 64 per round
+    // 3.-5. candidate pairs, 64 per round
     for (uint32_t p0 = 0; p0 < total; p0 += 64) {
       const uint32_t p = p0 + lane;
       const bool act = p < total;
@@ -959,7 +1049,7 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
       if (act) {
         int lo = 0, hi = 63;
         while (lo < hi) {
-          int mid = (lo + hi + 1) >> 1;
+          const int mid = (lo + hi + 1) >> 1;
           if (sh.off[mid] <= p) lo = mid;
           else hi = mid - 1;
         }
@@ -967,7 +1057,7 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
         uint32_t r = p - sh.off[Lc];
         for (int wd = 0; wd < nwords; ++wd) {
           uint32_t mw = sh.mask[Lc * kMaskWords + wd];
-          uint32_t pc = __popc(mw);
+          const uint32_t pc = __popc(mw);
           if (r < pc) {
             for (uint32_t q = 0; q < r; ++q) mw &= mw - 1u;
             e = wd * 32 + __ffs(mw) - 1;
@@ -982,61 +1072,99 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
       int bi = 0, single = 0;
       double a0 = 0.0, a1 = 0.0;
       if (act) {
-        const int pt0 = sh.e_pt0[e];
-        const int nb = sh.e_nb[e], i0 = sh.e_i0[e], i1 = sh.e_i1[e];
-        double bs = 0.0, br2;
-        double ej;
-        if (nb == 1) {
+        const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
+        const int k0 = sh.e_k0[e], i0 = sh.e_i0[e], i1 = sh.e_i1[e];
+        double bs = 0.0, br2 = INFINITY, ej;
+        int bj = 0;
+        if (i1 < 0) {
           single = 1;
-          double x, y, z;
-          wp.get(e, pt0, 0, x, y, z);
-          br2 = sqdist_exact(pcx, pcy, pcz, x, y, z);
-          ej = wp.geteps(e, pt0, 0);
+          const double *P = cs.Psp + 3 * (int64_t)k0;
+          br2 = sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]);
+          ej = cs.eps[k0];
         } else {
-          br2 = INFINITY;
-          bi = i0;
-          double ax, ay, az;
-          wp.get(e, pt0, 0, ax, ay, az);
-          for (int i = i0; i <= i1; ++i) {
-            double bx, by, bz, s, r2;
-            wp.get(e, pt0, i - i0 + 1, bx, by, bz);
-            seg_foot(pcx, pcy, pcz, ax, ay, az, bx, by, bz, s, r2);
-            if (r2 < br2) {
-              br2 = r2;
-              bi = i;
-              bs = s;
+          const int nseg = i1 - i0 + 1;
+          const double *X = cs.Psp + 3 * ((int64_t)k0 + i0);
+          bool full = pt0 < 0;
+          if (!full) {
+            // FP32 ranking: the three smallest (distance, index) keys
+            const float qx = (float)(pcx - ctx), qy = (float)(pcy - cty), qz = (float)(pcz - ctz);
+            uint32_t k1 = ~0u, k2 = ~0u, k3 = ~0u;
+            float4 A = sh.sa[pt0];
+            for (int j = 0; j < nseg; ++j) {
+              const float4 B = sh.sa[pt0 + j + 1];
+              const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
+              float dx = qx - A.x, dy = qy - A.y, dz = qz - A.z;
+              const float t = dx * ex + dy * ey + dz * ez;
+              const float sg = __saturatef(t * A.w);
+              dx -= sg * ex;
+              dy -= sg * ey;
+              dz -= sg * ez;
+              const float d2 = dx * dx + dy * dy + dz * dz;
+              const uint32_t key = (__float_as_uint(d2) & ~kSegIdxMask) | (uint32_t)j;
+              const uint32_t m1 = max(k1, key);
+              k1 = min(k1, key);
+              const uint32_t m2 = max(k2, m1);
+              k2 = min(k2, m1);
+              k3 = min(k3, m2);
+              A = B;
             }
-            ax = bx;
-            ay = by;
-            az = bz;
+            // keys drop 8 mantissa bits (relative 2^-15): the band below holds
+            // every segment whose exact distance can reach the best one
+            const float b1 = __uint_as_float(k1 & ~kSegIdxMask);
+            const float dl = b1 * 0x1p-14f + sh.e_dabs[e];
+            const float band = (b1 + 2.0f * dl) * (1.0f + 0x1p-20f);
+            full = k3 != ~0u && __uint_as_float(k3 & ~kSegIdxMask) <= band;
+            if (!full) {
+              const int j1 = (int)(k1 & kSegIdxMask);
+              exact_scan(X, j1, j1, pcx, pcy, pcz, bj, bs, br2);
+              if (k2 != ~0u && __uint_as_float(k2 & ~kSegIdxMask) <= band) {
+                const int j2 = (int)(k2 & kSegIdxMask);
+                int cj = j2;
+                double cs2 = 0.0, cr2 = INFINITY;
+                exact_scan(X, j2, j2, pcx, pcy, pcz, cj, cs2, cr2);
+                if (cr2 < br2 || (cr2 == br2 && j2 < bj)) {
+                  br2 = cr2;
+                  bj = j2;
+                  bs = cs2;
+                }
+              }
+            }
           }
-          ej = eps_at(bs, wp.geteps(e, pt0, bi - i0), wp.geteps(e, pt0, bi - i0 + 1));
+          if (full) {
+            br2 = INFINITY;
+            bj = 0;
+            bs = 0.0;
+            exact_scan(X, 0, nseg - 1, pcx, pcy, pcz, bj, bs, br2);
+          }
+          const double *E = cs.eps + (int64_t)k0 + i0;
+          ej = eps_at(bs, E[bj], E[bj + 1]);
         }
         in = inside_cutoff(br2, ej);
         if (in) {
           pair_weights(cs.prec, bs, br2, ej, a0, a1);
-          const int jl = nb == 1 ? 0 : bi - i0;
-          const int64_t node = cs.point_base + sh.e_kp[e] + (nb == 1 ? 0 : bi);
+          const int64_t node = cs.point_base + k0 + (single ? 0 : i0 + bj);
           long long h0, h1 = 0;
           unsigned long long l0, l1 = 0;
-          fx_encode(a0 * pv, W.wexp[node], h0, l0);
-          if (nb > 1) fx_encode(a1 * pv, W.wexp[node + 1], h1, l1);
           if (pt0 >= 0) {
-            atomicAdd((unsigned long long *)&sh.u.stg.ahi[pt0 + jl], (unsigned long long)h0);
-            atomicAdd(&sh.u.stg.alo[pt0 + jl], l0);
-            if (nb > 1) {
-              atomicAdd((unsigned long long *)&sh.u.stg.ahi[pt0 + jl + 1], (unsigned long long)h1);
-              atomicAdd(&sh.u.stg.alo[pt0 + jl + 1], l1);
+            fx_encode(a0 * pv, sh.wx[pt0 + bj], h0, l0);
+            atomicAdd((unsigned long long *)&sh.ahi[pt0 + bj], (unsigned long long)h0);
+            atomicAdd(&sh.alo[pt0 + bj], l0);
+            if (!single) {
+              fx_encode(a1 * pv, sh.wx[pt0 + bj + 1], h1, l1);
+              atomicAdd((unsigned long long *)&sh.ahi[pt0 + bj + 1], (unsigned long long)h1);
+              atomicAdd(&sh.alo[pt0 + bj + 1], l1);
             }
           } else {
+            fx_encode(a0 * pv, W.wexp[node], h0, l0);
             atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h0);
             atomicAdd(&W.w_lo[node], l0);
-            if (nb > 1) {
+            if (!single) {
+              fx_encode(a1 * pv, W.wexp[node + 1], h1, l1);
               atomicAdd((unsigned long long *)&W.w_hi[node + 1], (unsigned long long)h1);
               atomicAdd(&W.w_lo[node + 1], l1);
             }
           }
-          bi = (int)node;  // reuse: global node index for the record
+          bi = (int)node;  // global node index for the record
         }
       }
       const uint64_t bal = ballot64(act && in);
@@ -1063,19 +1191,12 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
     }
     __syncthreads();
     // flush the staged node accumulators
-    const int npts = sh.n_pts;
     for (int q = lane; q < npts; q += 64) {
-      long long h = sh.u.stg.ahi[q];
-      unsigned long long l = sh.u.stg.alo[q];
+      long long h = sh.ahi[q];
+      unsigned long long l = sh.alo[q];
       if (h == 0 && l == 0) continue;
-      int lo = 0, hi = n_staged - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (sh.e_pt0[mid] <= q) lo = mid;
-        else hi = mid - 1;
-      }
-      const int64_t node = cs.point_base + sh.e_kp[lo] + (sh.e_nb[lo] == 1 ? 0 : sh.e_i0[lo]) +
-                           (q - sh.e_pt0[lo]);
+      const int e = entry_of_point(sh, n_staged, q);
+      const int64_t node = cs.point_base + sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
       h += (long long)(l >> kLoBits);
       l &= (1ull << kLoBits) - 1ull;
       atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h);
@@ -1093,7 +1214,7 @@ __global__ __launch_bounds__(64) void k_weights(StepLaunch L) {
 }
 
 void launch_weights(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_weights, dim3(L.grid_persistent), dim3(64), 0, st, L);
+  hipLaunchKernelGGL(k_weights, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------------- norm --

@@ -169,6 +169,42 @@ def test_edge_cases(gu, ctx):
     run_and_compare(gu, ctx, wl, alp.PREC_FP64)
 
 
+def near_tie_scene():
+    """Beams whose segments lie at (nearly) equal distances from many cells: a
+    closed polygon around a cell centre, a beam folded back onto itself, and a
+    tight coil of 300 points whose window does not fit the staging area."""
+    h = 0.01
+    C, V = W.uniform_mesh(26, 26, 26, h)
+    pts, tan = [], []
+    a = np.linspace(0.0, 2.0 * np.pi, 25)
+    pts.append(np.stack([0.105 + 0.025 * np.cos(a), 0.105 + 0.025 * np.sin(a), np.full(25, 0.105)], 1))
+    tan.append(np.stack([-np.sin(a), np.cos(a), np.zeros(25)], 1))
+    up = 0.02 + 0.01 * np.arange(11)
+    z = np.concatenate([up, up[-2::-1]])
+    pts.append(np.stack([np.full(z.size, 0.2032), np.full(z.size, 0.1511), z], 1))
+    tan.append(np.tile([0.0, 0.0, 1.0], (z.size, 1)))
+    t = np.linspace(0.0, 20.0 * np.pi, 300)
+    pts.append(np.stack([0.12 + 0.015 * np.cos(t), 0.2 + 0.015 * np.sin(t), 0.15 + 0.0004 * t], 1))
+    d = np.stack([-0.015 * np.sin(t), 0.015 * np.cos(t), np.full(300, 0.0004)], 1)
+    tan.append(d / np.linalg.norm(d, axis=1, keepdims=True))
+    n = [p.shape[0] for p in pts]
+    beams = W._beamset(pts, tan, [np.zeros((k, 3)) for k in n], [np.full(k, 0.002) for k in n],
+                       [np.full(k, 0.005) for k in n], [np.full(k, 2.0 * h) for k in n],
+                       np.full(3, 1.2), np.full(3, 0.05), np.full(3, 0.05), np.zeros((3, 3)),
+                       np.tile([-1.0, 0, 0], (3, 1)))
+    U = np.tile([0.3, 0.05, 0.0], (C.shape[0], 1))
+    return {"name": "near-ties", "C": C, "V": V, "U": U, "box": None, "h": h, "beams": beams,
+            "params": {"rho": 1000.0, "alpha_f": 1.0, "tau": 1e-6, "drag_form": 0}}
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_near_tie_segments_and_long_windows(gu, ctx, prec):
+    """The closest-segment search ranks segments in FP32 and re-evaluates the
+    near-best ones exactly; ties between distant segments of one beam, and
+    windows too long to stage, must still give the FP64 scan's choice."""
+    run_and_compare(gu, ctx, near_tie_scene(), prec)
+
+
 def test_batch_equals_single_cases(gu, ctx):
     wls = [random_scene(20 + i, nx=18 + 3 * i, ny=16, nz=14, n_beams=2 + i) for i in range(4)]
     cases = [gu.GpuCase(ctx, wl, alp.PREC_FP64) for wl in wls]
