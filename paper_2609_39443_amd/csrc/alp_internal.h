@@ -72,6 +72,14 @@ struct Emit {
 constexpr uint32_t kRecSingle = 0x80u;
 __host__ __device__ inline int rec_size(int prec) { return prec == ALP_PREC_FP32_SPLIT ? 16 : 24; }
 
+// A window grouped by tile: the tile is implied by the position; k0 is the
+// beam's first point (case-local) and hi < 0 marks a single-point beam.
+struct Win {
+  int32_t beam;   // global beam index
+  int32_t lo, hi; // candidate segments (beam-local)
+  int32_t k0;
+};
+
 // A merged window: the candidate segments i0..i1 of one beam for one tile
 // (every window of that beam in the tile joined), written by the tile merge.
 struct Entry {
@@ -115,7 +123,7 @@ struct Work {
   uint32_t *tile_itoff; // exclusive scan of tile_items ([N_T+1])
   // lists
   Emit *emit_raw;       // [cap_emit] one slot per (chunk, box tile); beam < 0 = empty
-  Emit *emit;           // [cap_emit] windows grouped by tile
+  Win *emit;            // [cap_emit] windows grouped by tile
   Entry *entry;         // [cap_emit] merged windows, at the tile's window offset
   Item *item;           // [cap_item]
   unsigned long long *rec_base;  // per item, byte offset into rec
@@ -214,13 +222,18 @@ __device__ __forceinline__ void pair_weights(int prec, double s, double r2, doub
 // any work distribution or atomic order).  A non-negative or signed value v
 // with |v| < 2^E is split into hi = floor(v 2^(46-E)) and
 // lo = floor(frac * 2^40); both are summed as 64-bit integers.
+// Both parts are integers below 2^51 in magnitude, so adding 1.5 * 2^52 puts
+// them in the low mantissa bits exactly and an integer subtraction of the
+// constant's bit pattern converts them.
 __device__ __forceinline__ void fx_encode(double v, int E, long long &hi, unsigned long long &lo) {
+  const double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+  const long long kMagicBits = 0x4338000000000000ll;
   double t = ldexp(v, kHiShift - E);
   double th = floor(t);
   double r = t - th;  // exact, in [0, 1)
   double tl = floor(ldexp(r, kLoBits));
-  hi = (long long)th;
-  lo = (unsigned long long)tl;
+  hi = __double_as_longlong(th + kMagic) - kMagicBits;
+  lo = (unsigned long long)(__double_as_longlong(tl + kMagic) - kMagicBits);
 }
 __device__ __host__ inline double fx_decode(long long hi, unsigned long long lo, int E) {
   hi += (long long)(lo >> kLoBits);

@@ -55,10 +55,12 @@ __device__ __forceinline__ void set_overflow(Work &W, uint32_t bit) { atomicOr(&
 
 __device__ __forceinline__ void tile_origin(const MeshDev &m, int64_t tl, double &ox, double &oy,
                                             double &oz) {
-  int tx = (int)(tl % m.nt[0]);
-  int64_t r = tl / m.nt[0];
-  int ty = (int)(r % m.nt[1]);
-  int tz = (int)(r / m.nt[1]);
+  // tile counts are below 2^32 (bin keys are 32-bit)
+  const uint32_t t = (uint32_t)tl, nx = (uint32_t)m.nt[0], ny = (uint32_t)m.nt[1];
+  const uint32_t r = t / nx;
+  const int tx = (int)(t - r * nx);
+  const int tz = (int)(r / ny);
+  const int ty = (int)(r - (uint32_t)tz * ny);
   ox = m.lo[0] + (double)tx * m.tile_len;
   oy = m.lo[1] + (double)ty * m.tile_len;
   oz = m.lo[2] + (double)tz * m.tile_len;
@@ -390,10 +392,19 @@ __global__ void k_emit_scatter(StepLaunch L) {
   if (n > W.cap_emit) n = W.cap_emit;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    Emit e = W.emit_raw[i];
+    const Emit e = W.emit_raw[i];
     if (e.beam < 0) continue;
-    uint32_t slot = W.tile_off[e.tile] + atomicAdd(&W.tile_fill[e.tile], 1u);
-    W.emit[slot] = e;
+    const int c = case_of(L.tbase, L.n_cases, e.tile);
+    const CaseDev &cs = L.cases[c];
+    const int64_t b = e.beam - cs.beam_base;
+    const int64_t k0 = cs.offsets[b];
+    Win w;
+    w.beam = e.beam;
+    w.lo = e.lo;
+    w.hi = (cs.offsets[b + 1] - k0) == 1 ? -1 : e.hi;
+    w.k0 = (int32_t)k0;
+    const uint32_t slot = W.tile_off[e.tile] + atomicAdd(&W.tile_fill[e.tile], 1u);
+    W.emit[slot] = w;
   }
 }
 
@@ -407,6 +418,7 @@ void launch_emit_scatter(const StepLaunch &L, hipStream_t st) {
 struct MergeScratch {
   unsigned long long key[kMaxEmitTile];  // (beam << 32) | first segment
   int32_t hi[kMaxEmitTile];
+  int32_t k0[kMaxEmitTile];
 };
 
 __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
@@ -425,18 +437,18 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
     }
     return;
   }
-  const int c = case_of(L.tbase, L.n_cases, tg);
-  const CaseDev &cs = L.cases[c];
   uint32_t np2 = 1;
   while (np2 < n_emit) np2 <<= 1;
   for (uint32_t i = lane; i < np2; i += 64) {
     if (i < n_emit) {
-      const Emit e = W.emit[eoff + i];
-      sh.key[i] = ((unsigned long long)(uint32_t)(e.beam - (int32_t)cs.beam_base) << 32) | (uint32_t)e.lo;
+      const Win e = W.emit[eoff + i];
+      sh.key[i] = ((unsigned long long)(uint32_t)e.beam << 32) | (uint32_t)e.lo;
       sh.hi[i] = e.hi;
+      sh.k0[i] = e.k0;
     } else {
       sh.key[i] = ~0ull;
       sh.hi[i] = 0;
+      sh.k0[i] = 0;
     }
   }
   __syncthreads();
@@ -453,6 +465,9 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
             const int32_t t = sh.hi[i];
             sh.hi[i] = sh.hi[p];
             sh.hi[p] = t;
+            const int32_t u = sh.k0[i];
+            sh.k0[i] = sh.k0[p];
+            sh.k0[p] = u;
           }
         }
       }
@@ -475,12 +490,11 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
       for (uint32_t j = i + 1; j < n_emit && (uint32_t)(sh.key[j] >> 32) == beam; ++j)
         hi = max(hi, sh.hi[j]);
       if (idx < (uint32_t)kMaxEntries) {
-        const int64_t k0 = cs.offsets[beam];
         Entry en;
-        en.k0 = (int32_t)k0;
+        en.k0 = sh.k0[i];
         en.i0 = (int32_t)(sh.key[i] & 0xffffffffu);
-        en.i1 = hi;
-        en.single = (cs.offsets[beam + 1] - k0) == 1 ? 1 : 0;
+        en.i1 = hi < 0 ? 0 : hi;
+        en.single = hi < 0 ? 1 : 0;
         W.entry[eoff + idx] = en;
       }
     }
@@ -491,6 +505,8 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
     if (ne > (uint32_t)kMaxEntries) {
       set_overflow(W, 4u);
     } else {
+      const int c = case_of(L.tbase, L.n_cases, tg);
+      const CaseDev &cs = L.cases[c];
       const int64_t tl = tg - cs.tile_base;
       const uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
       ni = (ncell + 63u) / 64u;
@@ -573,14 +589,18 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
                                fabs(m.lo[1]) + fabs(m.lo[2]));
   int64_t best = -1;
   double bD = INFINITY;
-  for (int r = 0;; ++r) {
+  // the first pass covers the whole 3x3x3 block of bins (with bins about one
+  // cell wide it nearly always settles the search); later passes add one
+  // Chebyshev shell each
+  for (int r = 1;; ++r) {
     const int side = 2 * r + 1;
     const int ncube = side * side * side;
     for (int c = sub; c < ncube; c += kSampleLanes) {
       int dz = c / (side * side), dy = (c / side) % side, dx = c % side;
       int ix = qi[0] - r + dx, iy = qi[1] - r + dy, iz = qi[2] - r + dz;
       int ch = max(abs(dx - r), max(abs(dy - r), abs(dz - r)));
-      if (ch != r || ix < 0 || iy < 0 || iz < 0 || ix >= m.nb[0] || iy >= m.nb[1] || iz >= m.nb[2])
+      if ((r > 1 && ch != r) || ix < 0 || iy < 0 || iz < 0 || ix >= m.nb[0] || iy >= m.nb[1] ||
+          iz >= m.nb[2])
         continue;
       uint32_t k = bin_key(m, ix, iy, iz);
       uint32_t e = m.bin_start[k + 1];
@@ -1318,13 +1338,15 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // ----------------------------------------------------------------- spread --
 // Eq. (23): S_j = -sum over the cell's pairs (beam order) of
 // a0 f_hat_i + a1 f_hat_i+1, from the records of the weights pass (the same
-// a0, a1 that built w_k, so the transferred force balances exactly).  Each
-// cell is summed by one lane in record order; every cell of an active tile is
-// written.
+// a0, a1 that built w_k, so the transferred force balances exactly).  The
+// records of a work item are sorted by cell, so each cell owns one contiguous
+// run; its lane sums the run in record order.  Every cell of an active tile
+// is written.
+constexpr int kSpreadChunk = 256;  // records held per pass (4 per lane)
+
 struct SpreadScratch {
-  double cc[3][64];
-  uint32_t cnt[64];
-  uint32_t off[65];
+  double cc[3][kSpreadChunk];
+  uint16_t first[64], last[64];  // run of each cell inside the chunk (last exclusive)
 };
 
 __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
@@ -1335,10 +1357,28 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
   // per-wave accumulation (exact fixed point, flushed when the case changes)
   int acc_case = -1;
   unsigned long long acc_band = 0;
-  long long fh = 0;          // lanes 0..2 hold x, y, z
+  long long fh = 0;  // lanes 0..2 hold x, y, z
   unsigned long long fl = 0;
-  for (uint32_t item = blockIdx.x; item < n_items && (int64_t)item < W.cap_item; item += gridDim.x) {
-    const Item it = W.item[item];
+  const uint32_t stride = gridDim.x;
+  uint32_t item = blockIdx.x;
+  Item nxt;
+  uint32_t nrn = 0;
+  unsigned long long nrb = 0;
+  if (item < n_items && (int64_t)item < W.cap_item) {
+    nxt = W.item[item];
+    nrn = W.rec_cnt[item];
+    nrb = W.rec_base[item];
+  }
+  for (; item < n_items && (int64_t)item < W.cap_item; item += stride) {
+    const Item it = nxt;
+    const uint32_t rn = nrn;
+    const unsigned long long rb = nrb;
+    // the next item's descriptor is fetched while this one runs
+    if (item + stride < n_items && (int64_t)(item + stride) < W.cap_item) {
+      nxt = W.item[item + stride];
+      nrn = W.rec_cnt[item + stride];
+      nrb = W.rec_base[item + stride];
+    }
     if (it.cs != acc_case) {
       if (acc_case >= 0) {
         if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
@@ -1359,68 +1399,72 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
     const double v = valid ? m.vs[c] : 0.0;
-    const uint32_t rn = W.rec_cnt[item];
-    const unsigned char *rec = W.rec + W.rec_base[item];
+    const uint32_t pc = valid ? m.perm[c] : 0u;
+    const unsigned char *rec = W.rec + rb;
     const int rsz = rec_size(cs.prec);
-    sh.cnt[lane] = 0;
-    __syncthreads();
-    for (uint32_t j = lane; j < rn; j += 64)
-      atomicAdd(&sh.cnt[*(const uint32_t *)(rec + (size_t)j * rsz) & 63u], 1u);
-    __syncthreads();
-    uint32_t tot;
-    const uint32_t myoff = wave_excl_scan_u32(sh.cnt[lane], tot);
-    sh.off[lane] = myoff;
-    if (lane == 63) sh.off[64] = tot;
-    __syncthreads();
     double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-    for (uint32_t p0 = 0; p0 < rn; p0 += 64) {
-      const uint32_t p = p0 + lane;
-      if (p < rn) {
-        const unsigned char *r = rec + (size_t)p * rsz;
-        uint32_t meta, node;
-        double a0, a1;
-        if (rsz == 16) {
-          const uint4 q = *(const uint4 *)r;
-          meta = q.x;
-          node = q.y;
-          a0 = (double)__uint_as_float(q.z);
-          a1 = (double)__uint_as_float(q.w);
-        } else {
-          const uint2 q = *(const uint2 *)r;
-          meta = q.x;
-          node = q.y;
-          const double2 a = *(const double2 *)(r + 8);
-          a0 = a.x;
-          a1 = a.y;
-        }
-        const double *fh = W.fhat + 3 * (int64_t)node;
-        double q0 = a0 * fh[0], q1 = a0 * fh[1], q2 = a0 * fh[2];
-        if (!(meta & kRecSingle)) {
-          q0 += a1 * fh[3];
-          q1 += a1 * fh[4];
-          q2 += a1 * fh[5];
-        }
-        sh.cc[0][lane] = -q0;
-        sh.cc[1][lane] = -q1;
-        sh.cc[2][lane] = -q2;
+    bool any = false;
+    for (uint32_t p0 = 0; p0 < rn; p0 += kSpreadChunk) {
+      const uint32_t nch = min(rn - p0, (uint32_t)kSpreadChunk);
+      if (lane < 64) {
+        sh.first[lane] = 0;
+        sh.last[lane] = 0;
       }
       __syncthreads();
-      const uint32_t lo = sh.off[lane] > p0 ? sh.off[lane] : p0;
-      const uint32_t hi = sh.off[lane + 1] < p0 + 64 ? sh.off[lane + 1] : p0 + 64;
+#pragma unroll
+      for (int k = 0; k < kSpreadChunk / 64; ++k) {
+        const uint32_t j = (uint32_t)(k * 64 + lane);
+        if (j < nch) {
+          const unsigned char *r = rec + (size_t)(p0 + j) * rsz;
+          uint32_t meta, node;
+          double a0, a1;
+          if (rsz == 16) {
+            const uint4 q = *(const uint4 *)r;
+            meta = q.x;
+            node = q.y;
+            a0 = (double)__uint_as_float(q.z);
+            a1 = (double)__uint_as_float(q.w);
+          } else {
+            const uint2 q = *(const uint2 *)r;
+            meta = q.x;
+            node = q.y;
+            const double2 a = *(const double2 *)(r + 8);
+            a0 = a.x;
+            a1 = a.y;
+          }
+          const double *fp = W.fhat + 3 * (int64_t)node;
+          double q0 = a0 * fp[0], q1 = a0 * fp[1], q2 = a0 * fp[2];
+          if (!(meta & kRecSingle)) {
+            q0 += a1 * fp[3];
+            q1 += a1 * fp[4];
+            q2 += a1 * fp[5];
+          }
+          sh.cc[0][j] = -q0;
+          sh.cc[1][j] = -q1;
+          sh.cc[2][j] = -q2;
+          // run boundaries of the cell (records are sorted by cell)
+          const uint32_t cl = meta & 63u;
+          if (j == 0 || ((*(const uint32_t *)(r - rsz)) & 63u) != cl) sh.first[cl] = (uint16_t)j;
+          if (j + 1 == nch || ((*(const uint32_t *)(r + rsz)) & 63u) != cl) sh.last[cl] = (uint16_t)(j + 1);
+        }
+      }
+      __syncthreads();
+      const uint32_t lo = sh.first[lane], hi = sh.last[lane];
+      any = any || hi > lo;
       for (uint32_t j = lo; j < hi; ++j) {
-        S0 += sh.cc[0][j - p0];
-        S1 += sh.cc[1][j - p0];
-        S2 += sh.cc[2][j - p0];
+        S0 += sh.cc[0][j];
+        S1 += sh.cc[1][j];
+        S2 += sh.cc[2][j];
       }
       __syncthreads();
     }
     if (valid && cs.write_S) {
-      double *S = cs.S + 3 * (int64_t)m.perm[c];
+      double *S = cs.S + 3 * (int64_t)pc;
       S[0] = S0;
       S[1] = S1;
       S[2] = S2;
     }
-    acc_band += (unsigned long long)__popcll(ballot64(valid && sh.cnt[lane] > 0));
+    acc_band += (unsigned long long)__popcll(ballot64(valid && any));
     // force on the fluid: deterministic wave sum, then exact accumulation
     const double fx = wave_sum_f64(S0 * v), fy = wave_sum_f64(S1 * v), fz = wave_sum_f64(S2 * v);
     if (lane < 3) {
@@ -1433,7 +1477,6 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
         fl += l;
       }
     }
-    __syncthreads();
   }
   if (acc_case >= 0) {
     if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
