@@ -421,11 +421,17 @@ struct MergeScratch {
   int32_t k0[kMaxEmitTile];
 };
 
-__global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
+// Four waves per block, one tile each: the waves share nothing, so each
+// synchronises only itself (LDS operations of one wave complete in order; the
+// wave barrier keeps the compiler from moving them across phases).
+constexpr int kMergeWaves = 4;
+
+__global__ __launch_bounds__(64 * kMergeWaves) void k_tile_merge(StepLaunch L) {
   Work W = L.w;
-  __shared__ MergeScratch sh;
-  const int lane = threadIdx.x;
-  const int64_t tg = blockIdx.x;
+  __shared__ MergeScratch shw[kMergeWaves];
+  MergeScratch &sh = shw[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
+  const int64_t tg = (int64_t)blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
   if (tg >= W.n_tiles) return;
   const uint32_t eoff = W.tile_off[tg];
   const uint32_t n_emit = W.tile_off[tg + 1] - eoff;
@@ -451,7 +457,9 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
       sh.k0[i] = 0;
     }
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   for (uint32_t k = 2; k <= np2; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       for (uint32_t i = lane; i < np2; i += 64) {
@@ -471,7 +479,9 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
           }
         }
       }
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   uint32_t ne = 0;
@@ -518,7 +528,8 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
 
 void launch_tile_merge(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_tiles == 0) return;
-  hipLaunchKernelGGL(k_tile_merge, dim3((unsigned)L.w.n_tiles), dim3(64), 0, st, L);
+  hipLaunchKernelGGL(k_tile_merge, dim3((unsigned)((L.w.n_tiles + kMergeWaves - 1) / kMergeWaves)),
+                     dim3(64 * kMergeWaves), 0, st, L);
 }
 
 __global__ void k_items(StepLaunch L) {
@@ -1342,7 +1353,7 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // records of a work item are sorted by cell, so each cell owns one contiguous
 // run; its lane sums the run in record order.  Every cell of an active tile
 // is written.
-constexpr int kSpreadChunk = 256;  // records held per pass (4 per lane)
+constexpr int kSpreadChunk = 128;  // records held per pass (2 per lane)
 
 struct SpreadScratch {
   double cc[3][kSpreadChunk];
@@ -1490,7 +1501,7 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
 }
 
 void launch_spread(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_spread, dim3(L.grid_persistent * 3), dim3(64), 0, st, L);
+  hipLaunchKernelGGL(k_spread, dim3(L.grid_persistent * 4), dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------- zero dirty --
