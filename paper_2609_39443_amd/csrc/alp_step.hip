@@ -962,63 +962,83 @@ void k_weights(StepLaunch L) {
         sh.sa[q].w = ee > 0.f ? 1.0f / ee : 0.f;
       }
     }
-    // screening boxes (window AABB inflated by 3 eps_max, relative to the
-    // tile centre) in registers: lane l holds entry 64 b + l
-    float bl[2][3], bh[2][3];
+    // Screening capsules, in registers (lane l holds entry 64 b + l).  Each
+    // window gets a chord frame: origin P0 (its first point), unit axis u (to
+    // its last point), the axial extent [amin, amax] of its points along u and
+    // dev, the largest distance of its points from the chord line.  Every
+    // point x of the window's segments then has its axial coordinate inside
+    // [amin, amax] and lies within dev of the line, so for a cell at distance
+    // rho from the line and axial gap g from [amin, amax],
+    //   |c - x|^2 >= max(rho - dev, 0)^2 + g^2,
+    // and a pair needs |c - x| <= 3 eps_j <= 3 eps_max of the window.
+    float fr[2][10];
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
       const uint32_t e = 64u * bb + lane;
-      bl[bb][0] = bl[bb][1] = bl[bb][2] = INFINITY;
-      bh[bb][0] = bh[bb][1] = bh[bb][2] = -INFINITY;
+#pragma unroll
+      for (int q = 0; q < 10; ++q) fr[bb][q] = 0.f;
+      fr[bb][6] = INFINITY;   // amin > amax: empty capsule
+      fr[bb][7] = -INFINITY;
       if (e < ne) {
         const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
         const bool sgl = sh.e_i1[e] < 0;
         const int np = sgl ? 1 : sh.e_i1[e] - sh.e_i0[e] + 2;
-        float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY,
-              hi2 = -INFINITY, rr = 0.f, em;
-        if (pt0 >= 0) {
-          for (int p = 0; p < np; ++p) {
+        const int64_t k = sh.e_k0[e] + (sgl ? 0 : sh.e_i0[e]);
+        auto point = [&](int p) {
+          if (pt0 >= 0) {
             const float4 A = sh.sa[pt0 + p];
-            lo0 = fminf(lo0, A.x);
-            lo1 = fminf(lo1, A.y);
-            lo2 = fminf(lo2, A.z);
-            hi0 = fmaxf(hi0, A.x);
-            hi1 = fmaxf(hi1, A.y);
-            hi2 = fmaxf(hi2, A.z);
-            rr = fmaxf(rr, A.x * A.x + A.y * A.y + A.z * A.z);
+            return make_float3(A.x, A.y, A.z);
           }
-          em = __uint_as_float(sh.e_em[e]);
+          const double *P = cs.Psp + 3 * (k + p);
+          return make_float3((float)(P[0] - ctx), (float)(P[1] - cty), (float)(P[2] - ctz));
+        };
+        const float3 P0 = point(0), P1 = point(np - 1);
+        float ux = P1.x - P0.x, uy = P1.y - P0.y, uz = P1.z - P0.z;
+        const float len = sqrtf(ux * ux + uy * uy + uz * uz);
+        if (len > 0.f) {
+          const float il = 1.0f / len;
+          ux *= il;
+          uy *= il;
+          uz *= il;
         } else {
-          const int64_t k = sh.e_k0[e] + (sgl ? 0 : sh.e_i0[e]);
-          double dem = 0.0;
-          for (int p = 0; p < np; ++p) {
-            const double *P = cs.Psp + 3 * (k + p);
-            const float ax = (float)(P[0] - ctx), ay = (float)(P[1] - cty), az = (float)(P[2] - ctz);
-            lo0 = fminf(lo0, ax);
-            lo1 = fminf(lo1, ay);
-            lo2 = fminf(lo2, az);
-            hi0 = fmaxf(hi0, ax);
-            hi1 = fmaxf(hi1, ay);
-            hi2 = fmaxf(hi2, az);
-            rr = fmaxf(rr, ax * ax + ay * ay + az * az);
-            dem = fmax(dem, cs.eps[k + p]);
-          }
-          em = (float)(dem * (1.0 + 1e-6));
+          ux = 1.f;
+          uy = 0.f;
+          uz = 0.f;
         }
-        // margin for the FP32 rounding of the points and the cells
-        const float Rf = 3.0f * em * (1.0f + 1e-5f) + 1e-5f * sqrtf(rr) + 1e-5f * (float)m.tile_len;
-        bl[bb][0] = lo0 - Rf;
-        bl[bb][1] = lo1 - Rf;
-        bl[bb][2] = lo2 - Rf;
-        bh[bb][0] = hi0 + Rf;
-        bh[bb][1] = hi1 + Rf;
-        bh[bb][2] = hi2 + Rf;
+        float amin = INFINITY, amax = -INFINITY, dev2 = 0.f, rr = 0.f;
+        double dem = 0.0;
+        for (int p = 0; p < np; ++p) {
+          const float3 A = p == 0 ? P0 : point(p);
+          const float dx = A.x - P0.x, dy = A.y - P0.y, dz = A.z - P0.z;
+          const float a = dx * ux + dy * uy + dz * uz;
+          amin = fminf(amin, a);
+          amax = fmaxf(amax, a);
+          dev2 = fmaxf(dev2, dx * dx + dy * dy + dz * dz - a * a);
+          rr = fmaxf(rr, A.x * A.x + A.y * A.y + A.z * A.z);
+          if (pt0 < 0) dem = fmax(dem, cs.eps[k + p]);
+        }
+        const float em = pt0 >= 0 ? __uint_as_float(sh.e_em[e]) : (float)(dem * (1.0 + 1e-6));
+        // coordinates of points and cells lie within Rmax of the tile centre;
+        // rho and dev computed in FP32 are each within 2^-9 Rmax of their true
+        // values (|d| <= 2 Rmax), the axial gap within 2^-18 Rmax: the radius
+        // is widened by 2^-7 Rmax
+        const float r2max = fmaxf(rr, (float)(3.0 * hl * hl));
+        const float Rc = 3.0f * em * (1.0f + 1e-5f) + ldexpf(sqrtf(r2max), -7);
+        fr[bb][0] = P0.x;
+        fr[bb][1] = P0.y;
+        fr[bb][2] = P0.z;
+        fr[bb][3] = ux;
+        fr[bb][4] = uy;
+        fr[bb][5] = uz;
+        fr[bb][6] = amin;
+        fr[bb][7] = amax;
+        fr[bb][8] = sqrtf(fmaxf(dev2, 0.f));
+        fr[bb][9] = Rc * Rc;
         // |FP32 distance^2 - exact distance^2| stays below ~80 u Rmax^2
         // (u = 2^-24) for coordinates within Rmax of the tile centre: rounding
         // of the inputs moves the distance by at most 2 sqrt(3) u Rmax, and the
         // clamped projection adds at most ~64 u Rmax^2.  The allowance takes
         // 2^-14 Rmax^2 (256 u Rmax^2).
-        const float r2max = fmaxf(rr, (float)(3.0 * hl * hl));
         sh.e_dabs[e] = ldexpf(r2max, -14) * (1.0f + 1e-5f);
       }
     }
@@ -1027,24 +1047,21 @@ void k_weights(StepLaunch L) {
     const float lx = (float)(cx - ctx), ly = (float)(cy - cty), lz = (float)(cz - ctz);
     uint32_t word = 0, cnt = 0;
     for (uint32_t e = 0; e < ne; ++e) {
-      const int bb = (int)(e >> 6), l = (int)(e & 63);
-      float x0, y0, z0, x1, y1, z1;
-      if (bb == 0) {
-        x0 = rdlane(bl[0][0], l);
-        y0 = rdlane(bl[0][1], l);
-        z0 = rdlane(bl[0][2], l);
-        x1 = rdlane(bh[0][0], l);
-        y1 = rdlane(bh[0][1], l);
-        z1 = rdlane(bh[0][2], l);
+      const int l = (int)(e & 63);
+      float f[10];
+      if (e < 64) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) f[q] = rdlane(fr[0][q], l);
       } else {
-        x0 = rdlane(bl[1][0], l);
-        y0 = rdlane(bl[1][1], l);
-        z0 = rdlane(bl[1][2], l);
-        x1 = rdlane(bh[1][0], l);
-        y1 = rdlane(bh[1][1], l);
-        z1 = rdlane(bh[1][2], l);
+#pragma unroll
+        for (int q = 0; q < 10; ++q) f[q] = rdlane(fr[1][q], l);
       }
-      const bool hit = valid && lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1 && lz >= z0 && lz <= z1;
+      const float dx = lx - f[0], dy = ly - f[1], dz = lz - f[2];
+      const float a = dx * f[3] + dy * f[4] + dz * f[5];
+      const float rho = sqrtf(fmaxf(dx * dx + dy * dy + dz * dz - a * a, 0.f));
+      const float re = fmaxf(rho - f[8], 0.f);
+      const float g = fmaxf(fmaxf(f[6] - a, a - f[7]), 0.f);
+      const bool hit = valid && re * re + g * g <= f[9];
       if (hit) word |= 1u << (e & 31);
       if ((e & 31) == 31 || e == ne - 1) {
         sh.mask[lane * kMaskWords + (e >> 5)] = word;
