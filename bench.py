@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-stems", type=int, default=1000,
                     help="stems in the oracle's timed sample (about 10-30 s of CPU work)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison runs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary measurements (wave flume, batched scenarios, jittered net)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -80,6 +82,76 @@ def traffic_from_profiles(kernel, n_cells, n_stems):
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def measure_graph(alp, torch, np, wls, prec, steps, warmup):
+    """Device copies of `wls`, one batched graph-captured step over all of
+    them: ms per step and the diagnostics of every case."""
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    ctx = alp.Context(0)
+    keep, cases = [], []
+    try:
+        for wl in wls:
+            C, V, U = dev(wl["C"]), dev(wl["V"]), dev(wl["U"])
+            mesh = ctx.bin_cells(C, V, wl.get("box"))
+            beams = alp.DeviceBeams(wl["beams"])
+            f = torch.zeros(beams.n_points, 3, dtype=torch.float64, device="cuda")
+            S = torch.zeros_like(C)
+            keep.append((C, V, U, beams, f, S))
+            cases.append(alp.alp_case(mesh, U.data_ptr(), beams.struct, alp.make_params(wl["params"], prec),
+                                      None, f.data_ptr(), S.data_ptr(), None, None, None, None, None))
+        alp.alp_step_batched(ctx.h, cases, alp.USE_GRAPH)
+        for _ in range(warmup):
+            alp.alp_step_batched(ctx.h, cases, alp.USE_GRAPH)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            alp.alp_step_batched(ctx.h, cases, alp.USE_GRAPH)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        alp.alp_invalidate(ctx.h)
+        diags = [ctx.diag(i) for i in range(len(cases))]
+    finally:
+        ctx.close()
+    return dt, diags
+
+
+def secondary(alp, W, torch, np, steps):
+    """The other workloads at their full sizes, FP32-split and all-FP64."""
+    out = {}
+    specs = [
+        ("wave_flume", lambda: [W.wave_flume(snapshot=0)],
+         "1,987,200 graded cells, one bent stem of 100 CVs"),
+        ("jittered_net", lambda: [W.jittered_net()],
+         "8M jittered cells in random order, 700 x 700-strand net of 499,800 points"),
+        ("batched_scenarios", lambda: [W.scenario(c) for c in range(64)],
+         "64 cases of 0.5M-4M cells and 1-500 stems of 20-300 CVs in one graph step"),
+    ]
+    for name, make, desc in specs:
+        t0 = time.time()
+        wls = make()
+        npnt = sum(wl["beams"]["P"].shape[0] for wl in wls)
+        ncell = sum(wl["C"].shape[0] for wl in wls)
+        log(f"{name}: {len(wls)} case(s), {ncell} cells, {npnt} points ({time.time() - t0:.1f} s to generate)")
+        r = {"workload": desc, "n_cases": len(wls), "n_cells": ncell, "n_points": npnt}
+        for tag, prec in (("split", alp.PREC_FP32_SPLIT), ("fp64", alp.PREC_FP64)):
+            dt, diags = measure_graph(alp, torch, np, wls, prec, steps, 2)
+            pairs = sum(int(d["n_pairs"]) for d in diags)
+            r[f"{tag}_ms_per_step"] = dt * 1e3
+            r[f"{tag}_points_per_s"] = npnt / dt
+            r[f"{tag}_cell_updates_per_s"] = pairs / dt
+            r[f"{tag}_max_cons_rel_err"] = max(float(d["cons_rel_err"]) for d in diags
+                                               if int(d["n_zero_weight"]) == 0) if any(
+                int(d["n_zero_weight"]) == 0 for d in diags) else None
+            r["n_pairs"] = pairs
+            r["n_band_cells"] = sum(int(d["n_band_cells"]) for d in diags)
+            r["n_overflow"] = sum(int(d["n_overflow"]) for d in diags)
+            log(f"{name} {tag}: {dt * 1e3:.3f} ms/step")
+        r["speedup_split_vs_fp64"] = r["fp64_ms_per_step"] / r["split_ms_per_step"]
+        out[name] = r
+        del wls
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -210,6 +282,10 @@ def main():
                          f"{dt:.1f} s", "seconds": dt, "pairs": int(r["diag"]["n_pairs"])}
         log(f"oracle: {dt:.2f} s")
 
+    extra = None
+    if not args.no_extra:
+        extra = secondary(alp, W, torch, np, max(3, args.steps // 4))
+
     line = {
         "metric": "actuator points/s per coupling step", "value": npnt / t_split, "unit": "points/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_split * 1e3,
@@ -223,6 +299,7 @@ def main():
         "mesh_cells_per_s": n_cells / t_split, "alg_hbm_gbps": gbps, "alg_hbm_frac": gbps / HBM_PEAK_GBPS,
         "cons_rel_err": diag["cons_rel_err"], "stages_ms": stages, "roofline": roofline,
         "cpu_baseline": cpu, **res,
+        "other_workloads": extra,
     }
     print(json.dumps(line))
     ctx.close()

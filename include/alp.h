@@ -224,6 +224,25 @@ alp_status alp_step_profile(alp_context *ctx, int32_t n_cases, const alp_case *c
 /* Name of profiling stage i ("" when out of range). */
 const char *alp_stage_name(int32_t i);
 
+/* Autotuner of the cell binning for a given batch (the search structure of
+   Sec. 3.2.5 is built once per run, so its parameters can be chosen once).
+   For each candidate setting it bins the cells (bin size 0.75, 1, 1.5 or 2
+   times the default of alp_bin_cells; tile edge 2..6 bins), runs
+   alp_step_batched on `cases` with that mesh in place of
+   cases[tuned_case].mesh (flags as given, plus one sizing run), times `reps`
+   steps (<= 0: 3) with the host clock after synchronising, and returns the
+   fastest setting:
+     C, V, domain_box   as alp_bin_cells (the cells of cases[tuned_case])
+     out_bin_size       HOST out, bin size to pass to alp_bin_cells
+     out_tile_bins      HOST out, tile edge in bins to pass to alp_bin_cells
+     out_ms             HOST out (nullable), the measured milliseconds per step
+   The cases' outputs are overwritten by the trial steps.  Captured graphs
+   are dropped.  Synchronous; not allowed under capture. */
+alp_status alp_autotune(alp_context *ctx, int64_t n_cells, const double *C, const double *V,
+                        const double *domain_box, int32_t n_cases, const alp_case *cases,
+                        int32_t tuned_case, uint32_t flags, int32_t reps, double *out_bin_size,
+                        int32_t *out_tile_bins, double *out_ms);
+
 /* Library version string. */
 const char *alp_version(void);
 

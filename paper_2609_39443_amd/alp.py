@@ -24,7 +24,7 @@ USE_GRAPH, CHECKED = 1, 2
 # every symbol include/alp.h declares
 EXPORTS = ("alp_create", "alp_destroy", "alp_last_error", "alp_bin_cells", "alp_mesh_destroy",
            "alp_sample", "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag",
-           "alp_invalidate", "alp_version", "alp_step_profile", "alp_stage_name")
+           "alp_invalidate", "alp_version", "alp_step_profile", "alp_stage_name", "alp_autotune")
 
 
 class AlpError(RuntimeError):
@@ -96,6 +96,9 @@ def load():
     lib.alp_step_profile.argtypes = [vp, i32, ct.POINTER(alp_case), ct.POINTER(ct.c_double), i32,
                                      ct.POINTER(i32)]
     lib.alp_step_profile.restype = ct.c_int
+    lib.alp_autotune.argtypes = [vp, i64, vp, vp, vp, i32, ct.POINTER(alp_case), i32, u32, i32,
+                                 ct.POINTER(ct.c_double), ct.POINTER(i32), ct.POINTER(ct.c_double)]
+    lib.alp_autotune.restype = ct.c_int
     lib.alp_stage_name.argtypes = [i32]
     lib.alp_stage_name.restype = ct.c_char_p
     for name in ("alp_create", "alp_destroy", "alp_bin_cells", "alp_mesh_destroy", "alp_sample",
@@ -189,6 +192,18 @@ def alp_step_profile(ctx, cases, max_stages=16):
     n = ct.c_int32()
     _check(ctx, load().alp_step_profile(ctx, len(cases), arr, ms, max_stages, ct.byref(n)))
     return {load().alp_stage_name(i).decode(): ms[i] for i in range(n.value)}
+
+
+def alp_autotune(ctx, C, V, cases, tuned_case=0, flags=USE_GRAPH, reps=3, domain_box=None):
+    """Pick the binning (bin size, tile edge in bins) that gives the fastest
+    step for `cases`; returns {"bin_size", "tile_bins", "ms"}."""
+    arr = (alp_case * len(cases))(*cases)
+    box = None if domain_box is None else (ct.c_double * 6)(*[float(x) for x in domain_box])
+    bs, tb, ms = ct.c_double(), ct.c_int32(), ct.c_double()
+    _check(ctx, load().alp_autotune(ctx, C.shape[0], _ptr(C), _ptr(V), box, len(cases), arr,
+                                    int(tuned_case), int(flags), int(reps), ct.byref(bs), ct.byref(tb),
+                                    ct.byref(ms)))
+    return {"bin_size": bs.value, "tile_bins": tb.value, "ms": ms.value}
 
 
 # ---------------------------------------------------------------- helpers --

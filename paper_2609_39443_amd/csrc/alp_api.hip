@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <chrono>
 #include <vector>
 
 #include "alp_internal.h"
@@ -862,6 +863,62 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
     ctx->gflags = flags;
   }
   return leave(ctx);
+}
+
+alp_status alp_autotune(alp_context *ctx, int64_t n_cells, const double *C, const double *V,
+                        const double *domain_box, int32_t n_cases, const alp_case *cases,
+                        int32_t tuned_case, uint32_t flags, int32_t reps, double *out_bin_size,
+                        int32_t *out_tile_bins, double *out_ms) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!cases || n_cases < 1 || tuned_case < 0 || tuned_case >= n_cases || !out_bin_size ||
+      !out_tile_bins)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "need cases, 0 <= tuned_case < n_cases and outputs");
+  if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "alp_autotune cannot run under capture");
+  if (reps <= 0) reps = 3;
+  alp_status rc;
+  // the default bin size of alp_bin_cells is the reference of the search
+  alp_mesh *m0 = nullptr;
+  if ((rc = alp_bin_cells(ctx, n_cells, C, V, domain_box, 0.0, 4, &m0)) != ALP_OK) return rc;
+  const double base = m0->d.bin;
+  alp_mesh_destroy(m0);
+  const double scales[] = {0.75, 1.0, 1.5, 2.0};
+  const int32_t tiles[] = {2, 3, 4, 5, 6};
+  std::vector<alp_case> cs(cases, cases + n_cases);
+  double best_ms = INFINITY, best_bin = base;
+  int32_t best_t = 4;
+  for (int32_t T : tiles) {
+    for (double sc : scales) {
+      alp_mesh *m = nullptr;
+      if (alp_bin_cells(ctx, n_cells, C, V, domain_box, base * sc, T, &m) != ALP_OK) continue;
+      cs[tuned_case].mesh = m;
+      (void)alp_invalidate(ctx);
+      rc = alp_step_batched(ctx, n_cases, cs.data(), flags | ALP_CHECKED);
+      if (rc == ALP_OK) rc = alp_step_batched(ctx, n_cases, cs.data(), flags);
+      if (rc == ALP_OK && hipStreamSynchronize(ctx->user) != hipSuccess) rc = ALP_ERR_HIP;
+      double ms = INFINITY;
+      if (rc == ALP_OK) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; r < reps && rc == ALP_OK; ++r) rc = alp_step_batched(ctx, n_cases, cs.data(), flags);
+        if (rc == ALP_OK && hipStreamSynchronize(ctx->user) != hipSuccess) rc = ALP_ERR_HIP;
+        const auto t1 = std::chrono::steady_clock::now();
+        ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / reps;
+      }
+      (void)alp_invalidate(ctx);
+      alp_mesh_destroy(m);
+      if (rc != ALP_OK) return rc;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_bin = base * sc;
+        best_t = T;
+      }
+    }
+  }
+  if (!(best_ms < INFINITY)) return fail(ctx, ALP_ERR_INVALID_ARG, "no binning setting could be built");
+  *out_bin_size = best_bin;
+  *out_tile_bins = best_t;
+  if (out_ms) *out_ms = best_ms;
+  return ALP_OK;
 }
 
 const char *alp_stage_name(int32_t i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : ""; }

@@ -286,3 +286,14 @@ def test_invalid_arguments_launch_nothing(gu, ctx):
         alp.alp_spread(ctx.h, case.mesh, b.make_struct(), case.params, case.f, case.S)
     with pytest.raises(alp.AlpError):
         alp.alp_step_batched(ctx.h, [case.case_struct(), case.case_struct()], 0)  # mesh twice
+
+
+def test_autotune_picks_a_valid_binning(gu, ctx):
+    """alp_autotune times every candidate binning on the case and returns one
+    of them; a step on a mesh binned with it still matches the oracle."""
+    wl = W.canopy(n=48, n_stems=40, cv_range=(5, 40), inset=0.05)
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP32_SPLIT)
+    res = alp.alp_autotune(ctx.h, case.C, case.V, [case.case_struct()], 0, alp.USE_GRAPH, reps=2)
+    gu.log(f"[parity] autotune {res}")
+    assert res["tile_bins"] in (2, 3, 4, 5, 6) and res["bin_size"] > 0 and res["ms"] > 0
+    run_and_compare(gu, ctx, wl, alp.PREC_FP32_SPLIT, tile_bins=res["tile_bins"], bin_size=res["bin_size"])
