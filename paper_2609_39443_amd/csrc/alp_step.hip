@@ -207,10 +207,15 @@ void launch_chunks(const StepLaunch &L, hipStream_t st) {
 // segments can be the closest segment of the beam for some point of the tile
 // and lies within 3 eps_max of it:
 //   (a) the segment's AABB inflated by 3 eps_max(beam) overlaps the tile, and
-//   (b) slab rule: segment i is never the (lowest-index) closest segment of a
-//       point behind its start plane (the previous segment ends at the same
-//       vertex) or beyond its end plane while in front of the next segment's
-//       start plane (the next segment is strictly closer).
+//   (b) slab rule: segment i is never the closest segment of a point that is
+//       behind its start plane while in front of the previous segment's end
+//       plane (the previous segment is strictly closer), nor of a point beyond
+//       its end plane while in front of the next segment's start plane (the
+//       next segment is strictly closer).  Where both neighbouring segments
+//       clamp to their shared vertex the two distances are equal in exact
+//       arithmetic and the FP64 rounding of eq. (21) decides, so both stay
+//       candidates there; the planes carry a margin of 1e-7 (tile + R) so that
+//       "strictly closer" survives rounding.
 // The window [first, last] candidate segment of the chunk is appended for
 // every such tile, and counted per tile for the grouping scatter.
 struct SegInfo {
@@ -274,7 +279,7 @@ void launch_chunk_boxes(const StepLaunch &L, hipStream_t st) {
 
 __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
   Work W = L.w;
-  __shared__ SegInfo sg[kChunkSegs + 1];
+  __shared__ SegInfo sg[kChunkSegs + 2];  // [0]: the segment before the chunk, [nsg + 1]: after
   const int lane = threadIdx.x;
   const uint32_t n_chunks = W.bchunks[W.n_beams];
   const uint32_t *box_off = W.chunk_box;  // exclusive scan of the box sizes
@@ -297,11 +302,12 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
     const double *X = cs.Psp + 3 * k0;
     const double tl = m.tile_len;
     const double mrg = 1e-7 * (tl + R);
-    // segment data: the chunk's segments and the one after it (wedge test)
-    for (int j = lane; j <= nsg; j += 64) {
+    // segment data: the chunk's segments and the ones before and after it
+    for (int jj = lane; jj <= nsg + 1; jj += 64) {
+      const int j = jj - 1;
       int i = s0 + j;
       SegInfo q;
-      bool exists = (nb == 1) ? (j == 0) : (i <= nb - 2);
+      bool exists = (nb == 1) ? (j == 0) : (i >= 0 && i <= nb - 2);
       if (exists) {
         const double *A = X + 3 * (nb == 1 ? 0 : i), *B = X + 3 * (nb == 1 ? 0 : i + 1);
         double e[3];
@@ -327,7 +333,7 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
         q.len = 0.0;
         q.su = 0.0;
       }
-      sg[j] = q;
+      sg[jj] = q;
     }
     __syncthreads();
     const int nx = box[3] - box[0] + 1, ny = box[4] - box[1] + 1;
@@ -339,7 +345,7 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
       double tc[3] = {tlo[0] + 0.5 * tl, tlo[1] + 0.5 * tl, tlo[2] + 0.5 * tl};
       double half = 0.5 * tl + mrg;
       for (int j = 0; j < nsg; ++j) {
-        const SegInfo &g = sg[j];
+        const SegInfo &g = sg[j + 1];
         bool ov = true;
         for (int a = 0; a < 3; ++a)
           ov = ov && !(g.hi[a] < tlo[a] - mrg || g.lo[a] > tlo[a] + tl + mrg);
@@ -348,9 +354,16 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
         if (nb >= 2 && g.len > 0.0) {
           double ac = (tc[0] - g.a[0]) * g.u[0] + (tc[1] - g.a[1]) * g.u[1] + (tc[2] - g.a[2]) * g.u[2];
           double hw = half * g.su;
-          if (i > 0 && !(ac + hw > -mrg)) continue;
+          if (i > 0 && !(ac + hw > -mrg)) {
+            const SegInfo &gp = sg[j];
+            if (gp.len > 0.0) {
+              double acp = (tc[0] - gp.a[0]) * gp.u[0] + (tc[1] - gp.a[1]) * gp.u[1] +
+                           (tc[2] - gp.a[2]) * gp.u[2];
+              if (acp + half * gp.su < gp.len - mrg) continue;
+            }
+          }
           if (i < nseg - 1 && !(ac - hw < g.len + mrg)) {
-            const SegInfo &gn = sg[j + 1];
+            const SegInfo &gn = sg[j + 2];
             if (gn.len > 0.0) {
               double acn = (tc[0] - gn.a[0]) * gn.u[0] + (tc[1] - gn.a[1]) * gn.u[1] +
                            (tc[2] - gn.a[2]) * gn.u[2];

@@ -297,3 +297,50 @@ def test_autotune_picks_a_valid_binning(gu, ctx):
     gu.log(f"[parity] autotune {res}")
     assert res["tile_bins"] in (2, 3, 4, 5, 6) and res["bin_size"] > 0 and res["ms"] > 0
     run_and_compare(gu, ctx, wl, alp.PREC_FP32_SPLIT, tile_bins=res["tile_bins"], bin_size=res["bin_size"])
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_bitwise_identical_across_binnings(gu, ctx, prec):
+    """Every decision is exact and every output sum is either exact (w) or
+    taken per cell in beam order (S), so the bin size and the tile edge change
+    no output bit.  The fluid-side force of the balance check sums S_j V_j per
+    64-cell work item before its exact accumulation, so it may move in the
+    last bits with the tiling."""
+    wl = random_scene(21, nx=30, ny=28, nz=22, n_beams=9)
+    ref = None
+    for tb, bs in ((4, 0.0), (2, 0.0), (3, 0.0075), (6, 0.015), (5, 0.02)):
+        case = gu.GpuCase(ctx, wl, prec, tile_bins=tb, bin_size=bs)
+        gu.step_batched(ctx, [case], alp.USE_GRAPH)
+        res = case.results()
+        d = ctx.diag(0)
+        alp.alp_invalidate(ctx.h)
+        if ref is None:
+            ref, dref = res, d
+            continue
+        for k in ref:
+            assert np.array_equal(ref[k], res[k]), (tb, bs, k)
+        for k in d:
+            if k in ("F_fluid", "cons_rel_err"):
+                a, b = np.asarray(d[k]), np.asarray(dref[k])
+                assert np.max(np.abs(a - b)) <= 1e-15 * max(1.0, float(np.max(np.abs(dref["F_beam"])))), k
+            else:
+                assert d[k] == dref[k], (tb, bs, k)
+
+
+def test_hundred_graph_replays_bitwise(gu, ctx):
+    """Scheduling never changes a bit: 100 graph replays of a batch of two
+    cases give the first replay's outputs and diagnostics exactly."""
+    w1 = W.canopy(n=40, n_stems=30, cv_range=(5, 30), inset=0.04)
+    w2 = random_scene(33, n_beams=7)
+    c1, c2 = gu.GpuCase(ctx, w1, alp.PREC_FP32_SPLIT), gu.GpuCase(ctx, w2, alp.PREC_FP64)
+    gu.step_batched(ctx, [c1, c2], alp.USE_GRAPH)
+    first = (c1.results(), c2.results(), ctx.diag(0), ctx.diag(1))
+    for _ in range(100):
+        alp.alp_step_batched(ctx.h, [c1.case_struct(), c2.case_struct()], alp.USE_GRAPH)
+    torch.cuda.synchronize()
+    last = (c1.results(), c2.results(), ctx.diag(0), ctx.diag(1))
+    alp.alp_invalidate(ctx.h)
+    for a, b in zip(first[:2], last[:2]):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    assert first[2] == last[2] and first[3] == last[3]
