@@ -44,6 +44,12 @@
  *   R19 decision expressions in the order dot(a,b) = (ax bx + ay by) + az bz,
  *       no FMA contraction (built with -ffp-contract=off), IEEE division.
  *   R20 f_prev == NULL -> no relaxation.
+ *   R25 optional kernel-weighted sampling (the volume-average sampling the
+ *       conclusions name as future work): U_s = sum_j g_j V_j U_j /
+ *       sum_j g_j V_j over the cells with |C_j - P_s|^2 <= 9 eps_k^2,
+ *       g_j = exp(-|C_j - P_s|^2 / eps_k^2), the profile of eq. (22) whose
+ *       constant factor cancels; no cell in reach -> the single-cell sample of
+ *       eq. (18), counted.
  *
  * Sums over cells or nodes use Neumaier-compensated FP64 so the reference is
  * accurate to a few ulps whatever the number of terms.
@@ -59,6 +65,7 @@
 
 enum { ORC_BRUTE = 0, ORC_GRID = 1 };
 enum { ORC_FULLMAG = 0, ORC_COMPONENTWISE = 1 };
+enum { ORC_SAMPLE_CELL = 0, ORC_SAMPLE_KERNEL = 1 };
 
 /* point flags written by orc_sample */
 #define ORC_F_OUTSIDE 1
@@ -87,13 +94,14 @@ typedef struct {
 typedef struct {
   double rho, alpha_f, tau;
   int32_t drag_form;
-  int32_t pad_;
+  int32_t sample_mode; /* ORC_SAMPLE_CELL (eq. 18) or ORC_SAMPLE_KERNEL (R25) */
 } orc_params;
 
 typedef struct {
   int64_t n_outside, n_fallback, n_fallback_degenerate, n_zero_weight;
   int64_t n_band_cells, n_pairs;
   double F_beam[3], F_fluid[3], cons_rel_err;
+  int64_t n_sample_empty; /* kernel sampling with no cell in reach (R25) */
 } orc_diag;
 
 typedef struct orc_mesh {
@@ -321,13 +329,72 @@ static void unit_tangent(const double *et, double *e) {
   e[0] = et[0] / n; e[1] = et[1] / n; e[2] = et[2] / n;
 }
 
+static int cmp_i64(const void *a, const void *b) {
+  int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* R25: kernel-weighted average of U about x with width eps.  The cells in
+   reach are visited in increasing index order in both search modes, with
+   compensated sums, so both modes give the same bits.  Returns 0 (and leaves
+   us untouched) when no cell is in reach; -1 when out of memory. */
+static int kernel_sample(const orc_mesh *m, const double *U, const double *x, double eps,
+                         double *us) {
+  const double e2 = eps * eps, cut = 9.0 * e2;
+  nsum den = {0.0, 0.0}, num[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  int64_t *list = NULL, nl = 0;
+  if (m->mode == ORC_BRUTE) {
+    list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m->n > 0 ? m->n : 1));
+    if (!list) return -1;
+    for (int64_t j = 0; j < m->n; ++j) list[nl++] = j;
+  } else {
+    int64_t lo[3], hi[3], cap = 64;
+    const double r = 3.0 * eps;
+    for (int a = 0; a < 3; ++a) {
+      /* one extra bin on each side absorbs the rounding of x -/+ r */
+      lo[a] = clampi((int64_t)floor((x[a] - r - m->glo[a]) / m->gh) - 1, 0, m->gn[a] - 1);
+      hi[a] = clampi((int64_t)floor((x[a] + r - m->glo[a]) / m->gh) + 1, 0, m->gn[a] - 1);
+    }
+    list = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    if (!list) return -1;
+    for (int64_t iz = lo[2]; iz <= hi[2]; ++iz)
+      for (int64_t iy = lo[1]; iy <= hi[1]; ++iy)
+        for (int64_t ix = lo[0]; ix <= hi[0]; ++ix) {
+          int64_t bb = (iz * m->gn[1] + iy) * m->gn[0] + ix;
+          for (int64_t p = m->gstart[bb]; p < m->gstart[bb + 1]; ++p) {
+            if (nl == cap) {
+              cap *= 2;
+              int64_t *t = (int64_t *)realloc(list, sizeof(int64_t) * (size_t)cap);
+              if (!t) { free(list); return -1; }
+              list = t;
+            }
+            list[nl++] = m->gidx[p];
+          }
+        }
+    qsort(list, (size_t)nl, sizeof(int64_t), cmp_i64);
+  }
+  for (int64_t q = 0; q < nl; ++q) {
+    int64_t j = list[q];
+    double r2 = sqdist(x, m->C + 3 * j);
+    if (!(r2 <= cut)) continue;
+    double g = exp(-(r2 / e2)) * m->V[j];
+    ns_add(&den, g);
+    for (int a = 0; a < 3; ++a) ns_add(&num[a], g * U[3 * j + a]);
+  }
+  free(list);
+  double D = ns_val(&den);
+  if (!(D > 0.0)) return 0;
+  for (int a = 0; a < 3; ++a) us[a] = ns_val(&num[a]) / D;
+  return 1;
+}
+
 /* Eq. (16)-(18): sampled velocity U_s at the upstream sampling point.
    flags[k] receives ORC_F_* bits; counts go to diag (may be NULL). */
 int orc_sample(const orc_mesh *m, const double *U, const orc_beams *b, const orc_params *p,
                double *U_s, double *P_s, int64_t *cell_a, int64_t *cell_s,
                int32_t *flags, orc_diag *diag) {
   if (!m || !U || !p || !beams_valid(b) || !U_s) return ORC_EINVAL;
-  int64_t n_out = 0, n_fb = 0, n_deg = 0;
+  int64_t n_out = 0, n_fb = 0, n_deg = 0, n_empty = 0;
   for (int32_t bi = 0; bi < b->n_beams; ++bi) {
     const double *np = b->n_p + 3 * bi, *eup = b->e_up + 3 * bi;
     double ls = b->ls[bi];
@@ -369,8 +436,18 @@ int orc_sample(const orc_mesh *m, const double *U, const orc_beams *b, const orc
         for (int a = 0; a < 3; ++a) ps[a] = Pa[a] + ls * (es[a] - dn * np[a]);
         /* eq. (18): single-cell sample at the sampling point */
         cs = orc_locate(m, ps);
-        if (cs < 0) fl |= ORC_F_OUTSIDE;
-        else for (int a = 0; a < 3; ++a) us[a] = U[3 * cs + a];
+        if (cs < 0) {
+          fl |= ORC_F_OUTSIDE;
+        } else {
+          int got = 0;
+          if (p->sample_mode == ORC_SAMPLE_KERNEL) {
+            got = kernel_sample(m, U, ps, b->eps[k], us);
+            if (got < 0) return ORC_ENOMEM;
+            if (got == 0) n_empty++;
+          }
+          if (got == 0)
+            for (int a = 0; a < 3; ++a) us[a] = U[3 * cs + a];
+        }
       }
       if (fl & ORC_F_OUTSIDE) n_out++;
       if (fl & ORC_F_FALLBACK) n_fb++;
@@ -384,6 +461,7 @@ int orc_sample(const orc_mesh *m, const double *U, const orc_beams *b, const orc
   }
   if (diag) {
     diag->n_outside = n_out; diag->n_fallback = n_fb; diag->n_fallback_degenerate = n_deg;
+    diag->n_sample_empty = n_empty;
   }
   return ORC_OK;
 }
@@ -467,11 +545,6 @@ static int pv_push(pairvec *pv, pair_t p) {
   }
   pv->v[pv->n++] = p;
   return ORC_OK;
-}
-
-static int cmp_i64(const void *a, const void *b) {
-  int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
-  return (x > y) - (x < y);
 }
 
 /* cells to test for one beam: every cell (brute), or -- grid mode -- the cells

@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 BRUTE, GRID = 0, 1
 FULLMAG, COMPONENTWISE = 0, 1
+SAMPLE_CELL, SAMPLE_KERNEL = 0, 1
 F_OUTSIDE, F_FALLBACK, F_DEGENERATE = 1, 2, 4
 
 
@@ -48,7 +49,7 @@ class _Beams(ct.Structure):
 
 class _Params(ct.Structure):
     _fields_ = [("rho", ct.c_double), ("alpha_f", ct.c_double), ("tau", ct.c_double),
-                ("drag_form", ct.c_int32), ("pad_", ct.c_int32)]
+                ("drag_form", ct.c_int32), ("sample_mode", ct.c_int32)]
 
 
 class _Diag(ct.Structure):
@@ -56,14 +57,15 @@ class _Diag(ct.Structure):
                 ("n_fallback_degenerate", ct.c_int64), ("n_zero_weight", ct.c_int64),
                 ("n_band_cells", ct.c_int64), ("n_pairs", ct.c_int64),
                 ("F_beam", ct.c_double * 3), ("F_fluid", ct.c_double * 3),
-                ("cons_rel_err", ct.c_double)]
+                ("cons_rel_err", ct.c_double), ("n_sample_empty", ct.c_int64)]
 
     def as_dict(self) -> dict:
         return {"n_outside": self.n_outside, "n_fallback": self.n_fallback,
                 "n_fallback_degenerate": self.n_fallback_degenerate,
                 "n_zero_weight": self.n_zero_weight, "n_band_cells": self.n_band_cells,
                 "n_pairs": self.n_pairs, "F_beam": np.array(self.F_beam[:]),
-                "F_fluid": np.array(self.F_fluid[:]), "cons_rel_err": self.cons_rel_err}
+                "F_fluid": np.array(self.F_fluid[:]), "cons_rel_err": self.cons_rel_err,
+                "n_sample_empty": self.n_sample_empty}
 
 
 _lib = None
@@ -172,8 +174,11 @@ def _params(params: dict) -> _Params:
     form = params.get("drag_form", FULLMAG)
     if isinstance(form, str):
         form = {"fullmag": FULLMAG, "componentwise": COMPONENTWISE}[form]
+    mode = params.get("sample_mode", SAMPLE_CELL)
+    if isinstance(mode, str):
+        mode = {"cell": SAMPLE_CELL, "kernel": SAMPLE_KERNEL}[mode]
     return _Params(float(params["rho"]), float(params.get("alpha_f", 1.0)),
-                   float(params.get("tau", 1e-6)), int(form), 0)
+                   float(params.get("tau", 1e-6)), int(form), int(mode))
 
 
 def sample(mesh: Mesh, U, beams: dict, params: dict) -> dict:

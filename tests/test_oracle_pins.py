@@ -497,3 +497,100 @@ def test_edge_cases(oracle_mod):
     b1 = beams_of([[[0.5, 0.5, 0.45], [0.5, 0.5, 0.55]]], 0.05, L=0.05, ls=0.0)
     r = oracle_mod.step(m1, np.array([[1.0, 0.0, 0.0]]), b1, params())
     assert r["diag"]["cons_rel_err"] <= 1e-15 and r["diag"]["n_pairs"] == 1
+
+
+# ------------------------------------------------- kernel-weighted sampling --
+# R25: the optional volume-average sample about P_s with the profile of the
+# projection kernel, exp(-r^2/eps^2) V_j, over the cells within 3 eps.
+
+def _lattice(n=24, h=0.0625):
+    C, V = W.uniform_mesh(n, n, n, h)
+    return C, V, h
+
+
+def test_kernel_sample_uniform_field_is_exact(oracle_mod):
+    """A uniform field averages to itself (a convex combination of equal values)."""
+    C, V, h = _lattice()
+    U = np.tile([0.37, -0.11, 0.05], (C.shape[0], 1))
+    P = np.array([[12.3 * h, 11.7 * h, 9.2 * h]])
+    b = beams_of([P], eps=[2.0 * h], ls=4 * h)
+    for mode in (oracle_mod.BRUTE, oracle_mod.GRID):
+        m = oracle_mod.Mesh(C, V, None, mode)
+        r = oracle_mod.sample(m, U, b, params(sample_mode="kernel"))
+        assert np.max(np.abs(r["U_s"][0] - U[0]) / np.abs(U[0])) <= 4e-16
+        assert r["diag"]["n_sample_empty"] == 0
+
+
+def test_kernel_sample_linear_field_at_a_centre(oracle_mod):
+    """On a uniform lattice, with P_s on a cell centre whose whole 3 eps ball
+    lies inside the mesh, the weights are symmetric about P_s, so the average
+    of a linear field is its value at P_s (eq. 17 puts P_s = P_a - l_s x here)."""
+    C, V, h = _lattice()
+    a0, ax, ay, az = 0.3, 0.8, -0.45, 0.25
+    U = np.zeros_like(C)
+    U[:, 0] = a0 + ax * C[:, 0] + ay * C[:, 1] + az * C[:, 2]
+    ctr = np.array([11.5 * h, 12.5 * h, 10.5 * h])
+    ls = 4.0 * h
+    P = (ctr + [ls, 0.0, 0.0])[None, :]
+    b = beams_of([P], eps=[1.7 * h], ls=ls, tangents=[[[0.0, 0.0, 1.0]]])
+    m = oracle_mod.Mesh(C, V, None, oracle_mod.GRID)
+    r = oracle_mod.sample(m, U, b, params(sample_mode="kernel"))
+    assert np.array_equal(r["P_s"][0], ctr)
+    exact = a0 + ax * ctr[0] + ay * ctr[1] + az * ctr[2]
+    assert abs(r["U_s"][0, 0] - exact) <= 1e-14 * abs(exact)
+    assert r["U_s"][0, 1] == 0.0 and r["U_s"][0, 2] == 0.0
+    # a quadratic term is not averaged away: the kernel mode really averages
+    U2 = U.copy()
+    U2[:, 0] += 5.0 * (C[:, 1] - ctr[1]) ** 2
+    r2 = oracle_mod.sample(m, U2, b, params(sample_mode="kernel"))
+    assert r2["U_s"][0, 0] > exact + 1e-3 * h
+
+
+def test_kernel_sample_modes_agree_and_stay_in_range(oracle_mod):
+    """Brute and grid search give the same bits; every average lies within
+    the range of the cell values (the weights are positive)."""
+    rng = np.random.default_rng(71)
+    C, V, h = _lattice(n=20)
+    C = C + rng.uniform(-0.3 * h, 0.3 * h, size=C.shape)
+    V = V * np.exp(0.3 * rng.normal(size=V.shape))
+    U = rng.normal(size=C.shape)
+    pts = [np.array([6.0, 7.0, 4.0]) * h + np.cumsum(rng.normal(size=(9, 3)) * 0.4 * h, axis=0)
+           for _ in range(3)]
+    b = beams_of(pts, eps=[1.1 * h, 2.0 * h, 3.0 * h], ls=2.5 * h)
+    rb = oracle_mod.sample(oracle_mod.Mesh(C, V, None, oracle_mod.BRUTE), U, b, params(sample_mode="kernel"))
+    rg = oracle_mod.sample(oracle_mod.Mesh(C, V, None, oracle_mod.GRID), U, b, params(sample_mode="kernel"))
+    assert np.array_equal(rb["U_s"], rg["U_s"]) and np.array_equal(rb["cell_s"], rg["cell_s"])
+    ok = rb["cell_s"] >= 0
+    assert np.all(rb["U_s"][ok] >= U.min(axis=0) - 1e-15) and np.all(rb["U_s"][ok] <= U.max(axis=0) + 1e-15)
+    # the cell mode differs (the average is not the single-cell value)
+    rc = oracle_mod.sample(oracle_mod.Mesh(C, V, None, oracle_mod.GRID), U, b, params())
+    assert not np.allclose(rc["U_s"][ok], rb["U_s"][ok])
+
+
+def test_kernel_sample_single_cell_and_empty_reach(oracle_mod):
+    """A width that reaches one centre returns that cell's value (to rounding
+    of g U / g); one that reaches none falls back to the eq. (18) single-cell
+    sample exactly and is counted."""
+    C, V, h = _lattice(n=12)
+    rng = np.random.default_rng(3)
+    U = rng.normal(size=C.shape)
+    ctr = np.array([5.5, 6.5, 4.5]) * h
+    ls = 3.0 * h
+    tan = [[[0.0, 0.0, 1.0]]]
+    Uc = U.copy()
+    Uc[:, 1:] = 0.0
+    Uc[:, 0] = np.abs(Uc[:, 0]) + 0.5  # cross flow: P_s = P_a - l_s x
+    m = oracle_mod.Mesh(C, V, None, oracle_mod.GRID)
+    # P_s 0.1 h from a centre, eps = 0.1 h: only that centre is within 3 eps
+    P = (ctr + [ls + 0.1 * h, 0.0, 0.0])[None, :]
+    r = oracle_mod.sample(m, Uc, beams_of([P], eps=[0.1 * h], ls=ls, tangents=tan),
+                          params(sample_mode="kernel"))
+    j = r["cell_s"][0]
+    assert np.max(np.abs(r["U_s"][0] - Uc[j])) <= 2.3e-16 * np.max(np.abs(Uc[j]))
+    assert r["diag"]["n_sample_empty"] == 0
+    # P_s at a cell corner, eps = 0.05 h: no centre within 3 eps
+    P = (ctr + [ls + 0.5 * h, 0.5 * h, 0.5 * h])[None, :]
+    b = beams_of([P], eps=[0.05 * h], ls=ls, tangents=tan)
+    rk = oracle_mod.sample(m, Uc, b, params(sample_mode="kernel"))
+    rc = oracle_mod.sample(m, Uc, b, params())
+    assert np.array_equal(rk["U_s"], rc["U_s"]) and rk["diag"]["n_sample_empty"] == 1
