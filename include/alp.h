@@ -74,6 +74,16 @@ typedef enum {
   ALP_DRAG_COMPONENTWISE = 1 /* eq. (6):  1/2 rho d (Cdn |U_n| U_n + Cdt |U_t| U_t) */
 } alp_drag_form;
 
+typedef enum {
+  ALP_SAMPLE_CELL = 0,  /* eq. (18): the value of the cell holding P_s */
+  ALP_SAMPLE_KERNEL = 1 /* volume average about P_s with the profile of eq. (22):
+                           U_s = sum_j g_j V_j U_j / sum_j g_j V_j over the cells with
+                           |C_j - P_s| <= 3 eps_k, g_j = exp(-|C_j - P_s|^2 / eps_k^2)
+                           (the volume-average sampling named as future work in
+                           Sec. 8); with no cell in reach the eq. (18) value is used
+                           and counted in alp_diag.n_sample_empty */
+} alp_sample_mode;
+
 /* The beam set (Sec. 3.2.2): one actuator point per beam control volume.
    Beams are a CSR over points: beam b owns points offsets[b] .. offsets[b+1]-1,
    ordered along the centreline.  All pointers are DEVICE pointers. */
@@ -104,6 +114,8 @@ typedef struct {
   double tau;      /* fallback threshold on |u0_n| [m/s] (Sec. 3.2.2); 0 disables */
   int32_t prec;    /* alp_precision */
   int32_t drag_form; /* alp_drag_form */
+  int32_t sample_mode; /* alp_sample_mode */
+  int32_t reserved1;   /* must be 0 */
 } alp_params;
 
 /* Diagnostics of the last step of a case (written on the device, read by
@@ -120,6 +132,7 @@ typedef struct {
   double F_beam[3];   /* sum_k f_k L_k  (force on the beam, eq. 14) */
   double F_fluid[3];  /* sum_j S_j V_j  (force on the fluid, eq. 14) */
   double cons_rel_err; /* |F_fluid + F_beam| / sum_k |f_k L_k| */
+  int64_t n_sample_empty; /* ALP_SAMPLE_KERNEL points with no cell within 3 eps of P_s */
 } alp_diag;
 
 /* Create a context on HIP device `device` that launches on `hip_stream`

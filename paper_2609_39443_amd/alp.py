@@ -19,6 +19,7 @@ STATUS = {0: "ALP_OK", -1: "ALP_ERR_INVALID_ARG", -2: "ALP_ERR_HIP", -3: "ALP_ER
           -4: "ALP_ERR_CAPTURE", -5: "ALP_ERR_SHAPE", -6: "ALP_ERR_CAPACITY"}
 PREC_FP64, PREC_FP32_SPLIT = 0, 1
 DRAG_FULLMAG, DRAG_COMPONENTWISE = 0, 1
+SAMPLE_CELL, SAMPLE_KERNEL = 0, 1
 USE_GRAPH, CHECKED = 1, 2
 
 # every symbol include/alp.h declares
@@ -43,7 +44,8 @@ class alp_beams(ct.Structure):
 
 class alp_params(ct.Structure):
     _fields_ = [("rho", ct.c_double), ("alpha_f", ct.c_double), ("tau", ct.c_double),
-                ("prec", ct.c_int32), ("drag_form", ct.c_int32)]
+                ("prec", ct.c_int32), ("drag_form", ct.c_int32), ("sample_mode", ct.c_int32),
+                ("reserved1", ct.c_int32)]
 
 
 class alp_diag(ct.Structure):
@@ -51,7 +53,7 @@ class alp_diag(ct.Structure):
                 ("n_fallback_degenerate", ct.c_int64), ("n_zero_weight", ct.c_int64),
                 ("n_band_cells", ct.c_int64), ("n_pairs", ct.c_int64), ("n_overflow", ct.c_int64),
                 ("n_invalid", ct.c_int64), ("F_beam", ct.c_double * 3), ("F_fluid", ct.c_double * 3),
-                ("cons_rel_err", ct.c_double)]
+                ("cons_rel_err", ct.c_double), ("n_sample_empty", ct.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("F_beam", "F_fluid")}
@@ -240,8 +242,11 @@ def make_params(params: dict, prec=PREC_FP64):
     form = params.get("drag_form", DRAG_FULLMAG)
     if isinstance(form, str):
         form = {"fullmag": DRAG_FULLMAG, "componentwise": DRAG_COMPONENTWISE}[form]
+    mode = params.get("sample_mode", SAMPLE_CELL)
+    if isinstance(mode, str):
+        mode = {"cell": SAMPLE_CELL, "kernel": SAMPLE_KERNEL}[mode]
     return alp_params(float(params["rho"]), float(params.get("alpha_f", 1.0)),
-                      float(params.get("tau", 1e-6)), int(prec), int(form))
+                      float(params.get("tau", 1e-6)), int(prec), int(form), int(mode), 0)
 
 
 class Context:

@@ -170,6 +170,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(w_lo, P);
   WALLOC(fhat, 3 * P);
   WALLOC(Us, 3 * P);
+  WALLOC(Ps, 3 * P);
   WALLOC(f, 3 * P);
   WALLOC(bcase, B);
   WALLOC(beps_max, B);
@@ -287,6 +288,9 @@ alp_status check_params(alp_context *ctx, const alp_params *p, bool relax) {
     return fail(ctx, ALP_ERR_INVALID_ARG, "unknown precision %d", p->prec);
   if (p->drag_form != ALP_DRAG_FULLMAG && p->drag_form != ALP_DRAG_COMPONENTWISE)
     return fail(ctx, ALP_ERR_INVALID_ARG, "unknown drag form %d", p->drag_form);
+  if (p->sample_mode != ALP_SAMPLE_CELL && p->sample_mode != ALP_SAMPLE_KERNEL)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "unknown sample mode %d", p->sample_mode);
+  if (p->reserved1 != 0) return fail(ctx, ALP_ERR_INVALID_ARG, "params.reserved1 must be 0");
   return ALP_OK;
 }
 
@@ -297,6 +301,7 @@ void fill_case(CaseDev &c, const alp_mesh *m, const alp_beams *b, const alp_para
   c.n_beams = b->n_beams;
   c.prec = p->prec;
   c.drag_form = p->drag_form;
+  c.sample_mode = p->sample_mode;
   c.rho = p->rho;
   c.alpha_f = p->alpha_f;
   c.tau = p->tau;
@@ -417,7 +422,10 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
     (void)hipEventRecord(ctx->ev_fork, st);
     (void)hipStreamWaitEvent(sd, ctx->ev_fork, 0);
   }
-  if (stages & ST_SAMPLE) launch_sample(L, sd);
+  if (stages & ST_SAMPLE) {
+    launch_sample(L, sd);
+    launch_sample_kernel(L, sd);
+  }
   mark(2);
   if (stages & ST_DRAG) launch_drag(L, sd);
   mark(3);
@@ -975,6 +983,7 @@ alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out) {
     out->F_fluid[a] = d[4 + a];
   }
   out->cons_rel_err = d[7];
+  out->n_sample_empty = cnt[7];
   return ALP_OK;
 }
 

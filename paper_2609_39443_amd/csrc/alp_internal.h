@@ -54,7 +54,7 @@ struct CaseDev {
   int64_t *cell_a, *cell_s;
   uint8_t *tile_prev;   // [n_tiles] tiles written at the previous step of this mesh
   int32_t write_S;      // spread writes S (0 for sample/drag-only calls)
-  int32_t pad_;
+  int32_t sample_mode;  // alp_sample_mode
 };
 
 // A (chunk, tile) window: the candidate segments lo..hi of one chunk of a
@@ -106,6 +106,7 @@ struct Work {
   unsigned long long *w_lo;
   double *fhat;         // [N_P][3]
   double *Us;           // [N_P][3] internal sampled velocity
+  double *Ps;           // [N_P][3] internal sampling point
   double *f;            // [N_P][3] internal force (when the case has none)
   // beams (global)
   int32_t *bcase;       // beam -> case
@@ -137,7 +138,7 @@ struct Work {
   double *beam_part;    // [n_pblocks][4] (F_beam xyz, sum |f L|)
   int32_t *pblock_case; // [n_pblocks]
   int64_t *pblock_range;// [n_pblocks][2]
-  long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, spare
+  long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, empty kernel sample
   double *diag_out;     // [n_cases][16] finalised diagnostics
   // scalars
   uint32_t *counters;   // [16]: 3 overflow flags
@@ -304,6 +305,7 @@ void launch_emit_scatter(const StepLaunch &L, hipStream_t st);
 void launch_tile_merge(const StepLaunch &L, hipStream_t st);
 void launch_items(const StepLaunch &L, hipStream_t st);
 void launch_sample(const StepLaunch &L, hipStream_t st);
+void launch_sample_kernel(const StepLaunch &L, hipStream_t st);
 void launch_drag(const StepLaunch &L, hipStream_t st);
 void launch_weights(const StepLaunch &L, hipStream_t st);
 void launch_norm(const StepLaunch &L, hipStream_t st);

@@ -81,7 +81,7 @@ __global__ void k_step_reset(StepLaunch L, int what) {
   if (tid == 0 && (what & RESET_PROJECT)) *W.rec_alloc = 0;
   for (int64_t c = tid; c < (int64_t)L.n_cases * 8; c += stride) {
     int k = (int)(c & 7);
-    bool samp = k < 3;
+    bool samp = k < 3 || k == 7;
     if ((samp && (what & RESET_SAMPLE)) || (!samp && (what & RESET_PROJECT))) W.cnt[c] = 0;
   }
   if (!(what & RESET_PROJECT)) return;
@@ -729,6 +729,9 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
       }
     }
     if (sub == 0) {
+      W.Ps[3 * g] = ps[0];
+      W.Ps[3 * g + 1] = ps[1];
+      W.Ps[3 * g + 2] = ps[2];
       W.Us[3 * g] = us[0];
       W.Us[3 * g + 1] = us[1];
       W.Us[3 * g + 2] = us[2];
@@ -762,6 +765,80 @@ void launch_sample(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_points == 0) return;
   int64_t threads = L.w.n_points * kSampleLanes;
   hipLaunchKernelGGL(k_sample, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, st, L);
+}
+
+// ---------------------------------------------------------- kernel sample --
+// ALP_SAMPLE_KERNEL: the volume average of U about P_s with the profile of
+// eq. (22), U_s = sum_j g_j V_j U_j / sum_j g_j V_j over the cells within
+// 3 eps_k, g_j = exp(-|C_j - P_s|^2 / eps_k^2).  One wave per point: the
+// lanes share the bins around P_s, each keeps FP64 partial sums, and a fixed
+// butterfly joins them.  The cutoff test uses the same FP64 expressions as
+// every other distance decision.  With no cell in reach the single-cell value
+// written by k_sample stays and the point is counted.
+__global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
+#pragma clang fp contract(off)
+  Work W = L.w;
+  const int lane = threadIdx.x;
+  for (int64_t g = blockIdx.x; g < W.n_points; g += gridDim.x) {
+    const int c = case_of(L.pbase, L.n_cases, g);
+    const CaseDev &cs = L.cases[c];
+    if (cs.sample_mode != ALP_SAMPLE_KERNEL || (W.pflags[g] & 1)) continue;  // uniform per wave
+    const MeshDev &m = cs.m;
+    const int64_t k = g - cs.point_base;
+    const double p[3] = {W.Ps[3 * g], W.Ps[3 * g + 1], W.Ps[3 * g + 2]};
+    const double ep = cs.eps[k];
+    const double e2 = ep * ep, cut = 9.0 * e2, r = 3.0 * ep;
+    int lo[3], hi[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      // one extra bin on each side absorbs the rounding of p -/+ r
+      const double f0 = floor((p[a] - r - m.lo[a]) / m.bin) - 1.0, f1 = floor((p[a] + r - m.lo[a]) / m.bin) + 1.0;
+      ok = ok && f0 <= f1;  // false for non-finite input
+      lo[a] = !(f0 > 0.0) ? 0 : (f0 > (double)(m.nb[a] - 1) ? m.nb[a] - 1 : (int)f0);
+      hi[a] = !(f1 > 0.0) ? 0 : (f1 > (double)(m.nb[a] - 1) ? m.nb[a] - 1 : (int)f1);
+    }
+    double den = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0;
+    if (ok) {
+      const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+      const int64_t total = (int64_t)nx * ny * nz;
+      for (int64_t q = lane; q < total; q += 64) {
+        const int ix = lo[0] + (int)(q % nx), iy = lo[1] + (int)((q / nx) % ny),
+                  iz = lo[2] + (int)(q / ((int64_t)nx * ny));
+        const uint32_t key = bin_key(m, ix, iy, iz);
+        const uint32_t e = m.bin_start[key + 1];
+        for (uint32_t j = m.bin_start[key]; j < e; ++j) {
+          const double r2 = sqdist_exact(p[0], p[1], p[2], m.cx[j], m.cy[j], m.cz[j]);
+          if (!(r2 <= cut)) continue;
+          const double gw = exp(-(r2 / e2)) * m.vs[j];
+          const double *Uj = cs.U + 3 * (int64_t)m.perm[j];
+          den += gw;
+          n0 += gw * Uj[0];
+          n1 += gw * Uj[1];
+          n2 += gw * Uj[2];
+        }
+      }
+    }
+    den = wave_sum_f64(den);
+    n0 = wave_sum_f64(n0);
+    n1 = wave_sum_f64(n1);
+    n2 = wave_sum_f64(n2);
+    if (lane == 0) {
+      if (den > 0.0) {
+        const double us[3] = {n0 / den, n1 / den, n2 / den};
+        for (int a = 0; a < 3; ++a) W.Us[3 * g + a] = us[a];
+        if (cs.U_s)
+          for (int a = 0; a < 3; ++a) cs.U_s[3 * k + a] = us[a];
+      } else {
+        atomicAdd((unsigned long long *)(W.cnt + 8 * c + 7), 1ull);
+      }
+    }
+  }
+}
+
+void launch_sample_kernel(const StepLaunch &L, hipStream_t st) {
+  if (L.w.n_points == 0) return;
+  const int64_t g = L.w.n_points < (int64_t)L.grid_persistent * 4 ? L.w.n_points : (int64_t)L.grid_persistent * 4;
+  hipLaunchKernelGGL(k_sample_kernel, dim3((unsigned)g), dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------------- drag --

@@ -91,7 +91,7 @@ def normwise(a, b):
     return num / den if den > 0 else num
 
 
-def compare(res, ref, diag, ref_diag, tol_S, tol_w, tol_f=1e-12, check_sample=True):
+def compare(res, ref, diag, ref_diag, tol_S, tol_w, tol_f=1e-12, check_sample=True, tol_us=0.0):
     """Element-by-element comparison with the oracle; returns a dict of errors."""
     err = {}
     if check_sample:
@@ -99,7 +99,9 @@ def compare(res, ref, diag, ref_diag, tol_S, tol_w, tol_f=1e-12, check_sample=Tr
         assert np.array_equal(res["cell_s"], ref["cell_s"]), "cell_s differs"
         err["P_s"] = normwise(res["P_s"], ref["P_s"])
         err["U_s"] = normwise(res["U_s"], ref["U_s"])
-        assert err["P_s"] <= 1e-15 and err["U_s"] == 0.0, err
+        # the single-cell sample is a copy; the kernel-weighted one (R25) is a
+        # sum whose order differs from the oracle's
+        assert err["P_s"] <= 1e-15 and err["U_s"] <= tol_us, err
     err["f"] = normwise(res["f"], ref["f"])
     assert err["f"] <= tol_f, err
     zw = ref["w"] == 0
@@ -122,8 +124,8 @@ def compare(res, ref, diag, ref_diag, tol_S, tol_w, tol_f=1e-12, check_sample=Tr
         assert abs(diag["F_beam"][a] - ref_diag["F_beam"][a]) <= 1e-12 * scale, (diag, ref_diag)
         assert abs(diag["F_fluid"][a] - ref_diag["F_fluid"][a]) <= 1e-12 * scale, (diag, ref_diag)
     for k in ("n_outside", "n_fallback", "n_fallback_degenerate", "n_zero_weight", "n_pairs",
-              "n_band_cells"):
-        if check_sample or k not in ("n_outside", "n_fallback", "n_fallback_degenerate"):
+              "n_band_cells", "n_sample_empty"):
+        if check_sample or k not in ("n_outside", "n_fallback", "n_fallback_degenerate", "n_sample_empty"):
             assert diag[k] == ref_diag[k], (k, diag[k], ref_diag[k])
     assert diag["n_overflow"] == 0 and diag["n_invalid"] == 0, diag
     return err

@@ -78,7 +78,7 @@ def random_scene(seed, nx=26, ny=22, nz=18, h=0.01, n_beams=6, jitter=True, outs
 
 
 def run_and_compare(gu, ctx, wl, prec, batched=True, tile_bins=0, bin_size=0.0, f_prev=None,
-                    check_sample=True):
+                    check_sample=True, tol_us=0.0):
     gu.log(f"[parity] {wl['name']} prec={prec} batched={batched} tile_bins={tile_bins}")
     case = gu.GpuCase(ctx, wl, prec, tile_bins=tile_bins, bin_size=bin_size, f_prev=f_prev)
     if batched:
@@ -89,7 +89,7 @@ def run_and_compare(gu, ctx, wl, prec, batched=True, tile_bins=0, bin_size=0.0, 
     diag = ctx.diag(0)
     ref = gu.oracle_step(wl, f_prev=f_prev)
     tS, tw = TOL[prec]
-    err = gu.compare(res, ref, diag, ref["diag"], tS, tw, check_sample=check_sample)
+    err = gu.compare(res, ref, diag, ref["diag"], tS, tw, check_sample=check_sample, tol_us=tol_us)
     gu.log(f"[parity]   errors {err}")
     return case, res, ref, diag
 
@@ -344,3 +344,19 @@ def test_hundred_graph_replays_bitwise(gu, ctx):
         for k in a:
             assert np.array_equal(a[k], b[k]), k
     assert first[2] == last[2] and first[3] == last[3]
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_kernel_weighted_sampling(gu, ctx, prec):
+    """The optional volume-average sample about P_s (R25) against the oracle,
+    batched and unbatched, including points outside the domain and points
+    whose 3 eps ball holds no cell centre (counted, single-cell value kept)."""
+    tiny = random_scene(17, n_beams=5)
+    off = tiny["beams"]["offsets"]
+    tiny["beams"]["eps"][off[2]:off[3]] = 1e-4 * 0.01   # eps << h: empty reach
+    for wl, batched in ((W.channel(noise=True), True), (random_scene(6, outside=True), True),
+                        (random_scene(9), False), (tiny, True)):
+        wl["params"]["sample_mode"] = "kernel"
+        _, _, ref, diag = run_and_compare(gu, ctx, wl, prec, batched=batched, tol_us=1e-12)
+        gu.log(f"[parity]   kernel sampling: empty reach {diag['n_sample_empty']}")
+    assert ref["diag"]["n_sample_empty"] > 0
