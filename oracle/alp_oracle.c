@@ -44,6 +44,12 @@
  *   R19 decision expressions in the order dot(a,b) = (ax bx + ay by) + az bz,
  *       no FMA contraction (built with -ffp-contract=off), IEEE division.
  *   R20 f_prev == NULL -> no relaxation.
+ *   R26 optional Morison inertia, eq. (8), added to the drag before the
+ *       relaxation: f_a = rho A (CMt a_rt + CMn a_rn + a_f) with the relative
+ *       acceleration taken fluid minus beam, a_r = a_f - a_b (as U_r in eq. 16
+ *       and 19; the printed a_b - a_f would make the added-mass reaction push a
+ *       beam along its own acceleration), a_f the fluid acceleration sampled at
+ *       P_s by the same operator as U_s.
  *   R25 optional kernel-weighted sampling (the volume-average sampling the
  *       conclusions name as future work): U_s = sum_j g_j V_j U_j /
  *       sum_j g_j V_j over the cells with |C_j - P_s|^2 <= 9 eps_k^2,
@@ -89,6 +95,11 @@ typedef struct {
   const double *ls;       /* [n_beams] */
   const double *n_p;      /* [n_beams][3] */
   const double *e_up;     /* [n_beams][3] */
+  /* optional Morison inertia (eq. 8, R26); A == NULL: none */
+  const double *A;        /* [n] cross-section area */
+  const double *CMn;      /* [n_beams] normal added-mass coefficient */
+  const double *CMt;      /* [n_beams] tangential added-mass coefficient */
+  const double *a_b;      /* [n][3] beam acceleration, or NULL = 0 */
 } orc_beams;
 
 typedef struct {
@@ -317,6 +328,7 @@ int orc_locate_many(const orc_mesh *m, int64_t nq, const double *X, int64_t *cel
 /* ------------------------------------------------------------ sampling -- */
 static int beams_valid(const orc_beams *b) {
   if (!b || b->n_beams < 0 || b->n_points < 0) return 0;
+  if (b->A && (!b->CMn || !b->CMt)) return 0;
   if (b->n_beams > 0 && !b->offsets) return 0;
   if (b->n_beams > 0 && (b->offsets[0] != 0 || b->offsets[b->n_beams] != b->n_points)) return 0;
   for (int32_t i = 0; i < b->n_beams; ++i)
@@ -338,10 +350,11 @@ static int cmp_i64(const void *a, const void *b) {
    reach are visited in increasing index order in both search modes, with
    compensated sums, so both modes give the same bits.  Returns 0 (and leaves
    us untouched) when no cell is in reach; -1 when out of memory. */
-static int kernel_sample(const orc_mesh *m, const double *U, const double *x, double eps,
-                         double *us) {
+static int kernel_sample(const orc_mesh *m, const double *U, const double *A2, const double *x,
+                         double eps, double *us, double *as2) {
   const double e2 = eps * eps, cut = 9.0 * e2;
   nsum den = {0.0, 0.0}, num[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  nsum num2[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
   int64_t *list = NULL, nl = 0;
   if (m->mode == ORC_BRUTE) {
     list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m->n > 0 ? m->n : 1));
@@ -380,11 +393,15 @@ static int kernel_sample(const orc_mesh *m, const double *U, const double *x, do
     double g = exp(-(r2 / e2)) * m->V[j];
     ns_add(&den, g);
     for (int a = 0; a < 3; ++a) ns_add(&num[a], g * U[3 * j + a]);
+    if (A2)
+      for (int a = 0; a < 3; ++a) ns_add(&num2[a], g * A2[3 * j + a]);
   }
   free(list);
   double D = ns_val(&den);
   if (!(D > 0.0)) return 0;
   for (int a = 0; a < 3; ++a) us[a] = ns_val(&num[a]) / D;
+  if (A2)
+    for (int a = 0; a < 3; ++a) as2[a] = ns_val(&num2[a]) / D;
   return 1;
 }
 
@@ -392,7 +409,7 @@ static int kernel_sample(const orc_mesh *m, const double *U, const double *x, do
    flags[k] receives ORC_F_* bits; counts go to diag (may be NULL). */
 int orc_sample(const orc_mesh *m, const double *U, const orc_beams *b, const orc_params *p,
                double *U_s, double *P_s, int64_t *cell_a, int64_t *cell_s,
-               int32_t *flags, orc_diag *diag) {
+               int32_t *flags, orc_diag *diag, const double *dUdt, double *a_s) {
   if (!m || !U || !p || !beams_valid(b) || !U_s) return ORC_EINVAL;
   int64_t n_out = 0, n_fb = 0, n_deg = 0, n_empty = 0;
   for (int32_t bi = 0; bi < b->n_beams; ++bi) {
@@ -400,7 +417,7 @@ int orc_sample(const orc_mesh *m, const double *U, const orc_beams *b, const orc
     double ls = b->ls[bi];
     for (int64_t k = b->offsets[bi]; k < b->offsets[bi + 1]; ++k) {
       const double *Pa = b->P + 3 * k, *Pd = b->Pdot + 3 * k;
-      double e[3], ps[3] = {Pa[0], Pa[1], Pa[2]}, us[3] = {0.0, 0.0, 0.0};
+      double e[3], ps[3] = {Pa[0], Pa[1], Pa[2]}, us[3] = {0.0, 0.0, 0.0}, as[3] = {0.0, 0.0, 0.0};
       int32_t fl = 0;
       int64_t cs = -1;
       unit_tangent(b->e_t + 3 * k, e);
@@ -441,18 +458,22 @@ int orc_sample(const orc_mesh *m, const double *U, const orc_beams *b, const orc
         } else {
           int got = 0;
           if (p->sample_mode == ORC_SAMPLE_KERNEL) {
-            got = kernel_sample(m, U, ps, b->eps[k], us);
+            got = kernel_sample(m, U, dUdt, ps, b->eps[k], us, as);
             if (got < 0) return ORC_ENOMEM;
             if (got == 0) n_empty++;
           }
-          if (got == 0)
+          if (got == 0) {
             for (int a = 0; a < 3; ++a) us[a] = U[3 * cs + a];
+            if (dUdt)
+              for (int a = 0; a < 3; ++a) as[a] = dUdt[3 * cs + a];
+          }
         }
       }
       if (fl & ORC_F_OUTSIDE) n_out++;
       if (fl & ORC_F_FALLBACK) n_fb++;
       if (fl & ORC_F_DEGENERATE) n_deg++;
       for (int a = 0; a < 3; ++a) U_s[3 * k + a] = us[a];
+      if (a_s) for (int a = 0; a < 3; ++a) a_s[3 * k + a] = as[a];
       if (P_s) for (int a = 0; a < 3; ++a) P_s[3 * k + a] = ps[a];
       if (cell_a) cell_a[k] = ca;
       if (cell_s) cell_s[k] = cs;
@@ -470,7 +491,7 @@ int orc_sample(const orc_mesh *m, const double *U, const orc_beams *b, const orc
 /* Eq. (19) (R1 sign: force on the beam) or eq. (6), then relaxation eq. (20).
    A point whose sample is missing (cell_s < 0) carries no load (R13). */
 int orc_drag(const orc_beams *b, const orc_params *p, const double *U_s,
-             const int64_t *cell_s, const double *f_prev, double *f) {
+             const int64_t *cell_s, const double *f_prev, double *f, const double *a_s) {
   if (!p || !beams_valid(b) || !U_s || !f) return ORC_EINVAL;
   for (int32_t bi = 0; bi < b->n_beams; ++bi) {
     double cdn = b->Cdn[bi], cdt = b->Cdt[bi];
@@ -489,6 +510,16 @@ int orc_drag(const orc_beams *b, const orc_params *p, const double *U_s,
         } else {
           double mr = sqrt(dot3(ur, ur));
           for (int a = 0; a < 3; ++a) fs[a] = half * mr * (cdn * un[a] + cdt * ut[a]);
+        }
+        if (b->A && a_s) {
+          /* eq. (8) with a_r = a_f - a_b (R26) */
+          double ar[3], art[3], arn[3];
+          for (int a = 0; a < 3; ++a) ar[a] = a_s[3 * k + a] - (b->a_b ? b->a_b[3 * k + a] : 0.0);
+          double ta = dot3(ar, e);
+          for (int a = 0; a < 3; ++a) { art[a] = ta * e[a]; arn[a] = ar[a] - art[a]; }
+          double ra = p->rho * b->A[k], cmn = b->CMn[bi], cmt = b->CMt[bi];
+          for (int a = 0; a < 3; ++a)
+            fs[a] += ra * ((cmt * art[a] + cmn * arn[a]) + a_s[3 * k + a]);
         }
       }
       for (int a = 0; a < 3; ++a)
@@ -641,7 +672,7 @@ int orc_spread(const orc_mesh *m, const orc_beams *b, const double *f, double *S
   }
   if (rc != ORC_OK) goto done;
 
-  /* step 10: normalised nodal forces f_hat_k = f_k L_k / w_k (R3, R12) */
+  /* normalised nodal forces f_hat_k = f_k L_k / w_k (Sec. 3.2.4, R3, R12) */
   int64_t nzero = 0;
   for (int64_t k = 0; k < np; ++k) {
     double wk = ns_val(&wacc[k]);
@@ -651,7 +682,7 @@ int orc_spread(const orc_mesh *m, const orc_beams *b, const double *f, double *S
   }
   if (fhat) memcpy(fhat, fh, sizeof(double) * 3 * (size_t)np);
 
-  /* step 11: eq. (23), sources added over beams in index order (R16) */
+  /* eq. (23), sources added over beams in index order (R16) */
   for (int64_t t = 0; t < pv.n; ++t) {
     const pair_t *pr = &pv.v[t];
     band[pr->cell] = 1;
@@ -670,7 +701,7 @@ int orc_spread(const orc_mesh *m, const orc_beams *b, const double *f, double *S
     }
     nband += band[j];
   }
-  /* step 12: eq. (14) action-reaction check */
+  /* eq. (14) action-reaction check */
   nsum mag = {0, 0};
   for (int64_t k = 0; k < np; ++k) {
     double fl[3];
@@ -695,18 +726,24 @@ done:
   return rc;
 }
 
-/* One coupling step: sample -> drag -> spread (Algorithm 1, steps 2-5, 7-8). */
+/* One coupling step: sample -> line force -> projection (Sec. 3.2). */
 int orc_step(const orc_mesh *m, const double *U, const orc_beams *b, const orc_params *p,
              const double *f_prev, double *U_s, double *P_s, int64_t *cell_a, int64_t *cell_s,
-             double *f, double *S, double *w, double *fhat, orc_diag *diag) {
+             double *f, double *S, double *w, double *fhat, orc_diag *diag, const double *dUdt) {
   if (!m || !U || !p || !beams_valid(b) || !U_s || !f || !S) return ORC_EINVAL;
   int64_t np = b->n_points > 0 ? b->n_points : 1;
   int64_t *cs = cell_s ? cell_s : (int64_t *)malloc(sizeof(int64_t) * (size_t)np);
   if (!cs) return ORC_ENOMEM;
+  double *as = NULL;
+  if (dUdt) {
+    as = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    if (!as) { if (!cell_s) free(cs); return ORC_ENOMEM; }
+  }
   orc_diag d1;
   memset(&d1, 0, sizeof(d1));
-  int rc = orc_sample(m, U, b, p, U_s, P_s, cell_a, cs, NULL, &d1);
-  if (rc == ORC_OK) rc = orc_drag(b, p, U_s, cs, f_prev, f);
+  int rc = orc_sample(m, U, b, p, U_s, P_s, cell_a, cs, NULL, &d1, dUdt, as);
+  if (rc == ORC_OK) rc = orc_drag(b, p, U_s, cs, f_prev, f, as);
+  free(as);
   if (rc == ORC_OK) rc = orc_spread(m, b, f, S, w, fhat, &d1);
   if (!cell_s) free(cs);
   if (rc == ORC_OK && diag) *diag = d1;

@@ -44,7 +44,8 @@ class _Beams(ct.Structure):
                 ("e_t", ct.c_void_p), ("Pdot", ct.c_void_p), ("d", ct.c_void_p),
                 ("L", ct.c_void_p), ("eps", ct.c_void_p), ("Cdn", ct.c_void_p),
                 ("Cdt", ct.c_void_p), ("ls", ct.c_void_p), ("n_p", ct.c_void_p),
-                ("e_up", ct.c_void_p)]
+                ("e_up", ct.c_void_p), ("A", ct.c_void_p), ("CMn", ct.c_void_p),
+                ("CMt", ct.c_void_p), ("a_b", ct.c_void_p)]
 
 
 class _Params(ct.Structure):
@@ -84,11 +85,11 @@ def _load():
         lib.orc_mesh_box.restype = ct.POINTER(ct.c_double)
         lib.orc_locate_many.argtypes = [vp, ct.c_int64, vp, vp]
         lib.orc_sample.argtypes = [vp, vp, ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp,
-                                   vp, ct.POINTER(_Diag)]
-        lib.orc_drag.argtypes = [ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp]
+                                   vp, ct.POINTER(_Diag), vp, vp]
+        lib.orc_drag.argtypes = [ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp, vp]
         lib.orc_spread.argtypes = [vp, ct.POINTER(_Beams), vp, vp, vp, vp, ct.POINTER(_Diag)]
         lib.orc_step.argtypes = [vp, vp, ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp,
-                                 vp, vp, vp, vp, vp, ct.POINTER(_Diag)]
+                                 vp, vp, vp, vp, vp, ct.POINTER(_Diag), vp]
         lib.orc_nearest_segment.argtypes = [ct.c_int64, vp, vp, ct.POINTER(ct.c_double),
                                             ct.POINTER(ct.c_double)]
         lib.orc_nearest_segment.restype = ct.c_int64
@@ -164,9 +165,16 @@ class _BeamArgs:
                              ("e_up", self.e_up, nb)):
             if arr.shape[0] != n:
                 raise ValueError(f"beams[{name!r}] has {arr.shape[0]} rows, expected {n}")
+        # optional Morison inertia inputs (eq. 8)
+        opt = lambda k, shape: None if beams.get(k) is None else _f64(beams[k], shape)
+        self.A, self.CMn, self.CMt = opt("A", (-1,)), opt("CMn", (-1,)), opt("CMt", (-1,))
+        self.a_b = opt("a_b", (-1, 3))
+        if self.A is not None and (self.CMn is None or self.CMt is None):
+            raise ValueError("beams['A'] needs 'CMn' and 'CMt'")
         self.s = _Beams(nb, 0, npnt, _ptr(self.offsets), _ptr(self.P), _ptr(self.P_spread),
                         _ptr(self.e_t), _ptr(self.Pdot), _ptr(self.d), _ptr(self.L), _ptr(self.eps),
-                        _ptr(self.Cdn), _ptr(self.Cdt), _ptr(self.ls), _ptr(self.n_p), _ptr(self.e_up))
+                        _ptr(self.Cdn), _ptr(self.Cdt), _ptr(self.ls), _ptr(self.n_p), _ptr(self.e_up),
+                        _ptr(self.A), _ptr(self.CMn), _ptr(self.CMt), _ptr(self.a_b))
         self.n_points = npnt
 
 
@@ -181,31 +189,36 @@ def _params(params: dict) -> _Params:
                    float(params.get("tau", 1e-6)), int(form), int(mode))
 
 
-def sample(mesh: Mesh, U, beams: dict, params: dict) -> dict:
+def sample(mesh: Mesh, U, beams: dict, params: dict, dUdt=None) -> dict:
     lib = _load()
     U = _f64(U, (-1, 3))
+    A2 = None if dUdt is None else _f64(dUdt, (-1, 3))
     b = _BeamArgs(beams)
     n = b.n_points
     out = {"U_s": np.zeros((n, 3)), "P_s": np.zeros((n, 3)), "cell_a": np.zeros(n, np.int64),
            "cell_s": np.zeros(n, np.int64), "flags": np.zeros(n, np.int32)}
+    if A2 is not None:
+        out["a_s"] = np.zeros((n, 3))
     d = _Diag()
     rc = lib.orc_sample(mesh._h, _ptr(U), ct.byref(b.s), ct.byref(_params(params)), _ptr(out["U_s"]),
                         _ptr(out["P_s"]), _ptr(out["cell_a"]), _ptr(out["cell_s"]), _ptr(out["flags"]),
-                        ct.byref(d))
+                        ct.byref(d), _ptr(A2), _ptr(out.get("a_s")))
     if rc != 0:
         raise ValueError(f"orc_sample failed ({rc})")
     out["diag"] = d.as_dict()
     return out
 
 
-def drag(beams: dict, params: dict, U_s, cell_s=None, f_prev=None):
+def drag(beams: dict, params: dict, U_s, cell_s=None, f_prev=None, a_s=None):
     lib = _load()
     b = _BeamArgs(beams)
     U_s = _f64(U_s, (-1, 3))
     cs = None if cell_s is None else np.ascontiguousarray(cell_s, dtype=np.int64)
     fp = None if f_prev is None else _f64(f_prev, (-1, 3))
+    A2 = None if a_s is None else _f64(a_s, (-1, 3))
     f = np.zeros((b.n_points, 3))
-    rc = lib.orc_drag(ct.byref(b.s), ct.byref(_params(params)), _ptr(U_s), _ptr(cs), _ptr(fp), _ptr(f))
+    rc = lib.orc_drag(ct.byref(b.s), ct.byref(_params(params)), _ptr(U_s), _ptr(cs), _ptr(fp), _ptr(f),
+                      _ptr(A2))
     if rc != 0:
         raise ValueError(f"orc_drag failed ({rc})")
     return f
@@ -225,11 +238,12 @@ def spread(mesh: Mesh, beams: dict, f) -> dict:
     return out
 
 
-def step(mesh: Mesh, U, beams: dict, params: dict, f_prev=None) -> dict:
-    """One coupling step (Algorithm 1, steps 2-5 and 7-8)."""
+def step(mesh: Mesh, U, beams: dict, params: dict, f_prev=None, dUdt=None) -> dict:
+    """One coupling step: sampling, line force, projection (Sec. 3.2)."""
     lib = _load()
     b = _BeamArgs(beams)
     U = _f64(U, (-1, 3))
+    A2 = None if dUdt is None else _f64(dUdt, (-1, 3))
     n = b.n_points
     fp = None if f_prev is None else _f64(f_prev, (-1, 3))
     out = {"U_s": np.zeros((n, 3)), "P_s": np.zeros((n, 3)), "cell_a": np.zeros(n, np.int64),
@@ -238,7 +252,8 @@ def step(mesh: Mesh, U, beams: dict, params: dict, f_prev=None) -> dict:
     d = _Diag()
     rc = lib.orc_step(mesh._h, _ptr(U), ct.byref(b.s), ct.byref(_params(params)), _ptr(fp),
                       _ptr(out["U_s"]), _ptr(out["P_s"]), _ptr(out["cell_a"]), _ptr(out["cell_s"]),
-                      _ptr(out["f"]), _ptr(out["S"]), _ptr(out["w"]), _ptr(out["fhat"]), ct.byref(d))
+                      _ptr(out["f"]), _ptr(out["S"]), _ptr(out["w"]), _ptr(out["fhat"]), ct.byref(d),
+                      _ptr(A2))
     if rc != 0:
         raise ValueError(f"orc_step failed ({rc})")
     out["diag"] = d.as_dict()

@@ -594,3 +594,85 @@ def test_kernel_sample_single_cell_and_empty_reach(oracle_mod):
     rk = oracle_mod.sample(m, Uc, b, params(sample_mode="kernel"))
     rc = oracle_mod.sample(m, Uc, b, params())
     assert np.array_equal(rk["U_s"], rc["U_s"]) and rk["diag"]["n_sample_empty"] == 1
+
+
+# ------------------------------------------------------- Morison inertia --
+# R26: optional eq. (8) term, f_a = rho A (CMt a_rt + CMn a_rn + a_f), with
+# a_r = a_f - a_b (fluid relative to beam) and a_f sampled at P_s.
+
+def _inertia_scene(e_t=(0.0, 0.0, 1.0), a_f=(2.0, 0.0, 0.0), a_b=(0.0, 0.0, 0.0), U=(0.0, 0.0, 0.0),
+                   A=1e-4, CMn=1.0, CMt=0.3):
+    C, V = W.uniform_mesh(16, 16, 16, 0.01)
+    n = 6
+    e = np.asarray(e_t, float) / np.linalg.norm(e_t)
+    P = np.array([0.0805, 0.0795, 0.0405]) + np.outer(np.arange(n) * 0.01, e)
+    b = beams_of([P], eps=[0.02], ls=0.03, tangents=[np.tile(e, (n, 1))])
+    b["A"] = np.full(n, A)
+    b["CMn"] = np.array([CMn])
+    b["CMt"] = np.array([CMt])
+    b["a_b"] = np.tile(np.asarray(a_b, float), (n, 1))
+    Uf = np.tile(np.asarray(U, float), (C.shape[0], 1))
+    dUdt = np.tile(np.asarray(a_f, float), (C.shape[0], 1))
+    return C, V, Uf, dUdt, b
+
+
+def test_inertia_fixed_beam_in_accelerating_flow(oracle_mod):
+    """Fixed beam, still but accelerating fluid across it: the classical
+    inertia force rho A (1 + CMn) a_f (Froude-Krylov plus added mass)."""
+    C, V, U, dUdt, b = _inertia_scene()
+    m = oracle_mod.Mesh(C, V, None, oracle_mod.GRID)
+    r = oracle_mod.step(m, U, b, params(), dUdt=dUdt)
+    expect = 1000.0 * 1e-4 * (1.0 + 1.0) * 2.0
+    assert np.allclose(r["f"], [expect, 0.0, 0.0], rtol=1e-15, atol=1e-18)
+    # without the acceleration field the term is off and nothing moves
+    r0 = oracle_mod.step(m, U, b, params())
+    assert np.all(r0["f"] == 0.0)
+
+
+def test_inertia_accelerating_beam_in_still_fluid(oracle_mod):
+    """A beam accelerating through still fluid feels the added-mass reaction
+    -rho A CMn a_b, opposite to its acceleration."""
+    C, V, U, dUdt, b = _inertia_scene(a_f=(0.0, 0.0, 0.0), a_b=(0.0, 3.0, 0.0))
+    m = oracle_mod.Mesh(C, V, None, oracle_mod.GRID)
+    r = oracle_mod.step(m, U, b, params(), dUdt=dUdt)
+    assert np.allclose(r["f"], [0.0, -1000.0 * 1e-4 * 1.0 * 3.0, 0.0], rtol=1e-15, atol=1e-18)
+
+
+@pytest.mark.parametrize("theta_deg", [30.0, 60.0])
+def test_inertia_inclined_beam_tangential_and_normal(oracle_mod, theta_deg):
+    """Beam at angle theta to the acceleration: the tangential part of a_r
+    takes CMt, the normal part CMn, and a_f adds in full."""
+    th = math.radians(theta_deg)
+    e = (math.cos(th), 0.0, math.sin(th))
+    C, V, U, dUdt, b = _inertia_scene(e_t=e, a_f=(2.0, 0.0, 0.0), CMn=1.1, CMt=0.2)
+    m = oracle_mod.Mesh(C, V, None, oracle_mod.GRID)
+    r = oracle_mod.sample(m, U, b, params(), dUdt=dUdt)
+    f = oracle_mod.drag(b, params(), r["U_s"], r["cell_s"], a_s=r["a_s"])
+    a = np.array([2.0, 0.0, 0.0])
+    ev = np.array(e)
+    at = (a @ ev) * ev
+    expect = 1000.0 * 1e-4 * (0.2 * at + 1.1 * (a - at) + a)
+    ok = r["cell_s"] >= 0
+    assert np.any(ok) and np.allclose(f[ok], expect, rtol=1e-14, atol=1e-16)
+
+
+def test_inertia_adds_to_drag_and_relaxes_with_it(oracle_mod):
+    """The inertia term adds to the eq. (19) drag, and eq. (20) relaxes the
+    sum; the projected force still balances exactly."""
+    C, V, U, dUdt, b = _inertia_scene(U=(0.4, 0.1, 0.0), a_f=(1.5, -0.5, 0.2), a_b=(0.1, 0.2, 0.3))
+    rng = np.random.default_rng(12)
+    U = U + 0.05 * rng.normal(size=U.shape)
+    dUdt = dUdt + 0.1 * rng.normal(size=dUdt.shape)
+    m = oracle_mod.Mesh(C, V, None, oracle_mod.GRID)
+    full = oracle_mod.step(m, U, b, params(), dUdt=dUdt)
+    drag_only = oracle_mod.step(m, U, b, params())
+    s = oracle_mod.sample(m, U, b, params(), dUdt=dUdt)
+    b0 = dict(b)
+    b0["Cdn"] = np.zeros(1)
+    b0["Cdt"] = np.zeros(1)
+    inertia_only = oracle_mod.drag(b0, params(), s["U_s"], s["cell_s"], a_s=s["a_s"])
+    assert np.allclose(full["f"], drag_only["f"] + inertia_only, rtol=1e-14, atol=1e-17)
+    fp = rng.normal(size=full["f"].shape)
+    rel = oracle_mod.step(m, U, b, params(alpha_f=0.4), f_prev=fp, dUdt=dUdt)
+    assert np.allclose(rel["f"], 0.4 * full["f"] + 0.6 * fp, rtol=1e-14, atol=1e-16)
+    assert full["diag"]["cons_rel_err"] <= 1e-14
