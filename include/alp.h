@@ -106,6 +106,17 @@ typedef struct {
   const double *ls;       /* [n_beams] sampling distance l_s (eq. 17) */
   const double *n_p;      /* [n_beams][3] plane normal of eq. (17), unit, or zero = none */
   const double *e_up;     /* [n_beams][3] fallback upstream direction (Sec. 3.2.2) */
+  /* Optional Morison inertia, eq. (8), evaluated by alp_step_batched when A and
+     the case's fluid acceleration dUdt are both given:
+       f_a = rho A (CMt a_rt + CMn a_rn + a_f),  a_r = a_f - a_b
+     (relative acceleration fluid minus beam, as U_r in eq. 16 and 19; the
+     printed a_b - a_f would make the added-mass reaction push a beam along its
+     own acceleration), a_f = dUdt sampled at P_s like U_s, added to the drag
+     before the relaxation of eq. (20).  All NULL: drag only, as in the paper. */
+  const double *A;        /* [n_points] cross-section area, or NULL (no inertia) */
+  const double *CMn;      /* [n_beams] normal added-mass coefficient (required with A) */
+  const double *CMt;      /* [n_beams] tangential added-mass coefficient (required with A) */
+  const double *a_b;      /* [n_points][3] beam acceleration, or NULL = 0 */
 } alp_beams;
 
 typedef struct {
@@ -204,6 +215,7 @@ typedef struct {
   double *P_s;          /* DEVICE out [n_points][3] or NULL */
   int64_t *cell_a;      /* DEVICE out [n_points] cell of P_a (-1 outside) or NULL */
   int64_t *cell_s;      /* DEVICE out [n_points] cell of P_s (-1 outside) or NULL */
+  const double *dUdt;   /* DEVICE [n_cells][3] fluid acceleration (eq. 8), or NULL */
 } alp_case;
 
 #define ALP_USE_GRAPH 1u /* capture the step on the first call, replay it afterwards */

@@ -39,7 +39,8 @@ class alp_beams(ct.Structure):
                 ("offsets", ct.c_void_p), ("P", ct.c_void_p), ("P_spread", ct.c_void_p),
                 ("e_t", ct.c_void_p), ("Pdot", ct.c_void_p), ("d", ct.c_void_p), ("L", ct.c_void_p),
                 ("eps", ct.c_void_p), ("Cdn", ct.c_void_p), ("Cdt", ct.c_void_p), ("ls", ct.c_void_p),
-                ("n_p", ct.c_void_p), ("e_up", ct.c_void_p)]
+                ("n_p", ct.c_void_p), ("e_up", ct.c_void_p), ("A", ct.c_void_p), ("CMn", ct.c_void_p),
+                ("CMt", ct.c_void_p), ("a_b", ct.c_void_p)]
 
 
 class alp_params(ct.Structure):
@@ -66,7 +67,7 @@ class alp_case(ct.Structure):
     _fields_ = [("mesh", ct.c_void_p), ("U", ct.c_void_p), ("beams", alp_beams),
                 ("params", alp_params), ("f_prev", ct.c_void_p), ("f", ct.c_void_p),
                 ("S", ct.c_void_p), ("U_s", ct.c_void_p), ("w", ct.c_void_p), ("P_s", ct.c_void_p),
-                ("cell_a", ct.c_void_p), ("cell_s", ct.c_void_p)]
+                ("cell_a", ct.c_void_p), ("cell_s", ct.c_void_p), ("dUdt", ct.c_void_p)]
 
 
 _lib = None
@@ -224,8 +225,9 @@ class DeviceBeams:
         self.offsets = torch.as_tensor(np.ascontiguousarray(beams["offsets"], dtype=np.int64), device=device)
         self.t = {k: f64(beams[k]) for k in ("P", "e_t", "Pdot", "d", "L", "eps", "Cdn", "Cdt", "ls",
                                                "n_p", "e_up")}
-        ps = beams.get("P_spread")
-        self.t["P_spread"] = None if ps is None else f64(ps)
+        for k in ("P_spread", "A", "CMn", "CMt", "a_b"):  # optional
+            v = beams.get(k)
+            self.t[k] = None if v is None else f64(v)
         self.n_beams = int(self.offsets.shape[0] - 1)
         self.n_points = int(self.t["P"].shape[0])
         self.struct = self.make_struct()
@@ -235,7 +237,8 @@ class DeviceBeams:
         return alp_beams(self.n_beams, 0, self.n_points, _ptr(self.offsets), _ptr(t["P"]),
                          _ptr(t["P_spread"]), _ptr(t["e_t"]), _ptr(t["Pdot"]), _ptr(t["d"]),
                          _ptr(t["L"]), _ptr(t["eps"]), _ptr(t["Cdn"]), _ptr(t["Cdt"]), _ptr(t["ls"]),
-                         _ptr(t["n_p"]), _ptr(t["e_up"]))
+                         _ptr(t["n_p"]), _ptr(t["e_up"]), _ptr(t["A"]), _ptr(t["CMn"]), _ptr(t["CMt"]),
+                         _ptr(t["a_b"]))
 
 
 def make_params(params: dict, prec=PREC_FP64):

@@ -171,6 +171,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(fhat, 3 * P);
   WALLOC(Us, 3 * P);
   WALLOC(Ps, 3 * P);
+  WALLOC(As, 3 * P);
   WALLOC(f, 3 * P);
   WALLOC(bcase, B);
   WALLOC(beps_max, B);
@@ -259,6 +260,8 @@ alp_status check_beams(alp_context *ctx, const alp_beams *b, bool need_spread_fi
   }
   if (b->n_beams > 0 && (!b->Cdn || !b->Cdt || !b->ls || !b->n_p || !b->e_up))
     return fail(ctx, ALP_ERR_INVALID_ARG, "a per-beam array is NULL");
+  if (b->A && b->n_beams > 0 && (!b->CMn || !b->CMt))
+    return fail(ctx, ALP_ERR_INVALID_ARG, "beams.A needs beams.CMn and beams.CMt");
   (void)need_spread_fields;
   (void)need_sample_fields;
   if (copy_offsets && b->n_beams > 0) {
@@ -318,6 +321,10 @@ void fill_case(CaseDev &c, const alp_mesh *m, const alp_beams *b, const alp_para
   c.ls = b->ls;
   c.n_p = b->n_p;
   c.e_up = b->e_up;
+  c.A = b->A;
+  c.CMn = b->CMn;
+  c.CMt = b->CMt;
+  c.a_b = b->a_b;
   if (m) c.tile_prev = m->tile_prev;
 }
 
@@ -844,6 +851,7 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
     cs[i].P_s = c.P_s;
     cs[i].cell_a = c.cell_a;
     cs[i].cell_s = c.cell_s;
+    cs[i].dUdt = c.dUdt;
     cs[i].write_S = 1;
     meshes[i] = m;
     S[i] = c.S;

@@ -48,6 +48,8 @@ struct CaseDev {
   double rho, alpha_f, tau;
   const int64_t *offsets;
   const double *P, *Psp, *e_t, *Pdot, *d, *L, *eps, *Cdn, *Cdt, *ls, *n_p, *e_up;
+  const double *A, *CMn, *CMt, *a_b;  // Morison inertia (A == nullptr: none)
+  const double *dUdt;                  // fluid acceleration field, or nullptr
   const double *U;
   const double *f_prev;
   double *S, *f, *U_s, *P_s, *w, *fhat;
@@ -107,6 +109,7 @@ struct Work {
   double *fhat;         // [N_P][3]
   double *Us;           // [N_P][3] internal sampled velocity
   double *Ps;           // [N_P][3] internal sampling point
+  double *As;           // [N_P][3] fluid acceleration sampled at P_s (eq. 8)
   double *f;            // [N_P][3] internal force (when the case has none)
   // beams (global)
   int32_t *bcase;       // beam -> case

@@ -684,7 +684,7 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
     const double *Pa = cs.P + 3 * k, *Pd = cs.Pdot + 3 * k, *et = cs.e_t + 3 * k;
     double nrm = sqrt(dot3_exact(et[0], et[1], et[2], et[0], et[1], et[2]));
     double e[3] = {et[0] / nrm, et[1] / nrm, et[2] / nrm};
-    double ps[3] = {Pa[0], Pa[1], Pa[2]}, us[3] = {0.0, 0.0, 0.0};
+    double ps[3] = {Pa[0], Pa[1], Pa[2]}, us[3] = {0.0, 0.0, 0.0}, as[3] = {0.0, 0.0, 0.0};
     int64_t ca = locate_group(m, Pa[0], Pa[1], Pa[2], sub), cs_ = -1;
     if (ca < 0) {
       out = true;
@@ -726,12 +726,21 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
         us[0] = Us[0];
         us[1] = Us[1];
         us[2] = Us[2];
+        if (cs.dUdt) {
+          const double *As = cs.dUdt + 3 * (int64_t)m.perm[cs_];
+          as[0] = As[0];
+          as[1] = As[1];
+          as[2] = As[2];
+        }
       }
     }
     if (sub == 0) {
       W.Ps[3 * g] = ps[0];
       W.Ps[3 * g + 1] = ps[1];
       W.Ps[3 * g + 2] = ps[2];
+      W.As[3 * g] = as[0];
+      W.As[3 * g + 1] = as[1];
+      W.As[3 * g + 2] = as[2];
       W.Us[3 * g] = us[0];
       W.Us[3 * g + 1] = us[1];
       W.Us[3 * g + 2] = us[2];
@@ -797,7 +806,8 @@ __global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
       lo[a] = !(f0 > 0.0) ? 0 : (f0 > (double)(m.nb[a] - 1) ? m.nb[a] - 1 : (int)f0);
       hi[a] = !(f1 > 0.0) ? 0 : (f1 > (double)(m.nb[a] - 1) ? m.nb[a] - 1 : (int)f1);
     }
-    double den = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0;
+    double den = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    const bool acc = cs.dUdt != nullptr;
     if (ok) {
       const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
       const int64_t total = (int64_t)nx * ny * nz;
@@ -815,6 +825,12 @@ __global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
           n0 += gw * Uj[0];
           n1 += gw * Uj[1];
           n2 += gw * Uj[2];
+          if (acc) {
+            const double *Aj = cs.dUdt + 3 * (int64_t)m.perm[j];
+            m0 += gw * Aj[0];
+            m1 += gw * Aj[1];
+            m2 += gw * Aj[2];
+          }
         }
       }
     }
@@ -822,10 +838,20 @@ __global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
     n0 = wave_sum_f64(n0);
     n1 = wave_sum_f64(n1);
     n2 = wave_sum_f64(n2);
+    if (acc) {
+      m0 = wave_sum_f64(m0);
+      m1 = wave_sum_f64(m1);
+      m2 = wave_sum_f64(m2);
+    }
     if (lane == 0) {
       if (den > 0.0) {
         const double us[3] = {n0 / den, n1 / den, n2 / den};
         for (int a = 0; a < 3; ++a) W.Us[3 * g + a] = us[a];
+        if (acc) {
+          W.As[3 * g] = m0 / den;
+          W.As[3 * g + 1] = m1 / den;
+          W.As[3 * g + 2] = m2 / den;
+        }
         if (cs.U_s)
           for (int a = 0; a < 3; ++a) cs.U_s[3 * k + a] = us[a];
       } else {
@@ -872,6 +898,18 @@ __global__ void k_drag(StepLaunch L, int use_cell_s) {
     } else {
       double mr = sqrt(dot3_exact(ur[0], ur[1], ur[2], ur[0], ur[1], ur[2]));
       for (int a = 0; a < 3; ++a) fs[a] = half * mr * (cdn * un[a] + cdt * ut[a]);
+    }
+    if (cs.A && cs.dUdt && !use_cell_s) {
+      // eq. (8) with the relative acceleration fluid minus beam
+      const double *af = W.As + 3 * g;
+      double ar[3];
+      for (int a = 0; a < 3; ++a) ar[a] = af[a] - (cs.a_b ? cs.a_b[3 * k + a] : 0.0);
+      const double ta = dot3_exact(ar[0], ar[1], ar[2], e[0], e[1], e[2]);
+      const double ra = cs.rho * cs.A[k], cmn = cs.CMn[b], cmt = cs.CMt[b];
+      for (int a = 0; a < 3; ++a) {
+        const double art = ta * e[a], arn = ar[a] - art;
+        fs[a] += ra * ((cmt * art + cmn * arn) + af[a]);
+      }
     }
   }
   double *f = cs.f ? cs.f + 3 * k : W.f + 3 * g;

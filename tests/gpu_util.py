@@ -48,13 +48,14 @@ class GpuCase:
         self.cell_a = torch.zeros(npnt, dtype=torch.int64, device="cuda")
         self.cell_s = torch.zeros(npnt, dtype=torch.int64, device="cuda")
         self.f_prev = None if f_prev is None else dev(f_prev)
+        self.dUdt = None if wl.get("dUdt") is None else dev(wl["dUdt"])
 
     def case_struct(self):
         return alp.alp_case(self.mesh, self.U.data_ptr(), self.beams.struct, self.params,
                             None if self.f_prev is None else self.f_prev.data_ptr(),
                             self.f.data_ptr(), self.S.data_ptr(), self.U_s.data_ptr(),
                             self.w.data_ptr(), self.P_s.data_ptr(), self.cell_a.data_ptr(),
-                            self.cell_s.data_ptr())
+                            self.cell_s.data_ptr(), None if self.dUdt is None else self.dUdt.data_ptr())
 
     def step_unbatched(self):
         h = self.ctx.h
@@ -78,7 +79,7 @@ def step_batched(ctx: alp.Context, cases, flags=0):
 def oracle_step(wl, f_prev=None):
     from oracle import oracle
     m = oracle.Mesh(wl["C"], wl["V"], wl.get("box"), oracle.GRID)
-    return oracle.step(m, wl["U"], wl["beams"], wl["params"], f_prev=f_prev)
+    return oracle.step(m, wl["U"], wl["beams"], wl["params"], f_prev=f_prev, dUdt=wl.get("dUdt"))
 
 
 def normwise(a, b):

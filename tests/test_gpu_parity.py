@@ -360,3 +360,29 @@ def test_kernel_weighted_sampling(gu, ctx, prec):
         _, _, ref, diag = run_and_compare(gu, ctx, wl, prec, batched=batched, tol_us=1e-12)
         gu.log(f"[parity]   kernel sampling: empty reach {diag['n_sample_empty']}")
     assert ref["diag"]["n_sample_empty"] > 0
+
+
+def with_inertia(wl, seed):
+    """The scene plus a fluid acceleration field and the eq. (8) inputs."""
+    rng = np.random.default_rng(seed)
+    b = wl["beams"]
+    n, nb = b["P"].shape[0], len(b["offsets"]) - 1
+    b["A"] = rng.uniform(1e-6, 2e-5, n)
+    b["CMn"] = rng.uniform(0.5, 1.5, nb)
+    b["CMt"] = rng.uniform(0.0, 0.3, nb)
+    b["a_b"] = 0.3 * rng.normal(size=(n, 3))
+    wl["dUdt"] = np.tile([0.8, -0.2, 0.1], (wl["C"].shape[0], 1)) + 0.4 * rng.normal(size=wl["C"].shape)
+    return wl
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_morison_inertia(gu, ctx, prec):
+    """The optional eq. (8) term (R26) against the oracle: cell and kernel
+    sampling of the fluid acceleration, with relaxation."""
+    wl = with_inertia(random_scene(13, outside=True), 1)
+    run_and_compare(gu, ctx, wl, prec)
+    wl = with_inertia(random_scene(14), 2)
+    wl["params"]["sample_mode"] = "kernel"
+    wl["params"]["alpha_f"] = 0.6
+    fp = np.random.default_rng(5).normal(size=wl["beams"]["P"].shape)
+    run_and_compare(gu, ctx, wl, prec, f_prev=fp, tol_us=1e-12)
