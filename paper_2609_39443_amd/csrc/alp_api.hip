@@ -54,6 +54,7 @@ struct alp_context {
   std::vector<alp_case> gkey;
   uint32_t gflags = 0;
   int last_cases = 0;
+  int any_kernel_sample = 0;  // some case of the uploaded batch samples with the kernel
 };
 
 namespace {
@@ -202,12 +203,12 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(pblock_range, 2 * PB);
   WALLOC(cnt, 8 * NC);
   WALLOC(diag_out, 16 * NC);
-  WALLOC(counters, 16);
+  WALLOC(counters, 32);
 #undef WALLOC
   int64_t sc = scan_tmp_words(std::max({B + 1, T + 1, CH + 1, (int64_t)1}));
   if ((rc = dalloc(ctx, &ctx->scan_tmp, sc)) != ALP_OK) return rc;
   ctx->have_scan = sc;
-  HIPCHK(ctx, hipMemsetAsync(w.counters, 0, 16 * sizeof(uint32_t), ctx->st));
+  HIPCHK(ctx, hipMemsetAsync(w.counters, 0, 32 * sizeof(uint32_t), ctx->st));
   HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, 8 * NC * sizeof(long long), ctx->st));
   HIPCHK(ctx, hipMemsetAsync(w.diag_out, 0, 16 * NC * sizeof(double), ctx->st));
   w.cap_emit = EM;
@@ -371,6 +372,9 @@ StepShape shape_cases(alp_context *ctx, std::vector<CaseDev> &cs) {
 
 alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const StepShape &sh) {
   alp_status rc;
+  ctx->any_kernel_sample = 0;
+  for (const CaseDev &c : cs)
+    if (c.sample_mode == ALP_SAMPLE_KERNEL) ctx->any_kernel_sample = 1;
   if ((rc = ensure_cases(ctx, (int)cs.size())) != ALP_OK) return rc;
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_cases, cs.data(), cs.size() * sizeof(CaseDev),
                              hipMemcpyHostToDevice, ctx->st));
@@ -396,6 +400,7 @@ StepLaunch make_launch(alp_context *ctx, int n_cases) {
   L.w = ctx->w;
   L.n_cases = n_cases;
   L.grid_persistent = ctx->n_cu * 8;
+  L.kernel_sample = ctx->any_kernel_sample;
   return L;
 }
 

@@ -144,7 +144,7 @@ struct Work {
   long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, empty kernel sample
   double *diag_out;     // [n_cases][16] finalised diagnostics
   // scalars
-  uint32_t *counters;   // [16]: 3 overflow flags
+  uint32_t *counters;   // [32]: 3 overflow flags, 8-15 weights work queue
   int64_t cap_emit, cap_item, cap_rec, cap_chunk;
   int64_t n_points, n_beams, n_tiles;
   int32_t n_cases, n_pblocks;
@@ -294,6 +294,7 @@ struct StepLaunch {
   Work w;
   int n_cases;
   int grid_persistent;     // blocks for persistent wave kernels
+  int kernel_sample;       // some case uses ALP_SAMPLE_KERNEL
 };
 void launch_step_reset(const StepLaunch &L, hipStream_t st);
 void launch_step_reset_sample(const StepLaunch &L, hipStream_t st);

@@ -53,6 +53,51 @@ __device__ __forceinline__ void wave_count_add(long long *dst, bool pred) {
 
 __device__ __forceinline__ void set_overflow(Work &W, uint32_t bit) { atomicOr(&W.counters[3], bit); }
 
+// Dynamic work distribution for a persistent kernel: work items are cut into
+// chunks of `grab` consecutive items.  A wave's first chunk is its block index
+// (no atomic, so idle waves of a small step leave at once); later chunks come
+// from one of 8 counters (block index mod 8, so the counters share the load):
+// chunk G + 8 q + x for the q-th grab on counter x, G the grid size.  The
+// counters start at zero every step; a wave leaves once a chunk past the end
+// comes back.
+struct WorkQueue {
+  uint32_t *ctr;  // [8]
+  uint32_t n, grab, x, item, end;
+  bool started;
+  __device__ bool next(int lane) {
+    if (item + 1 < end) {
+      ++item;
+      return true;
+    }
+    uint64_t chunk;
+    if (!started) {
+      started = true;
+      chunk = blockIdx.x;
+    } else {
+      uint32_t q = 0;
+      if (lane == 0) q = atomicAdd(&ctr[x], 1u);
+      q = __shfl(q, 0, 64);
+      chunk = (uint64_t)gridDim.x + (uint64_t)q * 8u + x;
+    }
+    const uint64_t first = chunk * grab;
+    if (first >= n) return false;
+    item = (uint32_t)first;
+    end = (uint32_t)min((uint64_t)n, first + grab);
+    return true;
+  }
+};
+__device__ __forceinline__ WorkQueue work_queue(uint32_t *ctr, uint32_t n, uint32_t grab) {
+  WorkQueue q;
+  q.ctr = ctr;
+  q.n = n;
+  q.grab = grab;
+  q.x = blockIdx.x & 7u;
+  q.item = 0;
+  q.end = 0;
+  q.started = false;
+  return q;
+}
+
 __device__ __forceinline__ void tile_origin(const MeshDev &m, int64_t tl, double &ox, double &oy,
                                             double &oz) {
   // tile counts are below 2^32 (bin keys are 32-bit)
@@ -77,7 +122,7 @@ __global__ void k_step_reset(StepLaunch L, int what) {
   Work W = L.w;
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (tid < 16 && (what & RESET_PROJECT)) W.counters[tid] = 0;
+  if (tid < 32 && (what & RESET_PROJECT)) W.counters[tid] = 0;
   if (tid == 0 && (what & RESET_PROJECT)) *W.rec_alloc = 0;
   for (int64_t c = tid; c < (int64_t)L.n_cases * 8; c += stride) {
     int k = (int)(c & 7);
@@ -862,7 +907,7 @@ __global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
 }
 
 void launch_sample_kernel(const StepLaunch &L, hipStream_t st) {
-  if (L.w.n_points == 0) return;
+  if (L.w.n_points == 0 || !L.kernel_sample) return;
   const int64_t g = L.w.n_points < (int64_t)L.grid_persistent * 4 ? L.w.n_points : (int64_t)L.grid_persistent * 4;
   hipLaunchKernelGGL(k_sample_kernel, dim3((unsigned)g), dim3(64), 0, st, L);
 }
@@ -1004,14 +1049,10 @@ void k_weights(StepLaunch L) {
   unsigned long long blk_cur = 0, blk_end = 0;
   int acc_case = -1;
   unsigned long long acc_pairs = 0;
-  const uint32_t stride = gridDim.x;
-  uint32_t item = blockIdx.x;
-  Item nxt;
-  if (item < n_items && (int64_t)item < W.cap_item) nxt = W.item[item];
-  for (; item < n_items && (int64_t)item < W.cap_item; item += stride) {
-    const Item it = nxt;
-    // the next item's descriptor is fetched while this one runs
-    if (item + stride < n_items && (int64_t)(item + stride) < W.cap_item) nxt = W.item[item + stride];
+  WorkQueue wq = work_queue(W.counters + 8, (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
+  while (wq.next(lane)) {
+    const uint32_t item = wq.item;
+    const Item it = W.item[item];
     if (it.cs != acc_case) {
       if (lane == 0 && acc_case >= 0 && acc_pairs)
         atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
