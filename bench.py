@@ -18,7 +18,6 @@ sample.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -59,15 +58,6 @@ def log(msg):
     sys.stderr.flush()
 
 
-def source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2609_39443_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, fn), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(kernel, n_cells, n_stems):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, if it was taken on the current sources and this workload."""
@@ -78,6 +68,7 @@ def traffic_from_profiles(kernel, n_cells, n_stems):
         t = json.load(open(p))
     except Exception:
         return None
+    from paper_2609_39443_amd.profsum import source_hash
     if t.get("source_hash") != source_hash() or t.get("n_cells") != n_cells or t.get("stems") != n_stems:
         return None
     k = t.get("kernels", {}).get(kernel)
