@@ -50,6 +50,21 @@
  *       and 19; the printed a_b - a_f would make the added-mass reaction push a
  *       beam along its own acceleration), a_f the fluid acceleration sampled at
  *       P_s by the same operator as U_s.
+ *   R27 optional segment-integrated projection (the projection change the
+ *       conclusions name for removing the seams of the nearest-segment rule):
+ *       a cell takes a contribution from EVERY segment i of a beam whose
+ *       closed segment lies within 3 eps_seg of it (inclusive, R10's test on
+ *       the squared distance of eq. 21's clamped foot), eps_seg = (eps_i +
+ *       eps_{i+1}) / 2, with the 3D Gaussian
+ *       g(x) = exp(-|x|^2/eps^2) / (pi^{3/2} eps^3) integrated along the
+ *       segment against the linear weights of Sec. 3.2.4:
+ *         a_{j,i}   = int_0^l (1 - u/l) g(C_j - P(u)) du,
+ *         a_{j,i+1} = int_0^l (u/l)     g(C_j - P(u)) du,
+ *       l the segment length.  Along an infinite straight line the sum over
+ *       segments is the 2D kernel of eq. (22) at the radial distance.  A
+ *       zero-length segment contributes nothing; a single-CV beam keeps the
+ *       point kernel of R14.  Normalisation and eq. (23) are unchanged, with
+ *       one pair per (cell, segment).
  *   R25 optional kernel-weighted sampling (the volume-average sampling the
  *       conclusions name as future work): U_s = sum_j g_j V_j U_j /
  *       sum_j g_j V_j over the cells with |C_j - P_s|^2 <= 9 eps_k^2,
@@ -72,6 +87,7 @@
 enum { ORC_BRUTE = 0, ORC_GRID = 1 };
 enum { ORC_FULLMAG = 0, ORC_COMPONENTWISE = 1 };
 enum { ORC_SAMPLE_CELL = 0, ORC_SAMPLE_KERNEL = 1 };
+enum { ORC_PROJ_NEAREST = 0, ORC_PROJ_INTEGRATED = 1 };
 
 /* point flags written by orc_sample */
 #define ORC_F_OUTSIDE 1
@@ -106,6 +122,7 @@ typedef struct {
   double rho, alpha_f, tau;
   int32_t drag_form;
   int32_t sample_mode; /* ORC_SAMPLE_CELL (eq. 18) or ORC_SAMPLE_KERNEL (R25) */
+  int32_t proj_mode;   /* ORC_PROJ_NEAREST (eq. 21-23) or ORC_PROJ_INTEGRATED (R27) */
 } orc_params;
 
 typedef struct {
@@ -530,6 +547,22 @@ int orc_drag(const orc_beams *b, const orc_params *p, const double *U_s,
 }
 
 /* ------------------------------------------------------ nearest segment -- */
+/* Foot of the perpendicular from c onto the segment [A, B] with its
+   parameter clamped to [0, 1] (eq. 21, R9, R19): returns s and r^2. */
+static void seg_foot(const double *A, const double *B, const double *c, double *s_out, double *r2_out) {
+  double e[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+  double q0[3] = {c[0] - A[0], c[1] - A[1], c[2] - A[2]};
+  double t = dot3(q0, e), ee = dot3(e, e), s = 0.0;
+  if (ee > 0.0) {
+    s = t / ee;
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+  }
+  double q[3] = {q0[0] - s * e[0], q0[1] - s * e[1], q0[2] - s * e[2]};
+  *s_out = s;
+  *r2_out = dot3(q, q);
+}
+
 /* Eq. (21): closest segment of the polyline X[0..n-1] to the point c; returns
    the segment index, the foot parameter s and r^2 (R8, R9, R14, R19). */
 int64_t orc_nearest_segment(int64_t n, const double *X, const double *c, double *s_out, double *r2_out) {
@@ -541,22 +574,124 @@ int64_t orc_nearest_segment(int64_t n, const double *X, const double *c, double 
   int64_t bi = -1;
   double best = INFINITY, bs = 0.0;
   for (int64_t i = 0; i + 1 < n; ++i) {
-    const double *A = X + 3 * i, *B = X + 3 * (i + 1);
-    double e[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
-    double q0[3] = {c[0] - A[0], c[1] - A[1], c[2] - A[2]};
-    double t = dot3(q0, e), ee = dot3(e, e), s = 0.0;
-    if (ee > 0.0) {
-      s = t / ee;
-      if (s < 0.0) s = 0.0;
-      if (s > 1.0) s = 1.0;
-    }
-    double q[3] = {q0[0] - s * e[0], q0[1] - s * e[1], q0[2] - s * e[2]};
-    double r2 = dot3(q, q);
+    double s, r2;
+    seg_foot(X + 3 * i, X + 3 * (i + 1), c, &s, &r2);
     if (bi < 0 || r2 < best) { best = r2; bi = i; bs = s; }
   }
   *s_out = bs;
   *r2_out = best;
   return bi;
+}
+
+/* -------------------------------------------- segment-integrated kernel -- */
+/* erf(a) - erf(b) for a >= b, through erfc on the side where both arguments
+   share a sign, so that two values close to +-1 are never subtracted. */
+static double erf_diff(double a, double b) {
+  if (b >= 0.0) return erfc(b) - erfc(a);
+  if (a <= 0.0) return erfc(-a) - erfc(-b);
+  return erf(a) - erf(b);
+}
+
+/* exp(-x0^2) - exp(-x1^2), factoring out the larger exponential and taking
+   the remaining difference with expm1; d = x1^2 - x0^2. */
+static double exp_diff(double x0, double x1) {
+  double d = (x1 - x0) * (x1 + x0);
+  if (d >= 0.0) return -exp(-(x0 * x0)) * expm1(-d);
+  return exp(-(x1 * x1)) * expm1(d);
+}
+
+/* Nodes and weights of 8-point Gauss-Legendre quadrature on [0, 1]: the roots
+   of the Legendre polynomial P_8 by Newton's method from the Chebyshev
+   estimates cos(pi (k - 1/4) / (n + 1/2)), weights 2 / ((1 - x^2) P_8'(x)^2),
+   mapped from [-1, 1]. */
+#define ORC_GL 8
+static double gl_s[ORC_GL], gl_w[ORC_GL];
+static int gl_ready = 0;
+static void gl_init(void) {
+  if (gl_ready) return;
+  for (int k = 1; k <= ORC_GL; ++k) {
+    double x = cos(M_PI * (k - 0.25) / (ORC_GL + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int n = 2; n <= ORC_GL; ++n) {
+        double p2 = ((2 * n - 1) * x * p1 - (n - 1) * p0) / n;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = ORC_GL * (x * p1 - p0) / (x * x - 1.0);
+      double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-17) break;
+    }
+    gl_s[k - 1] = 0.5 * (1.0 - x);
+    gl_w[k - 1] = 1.0 / ((1.0 - x * x) * dp * dp);
+  }
+  gl_ready = 1;
+}
+
+/* R27: weights a0 (node i) and a1 (node i+1) of the 3D Gaussian integrated
+   along the segment [A, B] (length l > 0) against the linear weights.  With the
+   unclamped foot F = A + tau (B - A), the radial distance r_p = |c - F| and
+   the axial position t = tau l, the integrand factors as
+   exp(-r_p^2/eps^2) exp(-(u - t)^2/eps^2); in x = (u - t)/eps,
+   x0 = -t/eps, x1 = (l - t)/eps, lambda = l/eps,
+     a0 = Q (x1 E - M) / lambda,   a1 = Q (M - x0 E) / lambda,
+     E = int e^{-x^2} dx = (sqrt(pi)/2)(erf x1 - erf x0),
+     M = int x e^{-x^2} dx = (e^{-x0^2} - e^{-x1^2}) / 2,
+     Q = exp(-r_p^2/eps^2) / (pi^{3/2} eps^2).
+   For lambda < 1/8 the two bracketed terms nearly cancel; there the integral
+   is taken by 8-point Gauss-Legendre quadrature in s = u/l, exact to rounding
+   at that length (its error term is below 1e-25 of the integrand scale). */
+static void seg_integrated_weights(const double *c, const double *A, const double *B, double eps,
+                                   double *a0, double *a1) {
+  double e[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+  double q[3] = {c[0] - A[0], c[1] - A[1], c[2] - A[2]};
+  double ee = dot3(e, e), l = sqrt(ee);
+  double tau = dot3(q, e) / ee;
+  double p[3] = {q[0] - tau * e[0], q[1] - tau * e[1], q[2] - tau * e[2]};
+  double rp2 = dot3(p, p), t = tau * l;
+  double x0 = -t / eps, x1 = (l - t) / eps, lam = l / eps;
+  double Q = exp(-(rp2 / (eps * eps))) / (M_PI * sqrt(M_PI) * (eps * eps));
+  double W0, W1;
+  if (lam < 0.125) {
+    gl_init();
+    W0 = 0.0;
+    W1 = 0.0;
+    for (int k = 0; k < ORC_GL; ++k) {
+      double y = gl_s[k] * lam + x0, g = gl_w[k] * exp(-(y * y));
+      W0 += (1.0 - gl_s[k]) * g;
+      W1 += gl_s[k] * g;
+    }
+    W0 *= lam;
+    W1 *= lam;
+  } else {
+    double E = 0.5 * sqrt(M_PI) * erf_diff(x1, x0), M = 0.5 * exp_diff(x0, x1);
+    W0 = (x1 * E - M) / lam;
+    W1 = (M - x0 * E) / lam;
+  }
+  *a0 = Q * W0;
+  *a1 = Q * W1;
+}
+
+/* exported for the pins: R27 weights of one (cell, segment) pair, whether
+   the pair is inside the cutoff (1) or not (0) */
+int orc_seg_weights(const double *c, const double *A, const double *B, double eps_a, double eps_b,
+                    double *a0, double *a1) {
+  double s, r2, es = 0.5 * (eps_a + eps_b);
+  double e[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+  *a0 = 0.0;
+  *a1 = 0.0;
+  if (!(dot3(e, e) > 0.0)) return 0;
+  seg_foot(A, B, c, &s, &r2);
+  if (!(r2 <= 9.0 * (es * es))) return 0;
+  seg_integrated_weights(c, A, B, es, a0, a1);
+  return 1;
+}
+
+int orc_gl_nodes(double *s, double *w) {
+  gl_init();
+  for (int k = 0; k < ORC_GL; ++k) { s[k] = gl_s[k]; w[k] = gl_w[k]; }
+  return ORC_GL;
 }
 
 /* ------------------------------------------------------------- spread -- */
@@ -628,11 +763,12 @@ static int64_t *beam_candidates(const orc_mesh *m, int64_t nb, const double *X, 
 
 /* Sec. 3.2.4 and eq. (21)-(23): nodal weights w, normalised forces f_hat and
    the momentum source S (force per unit volume on the fluid), plus the
-   action-reaction check of eq. (14).  pair_cell/pair_node/pair_a (optional,
-   capacity max_pairs) receive the (cell, beam) pairs for inspection. */
+   action-reaction check of eq. (14).  proj_mode selects the nearest-segment
+   rule of eq. (21) or the segment-integrated kernel of R27. */
 int orc_spread(const orc_mesh *m, const orc_beams *b, const double *f, double *S, double *w,
-               double *fhat, orc_diag *diag) {
+               double *fhat, orc_diag *diag, int32_t proj_mode) {
   if (!m || !beams_valid(b) || !f || !S) return ORC_EINVAL;
+  if (proj_mode != ORC_PROJ_NEAREST && proj_mode != ORC_PROJ_INTEGRATED) return ORC_EINVAL;
   const double *X = b->P_spread ? b->P_spread : b->P;
   int64_t np = b->n_points;
   nsum *wacc = (nsum *)calloc((size_t)(np > 0 ? np : 1), sizeof(nsum));
@@ -643,14 +779,32 @@ int orc_spread(const orc_mesh *m, const orc_beams *b, const double *f, double *S
   int rc = ORC_OK;
   if (!wacc || !sacc || !band || !fh) { rc = ORC_ENOMEM; goto done; }
 
-  /* steps 7-9: per beam, per cell -- closest segment, kernel, weights */
+  /* per beam, per cell: the segment(s) within reach, the kernel, the weights */
   for (int32_t bi = 0; bi < b->n_beams && rc == ORC_OK; ++bi) {
     int64_t k0 = b->offsets[bi], nb = b->offsets[bi + 1] - k0;
     if (nb == 0) continue;
     int64_t ncand = 0;
     int64_t *cand = beam_candidates(m, nb, X + 3 * k0, b->eps + k0, &ncand);
     if (!cand) { rc = ORC_ENOMEM; break; }
-    for (int64_t t = 0; t < ncand; ++t) {
+    for (int64_t t = 0; t < ncand && proj_mode == ORC_PROJ_INTEGRATED && nb >= 2; ++t) {
+      /* R27: every segment within the cutoff, in segment order */
+      int64_t j = cand[t];
+      for (int64_t i = 0; i + 1 < nb; ++i) {
+        double a0, a1;
+        if (!orc_seg_weights(m->C + 3 * j, X + 3 * (k0 + i), X + 3 * (k0 + i + 1), b->eps[k0 + i],
+                             b->eps[k0 + i + 1], &a0, &a1))
+          continue;
+        pair_t pr;
+        pr.cell = j; pr.node = k0 + i; pr.single = 0;
+        pr.a0 = a0;
+        pr.a1 = a1;
+        ns_add(&wacc[pr.node], pr.a0 * m->V[j]);
+        ns_add(&wacc[pr.node + 1], pr.a1 * m->V[j]);
+        if ((rc = pv_push(&pv, pr)) != ORC_OK) break;
+      }
+      if (rc != ORC_OK) break;
+    }
+    for (int64_t t = 0; t < ncand && (proj_mode == ORC_PROJ_NEAREST || nb == 1); ++t) {
       int64_t j = cand[t];
       double s, r2;
       int64_t i = orc_nearest_segment(nb, X + 3 * k0, m->C + 3 * j, &s, &r2);
@@ -744,7 +898,7 @@ int orc_step(const orc_mesh *m, const double *U, const orc_beams *b, const orc_p
   int rc = orc_sample(m, U, b, p, U_s, P_s, cell_a, cs, NULL, &d1, dUdt, as);
   if (rc == ORC_OK) rc = orc_drag(b, p, U_s, cs, f_prev, f, as);
   free(as);
-  if (rc == ORC_OK) rc = orc_spread(m, b, f, S, w, fhat, &d1);
+  if (rc == ORC_OK) rc = orc_spread(m, b, f, S, w, fhat, &d1, p->proj_mode);
   if (!cell_s) free(cs);
   if (rc == ORC_OK && diag) *diag = d1;
   return rc;

@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 BRUTE, GRID = 0, 1
 FULLMAG, COMPONENTWISE = 0, 1
 SAMPLE_CELL, SAMPLE_KERNEL = 0, 1
+PROJ_NEAREST, PROJ_INTEGRATED = 0, 1
 F_OUTSIDE, F_FALLBACK, F_DEGENERATE = 1, 2, 4
 
 
@@ -50,7 +51,7 @@ class _Beams(ct.Structure):
 
 class _Params(ct.Structure):
     _fields_ = [("rho", ct.c_double), ("alpha_f", ct.c_double), ("tau", ct.c_double),
-                ("drag_form", ct.c_int32), ("sample_mode", ct.c_int32)]
+                ("drag_form", ct.c_int32), ("sample_mode", ct.c_int32), ("proj_mode", ct.c_int32)]
 
 
 class _Diag(ct.Structure):
@@ -87,7 +88,9 @@ def _load():
         lib.orc_sample.argtypes = [vp, vp, ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp,
                                    vp, ct.POINTER(_Diag), vp, vp]
         lib.orc_drag.argtypes = [ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp, vp]
-        lib.orc_spread.argtypes = [vp, ct.POINTER(_Beams), vp, vp, vp, vp, ct.POINTER(_Diag)]
+        lib.orc_spread.argtypes = [vp, ct.POINTER(_Beams), vp, vp, vp, vp, ct.POINTER(_Diag), ct.c_int32]
+        lib.orc_seg_weights.argtypes = [vp, vp, vp, ct.c_double, ct.c_double, vp, vp]
+        lib.orc_gl_nodes.argtypes = [vp, vp]
         lib.orc_step.argtypes = [vp, vp, ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp,
                                  vp, vp, vp, vp, vp, ct.POINTER(_Diag), vp]
         lib.orc_nearest_segment.argtypes = [ct.c_int64, vp, vp, ct.POINTER(ct.c_double),
@@ -185,8 +188,11 @@ def _params(params: dict) -> _Params:
     mode = params.get("sample_mode", SAMPLE_CELL)
     if isinstance(mode, str):
         mode = {"cell": SAMPLE_CELL, "kernel": SAMPLE_KERNEL}[mode]
+    proj = params.get("proj_mode", PROJ_NEAREST)
+    if isinstance(proj, str):
+        proj = {"nearest": PROJ_NEAREST, "integrated": PROJ_INTEGRATED}[proj]
     return _Params(float(params["rho"]), float(params.get("alpha_f", 1.0)),
-                   float(params.get("tau", 1e-6)), int(form), int(mode))
+                   float(params.get("tau", 1e-6)), int(form), int(mode), int(proj))
 
 
 def sample(mesh: Mesh, U, beams: dict, params: dict, dUdt=None) -> dict:
@@ -224,14 +230,16 @@ def drag(beams: dict, params: dict, U_s, cell_s=None, f_prev=None, a_s=None):
     return f
 
 
-def spread(mesh: Mesh, beams: dict, f) -> dict:
+def spread(mesh: Mesh, beams: dict, f, proj_mode=PROJ_NEAREST) -> dict:
     lib = _load()
+    if isinstance(proj_mode, str):
+        proj_mode = {"nearest": PROJ_NEAREST, "integrated": PROJ_INTEGRATED}[proj_mode]
     b = _BeamArgs(beams)
     f = _f64(f, (-1, 3))
     out = {"S": np.zeros((mesh.n, 3)), "w": np.zeros(b.n_points), "fhat": np.zeros((b.n_points, 3))}
     d = _Diag()
     rc = lib.orc_spread(mesh._h, ct.byref(b.s), _ptr(f), _ptr(out["S"]), _ptr(out["w"]),
-                        _ptr(out["fhat"]), ct.byref(d))
+                        _ptr(out["fhat"]), ct.byref(d), int(proj_mode))
     if rc != 0:
         raise ValueError(f"orc_spread failed ({rc})")
     out["diag"] = d.as_dict()
@@ -268,3 +276,22 @@ def nearest_segment(X, c):
     r2 = ct.c_double()
     i = _load().orc_nearest_segment(X.shape[0], _ptr(X), _ptr(c), ct.byref(s), ct.byref(r2))
     return int(i), s.value, r2.value
+
+
+def seg_weights(c, A, B, eps_a, eps_b):
+    """Segment-integrated weights (a0, a1) of one (cell, segment) pair (R27),
+    and whether the pair is inside the cutoff."""
+    c, A, B = (_f64(x, (3,)) for x in (c, A, B))
+    a0 = ct.c_double()
+    a1 = ct.c_double()
+    inside = _load().orc_seg_weights(_ptr(c), _ptr(A), _ptr(B), float(eps_a), float(eps_b),
+                                     ct.byref(a0), ct.byref(a1))
+    return a0.value, a1.value, bool(inside)
+
+
+def gl_nodes():
+    """The oracle's 8-point Gauss-Legendre nodes and weights on [0, 1]."""
+    s = np.zeros(8)
+    w = np.zeros(8)
+    _load().orc_gl_nodes(_ptr(s), _ptr(w))
+    return s, w
