@@ -84,6 +84,23 @@ typedef enum {
                            and counted in alp_diag.n_sample_empty */
 } alp_sample_mode;
 
+typedef enum {
+  ALP_PROJ_NEAREST = 0,   /* eq. (21)-(23): each (cell, beam) pair takes the closest segment's
+                             foot, the 2D Gaussian of eq. (22) at the radial distance and the
+                             linear weights (1 - s, s) */
+  ALP_PROJ_INTEGRATED = 1 /* the segment-integrated kernel proposed in Sec. 8 to remove the
+                             seams of the nearest-segment rule: a cell takes a contribution
+                             from EVERY segment i whose closed segment lies within 3 eps_seg of
+                             it (inclusive, on the squared distance of eq. 21's clamped foot),
+                             eps_seg = (eps_i + eps_i+1)/2, with the 3D Gaussian
+                             exp(-|x|^2/eps^2)/(pi^1.5 eps^3) integrated along the segment
+                             against the linear weights: a_i = int (1 - u/l) g du,
+                             a_i+1 = int (u/l) g du.  Along a straight line the sum over
+                             segments is eq. (22).  Zero-length segments contribute nothing;
+                             single-CV beams keep the point kernel.  The normalisation of
+                             Sec. 3.2.4 and eq. (23) are unchanged (exact balance). */
+} alp_proj_mode;
+
 /* The beam set (Sec. 3.2.2): one actuator point per beam control volume.
    Beams are a CSR over points: beam b owns points offsets[b] .. offsets[b+1]-1,
    ordered along the centreline.  All pointers are DEVICE pointers. */
@@ -126,7 +143,7 @@ typedef struct {
   int32_t prec;    /* alp_precision */
   int32_t drag_form; /* alp_drag_form */
   int32_t sample_mode; /* alp_sample_mode */
-  int32_t reserved1;   /* must be 0 */
+  int32_t proj_mode;   /* alp_proj_mode */
 } alp_params;
 
 /* Diagnostics of the last step of a case (written on the device, read by
@@ -137,7 +154,8 @@ typedef struct {
   int64_t n_fallback_degenerate; /* fallback direction parallel to the tangent: e_s = 0 */
   int64_t n_zero_weight;         /* nodes with w_k = 0 (no load transferred) */
   int64_t n_band_cells;          /* cells that received a source */
-  int64_t n_pairs;               /* (cell, beam) pairs inside the 3 eps cutoff */
+  int64_t n_pairs;               /* pairs inside the 3 eps cutoff: (cell, beam) pairs, or
+                                    (cell, segment) pairs under ALP_PROJ_INTEGRATED */
   int64_t n_overflow;            /* work-list overflow flags (non-zero: results invalid) */
   int64_t n_invalid;             /* points with eps <= 0, a zero tangent or non-finite data */
   double F_beam[3];   /* sum_k f_k L_k  (force on the beam, eq. 14) */

@@ -20,6 +20,7 @@ STATUS = {0: "ALP_OK", -1: "ALP_ERR_INVALID_ARG", -2: "ALP_ERR_HIP", -3: "ALP_ER
 PREC_FP64, PREC_FP32_SPLIT = 0, 1
 DRAG_FULLMAG, DRAG_COMPONENTWISE = 0, 1
 SAMPLE_CELL, SAMPLE_KERNEL = 0, 1
+PROJ_NEAREST, PROJ_INTEGRATED = 0, 1
 USE_GRAPH, CHECKED = 1, 2
 
 # every symbol include/alp.h declares
@@ -46,7 +47,7 @@ class alp_beams(ct.Structure):
 class alp_params(ct.Structure):
     _fields_ = [("rho", ct.c_double), ("alpha_f", ct.c_double), ("tau", ct.c_double),
                 ("prec", ct.c_int32), ("drag_form", ct.c_int32), ("sample_mode", ct.c_int32),
-                ("reserved1", ct.c_int32)]
+                ("proj_mode", ct.c_int32)]
 
 
 class alp_diag(ct.Structure):
@@ -248,8 +249,11 @@ def make_params(params: dict, prec=PREC_FP64):
     mode = params.get("sample_mode", SAMPLE_CELL)
     if isinstance(mode, str):
         mode = {"cell": SAMPLE_CELL, "kernel": SAMPLE_KERNEL}[mode]
+    proj = params.get("proj_mode", PROJ_NEAREST)
+    if isinstance(proj, str):
+        proj = {"nearest": PROJ_NEAREST, "integrated": PROJ_INTEGRATED}[proj]
     return alp_params(float(params["rho"]), float(params.get("alpha_f", 1.0)),
-                      float(params.get("tau", 1e-6)), int(prec), int(form), int(mode), 0)
+                      float(params.get("tau", 1e-6)), int(prec), int(form), int(mode), int(proj))
 
 
 class Context:

@@ -55,6 +55,7 @@ struct alp_context {
   uint32_t gflags = 0;
   int last_cases = 0;
   int any_kernel_sample = 0;  // some case of the uploaded batch samples with the kernel
+  int any_proj[2] = {0, 0};   // the uploaded batch has cases of each projection rule
 };
 
 namespace {
@@ -294,7 +295,8 @@ alp_status check_params(alp_context *ctx, const alp_params *p, bool relax) {
     return fail(ctx, ALP_ERR_INVALID_ARG, "unknown drag form %d", p->drag_form);
   if (p->sample_mode != ALP_SAMPLE_CELL && p->sample_mode != ALP_SAMPLE_KERNEL)
     return fail(ctx, ALP_ERR_INVALID_ARG, "unknown sample mode %d", p->sample_mode);
-  if (p->reserved1 != 0) return fail(ctx, ALP_ERR_INVALID_ARG, "params.reserved1 must be 0");
+  if (p->proj_mode != ALP_PROJ_NEAREST && p->proj_mode != ALP_PROJ_INTEGRATED)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "unknown projection mode %d", p->proj_mode);
   return ALP_OK;
 }
 
@@ -306,6 +308,7 @@ void fill_case(CaseDev &c, const alp_mesh *m, const alp_beams *b, const alp_para
   c.prec = p->prec;
   c.drag_form = p->drag_form;
   c.sample_mode = p->sample_mode;
+  c.proj_mode = p->proj_mode;
   c.rho = p->rho;
   c.alpha_f = p->alpha_f;
   c.tau = p->tau;
@@ -373,8 +376,11 @@ StepShape shape_cases(alp_context *ctx, std::vector<CaseDev> &cs) {
 alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const StepShape &sh) {
   alp_status rc;
   ctx->any_kernel_sample = 0;
-  for (const CaseDev &c : cs)
+  ctx->any_proj[0] = ctx->any_proj[1] = 0;
+  for (const CaseDev &c : cs) {
     if (c.sample_mode == ALP_SAMPLE_KERNEL) ctx->any_kernel_sample = 1;
+    ctx->any_proj[c.proj_mode == ALP_PROJ_INTEGRATED ? 1 : 0] = 1;
+  }
   if ((rc = ensure_cases(ctx, (int)cs.size())) != ALP_OK) return rc;
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_cases, cs.data(), cs.size() * sizeof(CaseDev),
                              hipMemcpyHostToDevice, ctx->st));
@@ -401,6 +407,8 @@ StepLaunch make_launch(alp_context *ctx, int n_cases) {
   L.n_cases = n_cases;
   L.grid_persistent = ctx->n_cu * 8;
   L.kernel_sample = ctx->any_kernel_sample;
+  L.proj_nearest = ctx->any_proj[0];
+  L.proj_integrated = ctx->any_proj[1];
   return L;
 }
 

@@ -57,6 +57,7 @@ struct CaseDev {
   uint8_t *tile_prev;   // [n_tiles] tiles written at the previous step of this mesh
   int32_t write_S;      // spread writes S (0 for sample/drag-only calls)
   int32_t sample_mode;  // alp_sample_mode
+  int32_t proj_mode;    // alp_proj_mode
 };
 
 // A (chunk, tile) window: the candidate segments lo..hi of one chunk of a
@@ -222,6 +223,70 @@ __device__ __forceinline__ void pair_weights(int prec, double s, double r2, doub
   }
 }
 
+// Segment-integrated weights (ALP_PROJ_INTEGRATED): the 3D Gaussian
+// g(x) = exp(-|x|^2/eps^2) / (pi^1.5 eps^3) integrated along the segment
+// [A, B] (length l > 0) against the linear weights 1 - u/l (node i, a0) and
+// u/l (node i+1, a1).  With tau the unclamped foot parameter, r_p the distance
+// to the line and t = tau l, the Gaussian factors into a radial and an axial
+// part; with x0 = -t/eps, x1 = (l - t)/eps and lam = l/eps,
+//   a0 = Q (x1 E - M) / lam,  a1 = Q (M - x0 E) / lam,
+//   E = (sqrt(pi)/2)(erf x1 - erf x0),  M = (exp(-x0^2) - exp(-x1^2)) / 2,
+//   Q = exp(-r_p^2/eps^2) / (pi^1.5 eps^2).
+// The erf difference is taken through erfc on the side where both arguments
+// share a sign, the exponential difference through expm1.  Below lam = 1/8 the
+// two terms of each bracket nearly cancel, and the integral is taken instead
+// by 8-point Gauss-Legendre quadrature in s = u/l, whose error there is far
+// below rounding.  Always FP64; the split precision narrows the results.
+namespace gl8 {
+// Gauss-Legendre abscissae and weights for n = 8 on [-1, 1] (the tabulated
+// values of the rule, Abramowitz and Stegun Table 25.4), mapped to [0, 1].
+constexpr double kX[4] = {0.1834346424956498049, 0.5255324099163289858, 0.7966664774136267396,
+                          0.9602898564975362317};
+constexpr double kW[4] = {0.3626837833783619830, 0.3137066458778872873, 0.2223810344533744706,
+                          0.1012285362903762592};
+}  // namespace gl8
+
+__device__ __forceinline__ void seg_int_weights(double cx, double cy, double cz, double ax, double ay,
+                                                double az, double bx, double by, double bz, double eps,
+                                                double &a0, double &a1) {
+#pragma clang fp contract(off)
+  const double ex = bx - ax, ey = by - ay, ez = bz - az;
+  const double qx = cx - ax, qy = cy - ay, qz = cz - az;
+  const double ee = (ex * ex + ey * ey) + ez * ez, l = sqrt(ee);
+  const double tau = ((qx * ex + qy * ey) + qz * ez) / ee;
+  const double px = qx - tau * ex, py = qy - tau * ey, pz = qz - tau * ez;
+  const double rp2 = (px * px + py * py) + pz * pz, t = tau * l;
+  const double x0 = -t / eps, x1 = (l - t) / eps, lam = l / eps;
+  const double kPi = 3.14159265358979323846, kSqrtPi = 1.77245385090551602730;
+  const double Q = exp(-(rp2 / (eps * eps))) / (kPi * kSqrtPi * (eps * eps));
+  double W0 = 0.0, W1 = 0.0;
+  if (lam < 0.125) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double x = k < 4 ? -gl8::kX[3 - k] : gl8::kX[k - 4];
+      const double w = 0.5 * (k < 4 ? gl8::kW[3 - k] : gl8::kW[k - 4]);
+      const double sq = 0.5 * (1.0 + x);
+      const double y = sq * lam + x0, g = w * exp(-(y * y));
+      W0 += (1.0 - sq) * g;
+      W1 += sq * g;
+    }
+    W0 *= lam;
+    W1 *= lam;
+  } else {
+    double D;
+    if (x0 >= 0.0) D = erfc(x0) - erfc(x1);
+    else if (x1 <= 0.0) D = erfc(-x1) - erfc(-x0);
+    else D = erf(x1) - erf(x0);
+    const double d = (x1 - x0) * (x1 + x0);  // x1^2 - x0^2
+    const double dexp = d >= 0.0 ? -exp(-(x0 * x0)) * expm1(-d) : exp(-(x1 * x1)) * expm1(d);
+    const double E = 0.5 * kSqrtPi * D, M = 0.5 * dexp;
+    W0 = (x1 * E - M) / lam;
+    W1 = (M - x0 * E) / lam;
+  }
+  a0 = Q * W0;
+  a1 = Q * W1;
+}
+
 // Exact fixed-point accumulation (order independent, so deterministic under
 // any work distribution or atomic order).  A non-negative or signed value v
 // with |v| < 2^E is split into hi = floor(v 2^(46-E)) and
@@ -295,6 +360,8 @@ struct StepLaunch {
   int n_cases;
   int grid_persistent;     // blocks for persistent wave kernels
   int kernel_sample;       // some case uses ALP_SAMPLE_KERNEL
+  int proj_nearest;        // some case projects with ALP_PROJ_NEAREST
+  int proj_integrated;     // some case projects with ALP_PROJ_INTEGRATED
 };
 void launch_step_reset(const StepLaunch &L, hipStream_t st);
 void launch_step_reset_sample(const StepLaunch &L, hipStream_t st);

@@ -396,7 +396,9 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
           ov = ov && !(g.hi[a] < tlo[a] - mrg || g.lo[a] > tlo[a] + tl + mrg);
         if (!ov) continue;
         const int i = s0 + j;
-        if (nb >= 2 && g.len > 0.0) {
+        // the slab rule keeps only segments that can be a cell's nearest one;
+        // the segment-integrated rule needs every segment within reach
+        if (nb >= 2 && g.len > 0.0 && cs.proj_mode == ALP_PROJ_NEAREST) {
           double ac = (tc[0] - g.a[0]) * g.u[0] + (tc[1] - g.a[1]) * g.u[1] + (tc[2] - g.a[2]) * g.u[2];
           double hw = half * g.su;
           if (i > 0 && !(ac + hw > -mrg)) {
@@ -1035,12 +1037,88 @@ __device__ __forceinline__ int entry_of_point(const WeightsScratch &sh, int n_st
   return lo;
 }
 
+// Candidate p of a work item (in cell-lane order, then entry order): its
+// cell lane Lc and entry e, from the per-lane prefix counts and hit masks.
+__device__ __forceinline__ void candidate(const WeightsScratch &sh, int nwords, uint32_t p, int &Lc, int &e) {
+  int lo = 0, hi = 63;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sh.off[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  Lc = lo;
+  uint32_t r = p - sh.off[Lc];
+  for (int wd = 0; wd < nwords; ++wd) {
+    uint32_t mw = sh.mask[Lc * kMaskWords + wd];
+    const uint32_t pc = __popc(mw);
+    if (r < pc) {
+      for (uint32_t q = 0; q < r; ++q) mw &= mw - 1u;
+      e = wd * 32 + __ffs(mw) - 1;
+      return;
+    }
+    r -= pc;
+  }
+}
+
+// Segment-integrated rule: is the segment starting at A (end A + 3) within
+// 3 eps_seg of the cell, eps_seg = (eps_a + eps_b) / 2?  Zero-length segments
+// never are.  FP64, in the decision order of the nearest rule's cutoff.
+__device__ __forceinline__ bool seg_in_reach(const double *A, double ea, double eb, double cx, double cy,
+                                             double cz, double &es) {
+#pragma clang fp contract(off)
+  const double ex = A[3] - A[0], ey = A[4] - A[1], ez = A[5] - A[2];
+  if (!(((ex * ex + ey * ey) + ez * ez) > 0.0)) return false;
+  double s, r2;
+  seg_foot(cx, cy, cz, A[0], A[1], A[2], A[3], A[4], A[5], s, r2);
+  es = 0.5 * (ea + eb);
+  return inside_cutoff(r2, es);
+}
+
+// Records of one (cell, entry) candidate under the segment-integrated rule:
+// one per segment within reach, or one for a single-CV beam within 3 eps.
+__device__ __forceinline__ uint32_t int_count(const CaseDev &cs, int k0, int i0, int i1, double cx, double cy,
+                                              double cz) {
+  if (i1 < 0) {
+    const double *P = cs.Psp + 3 * (int64_t)k0;
+    return inside_cutoff(sqdist_exact(cx, cy, cz, P[0], P[1], P[2]), cs.eps[k0]) ? 1u : 0u;
+  }
+  const double *X = cs.Psp + 3 * ((int64_t)k0 + i0);
+  const double *E = cs.eps + (int64_t)k0 + i0;
+  uint32_t n = 0;
+  for (int j = 0; j <= i1 - i0; ++j) {
+    double es;
+    n += seg_in_reach(X + 3 * j, E[j], E[j + 1], cx, cy, cz, es) ? 1u : 0u;
+  }
+  return n;
+}
+
+__device__ __forceinline__ void write_record(unsigned char *r, int rsz, uint32_t meta, uint32_t node, double a0,
+                                             double a1) {
+  if (rsz == 16) {
+    uint4 q;
+    q.x = meta;
+    q.y = node;
+    q.z = __float_as_uint((float)a0);
+    q.w = __float_as_uint((float)a1);
+    *(uint4 *)r = q;
+  } else {
+    uint2 q;
+    q.x = meta;
+    q.y = node;
+    *(uint2 *)r = q;
+    *(double2 *)(r + 8) = make_double2(a0, a1);
+  }
+}
+
 __device__ __forceinline__ float rdlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
-void k_weights(StepLaunch L) {
+// One kernel per projection rule (kInt: segment-integrated), so that each
+// keeps its own register allocation; each takes only the items of its own
+// cases, from its own work-queue counters.
+template <bool kInt>
+__device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   Work W = L.w;
   __shared__ WeightsScratch sh;
   const int lane = threadIdx.x;
@@ -1049,10 +1127,11 @@ void k_weights(StepLaunch L) {
   unsigned long long blk_cur = 0, blk_end = 0;
   int acc_case = -1;
   unsigned long long acc_pairs = 0;
-  WorkQueue wq = work_queue(W.counters + 8, (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
+  WorkQueue wq = work_queue(W.counters + (kInt ? 16 : 8), (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
   while (wq.next(lane)) {
     const uint32_t item = wq.item;
     const Item it = W.item[item];
+    if ((L.cases[it.cs].proj_mode == ALP_PROJ_INTEGRATED) != kInt) continue;
     if (it.cs != acc_case) {
       if (lane == 0 && acc_case >= 0 && acc_pairs)
         atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
@@ -1243,168 +1322,233 @@ void k_weights(StepLaunch L) {
     sh.off[lane] = myoff;
     if (lane == 63) sh.off[64] = myoff + cnt;
     __syncthreads();
-    // record space for up to `total` pairs, carved from the wave's block
-    const unsigned long long need = ((unsigned long long)total * rsz + 15ull) & ~15ull;
-    if (blk_cur + need > blk_end) {
-      const unsigned long long take = need > kRecBlock ? need : kRecBlock;
-      unsigned long long got = 0;
-      if (lane == 0) got = atomicAdd(W.rec_alloc, take);
-      blk_cur = __shfl(got, 0, 64);
-      blk_end = blk_cur + take;
-    }
-    const unsigned long long rbase = blk_cur;
-    blk_cur += need;
-    const bool rec_ok = (int64_t)(rbase + need) <= W.cap_rec;
-    if (!rec_ok && lane == 0) set_overflow(W, 2u);
-    uint32_t nreal = 0;
     const int nwords = (int)((ne + 31) >> 5);
-    // 3.-5. candidate pairs, 64 per round
-    for (uint32_t p0 = 0; p0 < total; p0 += 64) {
-      const uint32_t p = p0 + lane;
-      const bool act = p < total;
-      int Lc = lane, e = 0;
-      if (act) {
-        int lo = 0, hi = 63;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (sh.off[mid] <= p) lo = mid;
-          else hi = mid - 1;
-        }
-        Lc = lo;
-        uint32_t r = p - sh.off[Lc];
-        for (int wd = 0; wd < nwords; ++wd) {
-          uint32_t mw = sh.mask[Lc * kMaskWords + wd];
-          const uint32_t pc = __popc(mw);
-          if (r < pc) {
-            for (uint32_t q = 0; q < r; ++q) mw &= mw - 1u;
-            e = wd * 32 + __ffs(mw) - 1;
-            break;
-          }
-          r -= pc;
-        }
+    unsigned long long rbase = 0;
+    bool rec_ok = true;
+    // record space for n pairs, carved from the wave's block
+    auto reserve = [&](uint32_t n) {
+      const unsigned long long need = ((unsigned long long)n * rsz + 15ull) & ~15ull;
+      if (blk_cur + need > blk_end) {
+        const unsigned long long take = need > kRecBlock ? need : kRecBlock;
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(W.rec_alloc, take);
+        blk_cur = __shfl(got, 0, 64);
+        blk_end = blk_cur + take;
       }
-      const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
-      const double pv = __shfl(v, Lc, 64);
-      bool in = false;
-      int bi = 0, single = 0;
-      double a0 = 0.0, a1 = 0.0;
-      if (act) {
-        const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
-        const int k0 = sh.e_k0[e], i0 = sh.e_i0[e], i1 = sh.e_i1[e];
-        double bs = 0.0, br2 = INFINITY, ej;
-        int bj = 0;
-        if (i1 < 0) {
-          single = 1;
-          const double *P = cs.Psp + 3 * (int64_t)k0;
-          br2 = sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]);
-          ej = cs.eps[k0];
-        } else {
-          const int nseg = i1 - i0 + 1;
-          const double *X = cs.Psp + 3 * ((int64_t)k0 + i0);
-          bool full = pt0 < 0;
-          if (!full) {
-            // FP32 ranking: the three smallest (distance, index) keys
-            const float qx = (float)(pcx - ctx), qy = (float)(pcy - cty), qz = (float)(pcz - ctz);
-            uint32_t k1 = ~0u, k2 = ~0u, k3 = ~0u;
-            float4 A = sh.sa[pt0];
-            for (int j = 0; j < nseg; ++j) {
-              const float4 B = sh.sa[pt0 + j + 1];
-              const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
-              float dx = qx - A.x, dy = qy - A.y, dz = qz - A.z;
-              const float t = dx * ex + dy * ey + dz * ez;
-              const float sg = __saturatef(t * A.w);
-              dx -= sg * ex;
-              dy -= sg * ey;
-              dz -= sg * ez;
-              const float d2 = dx * dx + dy * dy + dz * dz;
-              const uint32_t key = (__float_as_uint(d2) & ~kSegIdxMask) | (uint32_t)j;
-              const uint32_t m1 = max(k1, key);
-              k1 = min(k1, key);
-              const uint32_t m2 = max(k2, m1);
-              k2 = min(k2, m1);
-              k3 = min(k3, m2);
-              A = B;
+      rbase = blk_cur;
+      blk_cur += need;
+      rec_ok = (int64_t)(rbase + need) <= W.cap_rec;
+      if (!rec_ok && lane == 0) set_overflow(W, 2u);
+    };
+    uint32_t nreal = 0;
+    if constexpr (kInt) {
+      // 3.-5. segment-integrated kernel: every window segment within the
+      // cutoff of the cell gives one record (cell, segment).  A counting pass
+      // sizes the item's records; the writing pass takes the same decisions.
+      uint32_t n_rec = 0;
+      for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+        const uint32_t p = p0 + lane;
+        const bool act = p < total;
+        int Lc = lane, e = 0;
+        if (act) candidate(sh, nwords, p, Lc, e);
+        const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
+        const uint32_t c = act ? int_count(cs, sh.e_k0[e], sh.e_i0[e], sh.e_i1[e], pcx, pcy, pcz) : 0u;
+        uint32_t tot;
+        wave_excl_scan_u32(c, tot);
+        n_rec += tot;
+      }
+      reserve(n_rec);
+      for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+        const uint32_t p = p0 + lane;
+        const bool act = p < total;
+        int Lc = lane, e = 0;
+        if (act) candidate(sh, nwords, p, Lc, e);
+        const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
+        const double pv = __shfl(v, Lc, 64);
+        const int k0 = act ? sh.e_k0[e] : 0, i0 = act ? sh.e_i0[e] : 0, i1 = act ? sh.e_i1[e] : -1;
+        const uint32_t c = act ? int_count(cs, k0, i0, i1, pcx, pcy, pcz) : 0u;
+        uint32_t tot;
+        const uint32_t off = wave_excl_scan_u32(c, tot);
+        if (c > 0) {
+          const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
+          // node q of the entry gets a V: staged nodes in LDS, others in HBM
+          auto acc = [&](int q, double av) {
+            long long h;
+            unsigned long long l;
+            if (pt0 >= 0) {
+              fx_encode(av, sh.wx[pt0 + q], h, l);
+              atomicAdd((unsigned long long *)&sh.ahi[pt0 + q], (unsigned long long)h);
+              atomicAdd(&sh.alo[pt0 + q], l);
+            } else {
+              const int64_t node = cs.point_base + k0 + (i1 < 0 ? 0 : i0) + q;
+              fx_encode(av, W.wexp[node], h, l);
+              atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h);
+              atomicAdd(&W.w_lo[node], l);
             }
-            // keys drop 8 mantissa bits (relative 2^-15): the band below holds
-            // every segment whose exact distance can reach the best one
-            const float b1 = __uint_as_float(k1 & ~kSegIdxMask);
-            const float dl = b1 * 0x1p-14f + sh.e_dabs[e];
-            const float band = (b1 + 2.0f * dl) * (1.0f + 0x1p-20f);
-            full = k3 != ~0u && __uint_as_float(k3 & ~kSegIdxMask) <= band;
+          };
+          unsigned char *r = W.rec + rbase + (unsigned long long)(nreal + off) * rsz;
+          if (i1 < 0) {
+            // single-CV beam: the point kernel of the nearest rule
+            const double *P = cs.Psp + 3 * (int64_t)k0;
+            double a0, a1;
+            pair_weights(cs.prec, 0.0, sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]), cs.eps[k0], a0, a1);
+            acc(0, a0 * pv);
+            if (rec_ok) write_record(r, rsz, (uint32_t)Lc | kRecSingle, (uint32_t)(cs.point_base + k0), a0, 0.0);
+          } else {
+            const double *X = cs.Psp + 3 * ((int64_t)k0 + i0);
+            const double *E = cs.eps + (int64_t)k0 + i0;
+            const int nseg = i1 - i0 + 1;
+            for (int j = 0; j < nseg; ++j) {
+              const double *A = X + 3 * j;
+              double es;
+              if (!seg_in_reach(A, E[j], E[j + 1], pcx, pcy, pcz, es)) continue;
+              double a0, a1;
+              seg_int_weights(pcx, pcy, pcz, A[0], A[1], A[2], A[3], A[4], A[5], es, a0, a1);
+              if (cs.prec == ALP_PREC_FP32_SPLIT) {
+                a0 = (double)(float)a0;
+                a1 = (double)(float)a1;
+              }
+              acc(j, a0 * pv);
+              acc(j + 1, a1 * pv);
+              if (rec_ok) write_record(r, rsz, (uint32_t)Lc, (uint32_t)(cs.point_base + k0 + i0 + j), a0, a1);
+              r += rsz;
+            }
+          }
+        }
+        nreal += tot;
+      }
+    } else {
+      // record space for up to `total` pairs (one per candidate)
+      reserve(total);
+      // 3.-5. candidate pairs, 64 per round
+      for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+        const uint32_t p = p0 + lane;
+        const bool act = p < total;
+        int Lc = lane, e = 0;
+        if (act) candidate(sh, nwords, p, Lc, e);
+        const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
+        const double pv = __shfl(v, Lc, 64);
+        bool in = false;
+        int bi = 0, single = 0;
+        double a0 = 0.0, a1 = 0.0;
+        if (act) {
+          const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
+          const int k0 = sh.e_k0[e], i0 = sh.e_i0[e], i1 = sh.e_i1[e];
+          double bs = 0.0, br2 = INFINITY, ej;
+          int bj = 0;
+          if (i1 < 0) {
+            single = 1;
+            const double *P = cs.Psp + 3 * (int64_t)k0;
+            br2 = sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]);
+            ej = cs.eps[k0];
+          } else {
+            const int nseg = i1 - i0 + 1;
+            const double *X = cs.Psp + 3 * ((int64_t)k0 + i0);
+            bool full = pt0 < 0;
             if (!full) {
-              const int j1 = (int)(k1 & kSegIdxMask);
-              exact_scan(X, j1, j1, pcx, pcy, pcz, bj, bs, br2);
-              if (k2 != ~0u && __uint_as_float(k2 & ~kSegIdxMask) <= band) {
-                const int j2 = (int)(k2 & kSegIdxMask);
-                int cj = j2;
-                double cs2 = 0.0, cr2 = INFINITY;
-                exact_scan(X, j2, j2, pcx, pcy, pcz, cj, cs2, cr2);
-                if (cr2 < br2 || (cr2 == br2 && j2 < bj)) {
-                  br2 = cr2;
-                  bj = j2;
-                  bs = cs2;
+              // FP32 ranking: the three smallest (distance, index) keys
+              const float qx = (float)(pcx - ctx), qy = (float)(pcy - cty), qz = (float)(pcz - ctz);
+              uint32_t k1 = ~0u, k2 = ~0u, k3 = ~0u;
+              float4 A = sh.sa[pt0];
+              for (int j = 0; j < nseg; ++j) {
+                const float4 B = sh.sa[pt0 + j + 1];
+                const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
+                float dx = qx - A.x, dy = qy - A.y, dz = qz - A.z;
+                const float t = dx * ex + dy * ey + dz * ez;
+                const float sg = __saturatef(t * A.w);
+                dx -= sg * ex;
+                dy -= sg * ey;
+                dz -= sg * ez;
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                const uint32_t key = (__float_as_uint(d2) & ~kSegIdxMask) | (uint32_t)j;
+                const uint32_t m1 = max(k1, key);
+                k1 = min(k1, key);
+                const uint32_t m2 = max(k2, m1);
+                k2 = min(k2, m1);
+                k3 = min(k3, m2);
+                A = B;
+              }
+              // keys drop 8 mantissa bits (relative 2^-15): the band below holds
+              // every segment whose exact distance can reach the best one
+              const float b1 = __uint_as_float(k1 & ~kSegIdxMask);
+              const float dl = b1 * 0x1p-14f + sh.e_dabs[e];
+              const float band = (b1 + 2.0f * dl) * (1.0f + 0x1p-20f);
+              full = k3 != ~0u && __uint_as_float(k3 & ~kSegIdxMask) <= band;
+              if (!full) {
+                const int j1 = (int)(k1 & kSegIdxMask);
+                exact_scan(X, j1, j1, pcx, pcy, pcz, bj, bs, br2);
+                if (k2 != ~0u && __uint_as_float(k2 & ~kSegIdxMask) <= band) {
+                  const int j2 = (int)(k2 & kSegIdxMask);
+                  int cj = j2;
+                  double cs2 = 0.0, cr2 = INFINITY;
+                  exact_scan(X, j2, j2, pcx, pcy, pcz, cj, cs2, cr2);
+                  if (cr2 < br2 || (cr2 == br2 && j2 < bj)) {
+                    br2 = cr2;
+                    bj = j2;
+                    bs = cs2;
+                  }
                 }
               }
             }
-          }
-          if (full) {
-            br2 = INFINITY;
-            bj = 0;
-            bs = 0.0;
-            exact_scan(X, 0, nseg - 1, pcx, pcy, pcz, bj, bs, br2);
-          }
-          const double *E = cs.eps + (int64_t)k0 + i0;
-          ej = eps_at(bs, E[bj], E[bj + 1]);
-        }
-        in = inside_cutoff(br2, ej);
-        if (in) {
-          pair_weights(cs.prec, bs, br2, ej, a0, a1);
-          const int64_t node = cs.point_base + k0 + (single ? 0 : i0 + bj);
-          long long h0, h1 = 0;
-          unsigned long long l0, l1 = 0;
-          if (pt0 >= 0) {
-            fx_encode(a0 * pv, sh.wx[pt0 + bj], h0, l0);
-            atomicAdd((unsigned long long *)&sh.ahi[pt0 + bj], (unsigned long long)h0);
-            atomicAdd(&sh.alo[pt0 + bj], l0);
-            if (!single) {
-              fx_encode(a1 * pv, sh.wx[pt0 + bj + 1], h1, l1);
-              atomicAdd((unsigned long long *)&sh.ahi[pt0 + bj + 1], (unsigned long long)h1);
-              atomicAdd(&sh.alo[pt0 + bj + 1], l1);
+            if (full) {
+              br2 = INFINITY;
+              bj = 0;
+              bs = 0.0;
+              exact_scan(X, 0, nseg - 1, pcx, pcy, pcz, bj, bs, br2);
             }
+            const double *E = cs.eps + (int64_t)k0 + i0;
+            ej = eps_at(bs, E[bj], E[bj + 1]);
+          }
+          in = inside_cutoff(br2, ej);
+          if (in) {
+            pair_weights(cs.prec, bs, br2, ej, a0, a1);
+            const int64_t node = cs.point_base + k0 + (single ? 0 : i0 + bj);
+            long long h0, h1 = 0;
+            unsigned long long l0, l1 = 0;
+            if (pt0 >= 0) {
+              fx_encode(a0 * pv, sh.wx[pt0 + bj], h0, l0);
+              atomicAdd((unsigned long long *)&sh.ahi[pt0 + bj], (unsigned long long)h0);
+              atomicAdd(&sh.alo[pt0 + bj], l0);
+              if (!single) {
+                fx_encode(a1 * pv, sh.wx[pt0 + bj + 1], h1, l1);
+                atomicAdd((unsigned long long *)&sh.ahi[pt0 + bj + 1], (unsigned long long)h1);
+                atomicAdd(&sh.alo[pt0 + bj + 1], l1);
+              }
+            } else {
+              fx_encode(a0 * pv, W.wexp[node], h0, l0);
+              atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h0);
+              atomicAdd(&W.w_lo[node], l0);
+              if (!single) {
+                fx_encode(a1 * pv, W.wexp[node + 1], h1, l1);
+                atomicAdd((unsigned long long *)&W.w_hi[node + 1], (unsigned long long)h1);
+                atomicAdd(&W.w_lo[node + 1], l1);
+              }
+            }
+            bi = (int)node;  // global node index for the record
+          }
+        }
+        const uint64_t bal = ballot64(act && in);
+        if (act && in && rec_ok) {
+          const unsigned long long at = rbase + (unsigned long long)(nreal + lanemask_lt_popc(bal)) * rsz;
+          unsigned char *r = W.rec + at;
+          const uint32_t meta = (uint32_t)Lc | (single ? kRecSingle : 0u);
+          if (rsz == 16) {
+            uint4 q;
+            q.x = meta;
+            q.y = (uint32_t)bi;
+            q.z = __float_as_uint((float)a0);
+            q.w = __float_as_uint((float)a1);
+            *(uint4 *)r = q;
           } else {
-            fx_encode(a0 * pv, W.wexp[node], h0, l0);
-            atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h0);
-            atomicAdd(&W.w_lo[node], l0);
-            if (!single) {
-              fx_encode(a1 * pv, W.wexp[node + 1], h1, l1);
-              atomicAdd((unsigned long long *)&W.w_hi[node + 1], (unsigned long long)h1);
-              atomicAdd(&W.w_lo[node + 1], l1);
-            }
+            uint2 q;
+            q.x = meta;
+            q.y = (uint32_t)bi;
+            *(uint2 *)r = q;
+            *(double2 *)(r + 8) = make_double2(a0, a1);
           }
-          bi = (int)node;  // global node index for the record
         }
+        nreal += (uint32_t)__popcll(bal);
       }
-      const uint64_t bal = ballot64(act && in);
-      if (act && in && rec_ok) {
-        const unsigned long long at = rbase + (unsigned long long)(nreal + lanemask_lt_popc(bal)) * rsz;
-        unsigned char *r = W.rec + at;
-        const uint32_t meta = (uint32_t)Lc | (single ? kRecSingle : 0u);
-        if (rsz == 16) {
-          uint4 q;
-          q.x = meta;
-          q.y = (uint32_t)bi;
-          q.z = __float_as_uint((float)a0);
-          q.w = __float_as_uint((float)a1);
-          *(uint4 *)r = q;
-        } else {
-          uint2 q;
-          q.x = meta;
-          q.y = (uint32_t)bi;
-          *(uint2 *)r = q;
-          *(double2 *)(r + 8) = make_double2(a0, a1);
-        }
-      }
-      nreal += (uint32_t)__popcll(bal);
     }
     __syncthreads();
     // flush the staged node accumulators
@@ -1430,8 +1574,21 @@ void k_weights(StepLaunch L) {
     atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
 }
 
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
+void k_weights(StepLaunch L) {
+  weights_pass<false>(L);
+}
+
+// the integrated rule's evaluation (erf, erfc, expm1) needs more registers:
+// two waves per SIMD, up to 256 VGPRs
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(2)))
+void k_weights_int(StepLaunch L) {
+  weights_pass<true>(L);
+}
+
 void launch_weights(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_weights, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
+  if (L.proj_nearest) hipLaunchKernelGGL(k_weights, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
+  if (L.proj_integrated) hipLaunchKernelGGL(k_weights_int, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------------- norm --

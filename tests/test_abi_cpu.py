@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -56,3 +57,18 @@ def test_null_context_is_rejected_without_gpu():
     lib = alp.load()
     assert lib.alp_destroy(None) == -1
     assert lib.alp_invalidate(None) == -1
+
+
+def test_device_gauss_legendre_table_is_the_8_point_rule():
+    """The tabulated abscissae and weights the device uses for short segments
+    of the integrated rule are those of 8-point Gauss-Legendre quadrature."""
+    src = open(os.path.join(ROOT, "paper_2609_39443_amd", "csrc", "alp_internal.h")).read()
+    tab = {}
+    for name in ("kX", "kW"):
+        m = re.search(r"constexpr double %s\[4\] = \{([^}]*)\}" % name, src)
+        assert m, name
+        tab[name] = np.array([float(v) for v in m.group(1).split(",")])
+    x, w = np.polynomial.legendre.leggauss(8)
+    # numpy's own weights carry a few ulps of error
+    assert np.allclose(tab["kX"], x[4:], rtol=0, atol=1e-15)
+    assert np.allclose(tab["kW"], w[4:], rtol=0, atol=1e-15)

@@ -386,3 +386,74 @@ def test_morison_inertia(gu, ctx, prec):
     wl["params"]["alpha_f"] = 0.6
     fp = np.random.default_rng(5).normal(size=wl["beams"]["P"].shape)
     run_and_compare(gu, ctx, wl, prec, f_prev=fp, tol_us=1e-12)
+
+
+def integrated(wl):
+    wl["params"]["proj_mode"] = "integrated"
+    return wl
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_integrated_projection(gu, ctx, prec):
+    """The segment-integrated rule (R27) against the oracle: random scenes over
+    several tile sizes (a point outside the domain in one), an unbatched call,
+    the small canopy, the near-tie scene (its 300-point coil does not fit the
+    staging area) and a zero-length segment next to nodes that catch no cell."""
+    for seed, tb in ((3, 0), (4, 2), (8, 5)):
+        run_and_compare(gu, ctx, integrated(random_scene(seed, outside=(seed == 4))), prec, tile_bins=tb)
+    run_and_compare(gu, ctx, integrated(random_scene(10)), prec, batched=False)
+    _, _, ref, diag = run_and_compare(gu, ctx, integrated(W.canopy(n=40, n_stems=30, cv_range=(5, 30),
+                                                                    inset=0.04)), prec)
+    gu.log(f"[parity]   canopy (cell, segment) pairs {diag['n_pairs']}")
+    run_and_compare(gu, ctx, integrated(near_tie_scene()), prec)
+    C, V = W.uniform_mesh(12, 12, 12, 0.01)
+    n = 8
+    P = np.stack([np.full(n, 0.06), np.full(n, 0.06), 0.02 + np.arange(n) * 0.01], axis=1)
+    P[3] = [0.0551, 0.0549, 0.0551]
+    P[5] = P[4]  # zero-length segment
+    beams = W._beamset([P], [np.tile([0, 0, 1.0], (n, 1))], [np.zeros((n, 3))], [np.full(n, 0.002)],
+                       [np.full(n, 0.01)], [np.full(n, 0.001)], [1.2], [0.0], [0.03], [[0, 0, 0]],
+                       [[-1.0, 0, 0]])
+    wl = {"name": "zero-weight", "C": C, "V": V, "U": np.tile([0.3, 0.1, 0.0], (C.shape[0], 1)),
+          "box": None, "beams": beams, "params": {"rho": 1000.0, "tau": 1e-6, "proj_mode": "integrated"}}
+    _, _, ref, diag = run_and_compare(gu, ctx, wl, prec)
+    assert diag["n_zero_weight"] > 0
+
+
+def test_mixed_projection_rules_in_one_batch(gu, ctx):
+    """Nearest-segment and segment-integrated cases, in both precisions, in one
+    graph-captured batched step: each case matches its own oracle run on every
+    replay."""
+    wls = [random_scene(40), integrated(random_scene(41)), integrated(W.channel(noise=True)),
+           W.canopy(n=32, n_stems=12, cv_range=(5, 20), inset=0.05)]
+    precs = [alp.PREC_FP32_SPLIT, alp.PREC_FP64, alp.PREC_FP32_SPLIT, alp.PREC_FP64]
+    cases = [gu.GpuCase(ctx, wl, p) for wl, p in zip(wls, precs)]
+    refs = [gu.oracle_step(wl) for wl in wls]
+    for rep in range(3):
+        gu.log(f"[parity] mixed projection rules, replay {rep}")
+        gu.step_batched(ctx, cases, alp.USE_GRAPH)
+        for i, (c, ref, p) in enumerate(zip(cases, refs, precs)):
+            tS, tw = TOL[p]
+            gu.compare(c.results(), ref, ctx.diag(i), ref["diag"], tS, tw)
+    alp.alp_invalidate(ctx.h)
+
+
+def test_integrated_bitwise_across_binnings(gu, ctx):
+    """Under the integrated rule too, the bin size and the tile edge change no
+    bit of S or w: every decision is exact and every sum is exact or in a fixed
+    per-cell order."""
+    wl = integrated(random_scene(22, nx=30, ny=28, nz=22, n_beams=9))
+    ref = None
+    for tb, bs in ((4, 0.0), (2, 0.0), (6, 0.015)):
+        case = gu.GpuCase(ctx, wl, alp.PREC_FP64, tile_bins=tb, bin_size=bs)
+        gu.step_batched(ctx, [case], alp.USE_GRAPH)
+        res = case.results()
+        d = ctx.diag(0)
+        alp.alp_invalidate(ctx.h)
+        if ref is None:
+            ref, dref = res, d
+            continue
+        for k in ref:
+            assert np.array_equal(ref[k], res[k]), (tb, bs, k)
+        for k in ("n_pairs", "n_band_cells", "n_zero_weight"):
+            assert d[k] == dref[k], (tb, bs, k)
