@@ -107,6 +107,11 @@ def measure_graph(alp, torch, np, wls, prec, steps, warmup):
     return dt, diags
 
 
+def _integrated(wl):
+    wl["params"] = dict(wl["params"], proj_mode="integrated")
+    return wl
+
+
 def secondary(alp, W, torch, np, steps):
     """The other workloads at their full sizes, FP32-split and all-FP64."""
     out = {}
@@ -117,6 +122,9 @@ def secondary(alp, W, torch, np, steps):
          "8M jittered cells in random order, 700 x 700-strand net of 499,800 points"),
         ("batched_scenarios", lambda: [W.scenario(c) for c in range(64)],
          "64 cases of 0.5M-4M cells and 1-500 stems of 20-300 CVs in one graph step"),
+        ("canopy_integrated", lambda: [_integrated(W.canopy(n=256, n_stems=2000))],
+         "the headline canopy (256^3 cells, 2000 stems) under the segment-integrated projection "
+         "(a Gaussian integrated along every segment within the cutoff); pairs are (cell, segment)"),
     ]
     for name, make, desc in specs:
         t0 = time.time()

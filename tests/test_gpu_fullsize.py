@@ -191,3 +191,19 @@ def test_batched_scenarios_full_size_sampled(gu, ctx):
         out = sampled_check(gu, wl, res, diags[i], alp.PREC_FP32_SPLIT, n_beam_sample=5,
                             n_cells_sample=60, seed=100 + i)
         gu.log(f"[full]   {out}")
+
+
+def test_canopy_integrated_full_size_sampled(gu, ctx):
+    """The bench canopy under the segment-integrated rule, FP32-split graph
+    step: sampled parity (each output depends only on the beams that reach it,
+    as under the nearest rule) and the exact balance."""
+    wl = W.canopy(n=256, n_stems=2000)
+    wl["params"] = dict(wl["params"], proj_mode="integrated")
+    gu.log("[full] canopy 256^3 / 2000 stems, integrated rule, FP32-split graph")
+    case, res, diag = run_graph(gu, ctx, wl, alp.PREC_FP32_SPLIT, replays=1)
+    del case
+    torch.cuda.empty_cache()
+    gu.log(f"[full]   (cell, segment) pairs {diag['n_pairs']}, band cells {diag['n_band_cells']}")
+    out = sampled_check(gu, wl, res, diag, alp.PREC_FP32_SPLIT, n_beam_sample=8, n_cells_sample=80,
+                        seed=15)
+    gu.log(f"[full]   {out}")
