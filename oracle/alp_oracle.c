@@ -65,6 +65,17 @@
  *       zero-length segment contributes nothing; a single-CV beam keeps the
  *       point kernel of R14.  Normalisation and eq. (23) are unchanged, with
  *       one pair per (cell, segment).
+ *   R28 the tangent of Sec. 3.2.2 "from a Hermite spline through the current
+ *       beam-cell centres" x_i = C^b_i + W_i: the spline's node derivatives
+ *       are the chord-length three-point (Bessel) derivatives, i.e. the
+ *       derivative at x_i of the parabola through x_{i-1}, x_i, x_{i+1}
+ *       parameterised by chord length, and at the ends the derivative of the
+ *       parabola through the first (last) three centres; two-point beams use
+ *       the chord; a zero-length chord falls back to its neighbour; a single
+ *       centre, or only coincident centres, gives the zero vector (counted).
+ *   R29 local kernel width (Sec. 8): eps_k = max(f dx_k, eps_phys_k) with
+ *       dx_k = V_c^{1/3} of the cell c = c(P_a,k) of R4 and f = 2 in the
+ *       paper; a point outside the domain keeps eps_phys (counted).
  *   R25 optional kernel-weighted sampling (the volume-average sampling the
  *       conclusions name as future work): U_s = sum_j g_j V_j U_j /
  *       sum_j g_j V_j over the cells with |C_j - P_s|^2 <= 9 eps_k^2,
@@ -878,6 +889,89 @@ int orc_spread(const orc_mesh *m, const orc_beams *b, const double *f, double *S
 done:
   free(wacc); free(sacc); free(band); free(fh); free(pv.v);
   return rc;
+}
+
+/* ------------------------------------------------------------- helpers -- */
+/* Eq. (15): P_a = C^b + W^ref + W per point (W^ref == NULL: zero offset).
+   The actuator-point velocity is the beam-cell velocity: the first two terms
+   do not depend on time. */
+int orc_actuator_points(int64_t n, const double *Cb, const double *Wref, const double *W, double *P) {
+  if (n < 0 || (n > 0 && (!Cb || !W || !P))) return ORC_EINVAL;
+  for (int64_t k = 0; k < 3 * n; ++k) P[k] = (Cb[k] + (Wref ? Wref[k] : 0.0)) + W[k];
+  return ORC_OK;
+}
+
+/* unit vector of b - a and its length */
+static double chord(const double *a, const double *b, double *u) {
+  double e[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  double l = sqrt(dot3(e, e));
+  for (int c = 0; c < 3; ++c) u[c] = l > 0.0 ? e[c] / l : 0.0;
+  return l;
+}
+
+/* R28: unit tangents of every beam from its current cell centres X. */
+int orc_tangents(int32_t n_beams, const int64_t *offsets, const double *X, double *e_t, int64_t *n_degenerate) {
+  if (n_beams < 0 || !offsets || (offsets[n_beams] > 0 && (!X || !e_t))) return ORC_EINVAL;
+  int64_t ndg = 0;
+  for (int32_t b = 0; b < n_beams; ++b) {
+    int64_t k0 = offsets[b], n = offsets[b + 1] - k0;
+    const double *x = X + 3 * k0;
+    for (int64_t i = 0; i < n; ++i) {
+      double m[3] = {0.0, 0.0, 0.0};
+      if (n == 2) {
+        chord(x, x + 3, m);
+      } else if (n >= 3) {
+        /* the three centres of the parabola: i-1, i, i+1 inside, the first or
+           last three at the ends; j is the node's place among them */
+        int64_t a = i == 0 ? 0 : (i == n - 1 ? n - 3 : i - 1);
+        int j = (int)(i - a);
+        double u0[3], u1[3];
+        double d0 = chord(x + 3 * a, x + 3 * (a + 1), u0);
+        double d1 = chord(x + 3 * (a + 1), x + 3 * (a + 2), u1);
+        if (d0 > 0.0 && d1 > 0.0) {
+          /* derivative of the parabola at t = 0, d0, d0 + d1 */
+          double w0, w1;
+          if (j == 0) { w0 = 2.0 * d0 + d1; w1 = -d0; }
+          else if (j == 1) { w0 = d1; w1 = d0; }
+          else { w0 = -d1; w1 = d0 + 2.0 * d1; }
+          for (int c = 0; c < 3; ++c) m[c] = (w0 * u0[c] + w1 * u1[c]) / (d0 + d1);
+        } else if (d0 > 0.0 && j <= 1) {
+          for (int c = 0; c < 3; ++c) m[c] = u0[c];
+        } else if (d1 > 0.0 && j >= 1) {
+          for (int c = 0; c < 3; ++c) m[c] = u1[c];
+        } else if (d0 > 0.0) {
+          for (int c = 0; c < 3; ++c) m[c] = u0[c];
+        } else if (d1 > 0.0) {
+          for (int c = 0; c < 3; ++c) m[c] = u1[c];
+        }
+      }
+      double l = sqrt(dot3(m, m));
+      for (int c = 0; c < 3; ++c) e_t[3 * (k0 + i) + c] = l > 0.0 ? m[c] / l : 0.0;
+      if (!(l > 0.0)) ndg++;
+    }
+  }
+  if (n_degenerate) *n_degenerate = ndg;
+  return ORC_OK;
+}
+
+/* R29: eps_k = max(factor V_c^{1/3}, eps_phys_k), c = c(P_k). */
+int orc_local_eps(const orc_mesh *m, int64_t n, const double *P, const double *eps_phys, double factor,
+                  double *eps, int64_t *n_outside) {
+  if (!m || n < 0 || (n > 0 && (!P || !eps_phys || !eps))) return ORC_EINVAL;
+  int64_t nout = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t c = orc_locate(m, P + 3 * k);
+    double e = eps_phys[k];
+    if (c < 0) {
+      nout++;
+    } else {
+      double dx = factor * cbrt(m->V[c]);
+      if (dx > e) e = dx;
+    }
+    eps[k] = e;
+  }
+  if (n_outside) *n_outside = nout;
+  return ORC_OK;
 }
 
 /* One coupling step: sample -> line force -> projection (Sec. 3.2). */

@@ -91,6 +91,9 @@ def _load():
         lib.orc_spread.argtypes = [vp, ct.POINTER(_Beams), vp, vp, vp, vp, ct.POINTER(_Diag), ct.c_int32]
         lib.orc_seg_weights.argtypes = [vp, vp, vp, ct.c_double, ct.c_double, vp, vp]
         lib.orc_gl_nodes.argtypes = [vp, vp]
+        lib.orc_actuator_points.argtypes = [ct.c_int64, vp, vp, vp, vp]
+        lib.orc_tangents.argtypes = [ct.c_int32, vp, vp, vp, ct.POINTER(ct.c_int64)]
+        lib.orc_local_eps.argtypes = [vp, ct.c_int64, vp, vp, ct.c_double, vp, ct.POINTER(ct.c_int64)]
         lib.orc_step.argtypes = [vp, vp, ct.POINTER(_Beams), ct.POINTER(_Params), vp, vp, vp, vp,
                                  vp, vp, vp, vp, vp, ct.POINTER(_Diag), vp]
         lib.orc_nearest_segment.argtypes = [ct.c_int64, vp, vp, ct.POINTER(ct.c_double),
@@ -295,3 +298,38 @@ def gl_nodes():
     w = np.zeros(8)
     _load().orc_gl_nodes(_ptr(s), _ptr(w))
     return s, w
+
+
+def actuator_points(Cb, W, Wref=None):
+    """Eq. (15): P_a = C^b + W^ref + W."""
+    Cb, W = _f64(Cb, (-1, 3)), _f64(W, (-1, 3))
+    Wr = None if Wref is None else _f64(Wref, (-1, 3))
+    P = np.zeros_like(Cb)
+    if _load().orc_actuator_points(Cb.shape[0], _ptr(Cb), _ptr(Wr), _ptr(W), _ptr(P)) != 0:
+        raise ValueError("orc_actuator_points failed")
+    return P
+
+
+def tangents(offsets, X):
+    """R28 unit tangents from the current beam-cell centres X; also the number
+    of points left with a zero tangent."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    X = _f64(X, (-1, 3))
+    e = np.zeros_like(X)
+    ndg = ct.c_int64()
+    if _load().orc_tangents(len(off) - 1, _ptr(off), _ptr(X), _ptr(e), ct.byref(ndg)) != 0:
+        raise ValueError("orc_tangents failed")
+    return e, ndg.value
+
+
+def local_eps(mesh: Mesh, P, eps_phys, factor=2.0):
+    """R29 eps_k = max(factor V_c^(1/3), eps_phys_k), c = c(P_k); also the
+    number of points outside the domain."""
+    P = _f64(P, (-1, 3))
+    ep = _f64(eps_phys, (-1,))
+    out = np.zeros(P.shape[0])
+    nout = ct.c_int64()
+    if _load().orc_local_eps(mesh._h, P.shape[0], _ptr(P), _ptr(ep), float(factor), _ptr(out),
+                             ct.byref(nout)) != 0:
+        raise ValueError("orc_local_eps failed")
+    return out, nout.value
