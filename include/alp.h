@@ -286,6 +286,46 @@ alp_status alp_autotune(alp_context *ctx, int64_t n_cells, const double *C, cons
                         int32_t tuned_case, uint32_t flags, int32_t reps, double *out_bin_size,
                         int32_t *out_tile_bins, double *out_ms);
 
+/* Beam state for the point-wise helpers (Sec. 3.2.2): one actuator point per
+   beam control volume, beams as a CSR over points as in alp_beams.  DEVICE
+   pointers. */
+typedef struct {
+  int32_t n_beams;
+  int32_t reserved0;        /* must be 0 */
+  int64_t n_points;
+  const int64_t *offsets;   /* [n_beams+1], 0 .. n_points, non-decreasing */
+  const double *Cb;         /* [n_points][3] initial beam-cell centres C^b */
+  const double *Wref;       /* [n_points][3] fixed offsets W^ref, or NULL = 0 */
+  const double *W;          /* [n_points][3] current displacements W */
+  const double *eps_phys;   /* [n_points] physical kernel width (needed for eps) */
+  double eps_factor;        /* multiplier of the local cell size, > 0 (2 in Sec. 8) */
+} alp_beam_state;
+
+/* Point-wise geometry ahead of a step, stream-ordered on the context's
+   stream, asynchronous:
+     P       DEVICE out [n_points][3] (nullable): the actuator points of
+             eq. (15), P = (C^b + W^ref) + W.  (Their velocity is the
+             beam-cell velocity; nothing to compute.)
+     e_t     DEVICE out [n_points][3] (nullable): unit tangents of the spline
+             through the current cell centres x = C^b + W (Sec. 3.2.2).  The
+             node derivative is that of the parabola through three consecutive
+             centres parameterised by chord length (i-1, i, i+1; the first or
+             last three at the ends); a two-point beam takes its chord; a
+             zero-length chord falls back to the neighbouring one; a single
+             point, or only coincident centres, gets the zero vector (counted;
+             the step rejects a zero tangent, so the caller supplies one).
+     eps     DEVICE out [n_points] (nullable): the local kernel width of
+             Sec. 8, eps = max(eps_factor V_c^(1/3), eps_phys) with c the cell
+             of P (nearest centre, as for sampling); a point outside the
+             domain box keeps eps_phys (counted).  Needs `mesh` and eps_phys.
+     counts  DEVICE out int64 [2] (nullable): zero tangents, points outside.
+   ALP_ERR_INVALID_ARG for inconsistent sizes or offsets (the offsets are
+   read back to validate them, which waits for the caller's stream), nothing
+   requested, or eps without a mesh, eps_phys or a positive factor; not
+   allowed under capture. */
+alp_status alp_beam_geometry(alp_context *ctx, const alp_mesh *mesh, const alp_beam_state *state,
+                             double *P, double *e_t, double *eps, int64_t *counts);
+
 /* Library version string. */
 const char *alp_version(void);
 

@@ -26,7 +26,8 @@ USE_GRAPH, CHECKED = 1, 2
 # every symbol include/alp.h declares
 EXPORTS = ("alp_create", "alp_destroy", "alp_last_error", "alp_bin_cells", "alp_mesh_destroy",
            "alp_sample", "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag",
-           "alp_invalidate", "alp_version", "alp_step_profile", "alp_stage_name", "alp_autotune")
+           "alp_invalidate", "alp_version", "alp_step_profile", "alp_stage_name", "alp_autotune",
+           "alp_beam_geometry")
 
 
 class AlpError(RuntimeError):
@@ -71,6 +72,12 @@ class alp_case(ct.Structure):
                 ("cell_a", ct.c_void_p), ("cell_s", ct.c_void_p), ("dUdt", ct.c_void_p)]
 
 
+class alp_beam_state(ct.Structure):
+    _fields_ = [("n_beams", ct.c_int32), ("reserved0", ct.c_int32), ("n_points", ct.c_int64),
+                ("offsets", ct.c_void_p), ("Cb", ct.c_void_p), ("Wref", ct.c_void_p), ("W", ct.c_void_p),
+                ("eps_phys", ct.c_void_p), ("eps_factor", ct.c_double)]
+
+
 _lib = None
 
 
@@ -103,6 +110,8 @@ def load():
     lib.alp_autotune.argtypes = [vp, i64, vp, vp, vp, i32, ct.POINTER(alp_case), i32, u32, i32,
                                  ct.POINTER(ct.c_double), ct.POINTER(i32), ct.POINTER(ct.c_double)]
     lib.alp_autotune.restype = ct.c_int
+    lib.alp_beam_geometry.argtypes = [vp, vp, ct.POINTER(alp_beam_state), vp, vp, vp, vp]
+    lib.alp_beam_geometry.restype = ct.c_int
     lib.alp_stage_name.argtypes = [i32]
     lib.alp_stage_name.restype = ct.c_char_p
     for name in ("alp_create", "alp_destroy", "alp_bin_cells", "alp_mesh_destroy", "alp_sample",
@@ -208,6 +217,14 @@ def alp_autotune(ctx, C, V, cases, tuned_case=0, flags=USE_GRAPH, reps=3, domain
                                     int(tuned_case), int(flags), int(reps), ct.byref(bs), ct.byref(tb),
                                     ct.byref(ms)))
     return {"bin_size": bs.value, "tile_bins": tb.value, "ms": ms.value}
+
+
+def alp_beam_geometry(ctx, mesh, state, P=None, e_t=None, eps=None, counts=None):
+    """Actuator points (eq. 15), tangents and local kernel widths of a beam
+    state (alp_beam_state with device pointers) into the given device tensors
+    (each nullable)."""
+    _check(ctx, load().alp_beam_geometry(ctx, mesh, ct.byref(state), _ptr(P), _ptr(e_t), _ptr(eps),
+                                         _ptr(counts)))
 
 
 # ---------------------------------------------------------------- helpers --

@@ -894,6 +894,54 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
   return leave(ctx);
 }
 
+alp_status alp_beam_geometry(alp_context *ctx, const alp_mesh *mesh, const alp_beam_state *st, double *P,
+                             double *e_t, double *eps, int64_t *counts) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!st) return fail(ctx, ALP_ERR_INVALID_ARG, "state is NULL");
+  if (st->n_beams < 0 || st->n_points < 0 || st->n_points >= (int64_t)INT32_MAX || st->reserved0 != 0)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "bad beam counts (n_beams=%d, n_points=%lld)", st->n_beams,
+                (long long)st->n_points);
+  if (st->n_beams == 0 && st->n_points != 0) return fail(ctx, ALP_ERR_INVALID_ARG, "points without beams");
+  if (st->n_beams > 0 && !st->offsets) return fail(ctx, ALP_ERR_INVALID_ARG, "state.offsets is NULL");
+  if (st->n_points > 0 && (!st->Cb || !st->W)) return fail(ctx, ALP_ERR_INVALID_ARG, "state.Cb or state.W is NULL");
+  if (!P && !e_t && !eps) return fail(ctx, ALP_ERR_INVALID_ARG, "nothing requested");
+  if (eps && (!mesh || !st->eps_phys || !(st->eps_factor > 0.0) || !std::isfinite(st->eps_factor)))
+    return fail(ctx, ALP_ERR_INVALID_ARG, "eps needs a mesh, state.eps_phys and eps_factor > 0");
+  if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "alp_beam_geometry is not capturable");
+  if (st->n_beams > 0) {
+    std::vector<int64_t> off((size_t)st->n_beams + 1);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipMemcpyAsync(off.data(), st->offsets, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                               ctx->user));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->user));
+    if (off[0] != 0 || off[st->n_beams] != st->n_points)
+      return fail(ctx, ALP_ERR_INVALID_ARG, "state.offsets must start at 0 and end at n_points");
+    for (int32_t i = 0; i < st->n_beams; ++i)
+      if (off[i + 1] < off[i]) return fail(ctx, ALP_ERR_INVALID_ARG, "state.offsets decreases at %d", i);
+  }
+  alp_status rc;
+  if ((rc = enter(ctx)) != ALP_OK) return rc;
+  if (counts) HIPCHK(ctx, hipMemsetAsync(counts, 0, 2 * sizeof(int64_t), ctx->st));
+  GeomLaunch G{};
+  if (mesh) G.m = mesh->d;
+  G.n_beams = st->n_beams;
+  G.n_points = st->n_points;
+  G.offsets = st->offsets;
+  G.Cb = st->Cb;
+  G.Wref = st->Wref;
+  G.W = st->W;
+  G.eps_phys = st->eps_phys;
+  G.factor = st->eps_factor;
+  G.P = P;
+  G.e_t = e_t;
+  G.eps = eps;
+  G.counts = (unsigned long long *)counts;
+  launch_beam_geometry(G, ctx->st);
+  HIPCHK(ctx, hipGetLastError());
+  return leave(ctx);
+}
+
 alp_status alp_autotune(alp_context *ctx, int64_t n_cells, const double *C, const double *V,
                         const double *domain_box, int32_t n_cases, const alp_case *cases,
                         int32_t tuned_case, uint32_t flags, int32_t reps, double *out_bin_size,

@@ -287,6 +287,53 @@ __device__ __forceinline__ void seg_int_weights(double cx, double cy, double cz,
   a1 = Q * W1;
 }
 
+// The same weights under the split precision: the geometry (foot, axial and
+// radial distances, each divided by eps) in FP64, the Gaussian integrals in
+// FP32.  Below lam = 2 the 8-point Gauss-Legendre rule is exact to FP32
+// rounding and avoids the cancellation of the closed form; above it the
+// closed form loses at most a few FP32 ulps.  x1 is formed in FP64 so the
+// cancellation in x0 + lam never reaches the far-end erf.  Relative error
+// against the FP64 evaluation: below 2e-6 of a0 + a1.
+__device__ __forceinline__ void seg_int_weights_split(double cx, double cy, double cz, double ax, double ay,
+                                                      double az, double bx, double by, double bz, double eps,
+                                                      double &a0, double &a1) {
+#pragma clang fp contract(off)
+  const double ex = bx - ax, ey = by - ay, ez = bz - az;
+  const double qx = cx - ax, qy = cy - ay, qz = cz - az;
+  const double ee = (ex * ex + ey * ey) + ez * ez, l = sqrt(ee);
+  const double tau = ((qx * ex + qy * ey) + qz * ez) / ee;
+  const double px = qx - tau * ex, py = qy - tau * ey, pz = qz - tau * ez;
+  const double rp2 = (px * px + py * py) + pz * pz, t = tau * l;
+  const float x0 = (float)(-t / eps), x1 = (float)((l - t) / eps), lam = (float)(l / eps);
+  const float rr = (float)(rp2 / (eps * eps));
+  const float Q = expf(-rr) / (float)(3.14159265358979323846 * 1.77245385090551602730 * (eps * eps));
+  float W0 = 0.0f, W1 = 0.0f;
+  if (lam < 2.0f) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float w = (float)(0.5 * (k < 4 ? gl8::kW[3 - k] : gl8::kW[k - 4]));
+      const float sq = (float)(0.5 * (1.0 + (k < 4 ? -gl8::kX[3 - k] : gl8::kX[k - 4])));
+      const float y = sq * lam + x0, g = w * expf(-(y * y));
+      W0 += (1.0f - sq) * g;
+      W1 += sq * g;
+    }
+    W0 *= lam;
+    W1 *= lam;
+  } else {
+    float D;
+    if (x0 >= 0.0f) D = erfcf(x0) - erfcf(x1);
+    else if (x1 <= 0.0f) D = erfcf(-x1) - erfcf(-x0);
+    else D = erff(x1) - erff(x0);
+    const float d = (x1 - x0) * (x1 + x0);
+    const float dexp = d >= 0.0f ? -expf(-(x0 * x0)) * expm1f(-d) : expf(-(x1 * x1)) * expm1f(d);
+    const float E = 0.88622692545275801365f * D, M = 0.5f * dexp;
+    W0 = (x1 * E - M) / lam;
+    W1 = (M - x0 * E) / lam;
+  }
+  a0 = (double)(Q * W0);
+  a1 = (double)(Q * W1);
+}
+
 // Exact fixed-point accumulation (order independent, so deterministic under
 // any work distribution or atomic order).  A non-negative or signed value v
 // with |v| < 2^E is split into hi = floor(v 2^(46-E)) and
@@ -376,6 +423,18 @@ void launch_emit_scatter(const StepLaunch &L, hipStream_t st);
 void launch_tile_merge(const StepLaunch &L, hipStream_t st);
 void launch_items(const StepLaunch &L, hipStream_t st);
 void launch_sample(const StepLaunch &L, hipStream_t st);
+// Point-wise beam geometry ahead of a step (alp_beam_geometry).
+struct GeomLaunch {
+  MeshDev m;
+  int32_t n_beams, reserved;
+  int64_t n_points;
+  const int64_t *offsets;
+  const double *Cb, *Wref, *W, *eps_phys;
+  double factor;
+  double *P, *e_t, *eps;
+  unsigned long long *counts;  // [2]: zero tangents, points outside (or null)
+};
+void launch_beam_geometry(const GeomLaunch &G, hipStream_t st);
 void launch_sample_kernel(const StepLaunch &L, hipStream_t st);
 void launch_drag(const StepLaunch &L, hipStream_t st);
 void launch_weights(const StepLaunch &L, hipStream_t st);

@@ -831,6 +831,120 @@ void launch_sample(const StepLaunch &L, hipStream_t st) {
 // butterfly joins them.  The cutoff test uses the same FP64 expressions as
 // every other distance decision.  With no cell in reach the single-cell value
 // written by k_sample stays and the point is counted.
+// ------------------------------------------------------- beam geometry --
+// Helpers ahead of a step, one group of kSampleLanes lanes per point: the
+// actuator point of eq. (15), P = (C^b + W^ref) + W; the unit tangent from
+// the spline through the current cell centres x = C^b + W, whose node
+// derivative is the derivative of the parabola through three consecutive
+// centres parameterised by chord length (the first or last three at the
+// ends; the chord for two-point beams; a zero chord falls back to its
+// neighbour; no chord at all leaves a zero tangent, counted); and the local
+// kernel width max(factor V_c^(1/3), eps_phys) with c the cell of P (a point
+// outside the domain keeps eps_phys, counted).
+__device__ __forceinline__ void cur_centre(const GeomLaunch &G, int64_t k, double *x) {
+#pragma clang fp contract(off)
+  for (int a = 0; a < 3; ++a) x[a] = G.Cb[3 * k + a] + G.W[3 * k + a];
+}
+
+__device__ __forceinline__ double unit_chord(const double *a, const double *b, double *u) {
+#pragma clang fp contract(off)
+  const double e0 = b[0] - a[0], e1 = b[1] - a[1], e2 = b[2] - a[2];
+  const double l = sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+  u[0] = l > 0.0 ? e0 / l : 0.0;
+  u[1] = l > 0.0 ? e1 / l : 0.0;
+  u[2] = l > 0.0 ? e2 / l : 0.0;
+  return l;
+}
+
+__global__ __launch_bounds__(64) void k_beam_geometry(GeomLaunch G) {
+#pragma clang fp contract(off)
+  const int sub = threadIdx.x % kSampleLanes;
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSampleLanes;
+  if (k >= G.n_points) return;  // whole groups leave together
+  double P[3];
+  for (int a = 0; a < 3; ++a)
+    P[a] = (G.Cb[3 * k + a] + (G.Wref ? G.Wref[3 * k + a] : 0.0)) + G.W[3 * k + a];
+  bool zero = false;
+  double et[3] = {0.0, 0.0, 0.0};
+  if (G.e_t) {
+    // the beam of the point: the last b with offsets[b] <= k
+    int lo = 0, hi = G.n_beams - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (G.offsets[mid] <= k) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t k0 = G.offsets[lo], n = G.offsets[lo + 1] - k0, i = k - k0;
+    double m[3] = {0.0, 0.0, 0.0};
+    if (n == 2) {
+      double xa[3], xb[3];
+      cur_centre(G, k0, xa);
+      cur_centre(G, k0 + 1, xb);
+      unit_chord(xa, xb, m);
+    } else if (n >= 3) {
+      const int64_t a = i == 0 ? 0 : (i == n - 1 ? n - 3 : i - 1);
+      const int j = (int)(i - a);
+      double x0[3], x1[3], x2[3], u0[3], u1[3];
+      cur_centre(G, k0 + a, x0);
+      cur_centre(G, k0 + a + 1, x1);
+      cur_centre(G, k0 + a + 2, x2);
+      const double d0 = unit_chord(x0, x1, u0), d1 = unit_chord(x1, x2, u1);
+      if (d0 > 0.0 && d1 > 0.0) {
+        double w0, w1;
+        if (j == 0) {
+          w0 = 2.0 * d0 + d1;
+          w1 = -d0;
+        } else if (j == 1) {
+          w0 = d1;
+          w1 = d0;
+        } else {
+          w0 = -d1;
+          w1 = d0 + 2.0 * d1;
+        }
+        for (int c = 0; c < 3; ++c) m[c] = (w0 * u0[c] + w1 * u1[c]) / (d0 + d1);
+      } else if (d0 > 0.0 && j <= 1) {
+        for (int c = 0; c < 3; ++c) m[c] = u0[c];
+      } else if (d1 > 0.0 && j >= 1) {
+        for (int c = 0; c < 3; ++c) m[c] = u1[c];
+      } else if (d0 > 0.0) {
+        for (int c = 0; c < 3; ++c) m[c] = u0[c];
+      } else if (d1 > 0.0) {
+        for (int c = 0; c < 3; ++c) m[c] = u1[c];
+      }
+    }
+    const double l = sqrt((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2]);
+    zero = !(l > 0.0);
+    for (int c = 0; c < 3; ++c) et[c] = zero ? 0.0 : m[c] / l;
+  }
+  double ek = 0.0;
+  bool out = false;
+  if (G.eps) {
+    const int64_t c = locate_group(G.m, P[0], P[1], P[2], sub);
+    ek = G.eps_phys[k];
+    if (c < 0) {
+      out = true;
+    } else {
+      const double dx = G.factor * cbrt(G.m.vs[c]);
+      if (dx > ek) ek = dx;
+    }
+  }
+  if (sub == 0) {
+    if (G.P)
+      for (int a = 0; a < 3; ++a) G.P[3 * k + a] = P[a];
+    if (G.e_t)
+      for (int a = 0; a < 3; ++a) G.e_t[3 * k + a] = et[a];
+    if (G.eps) G.eps[k] = ek;
+    if (G.counts && zero) atomicAdd(&G.counts[0], 1ull);
+    if (G.counts && out) atomicAdd(&G.counts[1], 1ull);
+  }
+}
+
+void launch_beam_geometry(const GeomLaunch &G, hipStream_t st) {
+  if (G.n_points == 0) return;
+  const int64_t threads = G.n_points * kSampleLanes;
+  hipLaunchKernelGGL(k_beam_geometry, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, st, G);
+}
+
 __global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
 #pragma clang fp contract(off)
   Work W = L.w;
@@ -1036,6 +1150,19 @@ __device__ __forceinline__ int entry_of_point(const WeightsScratch &sh, int n_st
   }
   return lo;
 }
+
+// Scratch of the integrated rule's weights pass: the candidates of a round
+// (cell lane, entry, first pair index) and a ring of pairs in reach waiting
+// for their weights (descriptor: cell lane | entry << 6 | segment << 14, and
+// the record index).
+constexpr uint32_t kIntRing = 128;
+struct IntScratch {
+  uint8_t lc[64], ent[64];
+  uint32_t pre[64];
+  uint32_t qd[kIntRing], qp[kIntRing];
+};
+constexpr uint32_t kIntMaxSeg = 1u << 18;  // window segments a descriptor can name
+static_assert(kMaxEntries <= 256, "entry field of the ring descriptor");
 
 // Candidate p of a work item (in cell-lane order, then entry order): its
 // cell lane Lc and entry e, from the per-lane prefix counts and hit masks.
@@ -1343,35 +1470,47 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     uint32_t nreal = 0;
     if constexpr (kInt) {
       // 3.-5. segment-integrated kernel: every window segment within the
-      // cutoff of the cell gives one record (cell, segment).  A counting pass
-      // sizes the item's records; the writing pass takes the same decisions.
-      uint32_t n_rec = 0;
+      // cutoff of the cell gives one record (cell, segment).  The (candidate,
+      // segment) pairs are spread over the lanes, 64 at a time; the pairs in
+      // reach go, in order, to a ring of descriptors whose weights are then
+      // evaluated 64 at a time.  Records follow candidate order, so they stay
+      // sorted by cell.
+      __shared__ IntScratch si;
+      // upper bound of the item's records (every window segment of every
+      // candidate); the unused tail goes back to the wave's block at the end
+      uint32_t ub = 0;
       for (uint32_t p0 = 0; p0 < total; p0 += 64) {
         const uint32_t p = p0 + lane;
-        const bool act = p < total;
         int Lc = lane, e = 0;
-        if (act) candidate(sh, nwords, p, Lc, e);
-        const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
-        const uint32_t c = act ? int_count(cs, sh.e_k0[e], sh.e_i0[e], sh.e_i1[e], pcx, pcy, pcz) : 0u;
+        uint32_t n = 0;
+        if (p < total) {
+          candidate(sh, nwords, p, Lc, e);
+          n = sh.e_i1[e] < 0 ? 1u : (uint32_t)(sh.e_i1[e] - sh.e_i0[e] + 1);
+          if (n > kIntMaxSeg) {
+            set_overflow(W, 16u);  // reported as a per-tile limit
+            n = 0;
+          }
+        }
         uint32_t tot;
-        wave_excl_scan_u32(c, tot);
-        n_rec += tot;
+        wave_excl_scan_u32(n, tot);
+        ub += tot;
       }
-      reserve(n_rec);
-      for (uint32_t p0 = 0; p0 < total; p0 += 64) {
-        const uint32_t p = p0 + lane;
-        const bool act = p < total;
-        int Lc = lane, e = 0;
-        if (act) candidate(sh, nwords, p, Lc, e);
+      reserve(ub);
+      uint32_t qh = 0, qt = 0;  // ring head and tail (wave-uniform)
+      // weights of ring entries qh .. qh + n - 1, one per lane
+      auto drain = [&](uint32_t n) {
+        const bool on = (uint32_t)lane < n;
+        uint32_t d = 0, pos = 0;
+        if (on) {
+          d = si.qd[(qh + lane) & (kIntRing - 1)];
+          pos = si.qp[(qh + lane) & (kIntRing - 1)];
+        }
+        const int Lc = (int)(d & 63u), e = (int)((d >> 6) & 255u), j = (int)(d >> 14);
         const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
         const double pv = __shfl(v, Lc, 64);
-        const int k0 = act ? sh.e_k0[e] : 0, i0 = act ? sh.e_i0[e] : 0, i1 = act ? sh.e_i1[e] : -1;
-        const uint32_t c = act ? int_count(cs, k0, i0, i1, pcx, pcy, pcz) : 0u;
-        uint32_t tot;
-        const uint32_t off = wave_excl_scan_u32(c, tot);
-        if (c > 0) {
-          const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
-          // node q of the entry gets a V: staged nodes in LDS, others in HBM
+        if (on) {
+          const int k0 = sh.e_k0[e], i0 = sh.e_i0[e], i1 = sh.e_i1[e];
+          const int pt0 = e < n_staged ? sh.e_pt0[e] : -1;
           auto acc = [&](int q, double av) {
             long long h;
             unsigned long long l;
@@ -1386,7 +1525,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               atomicAdd(&W.w_lo[node], l);
             }
           };
-          unsigned char *r = W.rec + rbase + (unsigned long long)(nreal + off) * rsz;
+          unsigned char *r = W.rec + rbase + (unsigned long long)pos * rsz;
           if (i1 < 0) {
             // single-CV beam: the point kernel of the nearest rule
             const double *P = cs.Psp + 3 * (int64_t)k0;
@@ -1395,28 +1534,102 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
             acc(0, a0 * pv);
             if (rec_ok) write_record(r, rsz, (uint32_t)Lc | kRecSingle, (uint32_t)(cs.point_base + k0), a0, 0.0);
           } else {
-            const double *X = cs.Psp + 3 * ((int64_t)k0 + i0);
-            const double *E = cs.eps + (int64_t)k0 + i0;
-            const int nseg = i1 - i0 + 1;
-            for (int j = 0; j < nseg; ++j) {
-              const double *A = X + 3 * j;
-              double es;
-              if (!seg_in_reach(A, E[j], E[j + 1], pcx, pcy, pcz, es)) continue;
-              double a0, a1;
-              seg_int_weights(pcx, pcy, pcz, A[0], A[1], A[2], A[3], A[4], A[5], es, a0, a1);
-              if (cs.prec == ALP_PREC_FP32_SPLIT) {
-                a0 = (double)(float)a0;
-                a1 = (double)(float)a1;
-              }
-              acc(j, a0 * pv);
-              acc(j + 1, a1 * pv);
-              if (rec_ok) write_record(r, rsz, (uint32_t)Lc, (uint32_t)(cs.point_base + k0 + i0 + j), a0, a1);
-              r += rsz;
-            }
+            const double *A = cs.Psp + 3 * ((int64_t)k0 + i0 + j);
+            const double *E = cs.eps + (int64_t)k0 + i0 + j;
+            double a0, a1;
+            if (cs.prec == ALP_PREC_FP32_SPLIT)
+              seg_int_weights_split(pcx, pcy, pcz, A[0], A[1], A[2], A[3], A[4], A[5], 0.5 * (E[0] + E[1]), a0, a1);
+            else
+              seg_int_weights(pcx, pcy, pcz, A[0], A[1], A[2], A[3], A[4], A[5], 0.5 * (E[0] + E[1]), a0, a1);
+            acc(j, a0 * pv);
+            acc(j + 1, a1 * pv);
+            if (rec_ok) write_record(r, rsz, (uint32_t)Lc, (uint32_t)(cs.point_base + k0 + i0 + j), a0, a1);
           }
         }
-        nreal += tot;
+        qh += n;
+      };
+      for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+        const uint32_t p = p0 + lane;
+        int Lc = lane, e = 0;
+        uint32_t n = 0;
+        if (p < total) {
+          candidate(sh, nwords, p, Lc, e);
+          n = sh.e_i1[e] < 0 ? 1u : (uint32_t)(sh.e_i1[e] - sh.e_i0[e] + 1);
+          if (n > kIntMaxSeg) {
+            set_overflow(W, 16u);  // reported as a per-tile limit
+            n = 0;
+          }
+        }
+        uint32_t T;
+        const uint32_t pre = wave_excl_scan_u32(n, T);
+        si.lc[lane] = (uint8_t)Lc;
+        si.ent[lane] = (uint8_t)e;
+        si.pre[lane] = pre;
+        __syncthreads();
+        for (uint32_t t0 = 0; t0 < T; t0 += 64) {
+          const uint32_t t = t0 + lane;
+          const bool on = t < T;
+          // the candidate owning pair t: the last o with pre[o] <= t
+          int o = 0;
+          if (on) {
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (si.pre[mid] <= t) lo = mid;
+              else hi = mid - 1;
+            }
+            o = lo;
+          }
+          const int cl = si.lc[o], ce = si.ent[o];
+          const int j = (int)(t - si.pre[o]);
+          const double pcx = __shfl(cx, cl, 64), pcy = __shfl(cy, cl, 64), pcz = __shfl(cz, cl, 64);
+          bool in = false;
+          if (on) {
+            const int k0 = sh.e_k0[ce], i0 = sh.e_i0[ce], i1 = sh.e_i1[ce];
+            if (i1 < 0) {
+              const double *P = cs.Psp + 3 * (int64_t)k0;
+              in = inside_cutoff(sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]), cs.eps[k0]);
+            } else {
+              const double *E = cs.eps + (int64_t)k0 + i0 + j;
+              const int pt0 = ce < n_staged ? sh.e_pt0[ce] : -1;
+              bool out = false;
+              if (pt0 >= 0) {
+                // FP32 distance from the staged points: a segment clearly
+                // beyond the cutoff (by more than the FP32 error allowance)
+                // is out; every other one takes the exact FP64 test
+                const float4 A = sh.sa[pt0 + j], B = sh.sa[pt0 + j + 1];
+                const float qx = (float)(pcx - ctx), qy = (float)(pcy - cty), qz = (float)(pcz - ctz);
+                const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
+                float dx = qx - A.x, dy = qy - A.y, dz = qz - A.z;
+                const float sg = __saturatef((dx * ex + dy * ey + dz * ez) * A.w);
+                dx -= sg * ex;
+                dy -= sg * ey;
+                dz -= sg * ez;
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                const float es = (float)(0.5 * (E[0] + E[1]));
+                out = d2 > 9.0f * es * es * (1.0f + 0x1p-20f) + sh.e_dabs[ce];
+              }
+              double es64;
+              in = !out && seg_in_reach(cs.Psp + 3 * ((int64_t)k0 + i0 + j), E[0], E[1], pcx, pcy, pcz, es64);
+            }
+          }
+          const uint64_t bal = ballot64(in);
+          if (in) {
+            const uint32_t rank = lanemask_lt_popc(bal);
+            si.qd[(qt + rank) & (kIntRing - 1)] = (uint32_t)cl | ((uint32_t)ce << 6) | ((uint32_t)j << 14);
+            si.qp[(qt + rank) & (kIntRing - 1)] = nreal + rank;
+          }
+          const uint32_t nin = (uint32_t)__popcll(bal);
+          nreal += nin;
+          qt += nin;
+          __syncthreads();
+          if (qt - qh >= 64) drain(64);
+        }
+        __syncthreads();
       }
+      if (qt > qh) drain(qt - qh);
+      // give back the unused tail of the reservation
+      blk_cur = rbase + (((unsigned long long)nreal * rsz + 15ull) & ~15ull);
     } else {
       // record space for up to `total` pairs (one per candidate)
       reserve(total);
