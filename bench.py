@@ -33,6 +33,7 @@ BYTES_PER_BAND_CELL = 92     # 2 x (FP64 centre 24 B + volume 8 B) + source 24 B
 BYTES_PER_POINT = 272        # P, e_t, Pdot (72) + d, L, eps (24) + 2 velocity gathers (48)
                              # + f, U_s, P_s, w (80) + f_hat written and read (48)
 BYTES_WEIGHTS_PER_BAND_CELL = 32   # weights pass: FP64 centre + volume
+OPS_WEIGHTS_PER_PAIR = 50          # foot of eq. 21, eps_j, cutoff, eta of eq. 22, a0 a1, a V (lane-ops)
 
 
 def parse():
@@ -263,6 +264,12 @@ def main():
     roofline = {"kernel": "k_weights", "bound": "hbm", "achieved": ach_w, "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": ach_w / HBM_PEAK_GBPS, "traffic": traffic,
                 "alg_bytes_per_launch": bytes_w, "avg_ms": stages["weights"]}
+    # the same kernel against the VALU roof: it issues far more instructions
+    # than the method's arithmetic needs, so this view is reported beside
+    ops_w = n_pairs * OPS_WEIGHTS_PER_PAIR
+    roofline_alu = {"kernel": "k_weights", "bound": "alu", "achieved": ops_w / t_w / 1e12,
+                    "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s", "frac": ops_w / t_w / 1e12 / VALU_PEAK_TOPS,
+                    "alg_ops_per_launch": ops_w}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -297,6 +304,7 @@ def main():
         "cell_updates_per_s": n_pairs / t_split, "band_cells_per_s": n_band / t_split,
         "mesh_cells_per_s": n_cells / t_split, "alg_hbm_gbps": gbps, "alg_hbm_frac": gbps / HBM_PEAK_GBPS,
         "cons_rel_err": diag["cons_rel_err"], "stages_ms": stages, "roofline": roofline,
+        "roofline_alu": roofline_alu,
         "cpu_baseline": cpu, **res,
         "other_workloads": extra,
     }

@@ -20,7 +20,7 @@ struct alp_mesh {
   int device = 0;
   MeshDev d{};
   uint32_t *bin_start = nullptr;
-  double *cx = nullptr, *cy = nullptr, *cz = nullptr, *vs = nullptr;
+  double *cx = nullptr, *cy = nullptr, *cz = nullptr, *vs = nullptr, *cxyz = nullptr;
   uint32_t *perm = nullptr;
   uint8_t *tile_prev = nullptr;
   const double *last_S = nullptr;  // output array the band state refers to
@@ -691,6 +691,7 @@ alp_status alp_bin_cells(alp_context *ctx, int64_t n_cells, const double *C, con
     return rc;                                    \
   }
   MALLOC_OR_FAIL(m->bin_start, nbins + 1);
+  MALLOC_OR_FAIL(m->cxyz, 3 * n_cells);
   MALLOC_OR_FAIL(m->cx, n_cells);
   MALLOC_OR_FAIL(m->cy, n_cells);
   MALLOC_OR_FAIL(m->cz, n_cells);
@@ -709,7 +710,7 @@ alp_status alp_bin_cells(alp_context *ctx, int64_t n_cells, const double *C, con
   launch_scan_u32(count, m->bin_start, nbins, tmp, st);
   launch_bin_scatter(key, n_cells, m->bin_start, fillc, m->perm, st);
   launch_bin_sort(m->bin_start, nbins, m->perm, st);
-  launch_bin_reorder(C, V, m->perm, n_cells, m->cx, m->cy, m->cz, m->vs, st);
+  launch_bin_reorder(C, V, m->perm, n_cells, m->cxyz, m->cx, m->cy, m->cz, m->vs, st);
   hipError_t e = hipStreamSynchronize(st);
   (void)hipFree(key);
   (void)hipFree(count);
@@ -720,6 +721,7 @@ alp_status alp_bin_cells(alp_context *ctx, int64_t n_cells, const double *C, con
     return fail(ctx, ALP_ERR_HIP, "binning failed: %s", hipGetErrorString(e));
   }
   d.bin_start = m->bin_start;
+  d.cxyz = m->cxyz;
   d.cx = m->cx;
   d.cy = m->cy;
   d.cz = m->cz;
@@ -733,7 +735,7 @@ alp_status alp_mesh_destroy(alp_mesh *m) {
   if (!m) return ALP_ERR_INVALID_ARG;
   (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
-  void *ps[] = {m->bin_start, m->cx, m->cy, m->cz, m->vs, m->perm, m->tile_prev};
+  void *ps[] = {m->bin_start, m->cxyz, m->cx, m->cy, m->cz, m->vs, m->perm, m->tile_prev};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   delete m;

@@ -32,6 +32,8 @@ struct MeshDev {
   double vmax;      // largest cell volume
   const uint32_t *bin_start;  // [n_bins+1] sorted-cell ranges, bins in tile-major order
   const double *cx, *cy, *cz; // [n] sorted centres (FP64, absolute)
+  const double *cxyz;         // [n][3] the same centres interleaved (point location reads
+                              // a cell's three coordinates from one place)
   const double *vs;           // [n] sorted volumes
   const uint32_t *perm;       // [n] sorted -> caller index
 };
@@ -394,7 +396,7 @@ void launch_bin_keys(const MeshDev &m, const double *C, int64_t n, uint32_t *key
 void launch_bin_scatter(const uint32_t *key, int64_t n, const uint32_t *start, uint32_t *fill,
                         uint32_t *sorted, hipStream_t st);
 void launch_bin_sort(const uint32_t *start, int64_t n_bins, uint32_t *sorted, hipStream_t st);
-void launch_bin_reorder(const double *C, const double *V, const uint32_t *sorted, int64_t n,
+void launch_bin_reorder(const double *C, const double *V, const uint32_t *sorted, int64_t n, double *cxyz,
                         double *cx, double *cy, double *cz, double *vs, hipStream_t st);
 
 // step

@@ -215,20 +215,24 @@ void launch_bin_sort(const uint32_t *start, int64_t n_bins, uint32_t *sorted, hi
 }
 
 __global__ void k_bin_reorder(const double *C, const double *V, const uint32_t *sorted, int64_t n,
-                              double *cx, double *cy, double *cz, double *vs) {
+                              double *cxyz, double *cx, double *cy, double *cz, double *vs) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   uint32_t c = sorted[p];
-  cx[p] = C[3 * (int64_t)c + 0];
-  cy[p] = C[3 * (int64_t)c + 1];
-  cz[p] = C[3 * (int64_t)c + 2];
+  const double x = C[3 * (int64_t)c + 0], y = C[3 * (int64_t)c + 1], z = C[3 * (int64_t)c + 2];
+  cx[p] = x;
+  cy[p] = y;
+  cz[p] = z;
+  cxyz[3 * p + 0] = x;
+  cxyz[3 * p + 1] = y;
+  cxyz[3 * p + 2] = z;
   vs[p] = V[c];
 }
 
-void launch_bin_reorder(const double *C, const double *V, const uint32_t *sorted, int64_t n,
+void launch_bin_reorder(const double *C, const double *V, const uint32_t *sorted, int64_t n, double *cxyz,
                         double *cx, double *cy, double *cz, double *vs, hipStream_t st) {
   hipLaunchKernelGGL(k_bin_reorder, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C, V,
-                     sorted, n, cx, cy, cz, vs);
+                     sorted, n, cxyz, cx, cy, cz, vs);
 }
 
 }  // namespace alp

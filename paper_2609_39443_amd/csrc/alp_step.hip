@@ -637,12 +637,10 @@ __device__ __forceinline__ bool closer_cell(const MeshDev &m, double D, int64_t 
   if (best < 0) return true;
   if (D < bD) return true;
   if (D > bD) return false;
-  double a0 = m.cx[j], b0 = m.cx[best];
-  if (a0 != b0) return a0 < b0;
-  double a1 = m.cy[j], b1 = m.cy[best];
-  if (a1 != b1) return a1 < b1;
-  double a2 = m.cz[j], b2 = m.cz[best];
-  if (a2 != b2) return a2 < b2;
+  const double *a = m.cxyz + 3 * j, *b = m.cxyz + 3 * best;
+  if (a[0] != b[0]) return a[0] < b[0];
+  if (a[1] != b[1]) return a[1] < b[1];
+  if (a[2] != b[2]) return a[2] < b[2];
   return m.perm[j] < m.perm[best];
 }
 
@@ -676,7 +674,8 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
       uint32_t k = bin_key(m, ix, iy, iz);
       uint32_t e = m.bin_start[k + 1];
       for (uint32_t j = m.bin_start[k]; j < e; ++j) {
-        double D = sqdist_exact(x, y, z, m.cx[j], m.cy[j], m.cz[j]);
+        const double *cj = m.cxyz + 3 * (int64_t)j;
+        double D = sqdist_exact(x, y, z, cj[0], cj[1], cj[2]);
         if (closer_cell(m, D, j, bD, best)) {
           best = j;
           bD = D;
