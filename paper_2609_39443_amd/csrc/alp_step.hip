@@ -1591,11 +1591,13 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
             } else {
               const double *E = cs.eps + (int64_t)k0 + i0 + j;
               const int pt0 = ce < n_staged ? sh.e_pt0[ce] : -1;
-              bool out = false;
+              bool out = false, sure_in = false;
               if (pt0 >= 0) {
                 // FP32 distance from the staged points: a segment clearly
                 // beyond the cutoff (by more than the FP32 error allowance)
-                // is out; every other one takes the exact FP64 test
+                // is out, one clearly inside it is in (a non-zero FP32 length
+                // implies distinct FP64 end points); the rest take the exact
+                // FP64 test, whose decision both shortcuts reproduce
                 const float4 A = sh.sa[pt0 + j], B = sh.sa[pt0 + j + 1];
                 const float qx = (float)(pcx - ctx), qy = (float)(pcy - cty), qz = (float)(pcz - ctz);
                 const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
@@ -1606,10 +1608,13 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
                 dz -= sg * ez;
                 const float d2 = dx * dx + dy * dy + dz * dz;
                 const float es = (float)(0.5 * (E[0] + E[1]));
-                out = d2 > 9.0f * es * es * (1.0f + 0x1p-20f) + sh.e_dabs[ce];
+                const float cut = 9.0f * es * es;
+                out = d2 > cut * (1.0f + 0x1p-20f) + sh.e_dabs[ce];
+                sure_in = A.w > 0.f && d2 < cut * (1.0f - 0x1p-20f) - sh.e_dabs[ce];
               }
               double es64;
-              in = !out && seg_in_reach(cs.Psp + 3 * ((int64_t)k0 + i0 + j), E[0], E[1], pcx, pcy, pcz, es64);
+              in = sure_in ||
+                   (!out && seg_in_reach(cs.Psp + 3 * ((int64_t)k0 + i0 + j), E[0], E[1], pcx, pcy, pcz, es64));
             }
           }
           const uint64_t bal = ballot64(in);
