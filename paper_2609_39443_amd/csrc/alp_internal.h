@@ -258,9 +258,11 @@ __device__ __forceinline__ void seg_int_weights(double cx, double cy, double cz,
   const double tau = ((qx * ex + qy * ey) + qz * ez) / ee;
   const double px = qx - tau * ex, py = qy - tau * ey, pz = qz - tau * ez;
   const double rp2 = (px * px + py * py) + pz * pz, t = tau * l;
-  const double x0 = -t / eps, x1 = (l - t) / eps, lam = l / eps;
+  // one reciprocal for the four quotients by eps (last-ulp differences only)
+  const double ie = 1.0 / eps;
+  const double x0 = -t * ie, x1 = (l - t) * ie, lam = l * ie;
   const double kPi = 3.14159265358979323846, kSqrtPi = 1.77245385090551602730;
-  const double Q = exp(-(rp2 / (eps * eps))) / (kPi * kSqrtPi * (eps * eps));
+  const double Q = exp(-(rp2 * (ie * ie))) * (ie * ie) * (1.0 / (kPi * kSqrtPi));
   double W0 = 0.0, W1 = 0.0;
   if (lam < 0.125) {
 #pragma unroll
@@ -306,9 +308,10 @@ __device__ __forceinline__ void seg_int_weights_split(double cx, double cy, doub
   const double tau = ((qx * ex + qy * ey) + qz * ez) / ee;
   const double px = qx - tau * ex, py = qy - tau * ey, pz = qz - tau * ez;
   const double rp2 = (px * px + py * py) + pz * pz, t = tau * l;
-  const float x0 = (float)(-t / eps), x1 = (float)((l - t) / eps), lam = (float)(l / eps);
-  const float rr = (float)(rp2 / (eps * eps));
-  const float Q = expf(-rr) / (float)(3.14159265358979323846 * 1.77245385090551602730 * (eps * eps));
+  const double ie = 1.0 / eps;  // one reciprocal for the quotients by eps
+  const float x0 = (float)(-t * ie), x1 = (float)((l - t) * ie), lam = (float)(l * ie);
+  const float rr = (float)(rp2 * (ie * ie));
+  const float Q = expf(-rr) * (float)((ie * ie) * (1.0 / (3.14159265358979323846 * 1.77245385090551602730)));
   float W0 = 0.0f, W1 = 0.0f;
   if (lam < 2.0f) {
 #pragma unroll

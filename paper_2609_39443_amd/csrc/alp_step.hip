@@ -1159,6 +1159,7 @@ struct IntScratch {
   uint8_t lc[64], ent[64];
   uint32_t pre[64];
   uint32_t qd[kIntRing], qp[kIntRing];
+  uint32_t emin[kMaxEntries];  // smallest eps of each staged window (FP32, rounded down)
 };
 constexpr uint32_t kIntMaxSeg = 1u << 18;  // window segments a descriptor can name
 static_assert(kMaxEntries <= 256, "entry field of the ring descriptor");
@@ -1475,6 +1476,19 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       // evaluated 64 at a time.  Records follow candidate order, so they stay
       // sorted by cell.
       __shared__ IntScratch si;
+      // smallest eps of each staged window, rounded down to FP32: with the
+      // largest (rounded up) it brackets eps_seg of every segment
+      for (uint32_t e = lane; e < ne; e += 64) si.emin[e] = 0x7f7fffffu;  // FLT_MAX
+      __syncthreads();
+      for (int q = lane; q < npts; q += 64) {
+        const int e = entry_of_point(sh, n_staged, q);
+        const int64_t k = sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
+        const double ep = cs.eps[k];
+        float ef = (float)ep;
+        if ((double)ef > ep) ef = nextafterf(ef, 0.f);
+        atomicMin(&si.emin[e], __float_as_uint(fmaxf(ef, 0.f)));
+      }
+      __syncthreads();
       // upper bound of the item's records (every window segment of every
       // candidate); the unused tail goes back to the wave's block at the end
       uint32_t ub = 0;
@@ -1607,10 +1621,10 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
                 dy -= sg * ey;
                 dz -= sg * ez;
                 const float d2 = dx * dx + dy * dy + dz * dz;
-                const float es = (float)(0.5 * (E[0] + E[1]));
-                const float cut = 9.0f * es * es;
-                out = d2 > cut * (1.0f + 0x1p-20f) + sh.e_dabs[ce];
-                sure_in = A.w > 0.f && d2 < cut * (1.0f - 0x1p-20f) - sh.e_dabs[ce];
+                // eps_seg lies between the window's smallest and largest eps
+                const float eh = __uint_as_float(sh.e_em[ce]), el = __uint_as_float(si.emin[ce]);
+                out = d2 > 9.0f * eh * eh * (1.0f + 0x1p-20f) + sh.e_dabs[ce];
+                sure_in = A.w > 0.f && d2 < 9.0f * el * el * (1.0f - 0x1p-20f) - sh.e_dabs[ce];
               }
               double es64;
               in = sure_in ||
