@@ -55,7 +55,7 @@ struct alp_context {
   uint32_t gflags = 0;
   int last_cases = 0;
   int any_kernel_sample = 0;  // some case of the uploaded batch samples with the kernel
-  int any_proj[2] = {0, 0};   // the uploaded batch has cases of each projection rule
+  int any_proj[3] = {0, 0, 0};  // the uploaded batch has nearest, integrated split, integrated FP64 cases
 };
 
 namespace {
@@ -376,10 +376,10 @@ StepShape shape_cases(alp_context *ctx, std::vector<CaseDev> &cs) {
 alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const StepShape &sh) {
   alp_status rc;
   ctx->any_kernel_sample = 0;
-  ctx->any_proj[0] = ctx->any_proj[1] = 0;
+  ctx->any_proj[0] = ctx->any_proj[1] = ctx->any_proj[2] = 0;
   for (const CaseDev &c : cs) {
     if (c.sample_mode == ALP_SAMPLE_KERNEL) ctx->any_kernel_sample = 1;
-    ctx->any_proj[c.proj_mode == ALP_PROJ_INTEGRATED ? 1 : 0] = 1;
+    ctx->any_proj[c.proj_mode != ALP_PROJ_INTEGRATED ? 0 : (c.prec == ALP_PREC_FP32_SPLIT ? 1 : 2)] = 1;
   }
   if ((rc = ensure_cases(ctx, (int)cs.size())) != ALP_OK) return rc;
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_cases, cs.data(), cs.size() * sizeof(CaseDev),
@@ -408,7 +408,8 @@ StepLaunch make_launch(alp_context *ctx, int n_cases) {
   L.grid_persistent = ctx->n_cu * 8;
   L.kernel_sample = ctx->any_kernel_sample;
   L.proj_nearest = ctx->any_proj[0];
-  L.proj_integrated = ctx->any_proj[1];
+  L.int_split = ctx->any_proj[1];
+  L.int_fp64 = ctx->any_proj[2];
   return L;
 }
 

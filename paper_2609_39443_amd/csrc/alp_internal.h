@@ -147,7 +147,8 @@ struct Work {
   long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, empty kernel sample
   double *diag_out;     // [n_cases][16] finalised diagnostics
   // scalars
-  uint32_t *counters;   // [32]: 3 overflow flags, 8-15 weights work queue
+  uint32_t *counters;   // [32]: 3 overflow flags; work queues: 8-15 nearest weights, 16-23 integrated
+                        // split, 24-31 integrated FP64
   int64_t cap_emit, cap_item, cap_rec, cap_chunk;
   int64_t n_points, n_beams, n_tiles;
   int32_t n_cases, n_pblocks;
@@ -413,7 +414,7 @@ struct StepLaunch {
   int grid_persistent;     // blocks for persistent wave kernels
   int kernel_sample;       // some case uses ALP_SAMPLE_KERNEL
   int proj_nearest;        // some case projects with ALP_PROJ_NEAREST
-  int proj_integrated;     // some case projects with ALP_PROJ_INTEGRATED
+  int int_split, int_fp64; // some case projects with ALP_PROJ_INTEGRATED in that precision
 };
 void launch_step_reset(const StepLaunch &L, hipStream_t st);
 void launch_step_reset_sample(const StepLaunch &L, hipStream_t st);

@@ -1244,7 +1244,7 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 // One kernel per projection rule (kInt: segment-integrated), so that each
 // keeps its own register allocation; each takes only the items of its own
 // cases, from its own work-queue counters.
-template <bool kInt>
+template <bool kInt, bool kSplit>
 __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   Work W = L.w;
   __shared__ WeightsScratch sh;
@@ -1254,11 +1254,13 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   unsigned long long blk_cur = 0, blk_end = 0;
   int acc_case = -1;
   unsigned long long acc_pairs = 0;
-  WorkQueue wq = work_queue(W.counters + (kInt ? 16 : 8), (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
+  WorkQueue wq = work_queue(W.counters + (kInt ? (kSplit ? 16 : 24) : 8), (uint32_t)min((int64_t)n_items, W.cap_item),
+                            4u);
   while (wq.next(lane)) {
     const uint32_t item = wq.item;
     const Item it = W.item[item];
     if ((L.cases[it.cs].proj_mode == ALP_PROJ_INTEGRATED) != kInt) continue;
+    if (kInt && (L.cases[it.cs].prec == ALP_PREC_FP32_SPLIT) != kSplit) continue;
     if (it.cs != acc_case) {
       if (lane == 0 && acc_case >= 0 && acc_pairs)
         atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
@@ -1550,7 +1552,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
             const double *A = cs.Psp + 3 * ((int64_t)k0 + i0 + j);
             const double *E = cs.eps + (int64_t)k0 + i0 + j;
             double a0, a1;
-            if (cs.prec == ALP_PREC_FP32_SPLIT)
+            if constexpr (kSplit)
               seg_int_weights_split(pcx, pcy, pcz, A[0], A[1], A[2], A[3], A[4], A[5], 0.5 * (E[0] + E[1]), a0, a1);
             else
               seg_int_weights(pcx, pcy, pcz, A[0], A[1], A[2], A[3], A[4], A[5], 0.5 * (E[0] + E[1]), a0, a1);
@@ -1807,19 +1809,25 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
 
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
 void k_weights(StepLaunch L) {
-  weights_pass<false>(L);
+  weights_pass<false, false>(L);
 }
 
-// the integrated rule's evaluation (erf, erfc, expm1) needs more registers:
-// two waves per SIMD, up to 256 VGPRs
-__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(2)))
+// the integrated rule, one kernel per precision: the split one (FP32
+// Gaussian integrals) runs at four waves per SIMD; the FP64 one (erf, erfc,
+// expm1 in FP64) needs more registers, two waves per SIMD
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
 void k_weights_int(StepLaunch L) {
-  weights_pass<true>(L);
+  weights_pass<true, true>(L);
+}
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(2)))
+void k_weights_int64(StepLaunch L) {
+  weights_pass<true, false>(L);
 }
 
 void launch_weights(const StepLaunch &L, hipStream_t st) {
   if (L.proj_nearest) hipLaunchKernelGGL(k_weights, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
-  if (L.proj_integrated) hipLaunchKernelGGL(k_weights_int, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
+  if (L.int_split) hipLaunchKernelGGL(k_weights_int, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
+  if (L.int_fp64) hipLaunchKernelGGL(k_weights_int64, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------------- norm --
