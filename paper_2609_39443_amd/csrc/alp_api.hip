@@ -55,7 +55,7 @@ struct alp_context {
   uint32_t gflags = 0;
   int last_cases = 0;
   int any_kernel_sample = 0;  // some case of the uploaded batch samples with the kernel
-  int any_proj[3] = {0, 0, 0};  // the uploaded batch has nearest, integrated split, integrated FP64 cases
+  int any_proj[4] = {0, 0, 0, 0};  // the uploaded batch has cases of each (rule, precision)
 };
 
 namespace {
@@ -204,12 +204,12 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(pblock_range, 2 * PB);
   WALLOC(cnt, 8 * NC);
   WALLOC(diag_out, 16 * NC);
-  WALLOC(counters, 32);
+  WALLOC(counters, kCounters);
 #undef WALLOC
   int64_t sc = scan_tmp_words(std::max({B + 1, T + 1, CH + 1, (int64_t)1}));
   if ((rc = dalloc(ctx, &ctx->scan_tmp, sc)) != ALP_OK) return rc;
   ctx->have_scan = sc;
-  HIPCHK(ctx, hipMemsetAsync(w.counters, 0, 32 * sizeof(uint32_t), ctx->st));
+  HIPCHK(ctx, hipMemsetAsync(w.counters, 0, kCounters * sizeof(uint32_t), ctx->st));
   HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, 8 * NC * sizeof(long long), ctx->st));
   HIPCHK(ctx, hipMemsetAsync(w.diag_out, 0, 16 * NC * sizeof(double), ctx->st));
   w.cap_emit = EM;
@@ -376,10 +376,10 @@ StepShape shape_cases(alp_context *ctx, std::vector<CaseDev> &cs) {
 alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const StepShape &sh) {
   alp_status rc;
   ctx->any_kernel_sample = 0;
-  ctx->any_proj[0] = ctx->any_proj[1] = ctx->any_proj[2] = 0;
+  ctx->any_proj[0] = ctx->any_proj[1] = ctx->any_proj[2] = ctx->any_proj[3] = 0;
   for (const CaseDev &c : cs) {
     if (c.sample_mode == ALP_SAMPLE_KERNEL) ctx->any_kernel_sample = 1;
-    ctx->any_proj[c.proj_mode != ALP_PROJ_INTEGRATED ? 0 : (c.prec == ALP_PREC_FP32_SPLIT ? 1 : 2)] = 1;
+    ctx->any_proj[(c.proj_mode == ALP_PROJ_INTEGRATED ? 2 : 0) + (c.prec == ALP_PREC_FP32_SPLIT ? 0 : 1)] = 1;
   }
   if ((rc = ensure_cases(ctx, (int)cs.size())) != ALP_OK) return rc;
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_cases, cs.data(), cs.size() * sizeof(CaseDev),
@@ -407,9 +407,10 @@ StepLaunch make_launch(alp_context *ctx, int n_cases) {
   L.n_cases = n_cases;
   L.grid_persistent = ctx->n_cu * 8;
   L.kernel_sample = ctx->any_kernel_sample;
-  L.proj_nearest = ctx->any_proj[0];
-  L.int_split = ctx->any_proj[1];
-  L.int_fp64 = ctx->any_proj[2];
+  L.near_split = ctx->any_proj[0];
+  L.near_fp64 = ctx->any_proj[1];
+  L.int_split = ctx->any_proj[2];
+  L.int_fp64 = ctx->any_proj[3];
   return L;
 }
 

@@ -11,6 +11,7 @@ namespace alp {
 constexpr int kWave = 64;
 constexpr int kChunkSegs = 16;      // segments per chunk in the segment binning
 constexpr int kMaxEmitTile = 256;   // (chunk, tile) windows of one tile a wave can merge
+constexpr int kCounters = 40;       // step counters and work-queue words
 constexpr int kMaxEntries = 128;    // merged (tile, beam) entries a wave can screen
 constexpr int kMaskWords = kMaxEntries / 32;
 constexpr int kStagePts = 160;      // window points (and node accumulators) staged in LDS
@@ -147,8 +148,8 @@ struct Work {
   long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, empty kernel sample
   double *diag_out;     // [n_cases][16] finalised diagnostics
   // scalars
-  uint32_t *counters;   // [32]: 3 overflow flags; work queues: 8-15 nearest weights, 16-23 integrated
-                        // split, 24-31 integrated FP64
+  uint32_t *counters;   // [kCounters]: 3 overflow flags; weights work queues (8 words each): 8 nearest
+                        // split, 16 integrated split, 24 integrated FP64, 32 nearest FP64
   int64_t cap_emit, cap_item, cap_rec, cap_chunk;
   int64_t n_points, n_beams, n_tiles;
   int32_t n_cases, n_pblocks;
@@ -413,8 +414,8 @@ struct StepLaunch {
   int n_cases;
   int grid_persistent;     // blocks for persistent wave kernels
   int kernel_sample;       // some case uses ALP_SAMPLE_KERNEL
-  int proj_nearest;        // some case projects with ALP_PROJ_NEAREST
-  int int_split, int_fp64; // some case projects with ALP_PROJ_INTEGRATED in that precision
+  int near_split, near_fp64;  // some case projects with ALP_PROJ_NEAREST in that precision
+  int int_split, int_fp64;    // some case projects with ALP_PROJ_INTEGRATED in that precision
 };
 void launch_step_reset(const StepLaunch &L, hipStream_t st);
 void launch_step_reset_sample(const StepLaunch &L, hipStream_t st);

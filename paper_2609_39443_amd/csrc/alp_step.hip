@@ -122,7 +122,7 @@ __global__ void k_step_reset(StepLaunch L, int what) {
   Work W = L.w;
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (tid < 32 && (what & RESET_PROJECT)) W.counters[tid] = 0;
+  if (tid < kCounters && (what & RESET_PROJECT)) W.counters[tid] = 0;
   if (tid == 0 && (what & RESET_PROJECT)) *W.rec_alloc = 0;
   for (int64_t c = tid; c < (int64_t)L.n_cases * 8; c += stride) {
     int k = (int)(c & 7);
@@ -1254,13 +1254,13 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   unsigned long long blk_cur = 0, blk_end = 0;
   int acc_case = -1;
   unsigned long long acc_pairs = 0;
-  WorkQueue wq = work_queue(W.counters + (kInt ? (kSplit ? 16 : 24) : 8), (uint32_t)min((int64_t)n_items, W.cap_item),
-                            4u);
+  WorkQueue wq = work_queue(W.counters + (kInt ? (kSplit ? 16 : 24) : (kSplit ? 8 : 32)),
+                            (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
   while (wq.next(lane)) {
     const uint32_t item = wq.item;
     const Item it = W.item[item];
     if ((L.cases[it.cs].proj_mode == ALP_PROJ_INTEGRATED) != kInt) continue;
-    if (kInt && (L.cases[it.cs].prec == ALP_PREC_FP32_SPLIT) != kSplit) continue;
+    if ((L.cases[it.cs].prec == ALP_PREC_FP32_SPLIT) != kSplit) continue;
     if (it.cs != acc_case) {
       if (lane == 0 && acc_case >= 0 && acc_pairs)
         atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
@@ -1545,7 +1545,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
             // single-CV beam: the point kernel of the nearest rule
             const double *P = cs.Psp + 3 * (int64_t)k0;
             double a0, a1;
-            pair_weights(cs.prec, 0.0, sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]), cs.eps[k0], a0, a1);
+            pair_weights(kSplit ? ALP_PREC_FP32_SPLIT : ALP_PREC_FP64, 0.0, sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]), cs.eps[k0], a0, a1);
             acc(0, a0 * pv);
             if (rec_ok) write_record(r, rsz, (uint32_t)Lc | kRecSingle, (uint32_t)(cs.point_base + k0), a0, 0.0);
           } else {
@@ -1734,7 +1734,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
           }
           in = inside_cutoff(br2, ej);
           if (in) {
-            pair_weights(cs.prec, bs, br2, ej, a0, a1);
+            pair_weights(kSplit ? ALP_PREC_FP32_SPLIT : ALP_PREC_FP64, bs, br2, ej, a0, a1);
             const int64_t node = cs.point_base + k0 + (single ? 0 : i0 + bj);
             long long h0, h1 = 0;
             unsigned long long l0, l1 = 0;
@@ -1809,6 +1809,10 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
 
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
 void k_weights(StepLaunch L) {
+  weights_pass<false, true>(L);
+}
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
+void k_weights64(StepLaunch L) {
   weights_pass<false, false>(L);
 }
 
@@ -1825,7 +1829,8 @@ void k_weights_int64(StepLaunch L) {
 }
 
 void launch_weights(const StepLaunch &L, hipStream_t st) {
-  if (L.proj_nearest) hipLaunchKernelGGL(k_weights, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
+  if (L.near_split) hipLaunchKernelGGL(k_weights, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
+  if (L.near_fp64) hipLaunchKernelGGL(k_weights64, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
   if (L.int_split) hipLaunchKernelGGL(k_weights_int, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
   if (L.int_fp64) hipLaunchKernelGGL(k_weights_int64, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
 }

@@ -46,7 +46,8 @@ WORKLOAD = "canopy 256^3 / 2000 stems, FP32-split graph step"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_KIB = 1024 * 1024  # the 1 GiB calibration copy, each way
 # kernels whose counters go into the traffic table (the per-step hot path)
-HOT = ("k_weights", "k_spread", "k_sample", "k_tile_merge", "k_chunk_tiles", "k_emit_scatter",
+HOT = ("k_weights", "k_weights64", "k_weights_int", "k_weights_int64", "k_spread", "k_sample", "k_tile_merge",
+       "k_chunk_tiles", "k_emit_scatter",
        "k_chunk_boxes", "k_points_prep", "k_items", "k_drag", "k_normalise")
 
 
