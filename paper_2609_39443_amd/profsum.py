@@ -34,14 +34,18 @@ BENCH = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-fp64 --no-
 BENCH_PMC = "python3 bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-fp64 --no-extra"
 SQ = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_INSTS_SMEM SQ_WAIT_INST_ANY "
       "SQ_BUSY_CYCLES SQ_WAVE_CYCLES")
-COMMANDS = {
-    "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof -o canopy -- {BENCH}",
-    "sq": f"timeout -s KILL 240 rocprofv3 --pmc {SQ} --output-format csv -d gpurun_out/pmc -o sq -- {BENCH_PMC}",
-    "fetch": ("timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc -o fetch -- "
-              f"{BENCH_PMC} --copy-probe-mb 1024"),
-    "write": ("timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc -o write -- "
-              f"{BENCH_PMC} --copy-probe-mb 1024"),
-}
+
+
+def commands(out: str) -> dict:
+    """The rocprofv3 runs whose output (under `out`) the summaries read."""
+    return {
+        "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d {out}/prof -o canopy -- {BENCH}",
+        "sq": f"timeout -s KILL 240 rocprofv3 --pmc {SQ} --output-format csv -d {out}/pmc -o sq -- {BENCH_PMC}",
+        "fetch": (f"timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/pmc -o fetch -- "
+                  f"{BENCH_PMC} --copy-probe-mb 1024"),
+        "write": (f"timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/pmc -o write -- "
+                  f"{BENCH_PMC} --copy-probe-mb 1024"),
+    }
 WORKLOAD = "canopy 256^3 / 2000 stems, FP32-split graph step"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_KIB = 1024 * 1024  # the 1 GiB calibration copy, each way
@@ -122,6 +126,8 @@ def main(argv):
     if len(argv) != 3:
         raise SystemExit("usage: python -m paper_2609_39443_amd.profsum <rocprof out dir> <profiles dir>")
     src, dst = argv[1], argv[2]
+    cmds = commands(src.rstrip("/"))
+    again = f"python -m paper_2609_39443_amd.profsum {src} {dst}"
     tag = "canopy_256cubed_2000stems"
     sh = source_hash()
     # kernel trace
@@ -134,8 +140,8 @@ def main(argv):
             "(alp_step_profile: unforked, one stream).  In the graph, sampling and drag run on a second stream\n"
             "beside the segment binning, so kernels that overlap k_sample show inflated maxima.  The mesh\n"
             "binning kernels run once (alp_bin_cells).\n\n"
-            "Command (from the repository root, TMPDIR=/tmp):\n  " + COMMANDS["trace"] + "\n"
-            "Summarised with: python -m paper_2609_39443_amd.profsum gpurun_out profiles\n\n")
+            "Command (from the repository root, TMPDIR=/tmp):\n  " + cmds["trace"] + "\n"
+            f"Summarised with: {again}\n\n")
     with open(os.path.join(dst, f"{tag}_kernel_trace.txt"), "w") as fh:
         fh.write(head + trace_table(stats) + "\n")
     # counters
@@ -162,8 +168,8 @@ def main(argv):
     head = (f"Hardware counters per dispatch (mean over dispatches): {WORKLOAD}.\n"
             f"Kernel sources: csrc hash {sh}.  Device: one MI355X (gfx950).\n\n"
             "Commands (from the repository root, TMPDIR=/tmp), one pass per counter group:\n  "
-            + "\n  ".join(COMMANDS[k] for k in ("sq", "fetch", "write")) + "\n"
-            "Summarised with: python -m paper_2609_39443_amd.profsum gpurun_out profiles\n\n"
+            + "\n  ".join(cmds[k] for k in ("sq", "fetch", "write")) + "\n"
+            f"Summarised with: {again}\n\n"
             f"Calibration: the 1 GiB device copy (--copy-probe-mb 1024, {COPY_KERNEL}) reads\n"
             f"FETCH_SIZE = {cf:.0f} KiB and WRITE_SIZE = {cw:.0f} KiB for {COPY_KIB:,} KiB moved each way,\n"
             f"so HBM bytes = FETCH_SIZE x {ff:.3f} + WRITE_SIZE x {wf:.3f} (KiB).\n\n")
