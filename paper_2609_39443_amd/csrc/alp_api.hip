@@ -34,6 +34,7 @@ struct alp_context {
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   int n_cu = 256;
+  int spread_per_cu = 8;  // resident spread blocks per CU
   // workspace
   Work w{};
   std::vector<void *> wallocs;
@@ -182,6 +183,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(chunk_s0, CH);
   WALLOC(chunk_s1, CH);
   WALLOC(chunk_box, CH + 1);
+  WALLOC(chunk_bx, 6 * CH);
   WALLOC(tile_cnt, T + 1);
   WALLOC(tile_off, T + 1);
   WALLOC(tile_fill, T + 1);
@@ -406,6 +408,7 @@ StepLaunch make_launch(alp_context *ctx, int n_cases) {
   L.w = ctx->w;
   L.n_cases = n_cases;
   L.grid_persistent = ctx->n_cu * 8;
+  L.grid_spread = ctx->n_cu * ctx->spread_per_cu;
   L.kernel_sample = ctx->any_kernel_sample;
   L.near_split = ctx->any_proj[0];
   L.near_fp64 = ctx->any_proj[1];
@@ -574,6 +577,8 @@ alp_status alp_create(int device, void *hip_stream, alp_context **out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->n_cu = prop.multiProcessorCount;
+  const int spc = spread_blocks_per_cu();
+  if (spc > 0) ctx->spread_per_cu = spc;
   *out = ctx;
   return ALP_OK;
 }

@@ -122,6 +122,7 @@ struct Work {
   // chunks
   int32_t *chunk_beam, *chunk_s0, *chunk_s1;
   uint32_t *chunk_box;  // tiles in each chunk's box, scanned into slot offsets ([cap_chunk+1])
+  int32_t *chunk_bx;    // each chunk's tile box: lo x, y, z, hi x, y, z ([cap_chunk][6])
   // tiles (global)
   uint32_t *tile_cnt;   // windows per tile ([N_T+1])
   uint32_t *tile_off;   // exclusive scan of tile_cnt ([N_T+1])
@@ -413,6 +414,7 @@ struct StepLaunch {
   Work w;
   int n_cases;
   int grid_persistent;     // blocks for persistent wave kernels
+  int grid_spread;         // blocks of the spread pass: one per resident wave slot
   int kernel_sample;       // some case uses ALP_SAMPLE_KERNEL
   int near_split, near_fp64;  // some case projects with ALP_PROJ_NEAREST in that precision
   int int_split, int_fp64;    // some case projects with ALP_PROJ_INTEGRATED in that precision
@@ -448,6 +450,7 @@ void launch_weights(const StepLaunch &L, hipStream_t st);
 void launch_norm(const StepLaunch &L, hipStream_t st);
 void launch_beam_sums(const StepLaunch &L, hipStream_t st);
 void launch_spread(const StepLaunch &L, hipStream_t st);
+int spread_blocks_per_cu();  // resident k_spread blocks per CU (0 if the query fails)
 void launch_zero_dirty(const StepLaunch &L, hipStream_t st);
 void launch_finalize(const StepLaunch &L, hipStream_t st);
 

@@ -270,9 +270,20 @@ struct SegInfo {
   double len, su;       // length, |ux| + |uy| + |uz|
 };
 
+// reach of a chunk's beam: 3 eps_max, widened by 1e-7 (tile + reach) so that
+// the tile tests below survive rounding
+__device__ __forceinline__ double chunk_reach(const Work &W, int gb, double tl) {
+  const double R = 3.0 * W.beps_max[gb];
+  return R + 1e-7 * (tl + R);
+}
+
 // tile box of a chunk: tiles overlapped by the union of its segments' AABBs
-// inflated by 3 eps_max; returns false when the box misses the tile grid
-__device__ bool chunk_box(const StepLaunch &L, int64_t ch, int32_t *box, double *Rout) {
+// inflated by the reach; returns false when the box misses the tile grid.
+// The points are read one after another: this keeps the kernel small in
+// registers, so that it finds room beside the sampling kernel, which runs
+// concurrently on the other stream (loading them all at once made the
+// overlapped step slower).
+__device__ bool chunk_box(const StepLaunch &L, int64_t ch, int32_t *box) {
   const Work &W = L.w;
   const int gb = W.chunk_beam[ch];
   const CaseDev &cs = L.cases[W.bcase[gb]];
@@ -283,12 +294,10 @@ __device__ bool chunk_box(const StepLaunch &L, int64_t ch, int32_t *box, double 
   const int s0 = W.chunk_s0[ch], s1 = W.chunk_s1[ch];
   const double *X = cs.Psp + 3 * k0;
   const double tl = m.tile_len;
-  double R = 3.0 * W.beps_max[gb];
-  R += 1e-7 * (tl + R);
-  *Rout = R;
+  const double R = chunk_reach(W, gb, tl);
+  const int pfirst = nb >= 2 ? s0 : 0, plast = nb >= 2 ? s1 + 1 : 0;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  const int plast = nb >= 2 ? s1 + 1 : 0;
-  for (int p = (nb >= 2 ? s0 : 0); p <= plast; ++p)
+  for (int p = pfirst; p <= plast; ++p)
     for (int a = 0; a < 3; ++a) {
       lo[a] = fmin(lo[a], X[3 * p + a]);
       hi[a] = fmax(hi[a], X[3 * p + a]);
@@ -303,6 +312,7 @@ __device__ bool chunk_box(const StepLaunch &L, int64_t ch, int32_t *box, double 
   return ok;
 }
 
+// tiles in each chunk's box (0 when it misses the grid), and the box itself
 __global__ void k_chunk_boxes(StepLaunch L) {
   const Work &W = L.w;
   const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -310,9 +320,11 @@ __global__ void k_chunk_boxes(StepLaunch L) {
   uint32_t n = 0;
   if (ch < (int64_t)W.bchunks[W.n_beams]) {
     int32_t box[6];
-    double R;
-    if (chunk_box(L, ch, box, &R))
+    if (chunk_box(L, ch, box)) {
       n = (uint32_t)((box[3] - box[0] + 1) * (box[4] - box[1] + 1) * (box[5] - box[2] + 1));
+      int32_t *o = W.chunk_bx + 6 * ch;
+      for (int a = 0; a < 6; ++a) o[a] = box[a];
+    }
   }
   W.chunk_box[ch] = n;
 }
@@ -333,8 +345,7 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
     const int64_t ntile = (int64_t)box_off[ch + 1] - slot0;
     if (ntile == 0) continue;
     int32_t box[6];
-    double R;
-    chunk_box(L, ch, box, &R);
+    for (int a = 0; a < 6; ++a) box[a] = W.chunk_bx[6 * ch + a];
     const int gb = W.chunk_beam[ch];
     const CaseDev &cs = L.cases[W.bcase[gb]];
     const MeshDev &m = cs.m;
@@ -346,6 +357,7 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
     const int nsg = s1 - s0 + 1;
     const double *X = cs.Psp + 3 * k0;
     const double tl = m.tile_len;
+    const double R = chunk_reach(W, gb, tl);
     const double mrg = 1e-7 * (tl + R);
     // segment data: the chunk's segments and the ones before and after it
     for (int jj = lane; jj <= nsg + 1; jj += 64) {
@@ -486,23 +498,9 @@ struct MergeScratch {
 // wave barrier keeps the compiler from moving them across phases).
 constexpr int kMergeWaves = 4;
 
-__global__ __launch_bounds__(64 * kMergeWaves) void k_tile_merge(StepLaunch L) {
-  Work W = L.w;
-  __shared__ MergeScratch shw[kMergeWaves];
-  MergeScratch &sh = shw[threadIdx.x >> 6];
-  const int lane = threadIdx.x & 63;
-  const int64_t tg = (int64_t)blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
-  if (tg >= W.n_tiles) return;
-  const uint32_t eoff = W.tile_off[tg];
-  const uint32_t n_emit = W.tile_off[tg + 1] - eoff;
-  if (n_emit == 0 || n_emit > (uint32_t)kMaxEmitTile) {
-    if (lane == 0) {
-      if (n_emit) set_overflow(W, 4u);
-      W.tile_nent[tg] = 0;
-      W.tile_items[tg] = 0;
-    }
-    return;
-  }
+// Tiles with more than 64 windows: sort the (beam, first segment) keys in
+// LDS (bitonic), then join each beam's run.  Returns the number of entries.
+__device__ uint32_t tile_merge_lds(const Work &W, MergeScratch &sh, int lane, uint32_t eoff, uint32_t n_emit) {
   uint32_t np2 = 1;
   while (np2 < n_emit) np2 <<= 1;
   for (uint32_t i = lane; i < np2; i += 64) {
@@ -540,8 +538,8 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_tile_merge(StepLaunch L) {
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   uint32_t ne = 0;
@@ -569,6 +567,69 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_tile_merge(StepLaunch L) {
       }
     }
     ne += (uint32_t)__popcll(bal);
+  }
+  return ne;
+}
+
+__global__ __launch_bounds__(64 * kMergeWaves) void k_tile_merge(StepLaunch L) {
+  Work W = L.w;
+  __shared__ MergeScratch shw[kMergeWaves];
+  MergeScratch &sh = shw[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
+  const int64_t tg = (int64_t)blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
+  if (tg >= W.n_tiles) return;
+  const uint32_t eoff = W.tile_off[tg];
+  const uint32_t n_emit = W.tile_off[tg + 1] - eoff;
+  if (n_emit == 0 || n_emit > (uint32_t)kMaxEmitTile) {
+    if (lane == 0) {
+      if (n_emit) set_overflow(W, 4u);
+      W.tile_nent[tg] = 0;
+      W.tile_items[tg] = 0;
+    }
+    return;
+  }
+  uint32_t ne = 0;
+  if (n_emit <= 64u) {
+    // one window per lane: the head of a beam is its window with the
+    // smallest first segment, the entry's last segment the largest over the
+    // beam's windows, and its place the number of smaller beams in the tile
+    uint32_t beam = ~0u, lo = 0;
+    int32_t hi = 0, k0 = 0;
+    if ((uint32_t)lane < n_emit) {
+      const Win e = W.emit[eoff + lane];
+      beam = (uint32_t)e.beam;
+      lo = (uint32_t)e.lo;
+      hi = e.hi;
+      k0 = e.k0;
+    }
+    bool head = (uint32_t)lane < n_emit;
+    int32_t mhi = hi;
+    for (uint32_t j = 0; j < n_emit; ++j) {
+      const uint32_t bj = (uint32_t)__builtin_amdgcn_readlane((int)beam, (int)j);
+      const uint32_t lj = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)j);
+      const int32_t hj = __builtin_amdgcn_readlane(hi, (int)j);
+      if (bj == beam) {
+        mhi = max(mhi, hj);
+        if (lj < lo || (lj == lo && j < (uint32_t)lane)) head = false;
+      }
+    }
+    const uint64_t hb = ballot64(head);
+    uint32_t idx = 0;
+    for (uint64_t mm = hb; mm; mm &= mm - 1) {
+      const int j = __builtin_ctzll(mm);
+      idx += (uint32_t)__builtin_amdgcn_readlane((int)beam, j) < beam ? 1u : 0u;
+    }
+    ne = (uint32_t)__popcll(hb);
+    if (head && idx < (uint32_t)kMaxEntries) {
+      Entry en;
+      en.k0 = k0;
+      en.i0 = (int32_t)lo;
+      en.i1 = mhi < 0 ? 0 : mhi;
+      en.single = mhi < 0 ? 1 : 0;
+      W.entry[eoff + idx] = en;
+    }
+  } else {
+    ne = tile_merge_lds(W, sh, lane, eoff, n_emit);
   }
   if (lane == 0) {
     uint32_t ni = 0;
@@ -1708,10 +1769,15 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               const float band = (b1 + 2.0f * dl) * (1.0f + 0x1p-20f);
               full = k3 != ~0u && __uint_as_float(k3 & ~kSegIdxMask) <= band;
               if (!full) {
+                // the node widths of the one or two re-checked segments are
+                // loaded with their end points, not after the choice
+                const double *E = cs.eps + (int64_t)k0 + i0;
                 const int j1 = (int)(k1 & kSegIdxMask);
+                double e0 = E[j1], e1 = E[j1 + 1];
                 exact_scan(X, j1, j1, pcx, pcy, pcz, bj, bs, br2);
                 if (k2 != ~0u && __uint_as_float(k2 & ~kSegIdxMask) <= band) {
                   const int j2 = (int)(k2 & kSegIdxMask);
+                  const double f0 = E[j2], f1 = E[j2 + 1];
                   int cj = j2;
                   double cs2 = 0.0, cr2 = INFINITY;
                   exact_scan(X, j2, j2, pcx, pcy, pcz, cj, cs2, cr2);
@@ -1719,8 +1785,11 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
                     br2 = cr2;
                     bj = j2;
                     bs = cs2;
+                    e0 = f0;
+                    e1 = f1;
                   }
                 }
+                ej = eps_at(bs, e0, e1);
               }
             }
             if (full) {
@@ -1728,9 +1797,9 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               bj = 0;
               bs = 0.0;
               exact_scan(X, 0, nseg - 1, pcx, pcy, pcz, bj, bs, br2);
+              const double *E = cs.eps + (int64_t)k0 + i0;
+              ej = eps_at(bs, E[bj], E[bj + 1]);
             }
-            const double *E = cs.eps + (int64_t)k0 + i0;
-            ej = eps_at(bs, E[bj], E[bj + 1]);
           }
           in = inside_cutoff(br2, ej);
           if (in) {
@@ -1940,43 +2009,79 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // records of a work item are sorted by cell, so each cell owns one contiguous
 // run; its lane sums the run in record order.  Every cell of an active tile
 // is written.
-constexpr int kSpreadChunk = 128;  // records held per pass (2 per lane)
+#ifndef ALP_SPREAD_K
+#define ALP_SPREAD_K 1
+#endif
+constexpr int kSpreadK = ALP_SPREAD_K;          // records per lane and pass
+constexpr int kSpreadChunk = 64 * kSpreadK;     // records held per pass
 
 struct SpreadScratch {
   double cc[3][kSpreadChunk];
   uint16_t first[64], last[64];  // run of each cell inside the chunk (last exclusive)
 };
 
+// The raw words of kSpreadK records per lane (records k 64 + lane of a
+// chunk): they are fetched one chunk ahead and decoded only when used, so the
+// fetch stays in flight while the previous chunk is summed.
+struct SpreadRaw {
+  uint4 r[kSpreadK];  // split: meta, node, a0, a1 (FP32); FP64: meta, node, lo and hi of a0
+  uint2 h[kSpreadK];  // FP64: a1
+};
+
+__device__ __forceinline__ SpreadRaw spread_fetch(const unsigned char *rec, int rsz, uint32_t p0, uint32_t rn,
+                                                  int lane) {
+  SpreadRaw R;
+#pragma unroll
+  for (int k = 0; k < kSpreadK; ++k) {
+    const uint32_t j = p0 + (uint32_t)(k * 64 + lane);
+    R.r[k] = make_uint4(0u, 0u, 0u, 0u);
+    R.h[k] = make_uint2(0u, 0u);
+    if (j < rn) {
+      const unsigned char *r = rec + (size_t)j * rsz;
+      if (rsz == 16) {
+        R.r[k] = *(const uint4 *)r;
+      } else {
+        const uint2 a = *(const uint2 *)r;
+        const uint4 b = *(const uint4 *)(r + 8);
+        R.r[k] = make_uint4(a.x, a.y, b.x, b.y);
+        R.h[k] = make_uint2(b.z, b.w);
+      }
+    }
+  }
+  return R;
+}
+
 __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
   Work W = L.w;
   __shared__ SpreadScratch sh;
   const int lane = threadIdx.x;
-  const uint32_t n_items = W.tile_itoff[W.n_tiles];
+  const uint32_t n_items = (uint32_t)min((int64_t)W.tile_itoff[W.n_tiles], W.cap_item);
+  const uint32_t stride = gridDim.x;
+  uint32_t item = blockIdx.x;
+  if (item >= n_items) return;
   // per-wave accumulation (exact fixed point, flushed when the case changes)
   int acc_case = -1;
   unsigned long long acc_band = 0;
   long long fh = 0;  // lanes 0..2 hold x, y, z
   unsigned long long fl = 0;
-  const uint32_t stride = gridDim.x;
-  uint32_t item = blockIdx.x;
-  Item nxt;
+  sh.first[lane] = 0;
+  sh.last[lane] = 0;
+  // the current item, the next one's descriptor, and the records of the
+  // current item's first chunk
+  Item it = W.item[item];
+  uint32_t rn = W.rec_cnt[item];
+  unsigned long long rb = W.rec_base[item];
+  Item nxt = it;
   uint32_t nrn = 0;
   unsigned long long nrb = 0;
-  if (item < n_items && (int64_t)item < W.cap_item) {
-    nxt = W.item[item];
-    nrn = W.rec_cnt[item];
-    nrb = W.rec_base[item];
+  if (item + stride < n_items) {
+    nxt = W.item[item + stride];
+    nrn = W.rec_cnt[item + stride];
+    nrb = W.rec_base[item + stride];
   }
-  for (; item < n_items && (int64_t)item < W.cap_item; item += stride) {
-    const Item it = nxt;
-    const uint32_t rn = nrn;
-    const unsigned long long rb = nrb;
-    // the next item's descriptor is fetched while this one runs
-    if (item + stride < n_items && (int64_t)(item + stride) < W.cap_item) {
-      nxt = W.item[item + stride];
-      nrn = W.rec_cnt[item + stride];
-      nrb = W.rec_base[item + stride];
-    }
+  SpreadRaw R = spread_fetch(W.rec + rb, rec_size(L.cases[it.cs].prec), 0, rn, lane);
+  __syncthreads();
+  for (;;) {
     if (it.cs != acc_case) {
       if (acc_case >= 0) {
         if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
@@ -1998,37 +2103,31 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
     const bool valid = c < it.c1;
     const double v = valid ? m.vs[c] : 0.0;
     const uint32_t pc = valid ? m.perm[c] : 0u;
-    const unsigned char *rec = W.rec + rb;
     const int rsz = rec_size(cs.prec);
+    const bool has_next = item + stride < n_items;
+    const int nrsz = has_next ? rec_size(L.cases[nxt.cs].prec) : 16;
     double S0 = 0.0, S1 = 0.0, S2 = 0.0;
     bool any = false;
     for (uint32_t p0 = 0; p0 < rn; p0 += kSpreadChunk) {
       const uint32_t nch = min(rn - p0, (uint32_t)kSpreadChunk);
-      if (lane < 64) {
-        sh.first[lane] = 0;
-        sh.last[lane] = 0;
-      }
-      __syncthreads();
+      const SpreadRaw C = R;
+      // the chunk after this one: the rest of this item, else the next item's first
+      if (p0 + kSpreadChunk < rn) R = spread_fetch(W.rec + rb, rsz, p0 + kSpreadChunk, rn, lane);
+      else if (has_next) R = spread_fetch(W.rec + nrb, nrsz, 0, nrn, lane);
+      uint32_t cl[kSpreadK];
 #pragma unroll
-      for (int k = 0; k < kSpreadChunk / 64; ++k) {
+      for (int k = 0; k < kSpreadK; ++k) {
         const uint32_t j = (uint32_t)(k * 64 + lane);
+        cl[k] = ~0u;
         if (j < nch) {
-          const unsigned char *r = rec + (size_t)(p0 + j) * rsz;
-          uint32_t meta, node;
+          const uint32_t meta = C.r[k].x, node = C.r[k].y;
           double a0, a1;
           if (rsz == 16) {
-            const uint4 q = *(const uint4 *)r;
-            meta = q.x;
-            node = q.y;
-            a0 = (double)__uint_as_float(q.z);
-            a1 = (double)__uint_as_float(q.w);
+            a0 = (double)__uint_as_float(C.r[k].z);
+            a1 = (double)__uint_as_float(C.r[k].w);
           } else {
-            const uint2 q = *(const uint2 *)r;
-            meta = q.x;
-            node = q.y;
-            const double2 a = *(const double2 *)(r + 8);
-            a0 = a.x;
-            a1 = a.y;
+            a0 = __hiloint2double((int)C.r[k].w, (int)C.r[k].z);
+            a1 = __hiloint2double((int)C.h[k].y, (int)C.h[k].x);
           }
           const double *fp = W.fhat + 3 * (int64_t)node;
           double q0 = a0 * fp[0], q1 = a0 * fp[1], q2 = a0 * fp[2];
@@ -2040,14 +2139,29 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
           sh.cc[0][j] = -q0;
           sh.cc[1][j] = -q1;
           sh.cc[2][j] = -q2;
-          // run boundaries of the cell (records are sorted by cell)
-          const uint32_t cl = meta & 63u;
-          if (j == 0 || ((*(const uint32_t *)(r - rsz)) & 63u) != cl) sh.first[cl] = (uint16_t)j;
-          if (j + 1 == nch || ((*(const uint32_t *)(r + rsz)) & 63u) != cl) sh.last[cl] = (uint16_t)(j + 1);
+          cl[k] = meta & 63u;
+        }
+      }
+      // run boundaries of each cell (records are sorted by cell): the
+      // neighbouring records' cells come from the neighbouring lanes
+#pragma unroll
+      for (int k = 0; k < kSpreadK; ++k) {
+        const uint32_t j = (uint32_t)(k * 64 + lane);
+        const uint32_t up = (uint32_t)__shfl((int)cl[k], lane - 1, 64);
+        const uint32_t dn = (uint32_t)__shfl((int)cl[k], lane + 1, 64);
+        const uint32_t wrap_up = k > 0 ? (uint32_t)__shfl((int)cl[k > 0 ? k - 1 : 0], 63, 64) : ~0u;
+        const uint32_t wrap_dn = k + 1 < kSpreadK ? (uint32_t)__shfl((int)cl[k + 1 < kSpreadK ? k + 1 : k], 0, 64) : ~0u;
+        if (j < nch) {
+          const uint32_t prev = lane > 0 ? up : wrap_up;
+          const uint32_t next = lane < 63 ? dn : wrap_dn;
+          if (j == 0 || prev != cl[k]) sh.first[cl[k]] = (uint16_t)j;
+          if (j + 1 == nch || next != cl[k]) sh.last[cl[k]] = (uint16_t)(j + 1);
         }
       }
       __syncthreads();
       const uint32_t lo = sh.first[lane], hi = sh.last[lane];
+      sh.first[lane] = 0;
+      sh.last[lane] = 0;
       any = any || hi > lo;
       for (uint32_t j = lo; j < hi; ++j) {
         S0 += sh.cc[0][j];
@@ -2056,6 +2170,7 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
       }
       __syncthreads();
     }
+    if (rn == 0 && has_next) R = spread_fetch(W.rec + nrb, nrsz, 0, nrn, lane);
     if (valid && cs.write_S) {
       double *S = cs.S + 3 * (int64_t)pc;
       S[0] = S0;
@@ -2075,6 +2190,16 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
         fl += l;
       }
     }
+    if (!has_next) break;
+    item += stride;
+    it = nxt;
+    rn = nrn;
+    rb = nrb;
+    if (item + stride < n_items) {
+      nxt = W.item[item + stride];
+      nrn = W.rec_cnt[item + stride];
+      nrb = W.rec_base[item + stride];
+    }
   }
   if (acc_case >= 0) {
     if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
@@ -2087,8 +2212,18 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
   }
 }
 
+// The spread walks its items with a static stride, so its grid is exactly
+// the number of blocks the device holds at once: none waits for a slot.
+int spread_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(k_spread), 64, 0) !=
+      hipSuccess)
+    return 0;
+  return nb;
+}
+
 void launch_spread(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_spread, dim3(L.grid_persistent * 4), dim3(64), 0, st, L);
+  hipLaunchKernelGGL(k_spread, dim3(L.grid_spread), dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------- zero dirty --

@@ -459,23 +459,38 @@ def test_integrated_bitwise_across_binnings(gu, ctx):
             assert d[k] == dref[k], (tb, bs, k)
 
 
-def test_per_tile_limit_is_reported(gu, ctx):
-    """More than 128 beams reaching one tile exceeds the documented per-tile
-    limit: the step returns ALP_ERR_CAPACITY without computing that tile, and
-    the context keeps working afterwards."""
+def crowded_column(n_b, seed=3):
+    """n_b straight vertical beams of 5 points, all inside one column of
+    4-bin tiles (h = 1 cm), so every tile they reach holds n_b windows."""
     C, V = W.uniform_mesh(16, 16, 16, 0.01)
-    rng = np.random.default_rng(3)
-    n_b, n = 140, 5
+    rng = np.random.default_rng(seed)
+    n = 5
     pts = []
     for _ in range(n_b):
-        x0, y0 = 0.05 + 0.02 * rng.random(2)  # all inside one column of tiles
+        x0, y0 = 0.05 + 0.02 * rng.random(2)
         pts.append(np.stack([np.full(n, x0), np.full(n, y0), 0.03 + 0.02 * np.arange(n)], axis=1))
     beams = W._beamset(pts, [np.tile([0, 0, 1.0], (n, 1))] * n_b, [np.zeros((n, 3))] * n_b,
                        [np.full(n, 0.002)] * n_b, [np.full(n, 0.02)] * n_b, [np.full(n, 0.01)] * n_b,
                        np.full(n_b, 1.2), np.full(n_b, 0.0), np.full(n_b, 0.03), np.zeros((n_b, 3)),
                        np.tile([-1.0, 0, 0], (n_b, 1)))
-    wl = {"name": "crowded-tile", "C": C, "V": V, "U": np.tile([0.3, 0.0, 0.0], (C.shape[0], 1)), "box": None,
-          "beams": beams, "params": {"rho": 1000.0, "tau": 1e-6}}
+    return {"name": f"crowded-column-{n_b}", "C": C, "V": V, "U": np.tile([0.3, 0.0, 0.0], (C.shape[0], 1)),
+            "box": None, "beams": beams, "params": {"rho": 1000.0, "tau": 1e-6}}
+
+
+@pytest.mark.parametrize("n_b", [40, 100])
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_crowded_tiles_both_merge_paths(gu, ctx, n_b, prec):
+    """A tile reached by at most 64 windows is merged in registers, a fuller
+    one by a sort in LDS (100 beams in one tile column): both match the
+    oracle."""
+    run_and_compare(gu, ctx, crowded_column(n_b), prec, tile_bins=4, bin_size=0.01)
+
+
+def test_per_tile_limit_is_reported(gu, ctx):
+    """More than 128 beams reaching one tile exceeds the documented per-tile
+    limit: the step returns ALP_ERR_CAPACITY without computing that tile, and
+    the context keeps working afterwards."""
+    wl = crowded_column(140)
     case = gu.GpuCase(ctx, wl, alp.PREC_FP64, tile_bins=4, bin_size=0.01)
     gu.log("[parity] crowded tile: 140 beams in one tile column")
     with pytest.raises(alp.AlpError) as err:
