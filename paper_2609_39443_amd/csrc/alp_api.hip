@@ -399,6 +399,12 @@ alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const 
   return ALP_OK;
 }
 
+#ifndef ALP_SAMPLE_BESIDE
+#define ALP_SAMPLE_BESIDE 6
+#endif
+// sampler waves per CU while it runs beside the segment binning
+constexpr int kSampleWavesBeside = ALP_SAMPLE_BESIDE;
+
 StepLaunch make_launch(alp_context *ctx, int n_cases) {
   StepLaunch L;
   L.cases = ctx->d_cases;
@@ -409,6 +415,7 @@ StepLaunch make_launch(alp_context *ctx, int n_cases) {
   L.n_cases = n_cases;
   L.grid_persistent = ctx->n_cu * 8;
   L.grid_spread = ctx->n_cu * ctx->spread_per_cu;
+  L.sample_waves = 0;
   L.kernel_sample = ctx->any_kernel_sample;
   L.near_split = ctx->any_proj[0];
   L.near_fp64 = ctx->any_proj[1];
@@ -448,7 +455,11 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
     (void)hipStreamWaitEvent(sd, ctx->ev_fork, 0);
   }
   if (stages & ST_SAMPLE) {
-    launch_sample(L, sd);
+    // beside the segment binning the sampler keeps to two waves per SIMD,
+    // which leaves the binning's small kernels room on every CU
+    StepLaunch Ls = L;
+    Ls.sample_waves = fork ? kSampleWavesBeside : 0;
+    launch_sample(Ls, sd);
     launch_sample_kernel(L, sd);
   }
   mark(2);
@@ -698,7 +709,7 @@ alp_status alp_bin_cells(alp_context *ctx, int64_t n_cells, const double *C, con
     return rc;                                    \
   }
   MALLOC_OR_FAIL(m->bin_start, nbins + 1);
-  MALLOC_OR_FAIL(m->cxyz, 3 * n_cells);
+  MALLOC_OR_FAIL(m->cxyz, 4 * n_cells);
   MALLOC_OR_FAIL(m->cx, n_cells);
   MALLOC_OR_FAIL(m->cy, n_cells);
   MALLOC_OR_FAIL(m->cz, n_cells);

@@ -33,8 +33,9 @@ struct MeshDev {
   double vmax;      // largest cell volume
   const uint32_t *bin_start;  // [n_bins+1] sorted-cell ranges, bins in tile-major order
   const double *cx, *cy, *cz; // [n] sorted centres (FP64, absolute)
-  const double *cxyz;         // [n][3] the same centres interleaved (point location reads
-                              // a cell's three coordinates from one place)
+  const double *cxyz;         // [n][4] the same centres interleaved with the caller index
+                              // (x, y, z, index as a double): point location reads a
+                              // cell's coordinates and index from one 32-byte record
   const double *vs;           // [n] sorted volumes
   const uint32_t *perm;       // [n] sorted -> caller index
 };
@@ -374,6 +375,16 @@ __device__ __host__ inline uint32_t bin_key(const MeshDev &m, int ix, int iy, in
   return tile * (uint32_t)(T * T * T) + (uint32_t)((lz * T + ly) * T + lx);
 }
 
+// A read-only pointer into device global memory.  Loads through it compile to
+// global memory instructions rather than flat ones, so that waits for them
+// and waits for LDS operations stay independent.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(const T *p) {
+  return (gptr<T>)p;
+}
+
 __device__ __forceinline__ int case_of(const int64_t *bases, int n, int64_t idx) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -416,6 +427,7 @@ struct StepLaunch {
   int grid_persistent;     // blocks for persistent wave kernels
   int grid_spread;         // blocks of the spread pass: one per resident wave slot
   int kernel_sample;       // some case uses ALP_SAMPLE_KERNEL
+  int sample_waves;        // sampler waves per CU (0: one wave per 4 points, no cap)
   int near_split, near_fp64;  // some case projects with ALP_PROJ_NEAREST in that precision
   int int_split, int_fp64;    // some case projects with ALP_PROJ_INTEGRATED in that precision
 };

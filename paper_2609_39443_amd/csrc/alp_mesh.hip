@@ -223,9 +223,7 @@ __global__ void k_bin_reorder(const double *C, const double *V, const uint32_t *
   cx[p] = x;
   cy[p] = y;
   cz[p] = z;
-  cxyz[3 * p + 0] = x;
-  cxyz[3 * p + 1] = y;
-  cxyz[3 * p + 2] = z;
+  *(double4 *)(cxyz + 4 * p) = make_double4(x, y, z, (double)c);
   vs[p] = V[c];
 }
 

@@ -346,7 +346,7 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
     if (ntile == 0) continue;
     int32_t box[6];
     for (int a = 0; a < 6; ++a) box[a] = W.chunk_bx[6 * ch + a];
-    const int gb = W.chunk_beam[ch];
+    const int gb = __builtin_amdgcn_readfirstlane(W.chunk_beam[ch]);  // uniform: scalar case loads
     const CaseDev &cs = L.cases[W.bcase[gb]];
     const MeshDev &m = cs.m;
     const int64_t b = gb - cs.beam_base;
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
     const int s0 = W.chunk_s0[ch], s1 = W.chunk_s1[ch];
     const int nseg = nb >= 2 ? nb - 1 : 1;
     const int nsg = s1 - s0 + 1;
-    const double *X = cs.Psp + 3 * k0;
+    const gptr<double> X = to_global(cs.Psp) + 3 * k0;
     const double tl = m.tile_len;
     const double R = chunk_reach(W, gb, tl);
     const double mrg = 1e-7 * (tl + R);
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
       SegInfo q;
       bool exists = (nb == 1) ? (j == 0) : (i >= 0 && i <= nb - 2);
       if (exists) {
-        const double *A = X + 3 * (nb == 1 ? 0 : i), *B = X + 3 * (nb == 1 ? 0 : i + 1);
+        const gptr<double> A = X + 3 * (nb == 1 ? 0 : i), B = X + 3 * (nb == 1 ? 0 : i + 1);
         double e[3];
         for (int a = 0; a < 3; ++a) {
           q.lo[a] = fmin(A[a], B[a]) - R;
@@ -393,24 +393,31 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
       sg[jj] = q;
     }
     __syncthreads();
-    const int nx = box[3] - box[0] + 1, ny = box[4] - box[1] + 1;
-    for (int64_t q = lane; q < ntile; q += 64) {
+    // case fields used in the tile loop, held in registers (the loop's
+    // stores would otherwise make the compiler read them again)
+    const bool slab = nb >= 2 && cs.proj_mode == ALP_PROJ_NEAREST;
+    const int64_t tbase = cs.tile_base;
+    const int ntx = m.nt[0], nty = m.nt[1];
+    const double mlo0 = m.lo[0], mlo1 = m.lo[1], mlo2 = m.lo[2];
+    // box offsets in 32 bits (the scanned box sizes are 32-bit counts)
+    const uint32_t nx = (uint32_t)(box[3] - box[0] + 1), ny = (uint32_t)(box[4] - box[1] + 1);
+    for (uint32_t q = lane; q < (uint32_t)ntile; q += 64) {
       int wlo = -1, whi = -1;
-      int tx = box[0] + (int)(q % nx), ty = box[1] + (int)((q / nx) % ny),
-          tz = box[2] + (int)(q / ((int64_t)nx * ny));
-      double tlo[3] = {m.lo[0] + tx * tl, m.lo[1] + ty * tl, m.lo[2] + tz * tl};
+      const uint32_t qy = q / nx, qz = qy / ny;
+      const int tx = box[0] + (int)(q - qy * nx), ty = box[1] + (int)(qy - qz * ny), tz = box[2] + (int)qz;
+      double tlo[3] = {mlo0 + tx * tl, mlo1 + ty * tl, mlo2 + tz * tl};
       double tc[3] = {tlo[0] + 0.5 * tl, tlo[1] + 0.5 * tl, tlo[2] + 0.5 * tl};
       double half = 0.5 * tl + mrg;
       for (int j = 0; j < nsg; ++j) {
         const SegInfo &g = sg[j + 1];
         bool ov = true;
-        for (int a = 0; a < 3; ++a)
-          ov = ov && !(g.hi[a] < tlo[a] - mrg || g.lo[a] > tlo[a] + tl + mrg);
+        for (int a = 0; a < 3; ++a)  // all six bounds, no early exit
+          ov = ov & !(g.hi[a] < tlo[a] - mrg) & !(g.lo[a] > tlo[a] + tl + mrg);
         if (!ov) continue;
         const int i = s0 + j;
         // the slab rule keeps only segments that can be a cell's nearest one;
         // the segment-integrated rule needs every segment within reach
-        if (nb >= 2 && g.len > 0.0 && cs.proj_mode == ALP_PROJ_NEAREST) {
+        if (slab && g.len > 0.0) {
           double ac = (tc[0] - g.a[0]) * g.u[0] + (tc[1] - g.a[1]) * g.u[1] + (tc[2] - g.a[2]) * g.u[2];
           double hw = half * g.su;
           if (i > 0 && !(ac + hw > -mrg)) {
@@ -442,7 +449,7 @@ __global__ __launch_bounds__(64) void k_chunk_tiles(StepLaunch L) {
       e.beam = wlo >= 0 ? gb : -1;
       e.lo = nb == 1 ? 0 : wlo;
       e.hi = nb == 1 ? 0 : whi;
-      e.tile = (int32_t)(cs.tile_base + ((int64_t)tz * m.nt[1] + ty) * m.nt[0] + tx);
+      e.tile = (int32_t)(tbase + ((int64_t)tz * nty + ty) * ntx + tx);
       W.emit_raw[slot] = e;
       if (wlo >= 0) atomicAdd(&W.tile_cnt[e.tile], 1u);
     }
@@ -588,6 +595,11 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_tile_merge(StepLaunch L) {
     }
     return;
   }
+  // cells of the tile (read before the windows, so that both loads overlap)
+  const int c = case_of(L.tbase, L.n_cases, tg);
+  const CaseDev &cs = L.cases[c];
+  const int64_t tl = tg - cs.tile_base;
+  const uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
   uint32_t ne = 0;
   if (n_emit <= 64u) {
     // one window per lane: the head of a beam is its window with the
@@ -633,15 +645,8 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_tile_merge(StepLaunch L) {
   }
   if (lane == 0) {
     uint32_t ni = 0;
-    if (ne > (uint32_t)kMaxEntries) {
-      set_overflow(W, 4u);
-    } else {
-      const int c = case_of(L.tbase, L.n_cases, tg);
-      const CaseDev &cs = L.cases[c];
-      const int64_t tl = tg - cs.tile_base;
-      const uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
-      ni = (ncell + 63u) / 64u;
-    }
+    if (ne > (uint32_t)kMaxEntries) set_overflow(W, 4u);
+    else ni = (ncell + 63u) / 64u;
     W.tile_nent[tg] = ni ? ne : 0u;
     W.tile_items[tg] = ni;
   }
@@ -698,14 +703,40 @@ __device__ __forceinline__ bool closer_cell(const MeshDev &m, double D, int64_t 
   if (best < 0) return true;
   if (D < bD) return true;
   if (D > bD) return false;
-  const double *a = m.cxyz + 3 * j, *b = m.cxyz + 3 * best;
+  const gptr<double> a = to_global(m.cxyz) + 4 * j, b = to_global(m.cxyz) + 4 * best;
   if (a[0] != b[0]) return a[0] < b[0];
   if (a[1] != b[1]) return a[1] < b[1];
   if (a[2] != b[2]) return a[2] < b[2];
-  return m.perm[j] < m.perm[best];
+  return a[3] < b[3];  // caller index
 }
 
-__device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, int sub) {
+// Search state of one lane: the best sorted index, its squared distance and
+// its caller index.
+struct Nearest {
+  int64_t best = -1;
+  double bD = INFINITY;
+  int32_t caller = -1;
+  __device__ __forceinline__ void consider(const MeshDev &m, double x, double y, double z, int64_t j,
+                                           const double4 &c) {
+    const double D = sqdist_exact(x, y, z, c.x, c.y, c.z);
+    if (closer_cell(m, D, j, bD, best)) {
+      best = j;
+      bD = D;
+      caller = (int32_t)c.w;
+    }
+  }
+};
+
+__device__ __forceinline__ double4 loc_record(const MeshDev &m, int64_t j) {
+  const gptr<double> r = to_global(m.cxyz) + 4 * j;
+  return make_double4(r[0], r[1], r[2], r[3]);
+}
+
+// Returns the sorted index (the same on every lane of the group) and, in
+// *caller, the caller's index of that cell; -1 for both when x is outside the
+// domain box.
+__device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, int sub, int32_t *caller) {
+  *caller = -1;
   if (!(x >= m.box[0] && x <= m.box[3] && y >= m.box[1] && y <= m.box[4] && z >= m.box[2] &&
         z <= m.box[5]))
     return -1;
@@ -717,40 +748,64 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
   }
   const double slack = 1e-9 * (m.bin * (double)(m.nb[0] + m.nb[1] + m.nb[2]) + fabs(m.lo[0]) +
                                fabs(m.lo[1]) + fabs(m.lo[2]));
-  int64_t best = -1;
-  double bD = INFINITY;
-  // the first pass covers the whole 3x3x3 block of bins (with bins about one
-  // cell wide it nearly always settles the search); later passes add one
-  // Chebyshev shell each
+  Nearest nr;
+  // The first pass covers the whole 3x3x3 block of bins (with bins about one
+  // cell wide it nearly always settles the search): each lane takes two bins
+  // and issues the loads of both together (bin ranges, then the first cell of
+  // each).  Later passes add one Chebyshev shell each.
+  static_assert(2 * kSampleLanes >= 27, "two bins per lane cover the first block");
   for (int r = 1;; ++r) {
-    const int side = 2 * r + 1;
-    const int ncube = side * side * side;
-    for (int c = sub; c < ncube; c += kSampleLanes) {
-      int dz = c / (side * side), dy = (c / side) % side, dx = c % side;
-      int ix = qi[0] - r + dx, iy = qi[1] - r + dy, iz = qi[2] - r + dz;
-      int ch = max(abs(dx - r), max(abs(dy - r), abs(dz - r)));
-      if ((r > 1 && ch != r) || ix < 0 || iy < 0 || iz < 0 || ix >= m.nb[0] || iy >= m.nb[1] ||
-          iz >= m.nb[2])
-        continue;
-      uint32_t k = bin_key(m, ix, iy, iz);
-      uint32_t e = m.bin_start[k + 1];
-      for (uint32_t j = m.bin_start[k]; j < e; ++j) {
-        const double *cj = m.cxyz + 3 * (int64_t)j;
-        double D = sqdist_exact(x, y, z, cj[0], cj[1], cj[2]);
-        if (closer_cell(m, D, j, bD, best)) {
-          best = j;
-          bD = D;
-        }
+    if (r == 1) {
+      uint32_t kb[2], st[2], en[2];
+      bool ok[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = sub + h * kSampleLanes;
+        const int ix = qi[0] - 1 + c % 3, iy = qi[1] - 1 + (c / 3) % 3, iz = qi[2] - 1 + c / 9;
+        ok[h] = c < 27 && ix >= 0 && iy >= 0 && iz >= 0 && ix < m.nb[0] && iy < m.nb[1] && iz < m.nb[2];
+        kb[h] = ok[h] ? bin_key(m, ix, iy, iz) : 0u;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        st[h] = to_global(m.bin_start)[kb[h]];
+        en[h] = to_global(m.bin_start)[kb[h] + 1];
+      }
+      double4 f[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (!ok[h]) en[h] = st[h];
+        f[h] = loc_record(m, st[h] < en[h] ? st[h] : 0);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (st[h] < en[h]) nr.consider(m, x, y, z, st[h], f[h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        for (uint32_t j = st[h] + 1; j < en[h]; ++j) nr.consider(m, x, y, z, j, loc_record(m, j));
+    } else {
+      const int side = 2 * r + 1;
+      const int ncube = side * side * side;
+      for (int c = sub; c < ncube; c += kSampleLanes) {
+        int dz = c / (side * side), dy = (c / side) % side, dx = c % side;
+        int ix = qi[0] - r + dx, iy = qi[1] - r + dy, iz = qi[2] - r + dz;
+        int ch = max(abs(dx - r), max(abs(dy - r), abs(dz - r)));
+        if (ch != r || ix < 0 || iy < 0 || iz < 0 || ix >= m.nb[0] || iy >= m.nb[1] || iz >= m.nb[2])
+          continue;
+        uint32_t k = bin_key(m, ix, iy, iz);
+        uint32_t e = to_global(m.bin_start)[k + 1];
+        for (uint32_t j = to_global(m.bin_start)[k]; j < e; ++j) nr.consider(m, x, y, z, j, loc_record(m, j));
       }
     }
     // group reduction (all lanes of the group end with the same best)
 #pragma unroll
     for (int o = kSampleLanes / 2; o > 0; o >>= 1) {
-      double oD = __shfl_xor(bD, o, 64);
-      long long ob = __shfl_xor((long long)best, o, 64);
-      if (closer_cell(m, oD, ob, bD, best)) {
-        best = ob;
-        bD = oD;
+      const double oD = __shfl_xor(nr.bD, o, 64);
+      const long long ob = __shfl_xor((long long)nr.best, o, 64);
+      const int oc = __shfl_xor(nr.caller, o, 64);
+      if (closer_cell(m, oD, ob, nr.bD, nr.best)) {
+        nr.best = ob;
+        nr.bD = oD;
+        nr.caller = oc;
       }
     }
     bool all = true;
@@ -767,9 +822,10 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
     }
     if (all) break;
     bound -= slack;
-    if (best >= 0 && bound > 0.0 && bD < bound * bound) break;
+    if (nr.best >= 0 && bound > 0.0 && nr.bD < bound * bound) break;
   }
-  return best;
+  *caller = nr.caller;
+  return nr.best;
 }
 
 // Eq. (16)-(18) per actuator point, in the paper's order.  Every lane of a
@@ -778,7 +834,9 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
 #pragma clang fp contract(off)
   Work W = L.w;
   const int sub = threadIdx.x % kSampleLanes;
-  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSampleLanes;
+  constexpr int kPts = 64 / kSampleLanes;  // points per wave and pass
+  for (int64_t g0 = (int64_t)blockIdx.x * kPts; g0 < W.n_points; g0 += (int64_t)gridDim.x * kPts) {
+  const int64_t g = g0 + threadIdx.x / kSampleLanes;
   const bool act = g < W.n_points;
   bool out = false, fb = false, dg = false;
   int c = 0;
@@ -787,16 +845,17 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
     const CaseDev &cs = L.cases[c];
     const MeshDev &m = cs.m;
     const int64_t k = g - cs.point_base;
-    const int64_t b = W.pbeam[g] - cs.beam_base;
-    const double *Pa = cs.P + 3 * k, *Pd = cs.Pdot + 3 * k, *et = cs.e_t + 3 * k;
+    const int64_t b = to_global(W.pbeam)[g] - cs.beam_base;
+    const gptr<double> Pa = to_global(cs.P) + 3 * k, Pd = to_global(cs.Pdot) + 3 * k, et = to_global(cs.e_t) + 3 * k;
     double nrm = sqrt(dot3_exact(et[0], et[1], et[2], et[0], et[1], et[2]));
     double e[3] = {et[0] / nrm, et[1] / nrm, et[2] / nrm};
     double ps[3] = {Pa[0], Pa[1], Pa[2]}, us[3] = {0.0, 0.0, 0.0}, as[3] = {0.0, 0.0, 0.0};
-    int64_t ca = locate_group(m, Pa[0], Pa[1], Pa[2], sub), cs_ = -1;
+    int32_t ca_c = -1, cs_c = -1;  // caller indices of the two cells
+    int64_t ca = locate_group(m, Pa[0], Pa[1], Pa[2], sub, &ca_c), cs_ = -1;
     if (ca < 0) {
       out = true;
     } else {
-      const double *Ua = cs.U + 3 * (int64_t)m.perm[ca];
+      const gptr<double> Ua = to_global(cs.U) + 3 * (int64_t)ca_c;
       double u0[3] = {Ua[0] - Pd[0], Ua[1] - Pd[1], Ua[2] - Pd[2]};
       double ut = dot3_exact(u0[0], u0[1], u0[2], e[0], e[1], e[2]);
       double un[3] = {u0[0] - ut * e[0], u0[1] - ut * e[1], u0[2] - ut * e[2]};
@@ -807,7 +866,7 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
         es[1] = -un[1] / mag;
         es[2] = -un[2] / mag;
       } else {
-        const double *eu = cs.e_up + 3 * b;
+        const gptr<double> eu = to_global(cs.e_up) + 3 * b;
         double ge = dot3_exact(eu[0], eu[1], eu[2], e[0], e[1], e[2]);
         double gv[3] = {eu[0] - ge * e[0], eu[1] - ge * e[1], eu[2] - ge * e[2]};
         double gn = sqrt(dot3_exact(gv[0], gv[1], gv[2], gv[0], gv[1], gv[2]));
@@ -821,20 +880,20 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
           dg = true;
         }
       }
-      const double *np = cs.n_p + 3 * b;
+      const gptr<double> np = to_global(cs.n_p) + 3 * b;
       double dn = dot3_exact(np[0], np[1], np[2], es[0], es[1], es[2]);
-      double ls = cs.ls[b];
+      double ls = to_global(cs.ls)[b];
       for (int a = 0; a < 3; ++a) ps[a] = Pa[a] + ls * (es[a] - dn * np[a]);
-      cs_ = locate_group(m, ps[0], ps[1], ps[2], sub);
+      cs_ = locate_group(m, ps[0], ps[1], ps[2], sub, &cs_c);
       if (cs_ < 0) {
         out = true;
       } else {
-        const double *Us = cs.U + 3 * (int64_t)m.perm[cs_];
+        const gptr<double> Us = to_global(cs.U) + 3 * (int64_t)cs_c;
         us[0] = Us[0];
         us[1] = Us[1];
         us[2] = Us[2];
         if (cs.dUdt) {
-          const double *As = cs.dUdt + 3 * (int64_t)m.perm[cs_];
+          const gptr<double> As = to_global(cs.dUdt) + 3 * (int64_t)cs_c;
           as[0] = As[0];
           as[1] = As[1];
           as[2] = As[2];
@@ -855,8 +914,8 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
         for (int a = 0; a < 3; ++a) cs.U_s[3 * k + a] = us[a];
       if (cs.P_s)
         for (int a = 0; a < 3; ++a) cs.P_s[3 * k + a] = ps[a];
-      if (cs.cell_a) cs.cell_a[k] = ca < 0 ? -1 : (int64_t)m.perm[ca];
-      if (cs.cell_s) cs.cell_s[k] = cs_ < 0 ? -1 : (int64_t)m.perm[cs_];
+      if (cs.cell_a) cs.cell_a[k] = ca < 0 ? -1 : (int64_t)ca_c;
+      if (cs.cell_s) cs.cell_s[k] = cs_ < 0 ? -1 : (int64_t)cs_c;
       W.pflags[g] = (out ? 1 : 0) | (fb ? 2 : 0) | (dg ? 4 : 0);
     }
   }
@@ -875,12 +934,17 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
     if (fb) atomicAdd((unsigned long long *)(cnt + 1), 1ull);
     if (dg) atomicAdd((unsigned long long *)(cnt + 2), 1ull);
   }
+  }
 }
 
+// One wave per four points, or (sample_waves > 0) at most that many waves per
+// CU walking the points with a stride.
 void launch_sample(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_points == 0) return;
-  int64_t threads = L.w.n_points * kSampleLanes;
-  hipLaunchKernelGGL(k_sample, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, st, L);
+  int64_t blocks = (L.w.n_points * kSampleLanes + 63) / 64;
+  const int64_t cap = (int64_t)(L.grid_persistent / 8) * L.sample_waves;
+  if (cap > 0 && blocks > cap) blocks = cap;
+  hipLaunchKernelGGL(k_sample, dim3((unsigned)blocks), dim3(64), 0, st, L);
 }
 
 // ---------------------------------------------------------- kernel sample --
@@ -979,7 +1043,8 @@ __global__ __launch_bounds__(64) void k_beam_geometry(GeomLaunch G) {
   double ek = 0.0;
   bool out = false;
   if (G.eps) {
-    const int64_t c = locate_group(G.m, P[0], P[1], P[2], sub);
+    int32_t c_caller;
+    const int64_t c = locate_group(G.m, P[0], P[1], P[2], sub, &c_caller);
     ek = G.eps_phys[k];
     if (c < 0) {
       out = true;
@@ -1029,6 +1094,10 @@ __global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
     }
     double den = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
     const bool acc = cs.dUdt != nullptr;
+    // mesh and field arrays as global pointers, read once per point
+    const gptr<uint32_t> bs = to_global(m.bin_start), gp = to_global(m.perm);
+    const gptr<double> gx = to_global(m.cx), gy = to_global(m.cy), gz = to_global(m.cz), gv = to_global(m.vs);
+    const gptr<double> gU = to_global(cs.U);
     if (ok) {
       const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
       const int64_t total = (int64_t)nx * ny * nz;
@@ -1036,18 +1105,18 @@ __global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
         const int ix = lo[0] + (int)(q % nx), iy = lo[1] + (int)((q / nx) % ny),
                   iz = lo[2] + (int)(q / ((int64_t)nx * ny));
         const uint32_t key = bin_key(m, ix, iy, iz);
-        const uint32_t e = m.bin_start[key + 1];
-        for (uint32_t j = m.bin_start[key]; j < e; ++j) {
-          const double r2 = sqdist_exact(p[0], p[1], p[2], m.cx[j], m.cy[j], m.cz[j]);
+        const uint32_t e = bs[key + 1];
+        for (uint32_t j = bs[key]; j < e; ++j) {
+          const double r2 = sqdist_exact(p[0], p[1], p[2], gx[j], gy[j], gz[j]);
           if (!(r2 <= cut)) continue;
-          const double gw = exp(-(r2 / e2)) * m.vs[j];
-          const double *Uj = cs.U + 3 * (int64_t)m.perm[j];
+          const double gw = exp(-(r2 / e2)) * gv[j];
+          const gptr<double> Uj = gU + 3 * (int64_t)gp[j];
           den += gw;
           n0 += gw * Uj[0];
           n1 += gw * Uj[1];
           n2 += gw * Uj[2];
           if (acc) {
-            const double *Aj = cs.dUdt + 3 * (int64_t)m.perm[j];
+            const gptr<double> Aj = to_global(cs.dUdt) + 3 * (int64_t)gp[j];
             m0 += gw * Aj[0];
             m1 += gw * Aj[1];
             m2 += gw * Aj[2];
@@ -1183,8 +1252,9 @@ struct WeightsScratch {
 
 // exact FP64 scan of window segments j0..j1 (local indices; points read from
 // the beam array at X), strict '<' so the lowest index wins a tie
-__device__ __forceinline__ void exact_scan(const double *X, int j0, int j1, double cx, double cy,
-                                           double cz, int &bj, double &bs, double &br2) {
+template <class Ptr>
+__device__ __forceinline__ void exact_scan(Ptr X, int j0, int j1, double cx, double cy, double cz, int &bj,
+                                           double &bs, double &br2) {
   double ax = X[3 * j0], ay = X[3 * j0 + 1], az = X[3 * j0 + 2];
   for (int j = j0; j <= j1; ++j) {
     const double bx = X[3 * j + 3], by = X[3 * j + 4], bz = X[3 * j + 5];
@@ -1251,8 +1321,9 @@ __device__ __forceinline__ void candidate(const WeightsScratch &sh, int nwords, 
 // Segment-integrated rule: is the segment starting at A (end A + 3) within
 // 3 eps_seg of the cell, eps_seg = (eps_a + eps_b) / 2?  Zero-length segments
 // never are.  FP64, in the decision order of the nearest rule's cutoff.
-__device__ __forceinline__ bool seg_in_reach(const double *A, double ea, double eb, double cx, double cy,
-                                             double cz, double &es) {
+template <class Ptr>
+__device__ __forceinline__ bool seg_in_reach(Ptr A, double ea, double eb, double cx, double cy, double cz,
+                                             double &es) {
 #pragma clang fp contract(off)
   const double ex = A[3] - A[0], ey = A[4] - A[1], ez = A[5] - A[2];
   if (!(((ex * ex + ey * ey) + ez * ez) > 0.0)) return false;
@@ -1318,7 +1389,9 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   WorkQueue wq = work_queue(W.counters + (kInt ? (kSplit ? 16 : 24) : (kSplit ? 8 : 32)),
                             (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
   while (wq.next(lane)) {
-    const uint32_t item = wq.item;
+    // the item index is wave-uniform: read it into a scalar register so that
+    // the descriptor and the case fields are scalar loads
+    const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane((int)wq.item);
     const Item it = W.item[item];
     if ((L.cases[it.cs].proj_mode == ALP_PROJ_INTEGRATED) != kInt) continue;
     if ((L.cases[it.cs].prec == ALP_PREC_FP32_SPLIT) != kSplit) continue;
@@ -1330,6 +1403,11 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     }
     const CaseDev &cs = L.cases[it.cs];
     const MeshDev &m = cs.m;
+    // case fields held in registers for the whole item: the loops below store
+    // and update atomically, after which the compiler would read them again
+    const gptr<double> Psp = to_global(cs.Psp);
+    const gptr<double> Eps = to_global(cs.eps);
+    const int64_t pbase = cs.point_base;
     const int64_t tl = it.tile - cs.tile_base;
     const int rsz = rec_size(cs.prec);
     const uint32_t ne = it.nent;  // <= kMaxEntries (the tile merge drops larger tiles)
@@ -1338,10 +1416,10 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     const bool valid = c < it.c1;
     double cx = 0, cy = 0, cz = 0, v = 0;
     if (valid) {
-      cx = m.cx[c];
-      cy = m.cy[c];
-      cz = m.cz[c];
-      v = m.vs[c];
+      cx = to_global(m.cx)[c];
+      cy = to_global(m.cy)[c];
+      cz = to_global(m.cz)[c];
+      v = to_global(m.vs)[c];
     }
     // 1. entries and the staging plan: the leading entries whose windows fit
     uint32_t carry = 0;
@@ -1378,13 +1456,13 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     for (int q = lane; q < npts; q += 64) {
       const int e = entry_of_point(sh, n_staged, q);
       const int64_t k = sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
-      const double *P = cs.Psp + 3 * k;
+      const gptr<double> P = Psp + 3 * k;
       sh.sa[q] = make_float4((float)(P[0] - ctx), (float)(P[1] - cty), (float)(P[2] - ctz), 0.f);
       sh.ahi[q] = 0;
       sh.alo[q] = 0;
-      sh.wx[q] = W.wexp[cs.point_base + k];
+      sh.wx[q] = W.wexp[pbase + k];
       // eps rounded up to FP32 (positive floats order like their bits)
-      const double ep = cs.eps[k];
+      const double ep = Eps[k];
       float ef = (float)ep;
       if ((double)ef < ep) ef = nextafterf(ef, INFINITY);
       if (ef > 0.f) atomicMax(&sh.e_em[e], __float_as_uint(ef));
@@ -1427,7 +1505,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
             const float4 A = sh.sa[pt0 + p];
             return make_float3(A.x, A.y, A.z);
           }
-          const double *P = cs.Psp + 3 * (k + p);
+          const gptr<double> P = Psp + 3 * (k + p);
           return make_float3((float)(P[0] - ctx), (float)(P[1] - cty), (float)(P[2] - ctz));
         };
         const float3 P0 = point(0), P1 = point(np - 1);
@@ -1453,7 +1531,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
           amax = fmaxf(amax, a);
           dev2 = fmaxf(dev2, dx * dx + dy * dy + dz * dz - a * a);
           rr = fmaxf(rr, A.x * A.x + A.y * A.y + A.z * A.z);
-          if (pt0 < 0) dem = fmax(dem, cs.eps[k + p]);
+          if (pt0 < 0) dem = fmax(dem, Eps[k + p]);
         }
         const float em = pt0 >= 0 ? __uint_as_float(sh.e_em[e]) : (float)(dem * (1.0 + 1e-6));
         // coordinates of points and cells lie within Rmax of the tile centre;
@@ -1546,7 +1624,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       for (int q = lane; q < npts; q += 64) {
         const int e = entry_of_point(sh, n_staged, q);
         const int64_t k = sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
-        const double ep = cs.eps[k];
+        const double ep = Eps[k];
         float ef = (float)ep;
         if ((double)ef > ep) ef = nextafterf(ef, 0.f);
         atomicMin(&si.emin[e], __float_as_uint(fmaxf(ef, 0.f)));
@@ -1595,7 +1673,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               atomicAdd((unsigned long long *)&sh.ahi[pt0 + q], (unsigned long long)h);
               atomicAdd(&sh.alo[pt0 + q], l);
             } else {
-              const int64_t node = cs.point_base + k0 + (i1 < 0 ? 0 : i0) + q;
+              const int64_t node = pbase + k0 + (i1 < 0 ? 0 : i0) + q;
               fx_encode(av, W.wexp[node], h, l);
               atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h);
               atomicAdd(&W.w_lo[node], l);
@@ -1604,14 +1682,14 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
           unsigned char *r = W.rec + rbase + (unsigned long long)pos * rsz;
           if (i1 < 0) {
             // single-CV beam: the point kernel of the nearest rule
-            const double *P = cs.Psp + 3 * (int64_t)k0;
+            const gptr<double> P = Psp + 3 * (int64_t)k0;
             double a0, a1;
-            pair_weights(kSplit ? ALP_PREC_FP32_SPLIT : ALP_PREC_FP64, 0.0, sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]), cs.eps[k0], a0, a1);
+            pair_weights(kSplit ? ALP_PREC_FP32_SPLIT : ALP_PREC_FP64, 0.0, sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]), Eps[k0], a0, a1);
             acc(0, a0 * pv);
-            if (rec_ok) write_record(r, rsz, (uint32_t)Lc | kRecSingle, (uint32_t)(cs.point_base + k0), a0, 0.0);
+            if (rec_ok) write_record(r, rsz, (uint32_t)Lc | kRecSingle, (uint32_t)(pbase + k0), a0, 0.0);
           } else {
-            const double *A = cs.Psp + 3 * ((int64_t)k0 + i0 + j);
-            const double *E = cs.eps + (int64_t)k0 + i0 + j;
+            const gptr<double> A = Psp + 3 * ((int64_t)k0 + i0 + j);
+            const gptr<double> E = Eps + (int64_t)k0 + i0 + j;
             double a0, a1;
             if constexpr (kSplit)
               seg_int_weights_split(pcx, pcy, pcz, A[0], A[1], A[2], A[3], A[4], A[5], 0.5 * (E[0] + E[1]), a0, a1);
@@ -1619,7 +1697,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               seg_int_weights(pcx, pcy, pcz, A[0], A[1], A[2], A[3], A[4], A[5], 0.5 * (E[0] + E[1]), a0, a1);
             acc(j, a0 * pv);
             acc(j + 1, a1 * pv);
-            if (rec_ok) write_record(r, rsz, (uint32_t)Lc, (uint32_t)(cs.point_base + k0 + i0 + j), a0, a1);
+            if (rec_ok) write_record(r, rsz, (uint32_t)Lc, (uint32_t)(pbase + k0 + i0 + j), a0, a1);
           }
         }
         qh += n;
@@ -1663,10 +1741,10 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
           if (on) {
             const int k0 = sh.e_k0[ce], i0 = sh.e_i0[ce], i1 = sh.e_i1[ce];
             if (i1 < 0) {
-              const double *P = cs.Psp + 3 * (int64_t)k0;
-              in = inside_cutoff(sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]), cs.eps[k0]);
+              const gptr<double> P = Psp + 3 * (int64_t)k0;
+              in = inside_cutoff(sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]), Eps[k0]);
             } else {
-              const double *E = cs.eps + (int64_t)k0 + i0 + j;
+              const gptr<double> E = Eps + (int64_t)k0 + i0 + j;
               const int pt0 = ce < n_staged ? sh.e_pt0[ce] : -1;
               bool out = false, sure_in = false;
               if (pt0 >= 0) {
@@ -1691,7 +1769,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               }
               double es64;
               in = sure_in ||
-                   (!out && seg_in_reach(cs.Psp + 3 * ((int64_t)k0 + i0 + j), E[0], E[1], pcx, pcy, pcz, es64));
+                   (!out && seg_in_reach(Psp + 3 * ((int64_t)k0 + i0 + j), E[0], E[1], pcx, pcy, pcz, es64));
             }
           }
           const uint64_t bal = ballot64(in);
@@ -1732,12 +1810,12 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
           int bj = 0;
           if (i1 < 0) {
             single = 1;
-            const double *P = cs.Psp + 3 * (int64_t)k0;
+            const gptr<double> P = Psp + 3 * (int64_t)k0;
             br2 = sqdist_exact(pcx, pcy, pcz, P[0], P[1], P[2]);
-            ej = cs.eps[k0];
+            ej = Eps[k0];
           } else {
             const int nseg = i1 - i0 + 1;
-            const double *X = cs.Psp + 3 * ((int64_t)k0 + i0);
+            const gptr<double> X = Psp + 3 * ((int64_t)k0 + i0);
             bool full = pt0 < 0;
             if (!full) {
               // FP32 ranking: the three smallest (distance, index) keys
@@ -1771,7 +1849,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               if (!full) {
                 // the node widths of the one or two re-checked segments are
                 // loaded with their end points, not after the choice
-                const double *E = cs.eps + (int64_t)k0 + i0;
+                const gptr<double> E = Eps + (int64_t)k0 + i0;
                 const int j1 = (int)(k1 & kSegIdxMask);
                 double e0 = E[j1], e1 = E[j1 + 1];
                 exact_scan(X, j1, j1, pcx, pcy, pcz, bj, bs, br2);
@@ -1797,14 +1875,14 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               bj = 0;
               bs = 0.0;
               exact_scan(X, 0, nseg - 1, pcx, pcy, pcz, bj, bs, br2);
-              const double *E = cs.eps + (int64_t)k0 + i0;
+              const gptr<double> E = Eps + (int64_t)k0 + i0;
               ej = eps_at(bs, E[bj], E[bj + 1]);
             }
           }
           in = inside_cutoff(br2, ej);
           if (in) {
             pair_weights(kSplit ? ALP_PREC_FP32_SPLIT : ALP_PREC_FP64, bs, br2, ej, a0, a1);
-            const int64_t node = cs.point_base + k0 + (single ? 0 : i0 + bj);
+            const int64_t node = pbase + k0 + (single ? 0 : i0 + bj);
             long long h0, h1 = 0;
             unsigned long long l0, l1 = 0;
             if (pt0 >= 0) {
@@ -1859,7 +1937,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       unsigned long long l = sh.alo[q];
       if (h == 0 && l == 0) continue;
       const int e = entry_of_point(sh, n_staged, q);
-      const int64_t node = cs.point_base + sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
+      const int64_t node = pbase + sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
       h += (long long)(l >> kLoBits);
       l &= (1ull << kLoBits) - 1ull;
       atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h);
@@ -2101,8 +2179,8 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
     const MeshDev &m = cs.m;
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
-    const double v = valid ? m.vs[c] : 0.0;
-    const uint32_t pc = valid ? m.perm[c] : 0u;
+    const double v = valid ? to_global(m.vs)[c] : 0.0;
+    const uint32_t pc = valid ? to_global(m.perm)[c] : 0u;
     const int rsz = rec_size(cs.prec);
     const bool has_next = item + stride < n_items;
     const int nrsz = has_next ? rec_size(L.cases[nxt.cs].prec) : 16;
@@ -2129,7 +2207,7 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
             a0 = __hiloint2double((int)C.r[k].w, (int)C.r[k].z);
             a1 = __hiloint2double((int)C.h[k].y, (int)C.h[k].x);
           }
-          const double *fp = W.fhat + 3 * (int64_t)node;
+          const gptr<double> fp = to_global(W.fhat) + 3 * (int64_t)node;
           double q0 = a0 * fp[0], q1 = a0 * fp[1], q2 = a0 * fp[2];
           if (!(meta & kRecSingle)) {
             q0 += a1 * fp[3];
