@@ -455,7 +455,7 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
     (void)hipStreamWaitEvent(sd, ctx->ev_fork, 0);
   }
   if (stages & ST_SAMPLE) {
-    // beside the segment binning the sampler keeps to two waves per SIMD,
+    // beside the segment binning the sampler keeps to a few waves per CU,
     // which leaves the binning's small kernels room on every CU
     StepLaunch Ls = L;
     Ls.sample_waves = fork ? kSampleWavesBeside : 0;

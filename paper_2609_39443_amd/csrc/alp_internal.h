@@ -11,7 +11,15 @@ namespace alp {
 constexpr int kWave = 64;
 constexpr int kChunkSegs = 16;      // segments per chunk in the segment binning
 constexpr int kMaxEmitTile = 256;   // (chunk, tile) windows of one tile a wave can merge
-constexpr int kCounters = 40;       // step counters and work-queue words
+#ifndef ALP_QUEUE_STRIPES
+#define ALP_QUEUE_STRIPES 16
+#endif
+constexpr int kQueueStripes = ALP_QUEUE_STRIPES;  // counters per work queue
+constexpr int kLineWords = 32;                    // uint32 words per 128-byte line
+// step counters: a line of flags, then four work queues whose counters each
+// sit on a line of their own (atomics on one line serialise)
+constexpr int kCounters = kLineWords + 4 * kQueueStripes * kLineWords;
+__host__ __device__ constexpr int queue_words(int q) { return kLineWords + q * kQueueStripes * kLineWords; }
 constexpr int kMaxEntries = 128;    // merged (tile, beam) entries a wave can screen
 constexpr int kMaskWords = kMaxEntries / 32;
 constexpr int kStagePts = 160;      // window points (and node accumulators) staged in LDS
@@ -150,8 +158,9 @@ struct Work {
   long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, empty kernel sample
   double *diag_out;     // [n_cases][16] finalised diagnostics
   // scalars
-  uint32_t *counters;   // [kCounters]: 3 overflow flags; weights work queues (8 words each): 8 nearest
-                        // split, 16 integrated split, 24 integrated FP64, 32 nearest FP64
+  uint32_t *counters;   // [kCounters]: [3] overflow flags; from queue_words(q) the weights work
+                        // queues q = 0 nearest split, 1 integrated split, 2 integrated FP64,
+                        // 3 nearest FP64 (counter x of a queue at word x * kLineWords)
   int64_t cap_emit, cap_item, cap_rec, cap_chunk;
   int64_t n_points, n_beams, n_tiles;
   int32_t n_cases, n_pblocks;

@@ -56,12 +56,13 @@ __device__ __forceinline__ void set_overflow(Work &W, uint32_t bit) { atomicOr(&
 // Dynamic work distribution for a persistent kernel: work items are cut into
 // chunks of `grab` consecutive items.  A wave's first chunk is its block index
 // (no atomic, so idle waves of a small step leave at once); later chunks come
-// from one of 8 counters (block index mod 8, so the counters share the load):
-// chunk G + 8 q + x for the q-th grab on counter x, G the grid size.  The
-// counters start at zero every step; a wave leaves once a chunk past the end
-// comes back.
+// from one of kQueueStripes counters (block index mod kQueueStripes, so the
+// counters share the load; each sits on its own cache line): chunk
+// G + S q + x for the q-th grab on counter x, G the grid size and S the
+// number of counters.  The counters start at zero every step; a wave leaves
+// once a chunk past the end comes back.
 struct WorkQueue {
-  uint32_t *ctr;  // [8]
+  uint32_t *ctr;  // counter x at ctr[x * kLineWords]
   uint32_t n, grab, x, item, end;
   bool started;
   __device__ bool next(int lane) {
@@ -75,9 +76,9 @@ struct WorkQueue {
       chunk = blockIdx.x;
     } else {
       uint32_t q = 0;
-      if (lane == 0) q = atomicAdd(&ctr[x], 1u);
+      if (lane == 0) q = atomicAdd(&ctr[x * kLineWords], 1u);
       q = __shfl(q, 0, 64);
-      chunk = (uint64_t)gridDim.x + (uint64_t)q * 8u + x;
+      chunk = (uint64_t)gridDim.x + (uint64_t)q * kQueueStripes + x;
     }
     const uint64_t first = chunk * grab;
     if (first >= n) return false;
@@ -91,7 +92,7 @@ __device__ __forceinline__ WorkQueue work_queue(uint32_t *ctr, uint32_t n, uint3
   q.ctr = ctr;
   q.n = n;
   q.grab = grab;
-  q.x = blockIdx.x & 7u;
+  q.x = blockIdx.x % (uint32_t)kQueueStripes;
   q.item = 0;
   q.end = 0;
   q.started = false;
@@ -1386,7 +1387,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   unsigned long long blk_cur = 0, blk_end = 0;
   int acc_case = -1;
   unsigned long long acc_pairs = 0;
-  WorkQueue wq = work_queue(W.counters + (kInt ? (kSplit ? 16 : 24) : (kSplit ? 8 : 32)),
+  WorkQueue wq = work_queue(W.counters + queue_words(kInt ? (kSplit ? 1 : 2) : (kSplit ? 0 : 3)),
                             (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
   while (wq.next(lane)) {
     // the item index is wave-uniform: read it into a scalar register so that
