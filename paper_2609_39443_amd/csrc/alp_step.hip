@@ -1247,7 +1247,12 @@ struct WeightsScratch {
   int32_t e_pt0[kMaxEntries + 1];
   uint32_t e_em[kMaxEntries];  // bits of the window's largest eps (FP32, rounded up)
   float e_dabs[kMaxEntries];   // absolute error allowance of the FP32 ranking
-  uint32_t mask[64 * kMaskWords];
+  // the item's candidates: listed in order as (cell lane | entry << 6) when
+  // they fit, else as per-lane hit masks searched by candidate()
+  union {
+    uint32_t mask[64 * kMaskWords];
+    uint16_t cand[64 * kMaskWords * 2];
+  };
   uint32_t off[65];
 };
 
@@ -1465,7 +1470,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       // eps rounded up to FP32 (positive floats order like their bits)
       const double ep = Eps[k];
       float ef = (float)ep;
-      if ((double)ef < ep) ef = nextafterf(ef, INFINITY);
+      if ((double)ef < ep) ef = __uint_as_float(__float_as_uint(ef) + 1u);  // next float up (ef > 0 is all that is used)
       if (ef > 0.f) atomicMax(&sh.e_em[e], __float_as_uint(ef));
     }
     __syncthreads();
@@ -1494,6 +1499,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       const uint32_t e = 64u * bb + lane;
 #pragma unroll
       for (int q = 0; q < 10; ++q) fr[bb][q] = 0.f;
+      if (bb == 1 && ne <= 64u) break;  // wave-uniform: no second batch of entries
       fr[bb][6] = INFINITY;   // amin > amax: empty capsule
       fr[bb][7] = -INFINITY;
       if (e < ne) {
@@ -1540,7 +1546,9 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         // values (|d| <= 2 Rmax), the axial gap within 2^-18 Rmax: the radius
         // is widened by 2^-7 Rmax
         const float r2max = fmaxf(rr, (float)(3.0 * hl * hl));
-        const float Rc = 3.0f * em * (1.0f + 1e-5f) + ldexpf(sqrtf(r2max), -7);
+        // (the square roots below and in the screening are the hardware's,
+        // within 1 ulp: far inside these allowances)
+        const float Rc = 3.0f * em * (1.0f + 1e-5f) + ldexpf(__builtin_amdgcn_sqrtf(r2max), -7);
         fr[bb][0] = P0.x;
         fr[bb][1] = P0.y;
         fr[bb][2] = P0.z;
@@ -1549,7 +1557,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         fr[bb][5] = uz;
         fr[bb][6] = amin;
         fr[bb][7] = amax;
-        fr[bb][8] = sqrtf(fmaxf(dev2, 0.f));
+        fr[bb][8] = __builtin_amdgcn_sqrtf(fmaxf(dev2, 0.f));
         fr[bb][9] = Rc * Rc;
         // |FP32 distance^2 - exact distance^2| stays below ~80 u Rmax^2
         // (u = 2^-24) for coordinates within Rmax of the tile centre: rounding
@@ -1563,6 +1571,9 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     // 2. screening
     const float lx = (float)(cx - ctx), ly = (float)(cy - cty), lz = (float)(cz - ctz);
     uint32_t word = 0, cnt = 0;
+    uint32_t mw[kMaskWords];
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) mw[w] = 0u;
     for (uint32_t e = 0; e < ne; ++e) {
       const int l = (int)(e & 63);
       float f[10];
@@ -1575,13 +1586,15 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       }
       const float dx = lx - f[0], dy = ly - f[1], dz = lz - f[2];
       const float a = dx * f[3] + dy * f[4] + dz * f[5];
-      const float rho = sqrtf(fmaxf(dx * dx + dy * dy + dz * dz - a * a, 0.f));
+      const float rho = __builtin_amdgcn_sqrtf(fmaxf(dx * dx + dy * dy + dz * dz - a * a, 0.f));
       const float re = fmaxf(rho - f[8], 0.f);
       const float g = fmaxf(fmaxf(f[6] - a, a - f[7]), 0.f);
       const bool hit = valid && re * re + g * g <= f[9];
       if (hit) word |= 1u << (e & 31);
       if ((e & 31) == 31 || e == ne - 1) {
-        sh.mask[lane * kMaskWords + (e >> 5)] = word;
+#pragma unroll
+        for (int w = 0; w < kMaskWords; ++w)
+          if (w == (int)(e >> 5)) mw[w] = word;
         cnt += __popc(word);
         word = 0;
       }
@@ -1590,8 +1603,30 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     const uint32_t myoff = wave_excl_scan_u32(cnt, total);
     sh.off[lane] = myoff;
     if (lane == 63) sh.off[64] = myoff + cnt;
-    __syncthreads();
     const int nwords = (int)((ne + 31) >> 5);
+    // candidate p of the item: one LDS read from the list, or a search of
+    // the per-lane counts and masks when the list does not fit
+    const bool listed = total <= (uint32_t)(64 * kMaskWords * 2);
+    if (listed) {
+      uint32_t pos = myoff;
+#pragma unroll
+      for (int w = 0; w < kMaskWords; ++w)
+        for (uint32_t m = mw[w]; m; m &= m - 1u)
+          sh.cand[pos++] = (uint16_t)((uint32_t)lane | ((uint32_t)(w * 32 + __ffs(m) - 1) << 6));
+    } else {
+#pragma unroll
+      for (int w = 0; w < kMaskWords; ++w) sh.mask[lane * kMaskWords + w] = mw[w];
+    }
+    __syncthreads();
+    auto cand_of = [&](uint32_t p, int &Lc, int &e) {
+      if (listed) {
+        const uint32_t c = sh.cand[p];
+        Lc = (int)(c & 63u);
+        e = (int)(c >> 6);
+      } else {
+        candidate(sh, nwords, p, Lc, e);
+      }
+    };
     unsigned long long rbase = 0;
     bool rec_ok = true;
     // record space for n pairs, carved from the wave's block
@@ -1639,7 +1674,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         int Lc = lane, e = 0;
         uint32_t n = 0;
         if (p < total) {
-          candidate(sh, nwords, p, Lc, e);
+          cand_of(p, Lc, e);
           n = sh.e_i1[e] < 0 ? 1u : (uint32_t)(sh.e_i1[e] - sh.e_i0[e] + 1);
           if (n > kIntMaxSeg) {
             set_overflow(W, 16u);  // reported as a per-tile limit
@@ -1708,7 +1743,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         int Lc = lane, e = 0;
         uint32_t n = 0;
         if (p < total) {
-          candidate(sh, nwords, p, Lc, e);
+          cand_of(p, Lc, e);
           n = sh.e_i1[e] < 0 ? 1u : (uint32_t)(sh.e_i1[e] - sh.e_i0[e] + 1);
           if (n > kIntMaxSeg) {
             set_overflow(W, 16u);  // reported as a per-tile limit
@@ -1798,7 +1833,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         const uint32_t p = p0 + lane;
         const bool act = p < total;
         int Lc = lane, e = 0;
-        if (act) candidate(sh, nwords, p, Lc, e);
+        if (act) cand_of(p, Lc, e);
         const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
         const double pv = __shfl(v, Lc, 64);
         bool in = false;
