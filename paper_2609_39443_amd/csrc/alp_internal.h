@@ -25,7 +25,10 @@ constexpr int kMaskWords = kMaxEntries / 32;
 constexpr int kStagePts = 160;      // window points (and node accumulators) staged in LDS
 constexpr int kHiShift = 46;        // fixed-point: hi word holds v * 2^(46-E)
 constexpr int kLoBits = 40;         // lo word holds the next 40 bits
-constexpr int kSampleLanes = 16;    // lanes per actuator point in the sampler
+#ifndef ALP_SAMPLE_LANES
+#define ALP_SAMPLE_LANES 4
+#endif
+constexpr int kSampleLanes = ALP_SAMPLE_LANES;  // lanes per actuator point in the sampler
 constexpr unsigned long long kRecBlock = 64ull << 10;  // pair-record bytes a wave reserves at once
 
 // Binned mesh, device view (built by alp_bin_cells).
@@ -224,9 +227,10 @@ __device__ __forceinline__ bool inside_cutoff(double r2, double ej) {
 __device__ __forceinline__ void pair_weights(int prec, double s, double r2, double ej, double &a0,
                                              double &a1) {
   if (prec == ALP_PREC_FP32_SPLIT) {
-    float e2 = (float)(ej * ej);
-    float x = (float)r2 / e2;
-    float eta = expf(-x) / (3.14159265358979323846f * e2);
+    const float e2 = (float)(ej * ej);
+    const float ie2 = 1.0f / e2;  // one division serves both quotients
+    const float x = (float)r2 * ie2;
+    const float eta = expf(-x) * (ie2 * 0.318309886183790671538f);  // 1/pi
     float sf = (float)s;
     a0 = (double)((1.0f - sf) * eta);
     a1 = (double)(sf * eta);

@@ -751,37 +751,38 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
                                fabs(m.lo[1]) + fabs(m.lo[2]));
   Nearest nr;
   // The first pass covers the whole 3x3x3 block of bins (with bins about one
-  // cell wide it nearly always settles the search): each lane takes two bins
-  // and issues the loads of both together (bin ranges, then the first cell of
-  // each).  Later passes add one Chebyshev shell each.
-  static_assert(2 * kSampleLanes >= 27, "two bins per lane cover the first block");
+  // cell wide it nearly always settles the search): each lane takes
+  // kFirstBins bins and issues the loads of all of them together (bin
+  // ranges, then the first cell of each).  Later passes add one Chebyshev
+  // shell each.
+  constexpr int kFirstBins = (27 + kSampleLanes - 1) / kSampleLanes;
   for (int r = 1;; ++r) {
     if (r == 1) {
-      uint32_t kb[2], st[2], en[2];
-      bool ok[2];
+      uint32_t kb[kFirstBins], st[kFirstBins], en[kFirstBins];
+      bool ok[kFirstBins];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kFirstBins; ++h) {
         const int c = sub + h * kSampleLanes;
         const int ix = qi[0] - 1 + c % 3, iy = qi[1] - 1 + (c / 3) % 3, iz = qi[2] - 1 + c / 9;
         ok[h] = c < 27 && ix >= 0 && iy >= 0 && iz >= 0 && ix < m.nb[0] && iy < m.nb[1] && iz < m.nb[2];
         kb[h] = ok[h] ? bin_key(m, ix, iy, iz) : 0u;
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kFirstBins; ++h) {
         st[h] = to_global(m.bin_start)[kb[h]];
         en[h] = to_global(m.bin_start)[kb[h] + 1];
       }
-      double4 f[2];
+      double4 f[kFirstBins];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kFirstBins; ++h) {
         if (!ok[h]) en[h] = st[h];
         f[h] = loc_record(m, st[h] < en[h] ? st[h] : 0);
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < kFirstBins; ++h)
         if (st[h] < en[h]) nr.consider(m, x, y, z, st[h], f[h]);
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < kFirstBins; ++h)
         for (uint32_t j = st[h] + 1; j < en[h]; ++j) nr.consider(m, x, y, z, j, loc_record(m, j));
     } else {
       const int side = 2 * r + 1;
@@ -1863,7 +1864,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
                 const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
                 float dx = qx - A.x, dy = qy - A.y, dz = qz - A.z;
                 const float t = dx * ex + dy * ey + dz * ez;
-                const float sg = __saturatef(t * A.w);
+                const float sg = __builtin_amdgcn_fmed3f(t * A.w, 0.f, 1.f);  // clamp to [0, 1]
                 dx -= sg * ex;
                 dy -= sg * ey;
                 dz -= sg * ez;
