@@ -10,6 +10,7 @@ TMPDIR=/tmp (each counter group in a pass of its own):
   rocprofv3 --pmc <SQ counters> --output-format csv -d OUT/pmc -o sq -- <BENCH_PMC>
   rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/pmc -o fetch -- <BENCH_PMC> --copy-probe-mb 1024
   rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pmc -o write -- <BENCH_PMC> --copy-probe-mb 1024
+  rocprofv3 --pmc <LDS counters> --output-format csv -d OUT/pmc -o lds -- <BENCH_PMC>
 
 then
 
@@ -34,6 +35,8 @@ BENCH = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-fp64 --no-
 BENCH_PMC = "python3 bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-fp64 --no-extra"
 SQ = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_INSTS_SMEM SQ_WAIT_INST_ANY "
       "SQ_BUSY_CYCLES SQ_WAVE_CYCLES")
+LDS = ("SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT SQ_LDS_IDX_ACTIVE SQ_INSTS_LDS SQ_ACTIVE_INST_LDS "
+       "SQ_WAIT_INST_LDS")
 
 
 def commands(out: str) -> dict:
@@ -45,6 +48,7 @@ def commands(out: str) -> dict:
                   f"{BENCH_PMC} --copy-probe-mb 1024"),
         "write": (f"timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/pmc -o write -- "
                   f"{BENCH_PMC} --copy-probe-mb 1024"),
+        "lds": f"timeout -s KILL 240 rocprofv3 --pmc {LDS} --output-format csv -d {out}/pmc -o lds -- {BENCH_PMC}",
     }
 WORKLOAD = "canopy 256^3 / 2000 stems, FP32-split graph step"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
@@ -168,13 +172,29 @@ def main(argv):
     head = (f"Hardware counters per dispatch (mean over dispatches): {WORKLOAD}.\n"
             f"Kernel sources: csrc hash {sh}.  Device: one MI355X (gfx950).\n\n"
             "Commands (from the repository root, TMPDIR=/tmp), one pass per counter group:\n  "
-            + "\n  ".join(cmds[k] for k in ("sq", "fetch", "write")) + "\n"
+            + "\n  ".join(cmds[k] for k in ("sq", "fetch", "write", "lds")) + "\n"
             f"Summarised with: {again}\n\n"
             f"Calibration: the 1 GiB device copy (--copy-probe-mb 1024, {COPY_KERNEL}) reads\n"
             f"FETCH_SIZE = {cf:.0f} KiB and WRITE_SIZE = {cw:.0f} KiB for {COPY_KIB:,} KiB moved each way,\n"
             f"so HBM bytes = FETCH_SIZE x {ff:.3f} + WRITE_SIZE x {wf:.3f} (KiB).\n\n")
     tail = ("\nHBM_MB = FETCH_SIZE x fetch factor + WRITE_SIZE x write factor (KiB -> MB); GB/s = HBM_MB over the\n"
             "mean duration of the same two passes.  VALU/LDS/SALU are instruction counts per dispatch (SQ pass).\n")
+    # LDS pass: bank conflicts against the cycles the LDS was busy
+    lpath = os.path.join(pmc, "lds_counter_collection.csv")
+    if os.path.exists(lpath):
+        ld = counters(lpath)
+        tail += ("\nLDS counters per dispatch (the fourth pass above):\n"
+                 f"{'kernel':16s} {'LDS_insts':>11s} {'LDS_active':>12s} {'bank_confl':>11s} {'addr_confl':>11s} "
+                 f"{'confl/active':>12s}\n")
+        for k in sorted((k for k in HOT if k in ld and ld[k].get("SQ_INSTS_LDS", 0) > 0),
+                        key=lambda k: -ld[k].get("SQ_LDS_IDX_ACTIVE", 0)):
+            c = ld[k]
+            act = c.get("SQ_LDS_IDX_ACTIVE", 0.0)
+            bc = c.get("SQ_LDS_BANK_CONFLICT", 0.0)
+            tail += (f"{k:16s} {c.get('SQ_INSTS_LDS', 0):11.0f} {act:12.0f} {bc:11.0f} "
+                     f"{c.get('SQ_LDS_ADDR_CONFLICT', 0):11.0f} {(bc / act if act else 0.0):12.3f}\n")
+        tail += ("LDS_active = SQ_LDS_IDX_ACTIVE (cycles the LDS served indexed operations), bank_confl =\n"
+                 "SQ_LDS_BANK_CONFLICT (cycles stalled on bank conflicts), both summed over the device per dispatch.\n")
     with open(os.path.join(dst, f"{tag}_pmc.txt"), "w") as fh:
         fh.write(head + "\n".join(lines) + "\n" + tail)
     with open(os.path.join(dst, "traffic.json"), "w") as fh:
