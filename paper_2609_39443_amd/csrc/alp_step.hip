@@ -1981,7 +1981,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       atomicAdd(&W.w_lo[node], l);
     }
     if (lane == 0) {
-      W.rec_base[item] = rbase;
+      W.rec_base[item] = rbase | (rsz == 24 ? 1ull : 0ull);  // record size in bit 0 (bases are 16-byte aligned)
       W.rec_cnt[item] = rec_ok ? nreal : 0u;
     }
     acc_pairs += nreal;
@@ -2124,46 +2124,66 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // records of a work item are sorted by cell, so each cell owns one contiguous
 // run; its lane sums the run in record order.  Every cell of an active tile
 // is written.
-#ifndef ALP_SPREAD_K
-#define ALP_SPREAD_K 1
-#endif
-constexpr int kSpreadK = ALP_SPREAD_K;          // records per lane and pass
-constexpr int kSpreadChunk = 64 * kSpreadK;     // records held per pass
+constexpr int kSpreadChunk = 64;  // records summed per pass, one per lane
 
 struct SpreadScratch {
   double cc[3][kSpreadChunk];
   uint16_t first[64], last[64];  // run of each cell inside the chunk (last exclusive)
 };
 
-// The raw words of kSpreadK records per lane (records k 64 + lane of a
-// chunk): they are fetched one chunk ahead and decoded only when used, so the
-// fetch stays in flight while the previous chunk is summed.
-struct SpreadRaw {
-  uint4 r[kSpreadK];  // split: meta, node, a0, a1 (FP32); FP64: meta, node, lo and hi of a0
-  uint2 h[kSpreadK];  // FP64: a1
+// The records of a wave's items, taken as one stream of 64-record chunks.  A
+// cursor runs two chunks ahead of the summation, so the records of the next
+// two chunks are in flight while one is summed; it holds the descriptor of
+// the item after its own, read ahead as well.  An item's record base carries
+// the record size in bit 0 (bases are 16-byte aligned): set for the 24-byte
+// FP64 records, whose a1 is read when the chunk is summed.
+struct RecCursor {
+  uint32_t item, p0, rn;     // item, first record of the chunk to fetch, item's record count
+  unsigned long long rb;     // item's record base (with the size bit)
+  uint32_t gitem, grn;       // the item after it
+  unsigned long long grb;
+  bool done;
 };
 
-__device__ __forceinline__ SpreadRaw spread_fetch(const unsigned char *rec, int rsz, uint32_t p0, uint32_t rn,
-                                                  int lane) {
-  SpreadRaw R;
-#pragma unroll
-  for (int k = 0; k < kSpreadK; ++k) {
-    const uint32_t j = p0 + (uint32_t)(k * 64 + lane);
-    R.r[k] = make_uint4(0u, 0u, 0u, 0u);
-    R.h[k] = make_uint2(0u, 0u);
-    if (j < rn) {
-      const unsigned char *r = rec + (size_t)j * rsz;
-      if (rsz == 16) {
-        R.r[k] = *(const uint4 *)r;
-      } else {
-        const uint2 a = *(const uint2 *)r;
-        const uint4 b = *(const uint4 *)(r + 8);
-        R.r[k] = make_uint4(a.x, a.y, b.x, b.y);
-        R.h[k] = make_uint2(b.z, b.w);
-      }
+// skip to the next chunk that has records
+__device__ __forceinline__ void rec_settle(const Work &W, RecCursor &c, uint32_t n_items, uint32_t stride) {
+  while (!c.done && c.p0 >= c.rn) {
+    if (c.gitem >= n_items) {
+      c.done = true;
+      break;
+    }
+    c.item = c.gitem;
+    c.rn = c.grn;
+    c.rb = c.grb;
+    c.p0 = 0;
+    c.gitem += stride;
+    if (c.gitem < n_items) {
+      c.grn = W.rec_cnt[c.gitem];
+      c.grb = W.rec_base[c.gitem];
     }
   }
-  return R;
+}
+
+// this lane's record of the cursor's chunk (meta, node, a0 as FP32 or the
+// two words of the FP64 a0), then the cursor moves on
+__device__ __forceinline__ uint4 rec_take(const Work &W, RecCursor &c, uint32_t n_items, uint32_t stride,
+                                          int lane) {
+  uint4 r = make_uint4(0u, 0u, 0u, 0u);
+  if (!c.done) {
+    const uint32_t j = c.p0 + (uint32_t)lane;
+    if (j < c.rn) {
+      const unsigned char *p = W.rec + (c.rb & ~15ull) + (size_t)j * ((c.rb & 1ull) ? 24 : 16);
+      if (c.rb & 1ull) {
+        const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 8);
+        r = make_uint4(lo.x, lo.y, hi.x, hi.y);
+      } else {
+        r = *(const uint4 *)p;
+      }
+    }
+    c.p0 += kSpreadChunk;
+    rec_settle(W, c, n_items, stride);
+  }
+  return r;
 }
 
 __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
@@ -2181,20 +2201,29 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
   unsigned long long fl = 0;
   sh.first[lane] = 0;
   sh.last[lane] = 0;
-  // the current item, the next one's descriptor, and the records of the
-  // current item's first chunk
+  // the current item and the next one's descriptor
   Item it = W.item[item];
   uint32_t rn = W.rec_cnt[item];
   unsigned long long rb = W.rec_base[item];
   Item nxt = it;
-  uint32_t nrn = 0;
-  unsigned long long nrb = 0;
-  if (item + stride < n_items) {
-    nxt = W.item[item + stride];
-    nrn = W.rec_cnt[item + stride];
-    nrb = W.rec_base[item + stride];
+  if (item + stride < n_items) nxt = W.item[item + stride];
+  // the record stream, two chunks ahead
+  RecCursor cur;
+  cur.item = item;
+  cur.p0 = 0;
+  cur.rn = rn;
+  cur.rb = rb;
+  cur.gitem = item + stride;
+  cur.grn = 0;
+  cur.grb = 0;
+  cur.done = false;
+  if (cur.gitem < n_items) {
+    cur.grn = W.rec_cnt[cur.gitem];
+    cur.grb = W.rec_base[cur.gitem];
   }
-  SpreadRaw R = spread_fetch(W.rec + rb, rec_size(L.cases[it.cs].prec), 0, rn, lane);
+  rec_settle(W, cur, n_items, stride);
+  uint4 R1 = rec_take(W, cur, n_items, stride, lane);
+  uint4 R2 = rec_take(W, cur, n_items, stride, lane);
   __syncthreads();
   for (;;) {
     if (it.cs != acc_case) {
@@ -2218,74 +2247,59 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
     const bool valid = c < it.c1;
     const double v = valid ? to_global(m.vs)[c] : 0.0;
     const uint32_t pc = valid ? to_global(m.perm)[c] : 0u;
-    const int rsz = rec_size(cs.prec);
-    const bool has_next = item + stride < n_items;
-    const int nrsz = has_next ? rec_size(L.cases[nxt.cs].prec) : 16;
+    const bool fp64 = (rb & 1ull) != 0;
+    const unsigned char *rbase = W.rec + (rb & ~15ull);
     double S0 = 0.0, S1 = 0.0, S2 = 0.0;
     bool any = false;
     for (uint32_t p0 = 0; p0 < rn; p0 += kSpreadChunk) {
       const uint32_t nch = min(rn - p0, (uint32_t)kSpreadChunk);
-      const SpreadRaw C = R;
-      // the chunk after this one: the rest of this item, else the next item's first
-      if (p0 + kSpreadChunk < rn) R = spread_fetch(W.rec + rb, rsz, p0 + kSpreadChunk, rn, lane);
-      else if (has_next) R = spread_fetch(W.rec + nrb, nrsz, 0, nrn, lane);
-      uint32_t cl[kSpreadK];
-#pragma unroll
-      for (int k = 0; k < kSpreadK; ++k) {
-        const uint32_t j = (uint32_t)(k * 64 + lane);
-        cl[k] = ~0u;
-        if (j < nch) {
-          const uint32_t meta = C.r[k].x, node = C.r[k].y;
-          double a0, a1;
-          if (rsz == 16) {
-            a0 = (double)__uint_as_float(C.r[k].z);
-            a1 = (double)__uint_as_float(C.r[k].w);
-          } else {
-            a0 = __hiloint2double((int)C.r[k].w, (int)C.r[k].z);
-            a1 = __hiloint2double((int)C.h[k].y, (int)C.h[k].x);
-          }
-          const gptr<double> fp = to_global(W.fhat) + 3 * (int64_t)node;
-          double q0 = a0 * fp[0], q1 = a0 * fp[1], q2 = a0 * fp[2];
-          if (!(meta & kRecSingle)) {
-            q0 += a1 * fp[3];
-            q1 += a1 * fp[4];
-            q2 += a1 * fp[5];
-          }
-          sh.cc[0][j] = -q0;
-          sh.cc[1][j] = -q1;
-          sh.cc[2][j] = -q2;
-          cl[k] = meta & 63u;
+      const uint4 C = R1;
+      R1 = R2;
+      R2 = rec_take(W, cur, n_items, stride, lane);
+      const uint32_t j = (uint32_t)lane;
+      uint32_t cl = ~0u;
+      if (j < nch) {
+        const uint32_t meta = C.x, node = C.y;
+        double a0, a1;
+        if (fp64) {
+          a0 = __hiloint2double((int)C.w, (int)C.z);
+          a1 = *(const double *)(rbase + (size_t)(p0 + j) * 24 + 16);
+        } else {
+          a0 = (double)__uint_as_float(C.z);
+          a1 = (double)__uint_as_float(C.w);
         }
+        const gptr<double> fp = to_global(W.fhat) + 3 * (int64_t)node;
+        double q0 = a0 * fp[0], q1 = a0 * fp[1], q2 = a0 * fp[2];
+        if (!(meta & kRecSingle)) {
+          q0 += a1 * fp[3];
+          q1 += a1 * fp[4];
+          q2 += a1 * fp[5];
+        }
+        sh.cc[0][j] = -q0;
+        sh.cc[1][j] = -q1;
+        sh.cc[2][j] = -q2;
+        cl = meta & 63u;
       }
       // run boundaries of each cell (records are sorted by cell): the
       // neighbouring records' cells come from the neighbouring lanes
-#pragma unroll
-      for (int k = 0; k < kSpreadK; ++k) {
-        const uint32_t j = (uint32_t)(k * 64 + lane);
-        const uint32_t up = (uint32_t)__shfl((int)cl[k], lane - 1, 64);
-        const uint32_t dn = (uint32_t)__shfl((int)cl[k], lane + 1, 64);
-        const uint32_t wrap_up = k > 0 ? (uint32_t)__shfl((int)cl[k > 0 ? k - 1 : 0], 63, 64) : ~0u;
-        const uint32_t wrap_dn = k + 1 < kSpreadK ? (uint32_t)__shfl((int)cl[k + 1 < kSpreadK ? k + 1 : k], 0, 64) : ~0u;
-        if (j < nch) {
-          const uint32_t prev = lane > 0 ? up : wrap_up;
-          const uint32_t next = lane < 63 ? dn : wrap_dn;
-          if (j == 0 || prev != cl[k]) sh.first[cl[k]] = (uint16_t)j;
-          if (j + 1 == nch || next != cl[k]) sh.last[cl[k]] = (uint16_t)(j + 1);
-        }
+      const uint32_t up = (uint32_t)__shfl((int)cl, lane - 1, 64);
+      const uint32_t dn = (uint32_t)__shfl((int)cl, lane + 1, 64);
+      if (j < nch) {
+        if (j == 0 || up != cl) sh.first[cl] = (uint16_t)j;
+        if (j + 1 == nch || dn != cl) sh.last[cl] = (uint16_t)(j + 1);
       }
       __syncthreads();
       const uint32_t lo = sh.first[lane], hi = sh.last[lane];
       sh.first[lane] = 0;
       sh.last[lane] = 0;
       any = any || hi > lo;
-      for (uint32_t j = lo; j < hi; ++j) {
-        S0 += sh.cc[0][j];
-        S1 += sh.cc[1][j];
-        S2 += sh.cc[2][j];
+      for (uint32_t q = lo; q < hi; ++q) {
+        S0 += sh.cc[0][q];
+        S1 += sh.cc[1][q];
+        S2 += sh.cc[2][q];
       }
       __syncthreads();
     }
-    if (rn == 0 && has_next) R = spread_fetch(W.rec + nrb, nrsz, 0, nrn, lane);
     if (valid && cs.write_S) {
       double *S = cs.S + 3 * (int64_t)pc;
       S[0] = S0;
@@ -2305,16 +2319,12 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
         fl += l;
       }
     }
-    if (!has_next) break;
     item += stride;
+    if (item >= n_items) break;
     it = nxt;
-    rn = nrn;
-    rb = nrb;
-    if (item + stride < n_items) {
-      nxt = W.item[item + stride];
-      nrn = W.rec_cnt[item + stride];
-      nrb = W.rec_base[item + stride];
-    }
+    rn = W.rec_cnt[item];
+    rb = W.rec_base[item];
+    if (item + stride < n_items) nxt = W.item[item + stride];
   }
   if (acc_case >= 0) {
     if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
