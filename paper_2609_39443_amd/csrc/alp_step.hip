@@ -492,9 +492,10 @@ void launch_emit_scatter(const StepLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL(k_emit_scatter, dim3(L.grid_persistent), dim3(256), 0, st, L);
 }
 
-// Tile merge, one wave per tile: sort the tile's windows by (beam, first
-// segment), join the windows of one beam into one entry (beam order), and
+// Tile merge, one wave per tile: join the windows of one beam into one entry
+// (entries in beam order; a beam's entry spans its windows' segments) and
 // count the work items of the tile (64 cells each; none without entries).
+// Up to 64 windows are merged in registers, more by a sort in LDS.
 struct MergeScratch {
   unsigned long long key[kMaxEmitTile];  // (beam << 32) | first segment
   int32_t hi[kMaxEmitTile];
