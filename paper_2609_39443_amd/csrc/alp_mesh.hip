@@ -84,12 +84,47 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const uint32_t *in, u
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tot[nblk];
 }
 
+// Second pass for up to kScanDirect blocks: each block adds the totals of
+// the blocks before it itself, so the scan of the totals needs no launch of
+// its own.
+constexpr int64_t kScanDirect = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_final_direct(const uint32_t *in, uint32_t *out, int64_t n,
+                                                                  const uint32_t *tot, int64_t nblk) {
+  uint32_t before = 0, all = 0;
+  for (int64_t b = threadIdx.x; b < nblk; b += kScanBlock) {
+    const uint32_t t = tot[b];
+    all += t;
+    if (b < (int64_t)blockIdx.x) before += t;
+  }
+  // block sums of `before` and `all` (integer, so the order does not matter)
+  uint32_t sb, sa;
+  block_excl_scan(before, &sb);
+  block_excl_scan(all, &sa);
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer], s = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t ex = block_excl_scan(s, nullptr) + sb;
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sa;
+}
+
 int64_t scan_tmp_words(int64_t n) { return (n + kScanTile - 1) / kScanTile + 2; }
 
 void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t st) {
   int64_t nblk = (n + kScanTile - 1) / kScanTile;
   if (nblk == 0) nblk = 1;
   hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, in, n, tmp);
+  if (nblk <= kScanDirect) {
+    hipLaunchKernelGGL(k_scan_final_direct, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, in, out, n, tmp, nblk);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(kScanBlock), 0, st, tmp, nblk);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, in, out, n, tmp,
                      nblk);
