@@ -464,6 +464,8 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   }
   mark(2);
   if (stages & ST_DRAG) launch_drag(L, sd);
+  // the beam-side sums need only f: with the drag, they stay on its stream
+  if ((stages & ST_DRAG) && (stages & ST_PROJECT)) launch_beam_sums(L, sd);
   mark(3);
   if (fork) (void)hipEventRecord(ctx->ev_join, sd);
   if (!(stages & ST_PROJECT)) return;
@@ -483,7 +485,7 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   mark(5);
   if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
   launch_norm(L, st);
-  launch_beam_sums(L, st);
+  if (!(stages & ST_DRAG)) launch_beam_sums(L, st);
   mark(6);
   launch_spread(L, st);
   mark(7);
