@@ -492,24 +492,24 @@ void launch_emit_scatter(const StepLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL(k_emit_scatter, dim3(L.grid_persistent), dim3(256), 0, st, L);
 }
 
-// Tile merge, one wave per tile: join the windows of one beam into one entry
-// (entries in beam order; a beam's entry spans its windows' segments) and
-// count the work items of the tile (64 cells each; none without entries).
-// Up to 64 windows are merged in registers, more by a sort in LDS.
+// Tile merge: join the windows of one beam into one entry (entries in beam
+// order; a beam's entry spans its windows' segments) and count the work items
+// of the tile (64 cells each; none without entries).  Up to 16 windows are
+// merged by a group of 16 lanes (four tiles per wave), up to 64 by the whole
+// wave in registers, more by a sort in LDS.
 struct MergeScratch {
   unsigned long long key[kMaxEmitTile];  // (beam << 32) | first segment
   int32_t hi[kMaxEmitTile];
   int32_t k0[kMaxEmitTile];
 };
 
-// Four waves per block, one tile each: the waves share nothing, so each
-// synchronises only itself (LDS operations of one wave complete in order; the
-// wave barrier keeps the compiler from moving them across phases).
-constexpr int kMergeWaves = 4;
-
 // Tiles with more than 64 windows: sort the (beam, first segment) keys in
 // LDS (bitonic), then join each beam's run.  Returns the number of entries.
 __device__ uint32_t tile_merge_lds(const Work &W, MergeScratch &sh, int lane, uint32_t eoff, uint32_t n_emit) {
+  // the scratch may still be read for the wave's previous tile
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   uint32_t np2 = 1;
   while (np2 < n_emit) np2 <<= 1;
   for (uint32_t i = lane; i < np2; i += 64) {
@@ -580,84 +580,144 @@ __device__ uint32_t tile_merge_lds(const Work &W, MergeScratch &sh, int lane, ui
   return ne;
 }
 
-__global__ __launch_bounds__(64 * kMergeWaves) void k_tile_merge(StepLaunch L) {
+// Tiles with at most 64 windows, one window per lane: the head of a beam is
+// its window with the smallest first segment, the entry's last segment the
+// largest over the beam's windows, and its place the number of smaller beams
+// in the tile.  Returns the number of entries.
+__device__ uint32_t tile_merge_regs(const Work &W, int lane, uint32_t eoff, uint32_t n_emit) {
+  uint32_t beam = ~0u, lo = 0;
+  int32_t hi = 0, k0 = 0;
+  if ((uint32_t)lane < n_emit) {
+    const Win e = W.emit[eoff + lane];
+    beam = (uint32_t)e.beam;
+    lo = (uint32_t)e.lo;
+    hi = e.hi;
+    k0 = e.k0;
+  }
+  bool head = (uint32_t)lane < n_emit;
+  int32_t mhi = hi;
+  for (uint32_t j = 0; j < n_emit; ++j) {
+    const uint32_t bj = (uint32_t)__builtin_amdgcn_readlane((int)beam, (int)j);
+    const uint32_t lj = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)j);
+    const int32_t hj = __builtin_amdgcn_readlane(hi, (int)j);
+    if (bj == beam) {
+      mhi = max(mhi, hj);
+      if (lj < lo || (lj == lo && j < (uint32_t)lane)) head = false;
+    }
+  }
+  const uint64_t hb = ballot64(head);
+  uint32_t idx = 0;
+  for (uint64_t mm = hb; mm; mm &= mm - 1) {
+    const int j = __builtin_ctzll(mm);
+    idx += (uint32_t)__builtin_amdgcn_readlane((int)beam, j) < beam ? 1u : 0u;
+  }
+  if (head && idx < (uint32_t)kMaxEntries) {
+    Entry en;
+    en.k0 = k0;
+    en.i0 = (int32_t)lo;
+    en.i1 = mhi < 0 ? 0 : mhi;
+    en.single = mhi < 0 ? 1 : 0;
+    W.entry[eoff + idx] = en;
+  }
+  return (uint32_t)__popcll(hb);
+}
+
+// The tile's item count and entry count, written once its merge is done.
+__device__ __forceinline__ void tile_done(Work &W, int64_t t, uint32_t ne, uint32_t ncell) {
+  uint32_t ni = 0;
+  if (ne > (uint32_t)kMaxEntries) set_overflow(W, 4u);
+  else ni = (ncell + 63u) / 64u;
+  W.tile_nent[t] = ni ? ne : 0u;
+  W.tile_items[t] = ni;
+}
+
+// One wave takes kMergeTiles consecutive tiles, a group of kMergeGroup lanes
+// each.  A tile with at most kMergeGroup windows is merged by its group (one
+// window per lane, the same rule as tile_merge_regs, within the group); fuller
+// tiles are merged afterwards by the whole wave, one at a time.
+constexpr int kMergeGroup = 16;
+constexpr int kMergeTiles = 64 / kMergeGroup;
+
+__global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
   Work W = L.w;
-  __shared__ MergeScratch shw[kMergeWaves];
-  MergeScratch &sh = shw[threadIdx.x >> 6];
-  const int lane = threadIdx.x & 63;
-  const int64_t tg = (int64_t)blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
-  if (tg >= W.n_tiles) return;
-  const uint32_t eoff = W.tile_off[tg];
-  const uint32_t n_emit = W.tile_off[tg + 1] - eoff;
-  if (n_emit == 0 || n_emit > (uint32_t)kMaxEmitTile) {
-    if (lane == 0) {
+  __shared__ MergeScratch sh;
+  const int lane = threadIdx.x;
+  const int gl = lane & (kMergeGroup - 1), gbase = lane & ~(kMergeGroup - 1);
+  const int64_t tg = (int64_t)blockIdx.x * kMergeTiles + lane / kMergeGroup;
+  const bool have = tg < W.n_tiles;
+  uint32_t eoff = 0, n_emit = 0, ncell = 0;
+  if (have) {
+    eoff = W.tile_off[tg];
+    n_emit = W.tile_off[tg + 1] - eoff;
+    const int c = case_of(L.tbase, L.n_cases, tg);
+    const CaseDev &cs = L.cases[c];
+    const int64_t tl = tg - cs.tile_base;
+    ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
+  }
+  const bool small = have && n_emit > 0 && n_emit <= (uint32_t)kMergeGroup;
+  const bool mine = small && (uint32_t)gl < n_emit;
+  uint32_t beam = ~0u, lo = 0;
+  int32_t hi = 0, k0 = 0;
+  if (mine) {
+    const Win e = W.emit[eoff + gl];
+    beam = (uint32_t)e.beam;
+    lo = (uint32_t)e.lo;
+    hi = e.hi;
+    k0 = e.k0;
+  }
+  bool head = mine;
+  int32_t mhi = hi;
+#pragma unroll
+  for (int j = 0; j < kMergeGroup; ++j) {
+    const int src = gbase | j;
+    const uint32_t bj = (uint32_t)__shfl((int)beam, src, 64);
+    const uint32_t lj = (uint32_t)__shfl((int)lo, src, 64);
+    const int32_t hj = __shfl(hi, src, 64);
+    if ((uint32_t)j < n_emit && bj == beam) {
+      mhi = max(mhi, hj);
+      if (lj < lo || (lj == lo && j < gl)) head = false;
+    }
+  }
+  const uint32_t gheads = (uint32_t)(ballot64(head) >> gbase) & 0xffffu;
+  uint32_t idx = 0;
+#pragma unroll
+  for (int j = 0; j < kMergeGroup; ++j) {
+    const uint32_t bj = (uint32_t)__shfl((int)beam, gbase | j, 64);
+    idx += (((gheads >> j) & 1u) != 0u && bj < beam) ? 1u : 0u;
+  }
+  if (head) {
+    Entry en;
+    en.k0 = k0;
+    en.i0 = (int32_t)lo;
+    en.i1 = mhi < 0 ? 0 : mhi;
+    en.single = mhi < 0 ? 1 : 0;
+    W.entry[eoff + idx] = en;
+  }
+  if (gl == 0 && have) {
+    if (small) {
+      tile_done(W, tg, (uint32_t)__popc(gheads), ncell);
+    } else if (n_emit == 0 || n_emit > (uint32_t)kMaxEmitTile) {
       if (n_emit) set_overflow(W, 4u);
       W.tile_nent[tg] = 0;
       W.tile_items[tg] = 0;
     }
-    return;
   }
-  // cells of the tile (read before the windows, so that both loads overlap)
-  const int c = case_of(L.tbase, L.n_cases, tg);
-  const CaseDev &cs = L.cases[c];
-  const int64_t tl = tg - cs.tile_base;
-  const uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
-  uint32_t ne = 0;
-  if (n_emit <= 64u) {
-    // one window per lane: the head of a beam is its window with the
-    // smallest first segment, the entry's last segment the largest over the
-    // beam's windows, and its place the number of smaller beams in the tile
-    uint32_t beam = ~0u, lo = 0;
-    int32_t hi = 0, k0 = 0;
-    if ((uint32_t)lane < n_emit) {
-      const Win e = W.emit[eoff + lane];
-      beam = (uint32_t)e.beam;
-      lo = (uint32_t)e.lo;
-      hi = e.hi;
-      k0 = e.k0;
-    }
-    bool head = (uint32_t)lane < n_emit;
-    int32_t mhi = hi;
-    for (uint32_t j = 0; j < n_emit; ++j) {
-      const uint32_t bj = (uint32_t)__builtin_amdgcn_readlane((int)beam, (int)j);
-      const uint32_t lj = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)j);
-      const int32_t hj = __builtin_amdgcn_readlane(hi, (int)j);
-      if (bj == beam) {
-        mhi = max(mhi, hj);
-        if (lj < lo || (lj == lo && j < (uint32_t)lane)) head = false;
-      }
-    }
-    const uint64_t hb = ballot64(head);
-    uint32_t idx = 0;
-    for (uint64_t mm = hb; mm; mm &= mm - 1) {
-      const int j = __builtin_ctzll(mm);
-      idx += (uint32_t)__builtin_amdgcn_readlane((int)beam, j) < beam ? 1u : 0u;
-    }
-    ne = (uint32_t)__popcll(hb);
-    if (head && idx < (uint32_t)kMaxEntries) {
-      Entry en;
-      en.k0 = k0;
-      en.i0 = (int32_t)lo;
-      en.i1 = mhi < 0 ? 0 : mhi;
-      en.single = mhi < 0 ? 1 : 0;
-      W.entry[eoff + idx] = en;
-    }
-  } else {
-    ne = tile_merge_lds(W, sh, lane, eoff, n_emit);
-  }
-  if (lane == 0) {
-    uint32_t ni = 0;
-    if (ne > (uint32_t)kMaxEntries) set_overflow(W, 4u);
-    else ni = (ncell + 63u) / 64u;
-    W.tile_nent[tg] = ni ? ne : 0u;
-    W.tile_items[tg] = ni;
+  for (uint64_t big = ballot64(gl == 0 && have && n_emit > (uint32_t)kMergeGroup && n_emit <= (uint32_t)kMaxEmitTile);
+       big; big &= big - 1) {
+    const int l = __builtin_ctzll(big);
+    const int64_t t = (int64_t)blockIdx.x * kMergeTiles + l / kMergeGroup;
+    const uint32_t te = (uint32_t)__builtin_amdgcn_readlane((int)eoff, l);
+    const uint32_t tn = (uint32_t)__builtin_amdgcn_readlane((int)n_emit, l);
+    const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)ncell, l);
+    const uint32_t ne = tn <= 64u ? tile_merge_regs(W, lane, te, tn) : tile_merge_lds(W, sh, lane, te, tn);
+    if (lane == 0) tile_done(W, t, ne, tc);
   }
 }
 
 void launch_tile_merge(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_tiles == 0) return;
-  hipLaunchKernelGGL(k_tile_merge, dim3((unsigned)((L.w.n_tiles + kMergeWaves - 1) / kMergeWaves)),
-                     dim3(64 * kMergeWaves), 0, st, L);
+  hipLaunchKernelGGL(k_tile_merge, dim3((unsigned)((L.w.n_tiles + kMergeTiles - 1) / kMergeTiles)), dim3(64), 0,
+                     st, L);
 }
 
 __global__ void k_items(StepLaunch L) {
