@@ -214,6 +214,27 @@ def test_batch_equals_single_cases(gu, ctx):
         gu.compare(case.results(), ref, ctx.diag(i), ref["diag"], 1e-12, 1e-12)
 
 
+def test_mixed_precision_batch_equals_single_cases(gu, ctx):
+    """FP64 and FP32-split cases alternating in one batch (their 24- and
+    16-byte pair records interleave in the spread's record stream) give
+    bitwise the results of the same cases run alone, and match the oracle."""
+    precs = [alp.PREC_FP64, alp.PREC_FP32_SPLIT, alp.PREC_FP64, alp.PREC_FP32_SPLIT]
+    wls = [random_scene(40 + i, nx=18 + 2 * i, ny=16, nz=14, n_beams=3 + i) for i in range(4)]
+    cases = [gu.GpuCase(ctx, wl, pr) for wl, pr in zip(wls, precs)]
+    gu.step_batched(ctx, cases)
+    batched = [c.results() for c in cases]
+    diags = [ctx.diag(i) for i in range(len(cases))]
+    for i, (wl, pr) in enumerate(zip(wls, precs)):
+        ref = gu.oracle_step(wl)
+        tS, tw = TOL[pr]
+        gu.compare(batched[i], ref, diags[i], ref["diag"], tS, tw)
+        alone = gu.GpuCase(ctx, wl, pr)
+        gu.step_batched(ctx, [alone])
+        res = alone.results()
+        for k in ("S", "w", "f", "fhat"):
+            assert np.array_equal(res[k], batched[i][k]), (i, k)
+
+
 def test_graph_replay_bitwise_and_updates(gu, ctx):
     wl = random_scene(31)
     case = gu.GpuCase(ctx, wl, alp.PREC_FP64)
