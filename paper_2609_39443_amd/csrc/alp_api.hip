@@ -400,7 +400,7 @@ alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const 
 }
 
 #ifndef ALP_SAMPLE_BESIDE
-#define ALP_SAMPLE_BESIDE 8
+#define ALP_SAMPLE_BESIDE 4
 #endif
 // sampler waves per CU while it runs beside the segment binning
 constexpr int kSampleWavesBeside = ALP_SAMPLE_BESIDE;

@@ -813,38 +813,43 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
   Nearest nr;
   // The first pass covers the whole 3x3x3 block of bins (with bins about one
   // cell wide it nearly always settles the search): each lane takes
-  // kFirstBins bins and issues the loads of all of them together (bin
-  // ranges, then the first cell of each).  Later passes add one Chebyshev
-  // shell each.
+  // kFirstBins bins, in batches of kFirstBatch whose loads are issued
+  // together (bin ranges, then the first cell of each).  Later passes add one
+  // Chebyshev shell each.
   constexpr int kFirstBins = (27 + kSampleLanes - 1) / kSampleLanes;
+  constexpr int kFirstBatch = 4;
   for (int r = 1;; ++r) {
     if (r == 1) {
-      uint32_t kb[kFirstBins], st[kFirstBins], en[kFirstBins];
-      bool ok[kFirstBins];
+      for (int h0 = 0; h0 < kFirstBins; h0 += kFirstBatch) {
+        uint32_t kb[kFirstBatch], st[kFirstBatch], en[kFirstBatch];
+        bool ok[kFirstBatch];
 #pragma unroll
-      for (int h = 0; h < kFirstBins; ++h) {
-        const int c = sub + h * kSampleLanes;
-        const int ix = qi[0] - 1 + c % 3, iy = qi[1] - 1 + (c / 3) % 3, iz = qi[2] - 1 + c / 9;
-        ok[h] = c < 27 && ix >= 0 && iy >= 0 && iz >= 0 && ix < m.nb[0] && iy < m.nb[1] && iz < m.nb[2];
-        kb[h] = ok[h] ? bin_key(m, ix, iy, iz) : 0u;
+        for (int hh = 0; hh < kFirstBatch; ++hh) {
+          const int h = h0 + hh;
+          const int c = sub + h * kSampleLanes;
+          const int ix = qi[0] - 1 + c % 3, iy = qi[1] - 1 + (c / 3) % 3, iz = qi[2] - 1 + c / 9;
+          ok[hh] = h < kFirstBins && c < 27 && ix >= 0 && iy >= 0 && iz >= 0 && ix < m.nb[0] && iy < m.nb[1] &&
+                   iz < m.nb[2];
+          kb[hh] = ok[hh] ? bin_key(m, ix, iy, iz) : 0u;
+        }
+#pragma unroll
+        for (int hh = 0; hh < kFirstBatch; ++hh) {
+          st[hh] = to_global(m.bin_start)[kb[hh]];
+          en[hh] = to_global(m.bin_start)[kb[hh] + 1];
+        }
+        double4 f[kFirstBatch];
+#pragma unroll
+        for (int hh = 0; hh < kFirstBatch; ++hh) {
+          if (!ok[hh]) en[hh] = st[hh];
+          f[hh] = loc_record(m, st[hh] < en[hh] ? st[hh] : 0);
+        }
+#pragma unroll
+        for (int hh = 0; hh < kFirstBatch; ++hh)
+          if (st[hh] < en[hh]) nr.consider(m, x, y, z, st[hh], f[hh]);
+#pragma unroll
+        for (int hh = 0; hh < kFirstBatch; ++hh)
+          for (uint32_t j = st[hh] + 1; j < en[hh]; ++j) nr.consider(m, x, y, z, j, loc_record(m, j));
       }
-#pragma unroll
-      for (int h = 0; h < kFirstBins; ++h) {
-        st[h] = to_global(m.bin_start)[kb[h]];
-        en[h] = to_global(m.bin_start)[kb[h] + 1];
-      }
-      double4 f[kFirstBins];
-#pragma unroll
-      for (int h = 0; h < kFirstBins; ++h) {
-        if (!ok[h]) en[h] = st[h];
-        f[h] = loc_record(m, st[h] < en[h] ? st[h] : 0);
-      }
-#pragma unroll
-      for (int h = 0; h < kFirstBins; ++h)
-        if (st[h] < en[h]) nr.consider(m, x, y, z, st[h], f[h]);
-#pragma unroll
-      for (int h = 0; h < kFirstBins; ++h)
-        for (uint32_t j = st[h] + 1; j < en[h]; ++j) nr.consider(m, x, y, z, j, loc_record(m, j));
     } else {
       const int side = 2 * r + 1;
       const int ncube = side * side * side;
