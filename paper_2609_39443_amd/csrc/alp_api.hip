@@ -399,11 +399,15 @@ alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const 
   return ALP_OK;
 }
 
-#ifndef ALP_SAMPLE_BESIDE
-#define ALP_SAMPLE_BESIDE 4
-#endif
-// sampler waves per CU while it runs beside the segment binning
-constexpr int kSampleWavesBeside = ALP_SAMPLE_BESIDE;
+// Sampler waves per CU while it runs beside the segment binning: four, which
+// leaves the binning's small kernels the most room, unless the sampler would
+// then need more than 16 passes over the CUs (a wave takes 64 / kSampleLanes
+// points per pass), in which case eight, so that it still ends near the
+// binning.
+int sample_waves_beside(int64_t n_points, int n_cu) {
+  const int64_t pass4 = (int64_t)n_cu * 4 * (64 / kSampleLanes);  // points per pass at four waves per CU
+  return n_points <= 16 * pass4 ? 4 : 8;
+}
 
 StepLaunch make_launch(alp_context *ctx, int n_cases) {
   StepLaunch L;
@@ -458,7 +462,7 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
     // beside the segment binning the sampler keeps to a few waves per CU,
     // which leaves the binning's small kernels room on every CU
     StepLaunch Ls = L;
-    Ls.sample_waves = fork ? kSampleWavesBeside : 0;
+    Ls.sample_waves = fork ? sample_waves_beside(L.w.n_points, ctx->n_cu) : 0;
     launch_sample(Ls, sd);
     launch_sample_kernel(L, sd);
   }
