@@ -11,10 +11,7 @@ namespace alp {
 constexpr int kWave = 64;
 constexpr int kChunkSegs = 16;      // segments per chunk in the segment binning
 constexpr int kMaxEmitTile = 256;   // (chunk, tile) windows of one tile a wave can merge
-#ifndef ALP_QUEUE_STRIPES
-#define ALP_QUEUE_STRIPES 16
-#endif
-constexpr int kQueueStripes = ALP_QUEUE_STRIPES;  // counters per work queue
+constexpr int kQueueStripes = 16;  // counters per work queue
 constexpr int kLineWords = 32;                    // uint32 words per 128-byte line
 // step counters: a line of flags, then four work queues whose counters each
 // sit on a line of their own (atomics on one line serialise)
@@ -25,10 +22,7 @@ constexpr int kMaskWords = kMaxEntries / 32;
 constexpr int kStagePts = 160;      // window points (and node accumulators) staged in LDS
 constexpr int kHiShift = 46;        // fixed-point: hi word holds v * 2^(46-E)
 constexpr int kLoBits = 40;         // lo word holds the next 40 bits
-#ifndef ALP_SAMPLE_LANES
-#define ALP_SAMPLE_LANES 4
-#endif
-constexpr int kSampleLanes = ALP_SAMPLE_LANES;  // lanes per actuator point in the sampler
+constexpr int kSampleLanes = 4;  // lanes per actuator point in the sampler
 constexpr unsigned long long kRecBlock = 64ull << 10;  // pair-record bytes a wave reserves at once
 
 // Binned mesh, device view (built by alp_bin_cells).

@@ -1005,8 +1005,8 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
   }
 }
 
-// One wave per four points, or (sample_waves > 0) at most that many waves per
-// CU walking the points with a stride.
+// One wave per 64 / kSampleLanes points, or (sample_waves > 0) at most that
+// many waves per CU walking the points with a stride.
 void launch_sample(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_points == 0) return;
   int64_t blocks = (L.w.n_points * kSampleLanes + 63) / 64;
