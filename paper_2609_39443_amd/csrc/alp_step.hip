@@ -1307,21 +1307,31 @@ static_assert(kStagePts <= 256, "segment index must fit the key");
 
 struct WeightsScratch {
   float4 sa[kStagePts];  // window point relative to the tile centre; w: 1/|e|^2 of the segment it starts
-  long long ahi[kStagePts];
-  unsigned long long alo[kStagePts];
   int32_t wx[kStagePts];  // fixed-point exponent of the node
   int32_t e_k0[kMaxEntries], e_i0[kMaxEntries], e_i1[kMaxEntries];  // e_i1 < 0: single point
   int32_t e_pt0[kMaxEntries + 1];
   uint32_t e_em[kMaxEntries];  // bits of the window's largest eps (FP32, rounded up)
   float e_dabs[kMaxEntries];   // absolute error allowance of the FP32 ranking
-  // the item's candidates: listed in order as (cell lane | entry << 6) when
-  // they fit, else as per-lane hit masks searched by candidate()
   union {
-    uint32_t mask[64 * kMaskWords];
-    uint16_t cand[64 * kMaskWords * 2];
+    // screening frames of up to 64 entries (three float4 each), read by all
+    // lanes at one address; live only during the screening
+    float4 frm[3 * 64];
+    struct {
+      // node accumulators of the staged points
+      long long ahi[kStagePts];
+      unsigned long long alo[kStagePts];
+      // the item's candidates: listed in order as (cell lane | entry << 6)
+      // when they fit, else as per-lane hit masks searched by candidate()
+      union {
+        uint32_t mask[64 * kMaskWords];
+        uint16_t cand[64 * kMaskWords * 2];
+      };
+    };
   };
   uint32_t off[65];
 };
+static_assert(sizeof(float4) * 3 * 64 <= 2 * 8 * kStagePts + 4 * 64 * kMaskWords,
+              "screening frames overlay the accumulators and the candidate list");
 
 // exact FP64 scan of window segments j0..j1 (local indices; points read from
 // the beam array at X), strict '<' so the lowest index wins a tie
@@ -1442,10 +1452,6 @@ __device__ __forceinline__ void write_record(unsigned char *r, int rsz, uint32_t
   }
 }
 
-__device__ __forceinline__ float rdlane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
 // One kernel per projection rule (kInt: segment-integrated), so that each
 // keeps its own register allocation; each takes only the items of its own
 // cases, from its own work-queue counters.
@@ -1531,8 +1537,6 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       const int64_t k = sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
       const gptr<double> P = Psp + 3 * k;
       sh.sa[q] = make_float4((float)(P[0] - ctx), (float)(P[1] - cty), (float)(P[2] - ctz), 0.f);
-      sh.ahi[q] = 0;
-      sh.alo[q] = 0;
       sh.wx[q] = W.wexp[pbase + k];
       // eps rounded up to FP32 (positive floats order like their bits)
       const double ep = Eps[k];
@@ -1637,34 +1641,47 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     __syncthreads();
     // 2. screening
     const float lx = (float)(cx - ctx), ly = (float)(cy - cty), lz = (float)(cz - ctz);
-    uint32_t word = 0, cnt = 0;
+    uint32_t cnt = 0;
     uint32_t mw[kMaskWords];
 #pragma unroll
     for (int w = 0; w < kMaskWords; ++w) mw[w] = 0u;
-    for (uint32_t e = 0; e < ne; ++e) {
-      const int l = (int)(e & 63);
-      float f[10];
-      if (e < 64) {
+    // the frames go to LDS 64 entries at a time and every lane reads entry e
+    // at the same address (a broadcast), one pass per mask word
 #pragma unroll
-        for (int q = 0; q < 10; ++q) f[q] = rdlane(fr[0][q], l);
-      } else {
+    for (int bb = 0; bb < 2; ++bb) {
+      if (64u * bb >= ne) break;  // wave-uniform
+      if (bb > 0) __syncthreads();
+      sh.frm[3 * lane] = make_float4(fr[bb][0], fr[bb][1], fr[bb][2], fr[bb][3]);
+      sh.frm[3 * lane + 1] = make_float4(fr[bb][4], fr[bb][5], fr[bb][6], fr[bb][7]);
+      sh.frm[3 * lane + 2] = make_float4(fr[bb][8], fr[bb][9], 0.f, 0.f);
+      __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 10; ++q) f[q] = rdlane(fr[1][q], l);
-      }
-      const float dx = lx - f[0], dy = ly - f[1], dz = lz - f[2];
-      const float a = dx * f[3] + dy * f[4] + dz * f[5];
-      const float rho = __builtin_amdgcn_sqrtf(fmaxf(dx * dx + dy * dy + dz * dz - a * a, 0.f));
-      const float re = fmaxf(rho - f[8], 0.f);
-      const float g = fmaxf(fmaxf(f[6] - a, a - f[7]), 0.f);
-      const bool hit = valid && re * re + g * g <= f[9];
-      if (hit) word |= 1u << (e & 31);
-      if ((e & 31) == 31 || e == ne - 1) {
-#pragma unroll
-        for (int w = 0; w < kMaskWords; ++w)
-          if (w == (int)(e >> 5)) mw[w] = word;
+      for (int ww = 0; ww < 2; ++ww) {
+        const int w = 2 * bb + ww;
+        const uint32_t e0 = 32u * (uint32_t)w;
+        if (e0 >= ne) break;  // wave-uniform
+        const uint32_t e1 = min(ne, e0 + 32u);
+        uint32_t word = 0;
+        for (uint32_t e = e0; e < e1; ++e) {
+          const int l = (int)(e & 63);
+          const float4 F0 = sh.frm[3 * l], F1 = sh.frm[3 * l + 1], F2 = sh.frm[3 * l + 2];
+          const float dx = lx - F0.x, dy = ly - F0.y, dz = lz - F0.z;
+          const float a = dx * F0.w + dy * F1.x + dz * F1.y;
+          const float rho = __builtin_amdgcn_sqrtf(fmaxf(dx * dx + dy * dy + dz * dz - a * a, 0.f));
+          const float re = fmaxf(rho - F2.x, 0.f);
+          const float g = fmaxf(fmaxf(F1.z - a, a - F1.w), 0.f);
+          if (re * re + g * g <= F2.y) word |= 1u << (e - e0);
+        }
+        if (!valid) word = 0u;
+        mw[w] = word;
         cnt += __popc(word);
-        word = 0;
       }
+    }
+    // the frames' space now holds the node accumulators and the candidates
+    __syncthreads();
+    for (int q = lane; q < npts; q += 64) {
+      sh.ahi[q] = 0;
+      sh.alo[q] = 0;
     }
     uint32_t total;
     const uint32_t myoff = wave_excl_scan_u32(cnt, total);
