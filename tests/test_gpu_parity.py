@@ -502,7 +502,8 @@ def crowded_column(n_b, seed=3):
 @pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
 def test_crowded_tiles_both_merge_paths(gu, ctx, n_b, prec):
     """A tile reached by at most 64 windows is merged in registers, a fuller
-    one by a sort in LDS (100 beams in one tile column): both match the
+    one by a sort in LDS (100 beams in one tile column), and the weights pass
+    screens its windows 65-100 in a second batch of frames: both match the
     oracle."""
     run_and_compare(gu, ctx, crowded_column(n_b), prec, tile_bins=4, bin_size=0.01)
 
