@@ -1307,7 +1307,9 @@ static_assert(kStagePts <= 256, "segment index must fit the key");
 
 struct WeightsScratch {
   float4 sa[kStagePts];  // window point relative to the tile centre; w: 1/|e|^2 of the segment it starts
-  int32_t wx[kStagePts];  // fixed-point exponent of the node
+  // the node's fixed-point exponent times 256 plus the index of the entry
+  // the point belongs to (staged_exp, staged_entry)
+  int32_t wx[kStagePts];
   int32_t e_k0[kMaxEntries], e_i0[kMaxEntries], e_i1[kMaxEntries];  // e_i1 < 0: single point
   int32_t e_pt0[kMaxEntries + 1];
   uint32_t e_em[kMaxEntries];  // bits of the window's largest eps (FP32, rounded up)
@@ -1353,6 +1355,10 @@ __device__ __forceinline__ void exact_scan(Ptr X, int j0, int j1, double cx, dou
     az = bz;
   }
 }
+
+static_assert(kMaxEntries <= 256, "the entry index of a staged point takes the low 8 bits");
+__device__ __forceinline__ int32_t staged_exp(int32_t wx) { return wx >> 8; }  // floor(wx / 256)
+__device__ __forceinline__ int staged_entry(int32_t wx) { return wx & 255; }
 
 __device__ __forceinline__ int entry_of_point(const WeightsScratch &sh, int n_staged, int q) {
   int lo = 0, hi = n_staged - 1;
@@ -1537,7 +1543,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       const int64_t k = sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
       const gptr<double> P = Psp + 3 * k;
       sh.sa[q] = make_float4((float)(P[0] - ctx), (float)(P[1] - cty), (float)(P[2] - ctz), 0.f);
-      sh.wx[q] = W.wexp[pbase + k];
+      sh.wx[q] = W.wexp[pbase + k] * 256 + e;
       // eps rounded up to FP32 (positive floats order like their bits)
       const double ep = Eps[k];
       float ef = (float)ep;
@@ -1546,7 +1552,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     }
     __syncthreads();
     for (int q = lane; q < npts; q += 64) {
-      const int e = entry_of_point(sh, n_staged, q);
+      const int e = staged_entry(sh.wx[q]);
       const int np = sh.e_i1[e] < 0 ? 1 : sh.e_i1[e] - sh.e_i0[e] + 2;
       if (q - sh.e_pt0[e] < np - 1) {
         const float4 A = sh.sa[q], B = sh.sa[q + 1];
@@ -1742,7 +1748,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       for (uint32_t e = lane; e < ne; e += 64) si.emin[e] = 0x7f7fffffu;  // FLT_MAX
       __syncthreads();
       for (int q = lane; q < npts; q += 64) {
-        const int e = entry_of_point(sh, n_staged, q);
+        const int e = staged_entry(sh.wx[q]);
         const int64_t k = sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
         const double ep = Eps[k];
         float ef = (float)ep;
@@ -1789,7 +1795,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
             long long h;
             unsigned long long l;
             if (pt0 >= 0) {
-              fx_encode(av, sh.wx[pt0 + q], h, l);
+              fx_encode(av, staged_exp(sh.wx[pt0 + q]), h, l);
               atomicAdd((unsigned long long *)&sh.ahi[pt0 + q], (unsigned long long)h);
               atomicAdd(&sh.alo[pt0 + q], l);
             } else {
@@ -2006,11 +2012,11 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
             long long h0, h1 = 0;
             unsigned long long l0, l1 = 0;
             if (pt0 >= 0) {
-              fx_encode(a0 * pv, sh.wx[pt0 + bj], h0, l0);
+              fx_encode(a0 * pv, staged_exp(sh.wx[pt0 + bj]), h0, l0);
               atomicAdd((unsigned long long *)&sh.ahi[pt0 + bj], (unsigned long long)h0);
               atomicAdd(&sh.alo[pt0 + bj], l0);
               if (!single) {
-                fx_encode(a1 * pv, sh.wx[pt0 + bj + 1], h1, l1);
+                fx_encode(a1 * pv, staged_exp(sh.wx[pt0 + bj + 1]), h1, l1);
                 atomicAdd((unsigned long long *)&sh.ahi[pt0 + bj + 1], (unsigned long long)h1);
                 atomicAdd(&sh.alo[pt0 + bj + 1], l1);
               }
@@ -2056,7 +2062,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       long long h = sh.ahi[q];
       unsigned long long l = sh.alo[q];
       if (h == 0 && l == 0) continue;
-      const int e = entry_of_point(sh, n_staged, q);
+      const int e = staged_entry(sh.wx[q]);
       const int64_t node = pbase + sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
       h += (long long)(l >> kLoBits);
       l &= (1ull << kLoBits) - 1ull;
