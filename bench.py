@@ -29,6 +29,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0       # MI355X HBM3E
 VALU_PEAK_TOPS = 39.32       # 256 CU x 64 lanes x 2.4 GHz (non-packed FP32 / FP64 lane-ops)
+N_SIMD = 256 * 4             # SIMDs: 4 per CU, 16 lanes each
+CLOCK_GHZ = 2.4
+VALU_CYCLES_PER_WAVE_INST = 4  # a wave64 VALU instruction on a 16-lane SIMD
 BYTES_PER_BAND_CELL = 92     # 2 x (FP64 centre 24 B + volume 8 B) + source 24 B + cell index 4 B
 BYTES_PER_POINT = 272        # P, e_t, Pdot (72) + d, L, eps (24) + 2 velocity gathers (48)
                              # + f, U_s, P_s, w (80) + f_hat written and read (48)
@@ -59,21 +62,21 @@ def log(msg):
     sys.stderr.flush()
 
 
-def traffic_from_profiles(kernel, n_cells, n_stems):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current sources and this workload."""
+def counters_from_profiles(kernel, n_cells, n_stems):
+    """The committed rocprofv3 counter summary of `kernel` (HBM bytes per
+    launch, VALU instructions, durations), if it was taken on the current
+    sources and this workload; else an empty dict."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
-        return None
+        return {}
     try:
         t = json.load(open(p))
     except Exception:
-        return None
+        return {}
     from paper_2609_39443_amd.profsum import source_hash
     if t.get("source_hash") != source_hash() or t.get("n_cells") != n_cells or t.get("stems") != n_stems:
-        return None
-    k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+        return {}
+    return t.get("kernels", {}).get(kernel) or {}
 
 
 def measure_graph(alp, torch, np, wls, prec, steps, warmup):
@@ -260,7 +263,8 @@ def main():
     t_w = stages["weights"] * 1e-3
     bytes_w = n_band * BYTES_WEIGHTS_PER_BAND_CELL
     ach_w = bytes_w / t_w / 1e9
-    traffic = traffic_from_profiles("k_weights", n_cells, args.stems)
+    prof_w = counters_from_profiles("k_weights", n_cells, args.stems)
+    traffic = prof_w.get("bytes_per_launch")
     roofline = {"kernel": "k_weights", "bound": "hbm", "achieved": ach_w, "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": ach_w / HBM_PEAK_GBPS, "traffic": traffic,
                 "alg_bytes_per_launch": bytes_w, "avg_ms": stages["weights"]}
@@ -270,6 +274,12 @@ def main():
     roofline_alu = {"kernel": "k_weights", "bound": "alu", "achieved": ops_w / t_w / 1e12,
                     "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s", "frac": ops_w / t_w / 1e12 / VALU_PEAK_TOPS,
                     "alg_ops_per_launch": ops_w}
+    # issued, not algorithmic: the counted VALU wave instructions of the same
+    # kernel (each holds a 16-lane SIMD for 4 cycles) over the SIMD cycles of
+    # its counted duration at 2.4 GHz
+    if prof_w.get("valu_insts") and prof_w.get("sq_avg_ns"):
+        busy = prof_w["valu_insts"] * VALU_CYCLES_PER_WAVE_INST
+        roofline_alu["issued_valu_frac"] = busy / (N_SIMD * CLOCK_GHZ * prof_w["sq_avg_ns"])
 
     cpu = None
     if not args.no_cpu_baseline:

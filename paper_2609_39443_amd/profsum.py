@@ -166,6 +166,10 @@ def main(argv):
         dur = 0.5 * (fe[k]["_dur_ns"] + wr[k]["_dur_ns"])
         traffic["kernels"][k] = {"fetch_kib": fk, "write_kib": wk, "bytes_per_launch": b, "avg_ns": dur}
         s = sq.get(k, {})
+        if "SQ_INSTS_VALU" in s:
+            # VALU wave instructions per dispatch and the SQ pass's own mean duration
+            traffic["kernels"][k]["valu_insts"] = s["SQ_INSTS_VALU"]
+            traffic["kernels"][k]["sq_avg_ns"] = s["_dur_ns"]
         lines.append(f"{k:16s} {fe[k]['_n']:5d} {dur / 1e3:8.1f} {fe[k]['_waves']:7d} "
                      f"{s.get('SQ_INSTS_VALU', 0):12.0f} {s.get('SQ_INSTS_LDS', 0):10.0f} "
                      f"{s.get('SQ_INSTS_SALU', 0):11.0f} {fk:10.0f} {wk:10.0f} {b / 1e6:8.1f} {b / dur:8.1f}")
