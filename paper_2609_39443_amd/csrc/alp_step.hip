@@ -2275,7 +2275,7 @@ __device__ __forceinline__ uint4 rec_take(const Work &W, RecCursor &c, uint32_t 
   return r;
 }
 
-__global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(8))) void k_spread(StepLaunch L) {
   Work W = L.w;
   __shared__ SpreadScratch sh;
   const int lane = threadIdx.x;
@@ -2290,12 +2290,18 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
   unsigned long long fl = 0;
   sh.first[lane] = 0;
   sh.last[lane] = 0;
-  // the current item and the next one's descriptor
+  // the current item, and the next one's descriptor and record range
   Item it = W.item[item];
   uint32_t rn = W.rec_cnt[item];
   unsigned long long rb = W.rec_base[item];
   Item nxt = it;
-  if (item + stride < n_items) nxt = W.item[item + stride];
+  uint32_t nrn = 0;
+  unsigned long long nrb = 0;
+  if (item + stride < n_items) {
+    nxt = W.item[item + stride];
+    nrn = W.rec_cnt[item + stride];
+    nrb = W.rec_base[item + stride];
+  }
   // the record stream, two chunks ahead
   RecCursor cur;
   cur.item = item;
@@ -2411,9 +2417,13 @@ __global__ __launch_bounds__(64) void k_spread(StepLaunch L) {
     item += stride;
     if (item >= n_items) break;
     it = nxt;
-    rn = W.rec_cnt[item];
-    rb = W.rec_base[item];
-    if (item + stride < n_items) nxt = W.item[item + stride];
+    rn = nrn;
+    rb = nrb;
+    if (item + stride < n_items) {
+      nxt = W.item[item + stride];
+      nrn = W.rec_cnt[item + stride];
+      nrb = W.rec_base[item + stride];
+    }
   }
   if (acc_case >= 0) {
     if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
