@@ -29,7 +29,9 @@
  *   R2  default drag form is eq. (19) (full magnitude); eq. (6) is optional.
  *   R3  Delta s_k = L_k, the CV length.
  *   R4  c(x) = nearest cell centre; ties -> smallest (Cx,Cy,Cz), then index.
- *   R5  fallback when sqrt(u0_n . u0_n) < tau (absolute, m/s).
+ *   R5  fallback when sqrt(u0_n . u0_n) < tau (absolute, m/s), and also where
+ *       u0_n vanishes exactly (eq. 17 has no direction there), which is the
+ *       only case left when tau = 0.
  *   R6  degenerate fallback (e_up parallel to e_t) -> e_s = 0.
  *   R7  n_p is used as printed (zero vector = no flattening); no renormalising.
  *   R8  closest segment per beam, ties -> lowest segment index.
@@ -460,7 +462,7 @@ int orc_sample(const orc_mesh *m, const double *U, const orc_beams *b, const orc
         double ut = dot3(u0, e);
         for (int a = 0; a < 3; ++a) un[a] = u0[a] - ut * e[a];
         double mag = sqrt(dot3(un, un));
-        if (mag >= p->tau) {
+        if (mag >= p->tau && mag > 0.0) {
           for (int a = 0; a < 3; ++a) es[a] = -un[a] / mag;
         } else {
           /* fallback: global upstream direction projected onto the plane

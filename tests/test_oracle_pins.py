@@ -212,6 +212,67 @@ def test_sampling_fallback_branches(oracle_mod, box_mesh):
     assert np.allclose(r["P_s"], P - np.array([0, 0.1, 0]), rtol=0, atol=1e-15)
 
 
+def test_fallback_threshold_zero(oracle_mod, box_mesh):
+    """R5 with tau = 0: the fallback is taken only where u0_n is exactly zero
+    (eq. 17 has no direction there); any non-zero |u0_n|, however small, keeps
+    the direction of eq. (17)."""
+    m, C = box_mesh
+    P = _vertical()
+    U = np.tile([0.0, 0.0, 0.5], (C.shape[0], 1))
+    b = beams_of([P], 0.02, L=0.01, ls=0.1)
+    r = oracle_mod.sample(m, U, b, params(tau=0.0))
+    assert r["diag"]["n_fallback"] == 5
+    assert np.array_equal(r["P_s"], P - np.array([0.1, 0, 0]))
+    U[:, 1] = 1e-12
+    r = oracle_mod.sample(m, U, b, params(tau=0.0))
+    assert r["diag"]["n_fallback"] == 0
+    assert np.allclose(r["P_s"], P - np.array([0, 0.1, 0]), rtol=0, atol=1e-15)
+
+
+def test_projection_uses_p_spread_and_sampling_ignores_it(oracle_mod):
+    """Algorithm 1 samples at the positions of t^n and projects at the updated
+    ones (R15).  Moving P_spread leaves every sampling output and the force
+    bitwise unchanged; moving it by whole cells along x on a uniform mesh moves
+    the source and keeps the nodal weights (translation by a lattice vector);
+    the balance of Sec. 3.2.4 stays exact."""
+    h = 0.01
+    C, V = W.uniform_mesh(30, 16, 16, h)
+    m = oracle_mod.Mesh(C, V, None, 1)
+    rng = np.random.default_rng(4)
+    U = np.tile([0.4, 0.0, 0.0], (C.shape[0], 1)) + 0.02 * rng.normal(size=C.shape)
+    P = _vertical(10, x=0.1037, y=0.0813)
+    b = beams_of([P], 0.02, L=0.01, ls=0.05, tangents=[np.tile([0, 0, 1.0], (10, 1))])
+    base = oracle_mod.step(m, U, b, params())
+    shift = np.array([3 * h, 0.0, 0.0])
+    bs = dict(b)
+    bs["P_spread"] = P + shift
+    moved = oracle_mod.step(m, U, bs, params())
+    for k in ("U_s", "P_s", "cell_a", "cell_s", "f"):
+        assert np.array_equal(moved[k], base[k]), k
+    ix = np.arange(C.shape[0])
+    i = ix % 30
+    src = ix - 3                      # the cell 3 h upstream in x
+    inner = i >= 3
+    assert np.all(moved["S"][~inner] == 0)
+    assert normwise(moved["S"][inner], base["S"][src[inner]]) <= 1e-13
+    assert np.allclose(moved["w"], base["w"], rtol=1e-13, atol=0)
+    assert moved["diag"]["cons_rel_err"] <= 1e-14
+    # a P_spread that differs from P point by point (a bent update) changes w
+    # and S but not the balance, and equals the projection of the same forces
+    # at those positions
+    bent = dict(b)
+    bent["P_spread"] = P + np.stack([0.004 * np.sin(np.arange(10)), 0.003 * np.cos(np.arange(10)),
+                                     np.zeros(10)], axis=1)
+    rb = oracle_mod.step(m, U, bent, params())
+    assert np.array_equal(rb["f"], base["f"])
+    assert not np.array_equal(rb["w"], base["w"])
+    assert rb["diag"]["cons_rel_err"] <= 1e-14
+    at = dict(b)
+    at["P"] = bent["P_spread"]
+    sp = oracle_mod.spread(m, at, rb["f"])
+    assert np.array_equal(sp["S"], rb["S"]) and np.array_equal(sp["w"], rb["w"])
+
+
 def test_outside_points_carry_no_load(oracle_mod, box_mesh):
     """R13: an actuator or sampling point outside the domain gives zero load."""
     m, C = box_mesh
