@@ -139,7 +139,10 @@ typedef struct {
 typedef struct {
   double rho;      /* fluid density > 0 */
   double alpha_f;  /* relaxation factor of eq. (20) in (0, 1]; used only when f_prev != NULL */
-  double tau;      /* fallback threshold on |u0_n| [m/s] (Sec. 3.2.2); 0 disables */
+  double tau;      /* fallback threshold on |u0_n| [m/s] (Sec. 3.2.2), >= 0: the fallback
+                      direction is used where |u0_n| < tau, and always where u0_n is
+                      exactly zero (eq. 17 has no direction there); with tau = 0 only
+                      the latter */
   int32_t prec;    /* alp_precision */
   int32_t drag_form; /* alp_drag_form */
   int32_t sample_mode; /* alp_sample_mode */

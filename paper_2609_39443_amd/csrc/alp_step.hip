@@ -929,7 +929,7 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
       double un[3] = {u0[0] - ut * e[0], u0[1] - ut * e[1], u0[2] - ut * e[2]};
       double mag = sqrt(dot3_exact(un[0], un[1], un[2], un[0], un[1], un[2]));
       double es[3];
-      if (mag >= cs.tau) {
+      if (mag >= cs.tau && mag > 0.0) {
         es[0] = -un[0] / mag;
         es[1] = -un[1] / mag;
         es[2] = -un[2] / mag;

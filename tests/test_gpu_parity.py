@@ -137,6 +137,81 @@ def test_small_wave_flume(gu, ctx):
         run_and_compare(gu, ctx, wl, alp.PREC_FP64)
 
 
+def fallback_scene(tau=1e-6, p_spread=False):
+    """Noise-free vertical flow U = (u_x(x), 0, 0.3) with Pdot = 0, so a
+    vertical beam sees u0 along its tangent: u0_n = (u_x, 0, 0) exactly.
+    Beams: u_x = 0 with e_up = -x (fallback of Sec. 3.2.2), u_x = 0 with
+    e_up = z parallel to the tangent (degenerate fallback, e_s = 0), u_x = 5e-7
+    below tau = 1e-6 (fallback by the threshold), u_x = 0.2 (eq. 17), and a
+    horizontal beam that sees the vertical flow across it (eq. 17).  With
+    p_spread the projection uses displaced positions (Algorithm 1, the update
+    before the projection)."""
+    h = 0.01
+    C, V = W.uniform_mesh(30, 20, 20, h)
+    ux = np.where(C[:, 0] < 0.09, 0.0, np.where(C[:, 0] < 0.18, 5e-7, 0.2))
+    U = np.stack([ux, np.zeros_like(ux), np.full_like(ux, 0.3)], axis=1)
+    vert = lambda x, y, n: np.stack([np.full(n, x), np.full(n, y), 0.031 + 0.01 * np.arange(n)], axis=1)
+    pts = [vert(0.0437, 0.0513, 12), vert(0.0463, 0.1411, 9), vert(0.1337, 0.0913, 11),
+           vert(0.2437, 0.1013, 10),
+           np.stack([0.05 + 0.01 * np.arange(14), np.full(14, 0.1613), np.full(14, 0.1437)], axis=1)]
+    tan = [np.tile([0, 0, 1.0], (p.shape[0], 1)) for p in pts[:4]] + [np.tile([1.0, 0, 0], (14, 1))]
+    e_up = [[-1.0, 0, 0], [0, 0, 1.0], [-0.6, 0.8, 0], [-1.0, 0, 0], [-1.0, 0, 0]]
+    n = [p.shape[0] for p in pts]
+    beams = W._beamset(pts, tan, [np.zeros((k, 3)) for k in n], [np.full(k, 0.003) for k in n],
+                       [np.full(k, 0.01) for k in n], [np.full(k, 2.0 * h) for k in n],
+                       np.full(5, 1.2), np.full(5, 0.05), np.full(5, 0.03), np.zeros((5, 3)), e_up)
+    if p_spread:
+        k = np.arange(beams["P"].shape[0])
+        beams["P_spread"] = beams["P"] + np.stack([0.004 * np.sin(0.7 * k), 0.002 * np.cos(1.3 * k),
+                                                   0.001 * np.sin(0.4 * k)], axis=1)
+    name = f"fallback-tau{tau:g}" + ("-pspread" if p_spread else "")
+    return {"name": name, "C": C, "V": V, "U": U, "box": None, "h": h, "beams": beams,
+            "params": {"rho": 1000.0, "alpha_f": 1.0, "tau": tau, "drag_form": 0}}
+
+
+@pytest.mark.parametrize("batched", [True, False])
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_sampling_fallback_branches(gu, ctx, prec, batched):
+    """The fallback direction of Sec. 3.2.2 and its degenerate case fire on the
+    GPU with the oracle's counts and sampling points; with tau = 0 only the
+    exactly vanishing u0_n falls back; the projection follows P_spread."""
+    wl = fallback_scene()
+    _, res, ref, diag = run_and_compare(gu, ctx, wl, prec, batched=batched)
+    o = wl["beams"]["offsets"]
+    assert diag["n_fallback"] == ref["diag"]["n_fallback"] == (o[1] - o[0]) + (o[3] - o[2])
+    assert diag["n_fallback_degenerate"] == ref["diag"]["n_fallback_degenerate"] == o[2] - o[1]
+    assert np.array_equal(res["P_s"][o[1]:o[2]], wl["beams"]["P"][o[1]:o[2]])  # e_s = 0
+    wl = fallback_scene(tau=0.0)
+    _, _, ref, diag = run_and_compare(gu, ctx, wl, prec, batched=batched)
+    assert diag["n_fallback"] == ref["diag"]["n_fallback"] == o[1] - o[0]
+    assert diag["n_fallback_degenerate"] == ref["diag"]["n_fallback_degenerate"] == o[2] - o[1]
+    wl = fallback_scene(p_spread=True)
+    _, res, ref, diag = run_and_compare(gu, ctx, wl, prec, batched=batched)
+    assert diag["n_fallback"] > 0 and diag["n_fallback_degenerate"] > 0
+    plain = gu.oracle_step(fallback_scene())
+    assert not np.array_equal(ref["w"], plain["w"])  # the projection moved with P_spread
+    assert np.array_equal(ref["f"], plain["f"])      # the sampling did not
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_p_spread_random_scenes(gu, ctx, prec):
+    """P_spread differing from P point by point on random scenes and the small
+    canopy, batched with graph replay: the segment binning, the weights and
+    the spread follow P_spread, the sampling follows P."""
+    for wl in (random_scene(7, outside=True), W.canopy(n=40, n_stems=30, cv_range=(5, 30), inset=0.04)):
+        rng = np.random.default_rng(8)
+        wl["beams"]["P_spread"] = wl["beams"]["P"] + 0.003 * rng.normal(size=wl["beams"]["P"].shape)
+        wl["name"] += "-pspread"
+        case = gu.GpuCase(ctx, wl, prec)
+        gu.log(f"[parity] {wl['name']} prec={prec} graph")
+        for _ in range(2):
+            gu.step_batched(ctx, [case], alp.USE_GRAPH)
+        ref = gu.oracle_step(wl)
+        tS, tw = TOL[prec]
+        gu.compare(case.results(), ref, ctx.diag(0), ref["diag"], tS, tw)
+        alp.alp_invalidate(ctx.h)
+
+
 def test_small_jittered_net(gu, ctx):
     wl = W.jittered_net(nx=60, ny=60, nz=16, h=0.005, n_strands=12, n_cv=40, net_lo=0.03,
                         net_hi=0.27, z0=0.05, sag=0.015)
