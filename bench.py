@@ -32,11 +32,17 @@ VALU_PEAK_TOPS = 39.32       # 256 CU x 64 lanes x 2.4 GHz (non-packed FP32 / FP
 N_SIMD = 256 * 4             # SIMDs: 4 per CU, 16 lanes each
 CLOCK_GHZ = 2.4
 VALU_CYCLES_PER_WAVE_INST = 4  # a wave64 VALU instruction on a 16-lane SIMD
-BYTES_PER_BAND_CELL = 92     # 2 x (FP64 centre 24 B + volume 8 B) + source 24 B + cell index 4 B
+# Algorithmic bytes the method itself moves per band cell over a whole step:
+# the centre and volume read by the weights pass and again by the spread pass
+# (centre FP32 in the split precision, FP64 otherwise; volume FP64), the
+# source written (24 B) and the 4-byte cell index of the scatter.
+BYTES_PER_BAND_CELL = {"split": 2 * (12 + 8) + 24 + 4, "fp64": 2 * (24 + 8) + 24 + 4}   # 68, 92
 BYTES_PER_POINT = 272        # P, e_t, Pdot (72) + d, L, eps (24) + 2 velocity gathers (48)
                              # + f, U_s, P_s, w (80) + f_hat written and read (48)
-BYTES_WEIGHTS_PER_BAND_CELL = 32   # weights pass: FP64 centre + volume
+# weights pass alone: centre + volume of each band cell
+BYTES_WEIGHTS_PER_BAND_CELL = {"split": 12 + 8, "fp64": 24 + 8}
 OPS_WEIGHTS_PER_PAIR = 50          # foot of eq. 21, eps_j, cutoff, eta of eq. 22, a0 a1, a V (lane-ops)
+STAT_REPLAYS = 100                 # replays behind the per-step median and percentiles
 
 
 def parse():
@@ -47,8 +53,11 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="cells per mesh edge (default 256)")
     ap.add_argument("--stems", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stems", type=int, default=1000,
-                    help="stems in the oracle's timed sample (about 10-30 s of CPU work)")
+    ap.add_argument("--cpu-stems", type=int, default=600,
+                    help="stems in the oracle's timed sample: the stems rooted nearest the x = 0 "
+                         "side of the canopy (a few seconds of CPU work per run)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the all-core oracle leg (0: the host's CPU share, at most 16)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison runs")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary measurements (wave flume, batched scenarios, jittered net)")
@@ -109,6 +118,129 @@ def measure_graph(alp, torch, np, wls, prec, steps, warmup):
     finally:
         ctx.close()
     return dt, diags
+
+
+def host_description():
+    """Host core count and CPU model (the oracle's timings depend on them)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count()
+    return {"nproc": os.cpu_count(), "affinity_cpus": share, "cpu_model": model}
+
+
+def beam_boxes(beams):
+    """Per beam, the AABB of its points inflated by 3 eps_max plus its longest
+    segment: every cell the beam reaches lies inside."""
+    import numpy as np
+    off = beams["offsets"]
+    nb = len(off) - 1
+    lo = np.full((nb, 3), np.inf)
+    hi = np.full((nb, 3), -np.inf)
+    for b in range(nb):
+        P = beams["P"][off[b]:off[b + 1]]
+        if P.shape[0] == 0:
+            continue
+        seg = np.linalg.norm(np.diff(P, axis=0), axis=1).max() if P.shape[0] > 1 else 0.0
+        r = 3.0 * beams["eps"][off[b]:off[b + 1]].max() + seg + 1e-9
+        lo[b], hi[b] = P.min(0) - r, P.max(0) + r
+    return lo, hi
+
+
+def cpu_baseline(wl, got, n_stems, n_cells):
+    """The oracle (plain FP64 C, grid mode) on a bounded sample of the
+    workload: the n_stems stems rooted nearest x = 0, over the full mesh, one
+    whole step (sample, drag, project; the grid is built beforehand and not
+    timed).  Median of three runs on one thread, and of three runs on all of
+    the host's CPU share (the sample's stems in contiguous blocks, one oracle
+    call per thread; per-point outputs depend only on their own beam and the
+    sources superpose over beams, so the blocks are summed in block order).
+    The first single-thread run also gives the accuracy of the GPU outputs on
+    that sample: w of the sampled nodes, and S at band cells that only sampled
+    stems can reach."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle
+    from paper_2609_39443_amd import workloads as W
+
+    host = host_description()
+    beams = wl["beams"]
+    off = beams["offsets"]
+    nb = len(off) - 1
+    order = np.argsort(beams["P"][off[:-1], 0], kind="stable")
+    pick = sorted(order[:min(n_stems, nb)].tolist())
+    sub = W.subset_beams(beams, pick)
+    npt = int(sub["P"].shape[0])
+    t0 = time.perf_counter()
+    om = oracle.Mesh(wl["C"], wl["V"], wl.get("box"), oracle.GRID)
+    t_grid = time.perf_counter() - t0
+    log(f"oracle CPU baseline: {len(pick)} stems ({npt} points), grid built in {t_grid:.1f} s")
+    singles, ref = [], None
+    for _ in range(3):
+        t = time.perf_counter()
+        r = oracle.step(om, wl["U"], sub, wl["params"])
+        singles.append(time.perf_counter() - t)
+        ref = ref or r
+    threads = host["affinity_cpus"] or 1
+    threads = max(1, min(16, threads))
+    per = -(-len(pick) // threads)
+    blocks = [pick[i:i + per] for i in range(0, len(pick), per)]
+    subs = [W.subset_beams(beams, b) for b in blocks]
+    multi = []
+    with ThreadPoolExecutor(max_workers=len(subs)) as ex:
+        for _ in range(3):
+            t = time.perf_counter()
+            parts = list(ex.map(lambda sb: oracle.step(om, wl["U"], sb, wl["params"]), subs))
+            Ssum = parts[0]["S"].copy()
+            for q in parts[1:]:
+                Ssum += q["S"]
+            multi.append(time.perf_counter() - t)
+            del parts, Ssum
+    ts, tm = float(np.median(singles)), float(np.median(multi))
+    cpu = {"value": npt / ts, "unit": "points/s", "cores": 1, "kind": "oracle",
+           "sample": f"{len(pick)} of {nb} stems (the ones rooted nearest x = 0; {npt} points) on the full "
+                     f"{n_cells}-cell mesh, one FP64 step (sample, drag, project), grid mode, median of 3 "
+                     f"runs of {ts:.2f} s",
+           "seconds": singles, "pairs": int(ref["diag"]["n_pairs"]),
+           "all_cores": {"value": npt / tm, "unit": "points/s", "cores": len(subs), "seconds": multi,
+                         "how": "contiguous beam blocks, one oracle call per thread, sources summed in block order"},
+           "grid_build_s": t_grid, **host}
+    log(f"oracle: 1 thread {ts:.2f} s, {len(subs)} threads {tm:.2f} s")
+    # accuracy on the sample
+    idx = np.concatenate([np.arange(off[b], off[b + 1]) for b in pick])
+    zw = ref["w"] == 0
+    rng = np.random.default_rng(11)
+    acc = {"sample": f"w of the {npt} sampled nodes; S at band cells reached only by sampled stems"}
+    # band cells of the sample that no other stem can reach
+    band = np.nonzero(np.any(ref["S"] != 0, axis=1))[0]
+    cand = rng.choice(band, size=min(3000, band.size), replace=False)
+    lo, hi = beam_boxes(beams)
+    other = np.ones(nb, dtype=bool)
+    other[pick] = False
+    X = wl["C"][cand]
+    reach = np.all((X[:, None, :] >= lo[None, other]) & (X[:, None, :] <= hi[None, other]), axis=2)
+    cells = np.sort(cand[~reach.any(axis=1)][:400])
+    for tag, g in got.items():
+        gw = g["w"][idx]
+        werr = float(np.max(np.abs(gw[~zw] - ref["w"][~zw]) / ref["w"][~zw])) if np.any(~zw) else 0.0
+        Sg, Sr = g["S"][cells], ref["S"][cells]
+        nr = np.linalg.norm(Sr, axis=1)
+        e_cell = float(np.max(np.linalg.norm(Sg - Sr, axis=1)) / np.max(nr)) if cells.size else None
+        big = nr > 1e-6 * np.max(nr) if cells.size else np.zeros(0, bool)
+        e_rel = float(np.max(np.linalg.norm(Sg - Sr, axis=1)[big] / nr[big])) if np.any(big) else None
+        acc[tag] = {"e_cell": e_cell, "e_cell_percell_rel_max": e_rel, "w_rel_max": werr,
+                    "cells_checked": int(cells.size), "tol_e_cell": 1e-5 if tag == "split" else 1e-12}
+    log(f"accuracy on the oracle sample: {acc}")
+    return cpu, acc
 
 
 def _integrated(wl):
@@ -205,7 +337,10 @@ def main():
                             out["f"].data_ptr(), S.data_ptr(), out["U_s"].data_ptr(),
                             out["w"].data_ptr(), out["P_s"].data_ptr(), None, None)
 
-    def timed_graph(prec, steps, warmup):
+    def timed_graph(prec, steps, warmup, stat_reps=STAT_REPLAYS):
+        """K replays timed by the host clock between two synchronisations, then
+        `stat_reps` replays timed one by one with events on the caller's
+        stream (each replay is ordered on it): median, p10, p90."""
         cs = [case(prec)]
         alp.alp_step_batched(ctx.h, cs, alp.USE_GRAPH)   # sizes, runs and captures
         for _ in range(warmup):
@@ -216,8 +351,17 @@ def main():
             alp.alp_step_batched(ctx.h, cs, alp.USE_GRAPH)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(stat_reps + 1)]
+        ev[0].record()
+        for i in range(stat_reps):
+            alp.alp_step_batched(ctx.h, cs, alp.USE_GRAPH)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(stat_reps)])
+        stats = {"replays": stat_reps, "median_ms": float(np.median(per)),
+                 "p10_ms": float(np.percentile(per, 10)), "p90_ms": float(np.percentile(per, 90))}
         alp.alp_invalidate(ctx.h)
-        return dt, ctx.diag(0)
+        return dt, ctx.diag(0), stats
 
     def timed_plain(prec, steps, warmup):
         p = alp.make_params(wl["params"], prec)
@@ -235,21 +379,31 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / steps
 
+    def host_outputs():
+        torch.cuda.synchronize()
+        return {"S": S.cpu().numpy(), "w": out["w"].cpu().numpy(), "f": out["f"].cpu().numpy()}
+
     # headline: FP32-split, batched persistent launches, graph replay
     log("timing the FP32-split graph step")
-    t_split, diag = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup)
-    log(f"split: {t_split * 1e3:.3f} ms/step, diag {diag}")
+    t_split, diag, st_split = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup)
+    got = {"split": host_outputs()}
+    log(f"split: {t_split * 1e3:.3f} ms/step (median {st_split['median_ms']:.3f}, "
+        f"p10 {st_split['p10_ms']:.3f}, p90 {st_split['p90_ms']:.3f}), diag {diag}")
     # live per-stage timings (HIP events on the stream the kernels run on)
     stage_runs = [alp.alp_step_profile(ctx.h, [case(alp.PREC_FP32_SPLIT)]) for _ in range(5)]
     stages = {k: float(np.median([r[k] for r in stage_runs])) for k in stage_runs[0]}
     log(f"stages (ms): {stages}")
     res = {}
+    stages64 = None
     if not args.no_fp64:
-        t64, d64 = timed_graph(alp.PREC_FP64, max(3, args.steps // 2), 1)
+        t64, d64, st64 = timed_graph(alp.PREC_FP64, max(3, args.steps // 2), 1)
+        got["fp64"] = host_outputs()
         res["fp64_graph_ms_per_step"] = t64 * 1e3
+        res["fp64_step_stats"] = st64
         res["fp64_cons_rel_err"] = d64["cons_rel_err"]
         stage64 = [alp.alp_step_profile(ctx.h, [case(alp.PREC_FP64)]) for _ in range(3)]
-        res["fp64_stages_ms"] = {k: float(np.median([r[k] for r in stage64])) for k in stage64[0]}
+        stages64 = {k: float(np.median([r[k] for r in stage64])) for k in stage64[0]}
+        res["fp64_stages_ms"] = stages64
         tp = timed_plain(alp.PREC_FP64, max(3, args.steps // 4), 1)
         res["plain_fp64_unbatched_ms_per_step"] = tp * 1e3
         res["speedup_split_vs_fp64_graph"] = t64 / t_split
@@ -257,17 +411,25 @@ def main():
         log(f"fp64 graph {t64 * 1e3:.3f} ms, plain fp64 {tp * 1e3:.3f} ms")
 
     n_band, n_pairs = int(diag["n_band_cells"]), int(diag["n_pairs"])
-    bytes_step = n_band * BYTES_PER_BAND_CELL + npnt * BYTES_PER_POINT
+    bytes_step = n_band * BYTES_PER_BAND_CELL["split"] + npnt * BYTES_PER_POINT
     gbps = bytes_step / t_split / 1e9
     # dominant kernel: the weights pass (closest segment per pair, eq. 21-22)
     t_w = stages["weights"] * 1e-3
-    bytes_w = n_band * BYTES_WEIGHTS_PER_BAND_CELL
+    bytes_w = n_band * BYTES_WEIGHTS_PER_BAND_CELL["split"]
     ach_w = bytes_w / t_w / 1e9
     prof_w = counters_from_profiles("k_weights", n_cells, args.stems)
     traffic = prof_w.get("bytes_per_launch")
     roofline = {"kernel": "k_weights", "bound": "hbm", "achieved": ach_w, "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": ach_w / HBM_PEAK_GBPS, "traffic": traffic,
-                "alg_bytes_per_launch": bytes_w, "avg_ms": stages["weights"]}
+                "alg_bytes_per_band_cell": BYTES_WEIGHTS_PER_BAND_CELL["split"],
+                "alg_bytes_per_launch": bytes_w, "avg_ms": stages["weights"],
+                "traffic_over_alg": (traffic / bytes_w) if traffic else None}
+    if stages64:
+        b64 = n_band * BYTES_WEIGHTS_PER_BAND_CELL["fp64"]
+        a64 = b64 / (stages64["weights"] * 1e-3) / 1e9
+        roofline["fp64"] = {"kernel": "k_weights64", "alg_bytes_per_band_cell": BYTES_WEIGHTS_PER_BAND_CELL["fp64"],
+                            "alg_bytes_per_launch": b64, "avg_ms": stages64["weights"], "achieved": a64,
+                            "frac": a64 / HBM_PEAK_GBPS}
     # the same kernel against the VALU roof: it issues far more instructions
     # than the method's arithmetic needs, so this view is reported beside
     ops_w = n_pairs * OPS_WEIGHTS_PER_PAIR
@@ -281,22 +443,9 @@ def main():
         busy = prof_w["valu_insts"] * VALU_CYCLES_PER_WAVE_INST
         roofline_alu["issued_valu_frac"] = busy / (N_SIMD * CLOCK_GHZ * prof_w["sq_avg_ns"])
 
-    cpu = None
+    cpu = accuracy = None
     if not args.no_cpu_baseline:
-        from oracle import oracle
-        rng = np.random.default_rng(7)
-        pick = sorted(rng.choice(args.stems, size=min(args.cpu_stems, args.stems), replace=False).tolist())
-        sub = W.subset_beams(wl["beams"], pick)
-        log(f"oracle CPU baseline on {len(pick)} stems ({sub['P'].shape[0]} points)")
-        om = oracle.Mesh(wl["C"], wl["V"], None, oracle.GRID)
-        t = time.perf_counter()
-        r = oracle.step(om, wl["U"], sub, wl["params"])
-        dt = time.perf_counter() - t
-        cpu = {"value": sub["P"].shape[0] / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(pick)} of {args.stems} stems ({sub['P'].shape[0]} points) on the full "
-                         f"{n_cells}-cell mesh, one FP64 step (sample, drag, project), grid mode, "
-                         f"{dt:.1f} s", "seconds": dt, "pairs": int(r["diag"]["n_pairs"])}
-        log(f"oracle: {dt:.2f} s")
+        cpu, accuracy = cpu_baseline(wl, got, args.cpu_stems, n_cells)
 
     extra = None
     if not args.no_extra:
@@ -312,8 +461,10 @@ def main():
                                f"hipGraph replay", "n_cells": n_cells, "n_points": npnt,
                    "n_band_cells": n_band, "n_pairs": n_pairs, "parallelism": "single GPU"},
         "cell_updates_per_s": n_pairs / t_split, "band_cells_per_s": n_band / t_split,
-        "mesh_cells_per_s": n_cells / t_split, "alg_hbm_gbps": gbps, "alg_hbm_frac": gbps / HBM_PEAK_GBPS,
-        "cons_rel_err": diag["cons_rel_err"], "stages_ms": stages, "roofline": roofline,
+        "mesh_cells_per_s": n_cells / t_split, "step_stats": st_split,
+        "alg_bytes_per_band_cell": BYTES_PER_BAND_CELL["split"], "alg_bytes_per_point": BYTES_PER_POINT,
+        "alg_bytes_per_step": bytes_step, "alg_hbm_gbps": gbps, "alg_hbm_frac": gbps / HBM_PEAK_GBPS,
+        "cons_rel_err": diag["cons_rel_err"], "accuracy": accuracy, "stages_ms": stages, "roofline": roofline,
         "roofline_alu": roofline_alu,
         "cpu_baseline": cpu, **res,
         "other_workloads": extra,

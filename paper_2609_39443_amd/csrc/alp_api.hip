@@ -52,6 +52,11 @@ struct alp_context {
   std::vector<int64_t> h_pbrange;
   // graph
   hipGraphExec_t gexec = nullptr;
+  // overflow word of the last replay, copied by the graph's last node into
+  // mapped host memory, and an event recorded after each replay
+  uint32_t *h_ovf = nullptr, *d_ovf = nullptr;
+  hipEvent_t ev_replay = nullptr;
+  bool replay_pending = false;
   std::vector<alp_case> gkey;
   uint32_t gflags = 0;
   int last_cases = 0;
@@ -102,6 +107,8 @@ void drop_graph(alp_context *ctx) {
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
   ctx->gexec = nullptr;
   ctx->gkey.clear();
+  ctx->replay_pending = false;
+  if (ctx->h_ovf) *ctx->h_ovf = 0u;
 }
 
 bool is_capturing(alp_context *ctx) {
@@ -211,6 +218,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   int64_t sc = scan_tmp_words(std::max({B + 1, T + 1, CH + 1, (int64_t)1}));
   if ((rc = dalloc(ctx, &ctx->scan_tmp, sc)) != ALP_OK) return rc;
   ctx->have_scan = sc;
+  w.scan_tmp = ctx->scan_tmp;
   HIPCHK(ctx, hipMemsetAsync(w.counters, 0, kCounters * sizeof(uint32_t), ctx->st));
   HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, 8 * NC * sizeof(long long), ctx->st));
   HIPCHK(ctx, hipMemsetAsync(w.diag_out, 0, 16 * NC * sizeof(double), ctx->st));
@@ -474,15 +482,15 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   if (fork) (void)hipEventRecord(ctx->ev_join, sd);
   if (!(stages & ST_PROJECT)) return;
   launch_beams_prep(L, st);
-  launch_scan_u32(w.bchunks, w.bchunks, w.n_beams, ctx->scan_tmp, st);
+  launch_scan_u32(w.bchunks, w.bchunks, w.n_beams, w.scan_tmp, st);
   launch_chunks(L, st);
   launch_chunk_boxes(L, st);
-  launch_scan_u32(w.chunk_box, w.chunk_box, w.cap_chunk, ctx->scan_tmp, st);
+  launch_scan_u32(w.chunk_box, w.chunk_box, w.cap_chunk, w.scan_tmp, st);
   launch_chunk_tiles(L, st);
-  launch_scan_u32(w.tile_cnt, w.tile_off, w.n_tiles, ctx->scan_tmp, st);
+  launch_scan_u32(w.tile_cnt, w.tile_off, w.n_tiles, w.scan_tmp, st);
   launch_emit_scatter(L, st);
   launch_tile_merge(L, st);
-  launch_scan_u32(w.tile_items, w.tile_itoff, w.n_tiles, ctx->scan_tmp, st);
+  launch_scan_u32(w.tile_items, w.tile_itoff, w.n_tiles, w.scan_tmp, st);
   launch_items(L, st);
   mark(4);
   launch_weights(L, st);
@@ -587,10 +595,14 @@ alp_status alp_create(int device, void *hip_stream, alp_context **out) {
       hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->st2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_replay, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void **)&ctx->h_ovf, sizeof(uint32_t), hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer((void **)&ctx->d_ovf, ctx->h_ovf, 0) != hipSuccess) {
     delete ctx;
     return ALP_ERR_HIP;
   }
+  *ctx->h_ovf = 0u;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->n_cu = prop.multiProcessorCount;
@@ -612,6 +624,8 @@ alp_status alp_destroy(alp_context *ctx) {
   (void)hipEventDestroy(ctx->ev_out);
   (void)hipEventDestroy(ctx->ev_fork);
   (void)hipEventDestroy(ctx->ev_join);
+  (void)hipEventDestroy(ctx->ev_replay);
+  if (ctx->h_ovf) (void)hipHostFree(ctx->h_ovf);
   (void)hipStreamDestroy(ctx->st2);
   (void)hipStreamDestroy(ctx->st);
   delete ctx;
@@ -855,8 +869,24 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
   // replay an existing graph for identical case descriptors
   if (use_graph && ctx->gexec && (int)ctx->gkey.size() == n_cases && ctx->gflags == flags &&
       std::memcmp(ctx->gkey.data(), cases, sizeof(alp_case) * (size_t)n_cases) == 0) {
+    // an earlier replay whose work lists overflowed (the arrays may have been
+    // updated in place past the captured capacities): report it, drop the
+    // graph, and let the next call size the lists again
+    if (ctx->replay_pending && hipEventQuery(ctx->ev_replay) == hipSuccess) {
+      ctx->replay_pending = false;
+      const uint32_t ovf = __atomic_load_n(ctx->h_ovf, __ATOMIC_ACQUIRE);
+      if (ovf) {
+        drop_graph(ctx);
+        return fail(ctx, ALP_ERR_CAPACITY,
+                    "an earlier graph replay overflowed its work lists (0x%x); its results are invalid "
+                    "and the graph was dropped",
+                    ovf);
+      }
+    }
     if ((rc = enter(ctx)) != ALP_OK) return rc;
     HIPCHK(ctx, hipGraphLaunch(ctx->gexec, ctx->st));
+    HIPCHK(ctx, hipEventRecord(ctx->ev_replay, ctx->st));
+    ctx->replay_pending = true;
     if (flags & ALP_CHECKED) {
       uint32_t ovf;
       int64_t ne, nr;
@@ -906,6 +936,7 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
     hipGraph_t g = nullptr;
     HIPCHK(ctx, hipStreamBeginCapture(ctx->st, hipStreamCaptureModeThreadLocal));
     launch_sequence(ctx, L, ST_ALL);
+    launch_export_overflow(L, ctx->d_ovf, ctx->st);
     hipError_t e = hipStreamEndCapture(ctx->st, &g);
     if (e != hipSuccess) return fail(ctx, ALP_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);

@@ -158,6 +158,7 @@ struct Work {
   uint32_t *counters;   // [kCounters]: [3] overflow flags; from queue_words(q) the weights work
                         // queues q = 0 nearest split, 1 integrated split, 2 integrated FP64,
                         // 3 nearest FP64 (counter x of a queue at word x * kLineWords)
+  uint32_t *scan_tmp;   // scan block totals (host-side launch use only)
   int64_t cap_emit, cap_item, cap_rec, cap_chunk;
   int64_t n_points, n_beams, n_tiles;
   int32_t n_cases, n_pblocks;
@@ -472,5 +473,7 @@ void launch_spread(const StepLaunch &L, hipStream_t st);
 int spread_blocks_per_cu();  // resident k_spread blocks per CU (0 if the query fails)
 void launch_zero_dirty(const StepLaunch &L, hipStream_t st);
 void launch_finalize(const StepLaunch &L, hipStream_t st);
+// copy the step's overflow word to a device-visible host word
+void launch_export_overflow(const StepLaunch &L, uint32_t *dst, hipStream_t st);
 
 }  // namespace alp

@@ -2496,6 +2496,20 @@ __global__ void k_finalize(StepLaunch L) {
   d[8] = (double)W.counters[3];
 }
 
+// The overflow word of the step, written to mapped host memory at the end of
+// a captured step, so that a later call can see that a replay overflowed
+// without synchronising.
+__global__ void k_export_overflow(StepLaunch L, uint32_t *dst) {
+  if (threadIdx.x == 0) {
+    __atomic_store_n(dst, L.w.counters[3], __ATOMIC_RELEASE);
+    __threadfence_system();
+  }
+}
+
+void launch_export_overflow(const StepLaunch &L, uint32_t *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_overflow, dim3(1), dim3(64), 0, st, L, dst);
+}
+
 void launch_finalize(const StepLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3((L.n_cases + 63) / 64), dim3(64), 0, st, L);
 }

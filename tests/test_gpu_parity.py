@@ -595,3 +595,43 @@ def test_per_tile_limit_is_reported(gu, ctx):
     assert err.value.status == -6 and "per-tile" in str(err.value)
     alp.alp_invalidate(ctx.h)
     run_and_compare(gu, ctx, random_scene(2), alp.PREC_FP64)
+
+
+def test_replay_overflow_is_reported(gu, ctx):
+    """Arrays updated in place between graph replays may need longer work
+    lists than the captured ones: a beam stretched across the mesh after
+    capture overflows the window list.  The replay drops the windows it cannot
+    hold (no access beyond the lists), alp_diag reports the overflow, the next
+    call returns ALP_ERR_CAPACITY and drops the graph, and the call after it
+    sizes the lists again and matches the oracle."""
+    C, V = W.uniform_mesh(40, 40, 40, 0.01)
+    n = 20
+    P0 = np.stack([np.full(n, 0.2013), np.full(n, 0.2011), 0.1 + 0.004 * np.arange(n)], axis=1)
+    P1 = np.stack([0.02 + 0.018 * np.arange(n), 0.02 + 0.018 * np.arange(n), 0.02 + 0.018 * np.arange(n)], axis=1)
+    et = lambda P: np.gradient(P, axis=0) / np.linalg.norm(np.gradient(P, axis=0), axis=1, keepdims=True)
+    beams = W._beamset([P0], [et(P0)], [np.zeros((n, 3))], [np.full(n, 0.002)], [np.full(n, 0.004)],
+                       [np.full(n, 0.012)], [1.2], [0.01], [0.02], [[0, 0, 0]], [[-1.0, 0, 0]])
+    wl = {"name": "stretch", "C": C, "V": V, "U": np.tile([0.3, 0.0, 0.0], (C.shape[0], 1)), "box": None,
+          "beams": beams, "params": {"rho": 1000.0, "tau": 1e-6}}
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP64, tile_bins=1, bin_size=0.01)
+    gu.log("[parity] replay overflow: capture on a compact beam")
+    gu.step_batched(ctx, [case], alp.USE_GRAPH)
+    assert ctx.diag(0)["n_overflow"] == 0
+    wl2 = dict(wl)
+    b2 = dict(beams)
+    b2["P"], b2["e_t"] = P1, et(P1)
+    wl2["beams"] = b2
+    case.beams.t["P"].copy_(gu.dev(P1))
+    case.beams.t["e_t"].copy_(gu.dev(b2["e_t"]))
+    gu.log("[parity] replay overflow: replay on the stretched beam")
+    gu.step_batched(ctx, [case], alp.USE_GRAPH)
+    assert ctx.diag(0)["n_overflow"] != 0
+    with pytest.raises(alp.AlpError) as err:
+        gu.step_batched(ctx, [case], alp.USE_GRAPH)
+    assert err.value.status == -6
+    gu.step_batched(ctx, [case], alp.USE_GRAPH)
+    ref = gu.oracle_step(wl2)
+    gu.compare(case.results(), ref, ctx.diag(0), ref["diag"], 1e-12, 1e-12)
+    gu.step_batched(ctx, [case], alp.USE_GRAPH)
+    gu.compare(case.results(), ref, ctx.diag(0), ref["diag"], 1e-12, 1e-12)
+    alp.alp_invalidate(ctx.h)
