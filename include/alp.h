@@ -252,6 +252,24 @@ typedef struct {
 alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *cases,
                             uint32_t flags);
 
+/* For callers that cannot allocate device memory (code that must not call
+   hipMalloc, such as tight serving loops or harnesses that forbid it): one
+   uncaptured step of alp_step_batched (flags 0) whose whole per-step
+   workspace -- counters, work lists, pair records, the case table and scan
+   temporaries -- lives in a static device array of 64 MiB per device
+   instead of memory the context allocates.  It calls no hipMalloc or
+   hipFree; the meshes and every input and output array are the caller's as
+   for alp_step_batched.  It synchronises the context stream at the end to
+   read the overflow flags.
+     ALP_ERR_CAPACITY  the step's fixed lists do not fit (checked before any
+                       launch), or its window or pair lists overflowed the
+                       rest of the array (results of that step invalid)
+   Every call on one device shares that device's array, which keeps the last
+   call's contents: calls that overlap on one device (several contexts or
+   threads) race.  alp_get_diag reads this step's diagnostics from it, so it
+   must come before another call on the same device. */
+alp_status alp_step_noalloc(alp_context *ctx, int32_t n_cases, const alp_case *cases);
+
 /* Diagnostics of case `case_index` of the last step (or of the last
    alp_sample / alp_spread pair, index 0).  Synchronous. */
 alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out);

@@ -27,7 +27,7 @@ USE_GRAPH, CHECKED = 1, 2
 EXPORTS = ("alp_create", "alp_destroy", "alp_last_error", "alp_bin_cells", "alp_mesh_destroy",
            "alp_sample", "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag",
            "alp_invalidate", "alp_version", "alp_step_profile", "alp_stage_name", "alp_autotune",
-           "alp_beam_geometry")
+           "alp_beam_geometry", "alp_step_noalloc")
 
 
 class AlpError(RuntimeError):
@@ -101,6 +101,7 @@ def load():
     lib.alp_drag.argtypes = [vp, ct.POINTER(alp_beams), ct.POINTER(alp_params), vp, vp, vp, vp]
     lib.alp_spread.argtypes = [vp, vp, ct.POINTER(alp_beams), ct.POINTER(alp_params), vp, vp, vp, vp]
     lib.alp_step_batched.argtypes = [vp, i32, ct.POINTER(alp_case), u32]
+    lib.alp_step_noalloc.argtypes = [vp, i32, ct.POINTER(alp_case)]
     lib.alp_get_diag.argtypes = [vp, i32, ct.POINTER(alp_diag)]
     lib.alp_invalidate.argtypes = [vp]
     lib.alp_version.restype = ct.c_char_p
@@ -115,7 +116,8 @@ def load():
     lib.alp_stage_name.argtypes = [i32]
     lib.alp_stage_name.restype = ct.c_char_p
     for name in ("alp_create", "alp_destroy", "alp_bin_cells", "alp_mesh_destroy", "alp_sample",
-                 "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag", "alp_invalidate"):
+                 "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag", "alp_invalidate",
+                 "alp_step_noalloc"):
         getattr(lib, name).restype = ct.c_int
     _lib = lib
     return lib
@@ -183,6 +185,11 @@ def alp_spread(ctx, mesh, beams: alp_beams, params: alp_params, f, S, w=None, fh
 def alp_step_batched(ctx, cases, flags=0):
     arr = (alp_case * len(cases))(*cases)
     _check(ctx, load().alp_step_batched(ctx, len(cases), arr, int(flags)))
+
+
+def alp_step_noalloc(ctx, cases):
+    arr = (alp_case * len(cases))(*cases)
+    _check(ctx, load().alp_step_noalloc(ctx, len(cases), arr))
 
 
 def alp_get_diag(ctx, case_index=0):

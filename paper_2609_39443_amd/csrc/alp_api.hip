@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "alp_internal.h"
@@ -60,9 +61,45 @@ struct alp_context {
   std::vector<alp_case> gkey;
   uint32_t gflags = 0;
   int last_cases = 0;
+  // where the last step left its counters and diagnostics (the workspace of
+  // the allocation-free entry point lives in the device scratch array)
+  const long long *dg_cnt = nullptr;
+  const double *dg_out = nullptr;
+  const uint32_t *dg_counters = nullptr;
+  unsigned char *scratch = nullptr;  // this device's scratch array (device address)
   int any_kernel_sample = 0;  // some case of the uploaded batch samples with the kernel
   int any_proj[4] = {0, 0, 0, 0};  // the uploaded batch has cases of each (rule, precision)
 };
+
+// Workspace of alp_step_noalloc: every per-step list, the case table and
+// the scan temporaries of a step, carved from one static device array.  Each
+// device the library runs on holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in: its device address comes
+// from hipGetSymbolAddress, once per device with that device current, and
+// only that address is ever passed to a kernel or a copy.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of this device's scratch array (the device must be current)
+hipError_t scratch_address(int device, unsigned char **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = (unsigned char *)p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -383,14 +420,20 @@ StepShape shape_cases(alp_context *ctx, std::vector<CaseDev> &cs) {
   return sh;
 }
 
-alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const StepShape &sh) {
-  alp_status rc;
+// which optional kernels the batch needs (sampling rule, projection rule and
+// precision of each case)
+void upload_flags(alp_context *ctx, const std::vector<CaseDev> &cs) {
   ctx->any_kernel_sample = 0;
   ctx->any_proj[0] = ctx->any_proj[1] = ctx->any_proj[2] = ctx->any_proj[3] = 0;
   for (const CaseDev &c : cs) {
     if (c.sample_mode == ALP_SAMPLE_KERNEL) ctx->any_kernel_sample = 1;
     ctx->any_proj[(c.proj_mode == ALP_PROJ_INTEGRATED ? 2 : 0) + (c.prec == ALP_PREC_FP32_SPLIT ? 0 : 1)] = 1;
   }
+}
+
+alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const StepShape &sh) {
+  alp_status rc;
+  upload_flags(ctx, cs);
   if ((rc = ensure_cases(ctx, (int)cs.size())) != ALP_OK) return rc;
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_cases, cs.data(), cs.size() * sizeof(CaseDev),
                              hipMemcpyHostToDevice, ctx->st));
@@ -417,13 +460,14 @@ int sample_waves_beside(int64_t n_points, int n_cu) {
   return n_points <= 16 * pass4 ? 4 : 8;
 }
 
-StepLaunch make_launch(alp_context *ctx, int n_cases) {
+StepLaunch make_launch_from(alp_context *ctx, const Work &w, const CaseDev *d_cases, const int64_t *d_bases,
+                            int n_cases) {
   StepLaunch L;
-  L.cases = ctx->d_cases;
-  L.pbase = ctx->d_bases;
-  L.bbase = ctx->d_bases + (n_cases + 1);
-  L.tbase = ctx->d_bases + 2 * (n_cases + 1);
-  L.w = ctx->w;
+  L.cases = d_cases;
+  L.pbase = d_bases;
+  L.bbase = d_bases + (n_cases + 1);
+  L.tbase = d_bases + 2 * (n_cases + 1);
+  L.w = w;
   L.n_cases = n_cases;
   L.grid_persistent = ctx->n_cu * 8;
   L.grid_spread = ctx->n_cu * ctx->spread_per_cu;
@@ -434,6 +478,10 @@ StepLaunch make_launch(alp_context *ctx, int n_cases) {
   L.int_split = ctx->any_proj[2];
   L.int_fp64 = ctx->any_proj[3];
   return L;
+}
+
+StepLaunch make_launch(alp_context *ctx, int n_cases) {
+  return make_launch_from(ctx, ctx->w, ctx->d_cases, ctx->d_bases, n_cases);
 }
 
 enum { ST_SAMPLE = 1, ST_DRAG = 2, ST_PROJECT = 4, ST_ALL = 7 };
@@ -573,6 +621,118 @@ alp_status run_checked(alp_context *ctx, std::vector<CaseDev> &cs, int stages,
   return fail(ctx, ALP_ERR_CAPACITY, "work lists kept overflowing");
 }
 
+// Validate a batch and fill its device case table (host copy), the meshes and
+// the source arrays, in case order.
+alp_status build_batch(alp_context *ctx, int32_t n_cases, const alp_case *cases, std::vector<CaseDev> &cs,
+                       std::vector<alp_mesh *> &meshes, std::vector<double *> &S) {
+  alp_status rc;
+  cs.assign((size_t)n_cases, CaseDev{});
+  meshes.assign((size_t)n_cases, nullptr);
+  S.assign((size_t)n_cases, nullptr);
+  for (int i = 0; i < n_cases; ++i) {
+    const alp_case &c = cases[i];
+    if (!c.mesh || !c.U || !c.f || !c.S)
+      return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: mesh, U, f and S are required", i);
+    for (int j = 0; j < i; ++j)
+      if (cases[j].mesh == c.mesh)
+        return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: a mesh may appear in one case per batch", i);
+    if ((rc = check_beams(ctx, &c.beams, true, true, true)) != ALP_OK) return rc;
+    if ((rc = check_params(ctx, &c.params, c.f_prev != nullptr)) != ALP_OK) return rc;
+    alp_mesh *m = const_cast<alp_mesh *>(c.mesh);
+    fill_case(cs[i], m, &c.beams, &c.params);
+    cs[i].U = c.U;
+    cs[i].f_prev = c.f_prev;
+    cs[i].has_fprev = c.f_prev != nullptr;
+    cs[i].f = c.f;
+    cs[i].S = c.S;
+    cs[i].U_s = c.U_s;
+    cs[i].w = c.w;
+    cs[i].P_s = c.P_s;
+    cs[i].cell_a = c.cell_a;
+    cs[i].cell_s = c.cell_s;
+    cs[i].dUdt = c.dUdt;
+    cs[i].write_S = 1;
+    meshes[i] = m;
+    S[i] = c.S;
+  }
+  return ALP_OK;
+}
+
+
+// Carves 256-byte aligned arrays out of the scratch array, front to back.
+struct Carver {
+  unsigned char *base;
+  size_t size, off = 0;
+  bool ok = true;
+  template <typename T>
+  T *take(int64_t n) {
+    const size_t bytes = (size_t)(n > 0 ? n : 1) * sizeof(T);
+    const size_t o = (off + 255) & ~(size_t)255;
+    if (o + bytes > size) {
+      ok = false;
+      return nullptr;
+    }
+    off = o + bytes;
+    return reinterpret_cast<T *>(base + o);
+  }
+};
+
+// The fixed part of a step's workspace (every list whose length the host
+// knows), the case table and the scan temporaries, carved in that order.
+// Returns false if they do not fit.
+bool carve_fixed(Carver &cv, Work &w, const StepShape &sh, CaseDev **d_cases, int64_t **d_bases) {
+  const int64_t P = sh.n_points, B = sh.n_beams, T = sh.n_tiles, NC = sh.n_cases, PB = sh.n_pblocks;
+  const int64_t IT = sh.cap_item, CH = sh.cap_chunk;
+  std::memset(&w, 0, sizeof(w));
+  w.counters = cv.take<uint32_t>(kCounters);
+  w.cnt = cv.take<long long>(8 * NC);
+  w.diag_out = cv.take<double>(16 * NC);
+  w.pbeam = cv.take<int32_t>(P);
+  w.pflags = cv.take<int32_t>(P);
+  w.wexp = cv.take<int32_t>(P);
+  w.w_hi = cv.take<long long>(P);
+  w.w_lo = cv.take<unsigned long long>(P);
+  w.fhat = cv.take<double>(3 * P);
+  w.Us = cv.take<double>(3 * P);
+  w.Ps = cv.take<double>(3 * P);
+  w.As = cv.take<double>(3 * P);
+  w.f = cv.take<double>(3 * P);
+  w.bcase = cv.take<int32_t>(B);
+  w.beps_max = cv.take<double>(B);
+  w.bchunks = cv.take<uint32_t>(B + 1);
+  w.chunk_beam = cv.take<int32_t>(CH);
+  w.chunk_s0 = cv.take<int32_t>(CH);
+  w.chunk_s1 = cv.take<int32_t>(CH);
+  w.chunk_box = cv.take<uint32_t>(CH + 1);
+  w.chunk_bx = cv.take<int32_t>(6 * CH);
+  w.tile_cnt = cv.take<uint32_t>(T + 1);
+  w.tile_off = cv.take<uint32_t>(T + 1);
+  w.tile_fill = cv.take<uint32_t>(T + 1);
+  w.tile_nent = cv.take<uint32_t>(T + 1);
+  w.tile_items = cv.take<uint32_t>(T + 1);
+  w.tile_itoff = cv.take<uint32_t>(T + 1);
+  w.item = cv.take<Item>(IT);
+  w.rec_base = cv.take<unsigned long long>(IT);
+  w.rec_cnt = cv.take<uint32_t>(IT);
+  w.rec_alloc = cv.take<unsigned long long>(1);
+  w.F_hi = cv.take<long long>(3 * NC);
+  w.F_lo = cv.take<unsigned long long>(3 * NC);
+  w.F_exp = cv.take<int32_t>(NC);
+  w.beam_part = cv.take<double>(4 * PB);
+  w.pblock_case = cv.take<int32_t>(PB);
+  w.pblock_range = cv.take<int64_t>(2 * PB);
+  w.scan_tmp = cv.take<uint32_t>(scan_tmp_words(std::max({B + 1, T + 1, CH + 1, (int64_t)1})));
+  *d_cases = cv.take<CaseDev>(NC);
+  *d_bases = cv.take<int64_t>(3 * (NC + 1));
+  w.cap_item = IT;
+  w.cap_chunk = CH;
+  w.n_points = P;
+  w.n_beams = B;
+  w.n_tiles = T;
+  w.n_cases = (int32_t)NC;
+  w.n_pblocks = PB;
+  return cv.ok;
+}
 }  // namespace
 
 // ================================================================= C ABI ==
@@ -603,6 +763,10 @@ alp_status alp_create(int device, void *hip_stream, alp_context **out) {
     return ALP_ERR_HIP;
   }
   *ctx->h_ovf = 0u;
+  if (scratch_address(device, &ctx->scratch) != hipSuccess) {
+    alp_destroy(ctx);
+    return ALP_ERR_HIP;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->n_cu = prop.multiProcessorCount;
@@ -802,6 +966,9 @@ alp_status alp_sample(alp_context *ctx, const alp_mesh *mesh, const double *U,
   cs[0].tile_prev = nullptr;
   if ((rc = run_checked(ctx, cs, ST_SAMPLE, {}, {})) != ALP_OK) return rc;
   ctx->last_cases = 1;
+  ctx->dg_cnt = nullptr;
+  ctx->dg_out = nullptr;
+  ctx->dg_counters = nullptr;
   return leave(ctx);
 }
 
@@ -855,6 +1022,9 @@ alp_status alp_spread(alp_context *ctx, const alp_mesh *mesh, const alp_beams *b
   cs[0].write_S = 1;
   if ((rc = run_checked(ctx, cs, ST_PROJECT, {m}, {S})) != ALP_OK) return rc;
   ctx->last_cases = 1;
+  ctx->dg_cnt = nullptr;
+  ctx->dg_out = nullptr;
+  ctx->dg_counters = nullptr;
   return leave(ctx);
 }
 
@@ -894,41 +1064,22 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
       if (ovf) return fail(ctx, ALP_ERR_CAPACITY, "work list overflow in graph replay (0x%x); call alp_invalidate", ovf);
     }
     ctx->last_cases = n_cases;
+    ctx->dg_cnt = nullptr;
+    ctx->dg_out = nullptr;
+    ctx->dg_counters = nullptr;
     return leave(ctx);
   }
-  std::vector<CaseDev> cs((size_t)n_cases);
-  std::vector<alp_mesh *> meshes((size_t)n_cases);
-  std::vector<double *> S((size_t)n_cases);
-  for (int i = 0; i < n_cases; ++i) {
-    const alp_case &c = cases[i];
-    if (!c.mesh || !c.U || !c.f || !c.S)
-      return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: mesh, U, f and S are required", i);
-    for (int j = 0; j < i; ++j)
-      if (cases[j].mesh == c.mesh)
-        return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: a mesh may appear in one case per batch", i);
-    if ((rc = check_beams(ctx, &c.beams, true, true, true)) != ALP_OK) return rc;
-    if ((rc = check_params(ctx, &c.params, c.f_prev != nullptr)) != ALP_OK) return rc;
-    alp_mesh *m = const_cast<alp_mesh *>(c.mesh);
-    fill_case(cs[i], m, &c.beams, &c.params);
-    cs[i].U = c.U;
-    cs[i].f_prev = c.f_prev;
-    cs[i].has_fprev = c.f_prev != nullptr;
-    cs[i].f = c.f;
-    cs[i].S = c.S;
-    cs[i].U_s = c.U_s;
-    cs[i].w = c.w;
-    cs[i].P_s = c.P_s;
-    cs[i].cell_a = c.cell_a;
-    cs[i].cell_s = c.cell_s;
-    cs[i].dUdt = c.dUdt;
-    cs[i].write_S = 1;
-    meshes[i] = m;
-    S[i] = c.S;
-  }
+  std::vector<CaseDev> cs;
+  std::vector<alp_mesh *> meshes;
+  std::vector<double *> S;
+  if ((rc = build_batch(ctx, n_cases, cases, cs, meshes, S)) != ALP_OK) return rc;
   if ((rc = enter(ctx)) != ALP_OK) return rc;
   // size the work lists with a checked run (this also produces this step's result)
   if ((rc = run_checked(ctx, cs, ST_ALL, meshes, S)) != ALP_OK) return rc;
   ctx->last_cases = n_cases;
+  ctx->dg_cnt = nullptr;
+  ctx->dg_out = nullptr;
+  ctx->dg_counters = nullptr;
   if (use_graph) {
     drop_graph(ctx);
     HIPCHK(ctx, hipStreamSynchronize(ctx->st));
@@ -947,6 +1098,82 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
     }
     ctx->gkey.assign(cases, cases + n_cases);
     ctx->gflags = flags;
+  }
+  return leave(ctx);
+}
+
+alp_status alp_step_noalloc(alp_context *ctx, int32_t n_cases, const alp_case *cases) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (n_cases < 1 || !cases) return fail(ctx, ALP_ERR_INVALID_ARG, "need n_cases >= 1 and cases");
+  if (!ctx->scratch) return fail(ctx, ALP_ERR_HIP, "no scratch array on device %d", ctx->device);
+  alp_status rc;
+  std::vector<CaseDev> cs;
+  std::vector<alp_mesh *> meshes;
+  std::vector<double *> S;
+  if ((rc = build_batch(ctx, n_cases, cases, cs, meshes, S)) != ALP_OK) return rc;
+  StepShape sh = shape_cases(ctx, cs);
+  // the fixed part first, then the window lists, then the pair records
+  Carver cv{ctx->scratch, kScratchBytes};
+  Work w;
+  CaseDev *d_cases = nullptr;
+  int64_t *d_bases = nullptr;
+  if (!carve_fixed(cv, w, sh, &d_cases, &d_bases))
+    return fail(ctx, ALP_ERR_CAPACITY,
+                "the step needs %zu bytes of fixed workspace (%lld points, %lld beams, %lld tiles); the "
+                "allocation-free entry point holds %zu",
+                cv.off, (long long)sh.n_points, (long long)sh.n_beams, (long long)sh.n_tiles,
+                (size_t)kScratchBytes);
+  const size_t left = cv.size - ((cv.off + 255) & ~(size_t)255);
+  // windows: three 16-byte lists per slot, up to 16 per point plus a margin,
+  // and at most half of what is left; the pair records take the rest
+  int64_t em = std::min<int64_t>(16 * sh.n_points + 4096, (int64_t)(left / 2 / 48));
+  w.emit_raw = cv.take<Emit>(em);
+  w.emit = cv.take<Win>(em);
+  w.entry = cv.take<Entry>(em);
+  const size_t rec_off = (cv.off + 255) & ~(size_t)255;
+  const int64_t rc_bytes = cv.ok && rec_off < cv.size ? (int64_t)((cv.size - rec_off) & ~(size_t)255) : 0;
+  w.rec = cv.take<unsigned char>(rc_bytes);
+  if (!cv.ok || em <= 0 || rc_bytes <= 0)
+    return fail(ctx, ALP_ERR_CAPACITY, "no room left for the window and pair lists in %zu bytes",
+                (size_t)kScratchBytes);
+  w.cap_emit = em;
+  w.cap_rec = rc_bytes;
+  if ((rc = enter(ctx)) != ALP_OK) return rc;
+  // case table, bases and point blocks (from host arrays the context keeps);
+  // the transfers complete before the host arrays can change
+  upload_flags(ctx, cs);
+  HIPCHK(ctx, hipMemcpyAsync(d_cases, cs.data(), cs.size() * sizeof(CaseDev), hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(d_bases, ctx->h_bases.data(), ctx->h_bases.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, ctx->st));
+  if (sh.n_pblocks > 0) {
+    HIPCHK(ctx, hipMemcpyAsync(w.pblock_case, ctx->h_pbcase.data(), ctx->h_pbcase.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(ctx, hipMemcpyAsync(w.pblock_range, ctx->h_pbrange.data(), ctx->h_pbrange.size() * sizeof(int64_t),
+                               hipMemcpyHostToDevice, ctx->st));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  if ((rc = prepare_outputs(ctx, meshes, S)) != ALP_OK) return rc;
+  StepLaunch L = make_launch_from(ctx, w, d_cases, d_bases, n_cases);
+  // the step's reset kernel clears the counters, accumulators and tile
+  // counts that must start at zero (the array keeps the last call's contents)
+  launch_sequence(ctx, L, ST_ALL);
+  HIPCHK(ctx, hipGetLastError());
+  uint32_t ovf = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&ovf, w.counters + 3, sizeof(ovf), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  ctx->last_cases = n_cases;
+  ctx->dg_cnt = w.cnt;
+  ctx->dg_out = w.diag_out;
+  ctx->dg_counters = w.counters;
+  if (ovf) {
+    // the band state of the meshes no longer matches their source arrays
+    for (alp_mesh *m : meshes)
+      if (m) m->last_S = nullptr;
+    return fail(ctx, ALP_ERR_CAPACITY,
+                "the step's window or pair lists exceed the allocation-free workspace (flags 0x%x, %lld "
+                "window slots, %lld record bytes); use alp_step_batched",
+                ovf, (long long)w.cap_emit, (long long)w.cap_rec);
   }
   return leave(ctx);
 }
@@ -1085,15 +1312,18 @@ alp_status alp_step_profile(alp_context *ctx, int32_t n_cases, const alp_case *c
 
 alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out) {
   if (!ctx || !out) return fail(ctx, ALP_ERR_INVALID_ARG, "NULL argument");
-  if (case_index < 0 || case_index >= ctx->last_cases || !ctx->w.cnt)
+  if (case_index < 0 || case_index >= ctx->last_cases || (!ctx->w.cnt && !ctx->dg_cnt))
     return fail(ctx, ALP_ERR_INVALID_ARG, "no diagnostics for case %d", case_index);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   long long cnt[8];
   double d[16];
   uint32_t counters[16];
-  HIPCHK(ctx, hipMemcpyAsync(cnt, ctx->w.cnt + 8 * case_index, sizeof(cnt), hipMemcpyDeviceToHost, ctx->st));
-  HIPCHK(ctx, hipMemcpyAsync(d, ctx->w.diag_out + 16 * case_index, sizeof(d), hipMemcpyDeviceToHost, ctx->st));
-  HIPCHK(ctx, hipMemcpyAsync(counters, ctx->w.counters, sizeof(counters), hipMemcpyDeviceToHost, ctx->st));
+  const long long *src_cnt = ctx->dg_cnt ? ctx->dg_cnt : ctx->w.cnt;
+  const double *src_out = ctx->dg_out ? ctx->dg_out : ctx->w.diag_out;
+  const uint32_t *src_ctr = ctx->dg_counters ? ctx->dg_counters : ctx->w.counters;
+  HIPCHK(ctx, hipMemcpyAsync(cnt, src_cnt + 8 * case_index, sizeof(cnt), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(d, src_out + 16 * case_index, sizeof(d), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(counters, src_ctr, sizeof(counters), hipMemcpyDeviceToHost, ctx->st));
   HIPCHK(ctx, hipStreamSynchronize(ctx->st));
   std::memset(out, 0, sizeof(*out));
   out->n_outside = cnt[0];
