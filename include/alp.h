@@ -165,6 +165,9 @@ typedef struct {
   double F_fluid[3];  /* sum_j S_j V_j  (force on the fluid, eq. 14) */
   double cons_rel_err; /* |F_fluid + F_beam| / sum_k |f_k L_k| */
   int64_t n_sample_empty; /* ALP_SAMPLE_KERNEL points with no cell within 3 eps of P_s */
+  int64_t n_guard_fp64;   /* (cell, beam) candidates whose closest segment the FP32 ranking
+                             could not single out within its proven error bound, so that more
+                             than one segment was evaluated in FP64 (nearest-segment rule) */
 } alp_diag;
 
 /* Create a context on HIP device `device` that launches on `hip_stream`

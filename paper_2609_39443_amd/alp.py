@@ -56,7 +56,8 @@ class alp_diag(ct.Structure):
                 ("n_fallback_degenerate", ct.c_int64), ("n_zero_weight", ct.c_int64),
                 ("n_band_cells", ct.c_int64), ("n_pairs", ct.c_int64), ("n_overflow", ct.c_int64),
                 ("n_invalid", ct.c_int64), ("F_beam", ct.c_double * 3), ("F_fluid", ct.c_double * 3),
-                ("cons_rel_err", ct.c_double), ("n_sample_empty", ct.c_int64)]
+                ("cons_rel_err", ct.c_double), ("n_sample_empty", ct.c_int64),
+                ("n_guard_fp64", ct.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("F_beam", "F_fluid")}

@@ -248,7 +248,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(beam_part, 4 * PB);
   WALLOC(pblock_case, PB);
   WALLOC(pblock_range, 2 * PB);
-  WALLOC(cnt, 8 * NC);
+  WALLOC(cnt, kCnt * NC);
   WALLOC(diag_out, 16 * NC);
   WALLOC(counters, kCounters);
 #undef WALLOC
@@ -257,7 +257,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   ctx->have_scan = sc;
   w.scan_tmp = ctx->scan_tmp;
   HIPCHK(ctx, hipMemsetAsync(w.counters, 0, kCounters * sizeof(uint32_t), ctx->st));
-  HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, 8 * NC * sizeof(long long), ctx->st));
+  HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, kCnt * NC * sizeof(long long), ctx->st));
   HIPCHK(ctx, hipMemsetAsync(w.diag_out, 0, 16 * NC * sizeof(double), ctx->st));
   w.cap_emit = EM;
   w.cap_item = IT;
@@ -685,7 +685,7 @@ bool carve_fixed(Carver &cv, Work &w, const StepShape &sh, CaseDev **d_cases, in
   const int64_t IT = sh.cap_item, CH = sh.cap_chunk;
   std::memset(&w, 0, sizeof(w));
   w.counters = cv.take<uint32_t>(kCounters);
-  w.cnt = cv.take<long long>(8 * NC);
+  w.cnt = cv.take<long long>(kCnt * NC);
   w.diag_out = cv.take<double>(16 * NC);
   w.pbeam = cv.take<int32_t>(P);
   w.pflags = cv.take<int32_t>(P);
@@ -1315,13 +1315,13 @@ alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out) {
   if (case_index < 0 || case_index >= ctx->last_cases || (!ctx->w.cnt && !ctx->dg_cnt))
     return fail(ctx, ALP_ERR_INVALID_ARG, "no diagnostics for case %d", case_index);
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  long long cnt[8];
+  long long cnt[kCnt];
   double d[16];
   uint32_t counters[16];
   const long long *src_cnt = ctx->dg_cnt ? ctx->dg_cnt : ctx->w.cnt;
   const double *src_out = ctx->dg_out ? ctx->dg_out : ctx->w.diag_out;
   const uint32_t *src_ctr = ctx->dg_counters ? ctx->dg_counters : ctx->w.counters;
-  HIPCHK(ctx, hipMemcpyAsync(cnt, src_cnt + 8 * case_index, sizeof(cnt), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(cnt, src_cnt + kCnt * case_index, sizeof(cnt), hipMemcpyDeviceToHost, ctx->st));
   HIPCHK(ctx, hipMemcpyAsync(d, src_out + 16 * case_index, sizeof(d), hipMemcpyDeviceToHost, ctx->st));
   HIPCHK(ctx, hipMemcpyAsync(counters, src_ctr, sizeof(counters), hipMemcpyDeviceToHost, ctx->st));
   HIPCHK(ctx, hipStreamSynchronize(ctx->st));
@@ -1340,6 +1340,7 @@ alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out) {
   }
   out->cons_rel_err = d[7];
   out->n_sample_empty = cnt[7];
+  out->n_guard_fp64 = cnt[8];
   return ALP_OK;
 }
 

@@ -24,6 +24,7 @@ constexpr int kHiShift = 46;        // fixed-point: hi word holds v * 2^(46-E)
 constexpr int kLoBits = 40;         // lo word holds the next 40 bits
 constexpr int kSampleLanes = 4;  // lanes per actuator point in the sampler
 constexpr unsigned long long kRecBlock = 64ull << 10;  // pair-record bytes a wave reserves at once
+constexpr int kCnt = 16;            // per-case counters (see Work::cnt)
 
 // Binned mesh, device view (built by alp_bin_cells).
 struct MeshDev {
@@ -152,7 +153,8 @@ struct Work {
   double *beam_part;    // [n_pblocks][4] (F_beam xyz, sum |f L|)
   int32_t *pblock_case; // [n_pblocks]
   int64_t *pblock_range;// [n_pblocks][2]
-  long long *cnt;       // [n_cases][8] counters: outside, fallback, degenerate, zero w, band, pairs, invalid, empty kernel sample
+  long long *cnt;       // [n_cases][kCnt] counters: outside, fallback, degenerate, zero w, band, pairs,
+                        // invalid, empty kernel sample, FP64 guard
   double *diag_out;     // [n_cases][16] finalised diagnostics
   // scalars
   uint32_t *counters;   // [kCounters]: [3] overflow flags; from queue_words(q) the weights work
@@ -372,6 +374,17 @@ __device__ __host__ inline double fx_decode(long long hi, unsigned long long lo,
   hi += (long long)(lo >> kLoBits);
   lo &= ((1ull << kLoBits) - 1ull);
   return ldexp((double)hi, E - kHiShift) + ldexp((double)lo, E - kHiShift - kLoBits);
+}
+
+// Centre of tile (tx, ty, tz): (lo + t tile_len) + tile_len / 2 per axis, in
+// this one evaluation order (no contraction), so that every kernel that
+// forms coordinates relative to it gets the same FP64 value.
+__device__ __host__ inline void tile_centre(const MeshDev &m, int tx, int ty, int tz, double *c) {
+#pragma clang fp contract(off)
+  const double h = 0.5 * m.tile_len;
+  c[0] = (m.lo[0] + (double)tx * m.tile_len) + h;
+  c[1] = (m.lo[1] + (double)ty * m.tile_len) + h;
+  c[2] = (m.lo[2] + (double)tz * m.tile_len) + h;
 }
 
 // bin key: tiles in x-fastest order, then bins inside the tile x-fastest

@@ -99,17 +99,14 @@ __device__ __forceinline__ WorkQueue work_queue(uint32_t *ctr, uint32_t n, uint3
   return q;
 }
 
-__device__ __forceinline__ void tile_origin(const MeshDev &m, int64_t tl, double &ox, double &oy,
-                                            double &oz) {
+// tile (tx, ty, tz) of a case-local linear tile index
+__device__ __forceinline__ void tile_xyz(const MeshDev &m, int64_t tl, int &tx, int &ty, int &tz) {
   // tile counts are below 2^32 (bin keys are 32-bit)
   const uint32_t t = (uint32_t)tl, nx = (uint32_t)m.nt[0], ny = (uint32_t)m.nt[1];
   const uint32_t r = t / nx;
-  const int tx = (int)(t - r * nx);
-  const int tz = (int)(r / ny);
-  const int ty = (int)(r - (uint32_t)tz * ny);
-  ox = m.lo[0] + (double)tx * m.tile_len;
-  oy = m.lo[1] + (double)ty * m.tile_len;
-  oz = m.lo[2] + (double)tz * m.tile_len;
+  tx = (int)(t - r * nx);
+  tz = (int)(r / ny);
+  ty = (int)(r - (uint32_t)tz * ny);
 }
 
 __device__ __forceinline__ uint32_t tile_cell_start(const MeshDev &m, int64_t tl) {
@@ -125,8 +122,8 @@ __global__ void k_step_reset(StepLaunch L, int what) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (tid < kCounters && (what & RESET_PROJECT)) W.counters[tid] = 0;
   if (tid == 0 && (what & RESET_PROJECT)) *W.rec_alloc = 0;
-  for (int64_t c = tid; c < (int64_t)L.n_cases * 8; c += stride) {
-    int k = (int)(c & 7);
+  for (int64_t c = tid; c < (int64_t)L.n_cases * kCnt; c += stride) {
+    int k = (int)(c % kCnt);
     bool samp = k < 3 || k == 7;
     if ((samp && (what & RESET_SAMPLE)) || (!samp && (what & RESET_PROJECT))) W.cnt[c] = 0;
   }
@@ -182,7 +179,7 @@ __global__ void k_points_prep(StepLaunch L) {
   const double *et = cs.e_t + 3 * k;
   double tt = et[0] * et[0] + et[1] * et[1] + et[2] * et[2];
   if (!(cs.eps[k] > 0.0 && cs.eps[k] < INFINITY) || !(tt > 0.0 && tt < INFINITY))
-    atomicAdd((unsigned long long *)(W.cnt + 8 * c + 6), 1ull);
+    atomicAdd((unsigned long long *)(W.cnt + kCnt * c + 6), 1ull);
 }
 
 void launch_points_prep(const StepLaunch &L, hipStream_t st) {
@@ -992,12 +989,12 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
   int c0 = __shfl(c, 0, 64);
   bool same = __all(!act || c == c0);
   if (same) {
-    long long *cnt = W.cnt + 8 * c0;
+    long long *cnt = W.cnt + kCnt * c0;
     wave_count_add(cnt + 0, lead && out);
     wave_count_add(cnt + 1, lead && fb);
     wave_count_add(cnt + 2, lead && dg);
   } else if (lead) {
-    long long *cnt = W.cnt + 8 * c;
+    long long *cnt = W.cnt + kCnt * c;
     if (out) atomicAdd((unsigned long long *)(cnt + 0), 1ull);
     if (fb) atomicAdd((unsigned long long *)(cnt + 1), 1ull);
     if (dg) atomicAdd((unsigned long long *)(cnt + 2), 1ull);
@@ -1213,7 +1210,7 @@ __global__ __launch_bounds__(64) void k_sample_kernel(StepLaunch L) {
         if (cs.U_s)
           for (int a = 0; a < 3; ++a) cs.U_s[3 * k + a] = us[a];
       } else {
-        atomicAdd((unsigned long long *)(W.cnt + 8 * c + 7), 1ull);
+        atomicAdd((unsigned long long *)(W.cnt + kCnt * c + 7), 1ull);
       }
     }
   }
@@ -1470,7 +1467,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   // record space is reserved in blocks per wave; pair counts are flushed per case
   unsigned long long blk_cur = 0, blk_end = 0;
   int acc_case = -1;
-  unsigned long long acc_pairs = 0;
+  unsigned long long acc_pairs = 0, acc_guard = 0;
   WorkQueue wq = work_queue(W.counters + queue_words(kInt ? (kSplit ? 1 : 2) : (kSplit ? 0 : 3)),
                             (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
   while (wq.next(lane)) {
@@ -1482,9 +1479,12 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     if ((L.cases[it.cs].prec == ALP_PREC_FP32_SPLIT) != kSplit) continue;
     if (it.cs != acc_case) {
       if (lane == 0 && acc_case >= 0 && acc_pairs)
-        atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
+        atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 5), acc_pairs);
+      if (lane == 0 && acc_case >= 0 && acc_guard)
+        atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 8), acc_guard);
       acc_case = it.cs;
       acc_pairs = 0;
+      acc_guard = 0;
     }
     const CaseDev &cs = L.cases[it.cs];
     const MeshDev &m = cs.m;
@@ -1496,16 +1496,27 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     const int64_t tl = it.tile - cs.tile_base;
     const int rsz = rec_size(cs.prec);
     const uint32_t ne = it.nent;  // <= kMaxEntries (the tile merge drops larger tiles)
-    // cells of the item
+    // cells of the item, and their FP32 coordinates relative to the tile centre
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
     double cx = 0, cy = 0, cz = 0, v = 0;
+    float lx = 0.f, ly = 0.f, lz = 0.f;
+    int tx, ty, tz;
+    tile_xyz(m, tl, tx, ty, tz);
+    double tcen[3];
+    tile_centre(m, tx, ty, tz, tcen);
+    const double ctx = tcen[0], cty = tcen[1], ctz = tcen[2];
+    const double hl = 0.5 * m.tile_len;
     if (valid) {
       cx = to_global(m.cx)[c];
       cy = to_global(m.cy)[c];
       cz = to_global(m.cz)[c];
       v = to_global(m.vs)[c];
+      lx = (float)(cx - ctx);
+      ly = (float)(cy - cty);
+      lz = (float)(cz - ctz);
     }
+
     // 1. entries and the staging plan: the leading entries whose windows fit
     uint32_t carry = 0;
     int nst = 0;
@@ -1534,10 +1545,6 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       const int last = nst - 1;
       npts = sh.e_pt0[last] + (sh.e_i1[last] < 0 ? 1 : sh.e_i1[last] - sh.e_i0[last] + 2);
     }
-    double ox, oy, oz;
-    tile_origin(m, tl, ox, oy, oz);
-    const double hl = 0.5 * m.tile_len;
-    const double ctx = ox + hl, cty = oy + hl, ctz = oz + hl;
     for (int q = lane; q < npts; q += 64) {
       const int e = entry_of_point(sh, n_staged, q);
       const int64_t k = sh.e_k0[e] + (sh.e_i1[e] < 0 ? 0 : sh.e_i0[e]) + (q - sh.e_pt0[e]);
@@ -1646,7 +1653,6 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     }
     __syncthreads();
     // 2. screening
-    const float lx = (float)(cx - ctx), ly = (float)(cy - cty), lz = (float)(cz - ctz);
     uint32_t cnt = 0;
     uint32_t mw[kMaskWords];
 #pragma unroll
@@ -1924,15 +1930,16 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         const bool act = p < total;
         int Lc = lane, e = 0;
         if (act) cand_of(p, Lc, e);
+        // the candidate's cell, from the lane that holds it
         const double pcx = __shfl(cx, Lc, 64), pcy = __shfl(cy, Lc, 64), pcz = __shfl(cz, Lc, 64);
         const double pv = __shfl(v, Lc, 64);
-        bool in = false;
+        bool in = false, guard = false;
         int bi = 0, single = 0;
         double a0 = 0.0, a1 = 0.0;
         if (act) {
           const int pt0 = (int)e < n_staged ? sh.e_pt0[e] : -1;
           const int k0 = sh.e_k0[e], i0 = sh.e_i0[e], i1 = sh.e_i1[e];
-          double bs = 0.0, br2 = INFINITY, ej;
+          double bs = 0.0, br2 = INFINITY, ej = 1.0;
           int bj = 0;
           if (i1 < 0) {
             single = 1;
@@ -1972,14 +1979,18 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               const float dl = b1 * 0x1p-14f + sh.e_dabs[e];
               const float band = (b1 + 2.0f * dl) * (1.0f + 0x1p-20f);
               full = k3 != ~0u && __uint_as_float(k3 & ~kSegIdxMask) <= band;
+              guard = full;
               if (!full) {
-                // the node widths of the one or two re-checked segments are
-                // loaded with their end points, not after the choice
-                const gptr<double> E = Eps + (int64_t)k0 + i0;
+                // the one or two segments in the band are evaluated exactly;
+                // their node widths are loaded with their end points, not
+                // after the choice
                 const int j1 = (int)(k1 & kSegIdxMask);
+                const bool two = k2 != ~0u && __uint_as_float(k2 & ~kSegIdxMask) <= band;
+                guard = two;
+                const gptr<double> E = Eps + (int64_t)k0 + i0;
                 double e0 = E[j1], e1 = E[j1 + 1];
                 exact_scan(X, j1, j1, pcx, pcy, pcz, bj, bs, br2);
-                if (k2 != ~0u && __uint_as_float(k2 & ~kSegIdxMask) <= band) {
+                if (two) {
                   const int j2 = (int)(k2 & kSegIdxMask);
                   const double f0 = E[j2], f1 = E[j2 + 1];
                   int cj = j2;
@@ -2054,6 +2065,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
           }
         }
         nreal += (uint32_t)__popcll(bal);
+        acc_guard += (unsigned long long)__popcll(ballot64(act && guard));
       }
     }
     __syncthreads();
@@ -2077,7 +2089,9 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     __syncthreads();
   }
   if (lane == 0 && acc_case >= 0 && acc_pairs)
-    atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 5), acc_pairs);
+    atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 5), acc_pairs);
+  if (lane == 0 && acc_case >= 0 && acc_guard)
+    atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 8), acc_guard);
 }
 
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
@@ -2133,8 +2147,8 @@ __global__ void k_norm(StepLaunch L) {
       for (int a = 0; a < 3; ++a) cs.fhat[3 * k + a] = fh[a];
   }
   int c0 = __shfl(c, 0, 64);
-  if (__all(!act || c == c0)) wave_count_add(W.cnt + 8 * c0 + 3, act && zero);
-  else if (act && zero) atomicAdd((unsigned long long *)(W.cnt + 8 * c + 3), 1ull);
+  if (__all(!act || c == c0)) wave_count_add(W.cnt + kCnt * c0 + 3, act && zero);
+  else if (act && zero) atomicAdd((unsigned long long *)(W.cnt + kCnt * c + 3), 1ull);
 }
 
 void launch_norm(const StepLaunch &L, hipStream_t st) {
@@ -2323,7 +2337,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
   for (;;) {
     if (it.cs != acc_case) {
       if (acc_case >= 0) {
-        if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
+        if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 4), acc_band);
         if (lane < 3 && (fh || fl)) {
           fh += (long long)(fl >> kLoBits);
           fl &= (1ull << kLoBits) - 1ull;
@@ -2426,7 +2440,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
     }
   }
   if (acc_case >= 0) {
-    if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + 8 * acc_case + 4), acc_band);
+    if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 4), acc_band);
     if (lane < 3 && (fh || fl)) {
       fh += (long long)(fl >> kLoBits);
       fl &= (1ull << kLoBits) - 1ull;

@@ -419,7 +419,7 @@ def test_bitwise_identical_across_binnings(gu, ctx, prec):
             if k in ("F_fluid", "cons_rel_err"):
                 a, b = np.asarray(d[k]), np.asarray(dref[k])
                 assert np.max(np.abs(a - b)) <= 1e-15 * max(1.0, float(np.max(np.abs(dref["F_beam"])))), k
-            else:
+            elif k != "n_guard_fp64":  # a work count: the FP32 allowances follow the tile geometry
                 assert d[k] == dref[k], (tb, bs, k)
 
 
