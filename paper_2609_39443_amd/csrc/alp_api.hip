@@ -234,10 +234,12 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(tile_nent, T + 1);
   WALLOC(tile_items, T + 1);
   WALLOC(tile_itoff, T + 1);
+  WALLOC(big_tiles, T + 1);
   WALLOC(emit_raw, EM);
   WALLOC(emit, EM);
   WALLOC(entry, EM);
   WALLOC(item, IT);
+  WALLOC(multi_items, IT);
   WALLOC(rec_base, IT);
   WALLOC(rec_cnt, IT);
   WALLOC(rec, RC);
@@ -609,9 +611,8 @@ alp_status run_checked(alp_context *ctx, std::vector<CaseDev> &cs, int stages,
     if (ovf == 0) return ALP_OK;
     if (ovf & (4u | 8u | 16u))
       return fail(ctx, ALP_ERR_CAPACITY,
-                  "per-tile limits exceeded (flags 0x%x): more than %d beams or %d segment windows "
-                  "in one tile",
-                  ovf, kMaxEntries, kMaxEmitTile);
+                  "per-tile limits exceeded (flags 0x%x): more than %d segment windows in one tile",
+                  ovf, kMaxEmitBig);
     want_emit = std::max(want_emit, ne + ne / 2 + 1024);
     want_rec = std::max(want_rec, nr + nr / 2 + (int64_t)ctx->n_cu * 8 * (int64_t)kRecBlock);
     // the band state was updated by the failed attempt: force a full clear
@@ -711,7 +712,9 @@ bool carve_fixed(Carver &cv, Work &w, const StepShape &sh, CaseDev **d_cases, in
   w.tile_nent = cv.take<uint32_t>(T + 1);
   w.tile_items = cv.take<uint32_t>(T + 1);
   w.tile_itoff = cv.take<uint32_t>(T + 1);
+  w.big_tiles = cv.take<uint32_t>(T + 1);
   w.item = cv.take<Item>(IT);
+  w.multi_items = cv.take<uint32_t>(IT);
   w.rec_base = cv.take<unsigned long long>(IT);
   w.rec_cnt = cv.take<uint32_t>(IT);
   w.rec_alloc = cv.take<unsigned long long>(1);

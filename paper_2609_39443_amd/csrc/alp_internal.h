@@ -10,14 +10,17 @@ namespace alp {
 
 constexpr int kWave = 64;
 constexpr int kChunkSegs = 16;      // segments per chunk in the segment binning
-constexpr int kMaxEmitTile = 256;   // (chunk, tile) windows of one tile a wave can merge
+constexpr int kMaxEmitTile = 256;   // (chunk, tile) windows of a tile merged by k_tile_merge
+constexpr int kMaxEmitBig = 4096;   // windows of a tile merged by k_tile_merge_big (the limit)
+constexpr int kBigTileCounter = 4;  // step counter word: tiles listed for k_tile_merge_big
+constexpr int kMultiItemCounter = 5;  // step counter word: items listed for k_weights_multi
 constexpr int kQueueStripes = 16;  // counters per work queue
 constexpr int kLineWords = 32;                    // uint32 words per 128-byte line
 // step counters: a line of flags, then four work queues whose counters each
 // sit on a line of their own (atomics on one line serialise)
 constexpr int kCounters = kLineWords + 4 * kQueueStripes * kLineWords;
 __host__ __device__ constexpr int queue_words(int q) { return kLineWords + q * kQueueStripes * kLineWords; }
-constexpr int kMaxEntries = 128;    // merged (tile, beam) entries a wave can screen
+constexpr int kMaxEntries = 128;    // merged (tile, beam) entries the weights pass takes at once
 constexpr int kMaskWords = kMaxEntries / 32;
 constexpr int kStagePts = 160;      // window points (and node accumulators) staged in LDS
 constexpr int kHiShift = 46;        // fixed-point: hi word holds v * 2^(46-E)
@@ -137,11 +140,13 @@ struct Work {
   uint32_t *tile_nent;  // merged entries per tile ([N_T+1])
   uint32_t *tile_items; // work items per tile ([N_T+1])
   uint32_t *tile_itoff; // exclusive scan of tile_items ([N_T+1])
+  uint32_t *big_tiles;  // tiles for k_tile_merge_big ([N_T]; count in counters[kBigTileCounter])
   // lists
   Emit *emit_raw;       // [cap_emit] one slot per (chunk, box tile); beam < 0 = empty
   Win *emit;            // [cap_emit] windows grouped by tile
   Entry *entry;         // [cap_emit] merged windows, at the tile's window offset
   Item *item;           // [cap_item]
+  uint32_t *multi_items; // [cap_item] items of tiles with more than kMaxEntries entries
   unsigned long long *rec_base;  // per item, byte offset into rec
   uint32_t *rec_cnt;    // per item
   unsigned char *rec;   // [cap_rec bytes] pair records

@@ -39,6 +39,13 @@ __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &tot
   return inc - v;
 }
 
+// lane 0's value in a scalar register (the value is the same for the wave)
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // deterministic wave sum (fixed butterfly order)
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
@@ -494,15 +501,17 @@ void launch_emit_scatter(const StepLaunch &L, hipStream_t st) {
 // of the tile (64 cells each; none without entries).  Up to 16 windows are
 // merged by a group of 16 lanes (four tiles per wave), up to 64 by the whole
 // wave in registers, more by a sort in LDS.
+template <int kCap>
 struct MergeScratch {
-  unsigned long long key[kMaxEmitTile];  // (beam << 32) | first segment
-  int32_t hi[kMaxEmitTile];
-  int32_t k0[kMaxEmitTile];
+  unsigned long long key[kCap];  // (beam << 32) | first segment
+  int32_t hi[kCap];
+  int32_t k0[kCap];
 };
 
 // Tiles with more than 64 windows: sort the (beam, first segment) keys in
 // LDS (bitonic), then join each beam's run.  Returns the number of entries.
-__device__ uint32_t tile_merge_lds(const Work &W, MergeScratch &sh, int lane, uint32_t eoff, uint32_t n_emit) {
+template <int kCap>
+__device__ uint32_t tile_merge_lds(const Work &W, MergeScratch<kCap> &sh, int lane, uint32_t eoff, uint32_t n_emit) {
   // the scratch may still be read for the wave's previous tile
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -563,14 +572,12 @@ __device__ uint32_t tile_merge_lds(const Work &W, MergeScratch &sh, int lane, ui
       int32_t hi = sh.hi[i];
       for (uint32_t j = i + 1; j < n_emit && (uint32_t)(sh.key[j] >> 32) == beam; ++j)
         hi = max(hi, sh.hi[j]);
-      if (idx < (uint32_t)kMaxEntries) {
-        Entry en;
-        en.k0 = sh.k0[i];
-        en.i0 = (int32_t)(sh.key[i] & 0xffffffffu);
-        en.i1 = hi < 0 ? 0 : hi;
-        en.single = hi < 0 ? 1 : 0;
-        W.entry[eoff + idx] = en;
-      }
+      Entry en;
+      en.k0 = sh.k0[i];
+      en.i0 = (int32_t)(sh.key[i] & 0xffffffffu);
+      en.i1 = hi < 0 ? 0 : hi;
+      en.single = hi < 0 ? 1 : 0;
+      W.entry[eoff + idx] = en;  // idx < beams of the tile <= windows of the tile
     }
     ne += (uint32_t)__popcll(bal);
   }
@@ -608,7 +615,7 @@ __device__ uint32_t tile_merge_regs(const Work &W, int lane, uint32_t eoff, uint
     const int j = __builtin_ctzll(mm);
     idx += (uint32_t)__builtin_amdgcn_readlane((int)beam, j) < beam ? 1u : 0u;
   }
-  if (head && idx < (uint32_t)kMaxEntries) {
+  if (head) {
     Entry en;
     en.k0 = k0;
     en.i0 = (int32_t)lo;
@@ -621,9 +628,7 @@ __device__ uint32_t tile_merge_regs(const Work &W, int lane, uint32_t eoff, uint
 
 // The tile's item count and entry count, written once its merge is done.
 __device__ __forceinline__ void tile_done(Work &W, int64_t t, uint32_t ne, uint32_t ncell) {
-  uint32_t ni = 0;
-  if (ne > (uint32_t)kMaxEntries) set_overflow(W, 4u);
-  else ni = (ncell + 63u) / 64u;
+  const uint32_t ni = (ncell + 63u) / 64u;
   W.tile_nent[t] = ni ? ne : 0u;
   W.tile_items[t] = ni;
 }
@@ -637,7 +642,7 @@ constexpr int kMergeTiles = 64 / kMergeGroup;
 
 __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
   Work W = L.w;
-  __shared__ MergeScratch sh;
+  __shared__ MergeScratch<kMaxEmitTile> sh;
   const int lane = threadIdx.x;
   const int gl = lane & (kMergeGroup - 1), gbase = lane & ~(kMergeGroup - 1);
   const int64_t tg = (int64_t)blockIdx.x * kMergeTiles + lane / kMergeGroup;
@@ -693,10 +698,14 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
   if (gl == 0 && have) {
     if (small) {
       tile_done(W, tg, (uint32_t)__popc(gheads), ncell);
-    } else if (n_emit == 0 || n_emit > (uint32_t)kMaxEmitTile) {
+    } else if (n_emit == 0 || n_emit > (uint32_t)kMaxEmitBig) {
       if (n_emit) set_overflow(W, 4u);
       W.tile_nent[tg] = 0;
       W.tile_items[tg] = 0;
+    } else if (n_emit > (uint32_t)kMaxEmitTile) {
+      // merged by k_tile_merge_big, which sorts in a larger LDS area
+      const uint32_t slot = atomicAdd(&W.counters[kBigTileCounter], 1u);
+      W.big_tiles[slot] = (uint32_t)tg;
     }
   }
   for (uint64_t big = ballot64(gl == 0 && have && n_emit > (uint32_t)kMergeGroup && n_emit <= (uint32_t)kMaxEmitTile);
@@ -711,10 +720,30 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
   }
 }
 
+// Tiles with more than kMaxEmitTile windows (up to kMaxEmitBig), listed by
+// k_tile_merge: one wave per tile with a 64 KB sort area.
+__global__ __launch_bounds__(64) void k_tile_merge_big(StepLaunch L) {
+  Work W = L.w;
+  __shared__ MergeScratch<kMaxEmitBig> sh;
+  const int lane = threadIdx.x;
+  const uint32_t n_big = W.counters[kBigTileCounter];
+  for (uint32_t i = blockIdx.x; i < n_big; i += gridDim.x) {
+    const int64_t t = W.big_tiles[i];
+    const uint32_t eoff = W.tile_off[t], n_emit = W.tile_off[t + 1] - eoff;
+    const int c = case_of(L.tbase, L.n_cases, t);
+    const CaseDev &cs = L.cases[c];
+    const int64_t tl = t - cs.tile_base;
+    const uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
+    const uint32_t ne = tile_merge_lds(W, sh, lane, eoff, n_emit);
+    if (lane == 0) tile_done(W, t, ne, ncell);
+  }
+}
+
 void launch_tile_merge(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_tiles == 0) return;
   hipLaunchKernelGGL(k_tile_merge, dim3((unsigned)((L.w.n_tiles + kMergeTiles - 1) / kMergeTiles)), dim3(64), 0,
                      st, L);
+  hipLaunchKernelGGL(k_tile_merge_big, dim3(64), dim3(64), 0, st, L);
 }
 
 __global__ void k_items(StepLaunch L) {
@@ -742,6 +771,7 @@ __global__ void k_items(StepLaunch L) {
     it.eoff = W.tile_off[tg];
     it.nent = W.tile_nent[tg];
     W.item[id] = it;
+    if (it.nent > (uint32_t)kMaxEntries) W.multi_items[atomicAdd(&W.counters[kMultiItemCounter], 1u)] = (uint32_t)id;
   }
 }
 
@@ -1455,10 +1485,13 @@ __device__ __forceinline__ void write_record(unsigned char *r, int rsz, uint32_t
   }
 }
 
-// One kernel per projection rule (kInt: segment-integrated), so that each
-// keeps its own register allocation; each takes only the items of its own
-// cases, from its own work-queue counters.
-template <bool kInt, bool kSplit>
+// One kernel per projection rule (kInt: segment-integrated) and precision,
+// so that each keeps its own register allocation; each takes only the items
+// of its own cases, from its own work-queue counters.  Items of tiles with
+// more than kMaxEntries entries are left to a kernel of their own (kMulti),
+// which takes the entries in groups of kMaxEntries; the group loop would
+// otherwise cost the common kernels registers.
+template <bool kInt, bool kSplit, bool kMulti>
 __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   Work W = L.w;
   __shared__ WeightsScratch sh;
@@ -1470,11 +1503,23 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   unsigned long long acc_pairs = 0, acc_guard = 0;
   WorkQueue wq = work_queue(W.counters + queue_words(kInt ? (kSplit ? 1 : 2) : (kSplit ? 0 : 3)),
                             (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
-  while (wq.next(lane)) {
+  const uint32_t n_multi = kMulti ? min(W.counters[kMultiItemCounter], (uint32_t)min((int64_t)n_items, W.cap_item)) : 0u;
+  uint32_t mi = blockIdx.x;
+  for (;;) {
+    uint32_t item;
+    if constexpr (kMulti) {
+      if (mi >= n_multi) break;
+      item = W.multi_items[mi];
+      mi += gridDim.x;
+    } else {
+      if (!wq.next(lane)) break;
+      item = wq.item;
+    }
     // the item index is wave-uniform: read it into a scalar register so that
     // the descriptor and the case fields are scalar loads
-    const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane((int)wq.item);
+    item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
     const Item it = W.item[item];
+    if (!kMulti && it.nent > (uint32_t)kMaxEntries) continue;
     if ((L.cases[it.cs].proj_mode == ALP_PROJ_INTEGRATED) != kInt) continue;
     if ((L.cases[it.cs].prec == ALP_PREC_FP32_SPLIT) != kSplit) continue;
     if (it.cs != acc_case) {
@@ -1495,7 +1540,10 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     const int64_t pbase = cs.point_base;
     const int64_t tl = it.tile - cs.tile_base;
     const int rsz = rec_size(cs.prec);
-    const uint32_t ne = it.nent;  // <= kMaxEntries (the tile merge drops larger tiles)
+    // the tile's entries, in beam order; more than kMaxEntries are taken in
+    // groups of kMaxEntries, one after another
+    const uint32_t ne_all = it.nent;
+    constexpr bool multi = kMulti;
     // cells of the item, and their FP32 coordinates relative to the tile centre
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
@@ -1517,6 +1565,40 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       lz = (float)(cz - ctz);
     }
 
+    unsigned long long rbase = 0;
+    bool rec_ok = true;
+    // record space for n pairs, carved from the wave's block
+    auto reserve = [&](uint64_t n) {
+      const unsigned long long need = ((unsigned long long)n * rsz + 15ull) & ~15ull;
+      if (blk_cur + need > blk_end) {
+        const unsigned long long take = need > kRecBlock ? need : kRecBlock;
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(W.rec_alloc, take);
+        blk_cur = uniform_u64(got);
+        blk_end = blk_cur + take;
+      }
+      rbase = blk_cur;
+      blk_cur += need;
+      rec_ok = (int64_t)(rbase + need) <= W.cap_rec;
+      if (!rec_ok && lane == 0) set_overflow(W, 2u);
+    };
+    uint32_t nreal = 0;  // records of the item so far
+    if (multi) {
+      // the records of every group follow each other: reserve for the most
+      // the item can have (each cell with every entry, or with every window
+      // segment under the integrated rule), and give the rest back at the end
+      uint64_t per_cell = 0;
+      for (uint32_t e = lane; e < ne_all; e += 64) {
+        const Entry en = W.entry[it.eoff + e];
+        per_cell += kInt && !en.single ? (uint64_t)(en.i1 - en.i0 + 1) : 1u;
+      }
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) per_cell += __shfl_xor(per_cell, d, 64);
+      reserve(per_cell * (uint64_t)(it.c1 - it.c0));
+    }
+    for (uint32_t g0 = 0;;) {
+    const uint32_t ne = kMulti ? min(ne_all - g0, (uint32_t)kMaxEntries) : ne_all;
+    const uint32_t eoff = it.eoff + g0;
     // 1. entries and the staging plan: the leading entries whose windows fit
     uint32_t carry = 0;
     int nst = 0;
@@ -1524,7 +1606,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       const uint32_t e = e0 + lane;
       uint32_t cntp = 0;
       if (e < ne) {
-        const Entry en = W.entry[it.eoff + e];
+        const Entry en = W.entry[eoff + e];
         sh.e_k0[e] = en.k0;
         sh.e_i0[e] = en.i0;
         sh.e_i1[e] = en.single ? -1 : en.i1;
@@ -1723,24 +1805,6 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         candidate(sh, nwords, p, Lc, e);
       }
     };
-    unsigned long long rbase = 0;
-    bool rec_ok = true;
-    // record space for n pairs, carved from the wave's block
-    auto reserve = [&](uint32_t n) {
-      const unsigned long long need = ((unsigned long long)n * rsz + 15ull) & ~15ull;
-      if (blk_cur + need > blk_end) {
-        const unsigned long long take = need > kRecBlock ? need : kRecBlock;
-        unsigned long long got = 0;
-        if (lane == 0) got = atomicAdd(W.rec_alloc, take);
-        blk_cur = __shfl(got, 0, 64);
-        blk_end = blk_cur + take;
-      }
-      rbase = blk_cur;
-      blk_cur += need;
-      rec_ok = (int64_t)(rbase + need) <= W.cap_rec;
-      if (!rec_ok && lane == 0) set_overflow(W, 2u);
-    };
-    uint32_t nreal = 0;
     if constexpr (kInt) {
       // 3.-5. segment-integrated kernel: every window segment within the
       // cutoff of the cell gives one record (cell, segment).  The (candidate,
@@ -1781,7 +1845,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         wave_excl_scan_u32(n, tot);
         ub += tot;
       }
-      reserve(ub);
+      if (!multi) reserve(ub);
       uint32_t qh = 0, qt = 0;  // ring head and tail (wave-uniform)
       // weights of ring entries qh .. qh + n - 1, one per lane
       auto drain = [&](uint32_t n) {
@@ -1920,10 +1984,10 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       }
       if (qt > qh) drain(qt - qh);
       // give back the unused tail of the reservation
-      blk_cur = rbase + (((unsigned long long)nreal * rsz + 15ull) & ~15ull);
+      if (!multi) blk_cur = rbase + (((unsigned long long)nreal * rsz + 15ull) & ~15ull);
     } else {
       // record space for up to `total` pairs (one per candidate)
-      reserve(total);
+      if (!multi) reserve(total);
       // 3.-5. candidate pairs, 64 per round
       for (uint32_t p0 = 0; p0 < total; p0 += 64) {
         const uint32_t p = p0 + lane;
@@ -2081,8 +2145,17 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       atomicAdd((unsigned long long *)&W.w_hi[node], (unsigned long long)h);
       atomicAdd(&W.w_lo[node], l);
     }
+    if constexpr (!kMulti) break;
+    g0 += (uint32_t)kMaxEntries;
+    if (g0 >= ne_all) break;
+    __syncthreads();  // the previous group's scratch is done with
+    }  // entry groups
+    if (multi) blk_cur = rbase + (((unsigned long long)nreal * rsz + 15ull) & ~15ull);
     if (lane == 0) {
-      W.rec_base[item] = rbase | (rsz == 24 ? 1ull : 0ull);  // record size in bit 0 (bases are 16-byte aligned)
+      // bases are 16-byte aligned: bit 0 carries the record size (set for 24
+      // bytes), bit 1 marks an item whose cells have records in several runs
+      // (one per entry group)
+      W.rec_base[item] = rbase | (rsz == 24 ? 1ull : 0ull) | (multi ? 2ull : 0ull);
       W.rec_cnt[item] = rec_ok ? nreal : 0u;
     }
     acc_pairs += nreal;
@@ -2096,11 +2169,26 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
 
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
 void k_weights(StepLaunch L) {
-  weights_pass<false, true>(L);
+  weights_pass<false, true, false>(L);
 }
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
 void k_weights64(StepLaunch L) {
-  weights_pass<false, false>(L);
+  weights_pass<false, false, false>(L);
+}
+// the items of tiles with more than kMaxEntries entries, every rule and
+// precision in one kernel (few items: registers do not matter here); a small
+// grid, so that a step without such items pays little for the launch
+constexpr int kMultiBlocks = 32;
+template <bool kInt, bool kSplit>
+__device__ __forceinline__ void weights_multi_one(const StepLaunch &L) {
+  weights_pass<kInt, kSplit, true>(L);
+}
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(2)))
+void k_weights_multi(StepLaunch L, int which) {
+  if (which == 0) weights_multi_one<false, true>(L);
+  else if (which == 1) weights_multi_one<false, false>(L);
+  else if (which == 2) weights_multi_one<true, true>(L);
+  else weights_multi_one<true, false>(L);
 }
 
 // the integrated rule, one kernel per precision: the split one (FP32
@@ -2108,11 +2196,11 @@ void k_weights64(StepLaunch L) {
 // expm1 in FP64) needs more registers, two waves per SIMD
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
 void k_weights_int(StepLaunch L) {
-  weights_pass<true, true>(L);
+  weights_pass<true, true, false>(L);
 }
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(2)))
 void k_weights_int64(StepLaunch L) {
-  weights_pass<true, false>(L);
+  weights_pass<true, false, false>(L);
 }
 
 void launch_weights(const StepLaunch &L, hipStream_t st) {
@@ -2120,6 +2208,9 @@ void launch_weights(const StepLaunch &L, hipStream_t st) {
   if (L.near_fp64) hipLaunchKernelGGL(k_weights64, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
   if (L.int_split) hipLaunchKernelGGL(k_weights_int, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
   if (L.int_fp64) hipLaunchKernelGGL(k_weights_int64, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
+  const int flags[4] = {L.near_split, L.near_fp64, L.int_split, L.int_fp64};
+  for (int q = 0; q < 4; ++q)
+    if (flags[q]) hipLaunchKernelGGL(k_weights_multi, dim3(kMultiBlocks), dim3(64), 0, st, L, q);
 }
 
 // ------------------------------------------------------------------- norm --
@@ -2232,6 +2323,7 @@ constexpr int kSpreadChunk = 64;  // records summed per pass, one per lane
 struct SpreadScratch {
   double cc[3][kSpreadChunk];
   uint16_t first[64], last[64];  // run of each cell inside the chunk (last exclusive)
+  uint8_t cl[kSpreadChunk];      // cell lane of each record (items with several runs per cell)
 };
 
 // The records of a wave's items, taken as one stream of 64-record chunks.  A
@@ -2357,6 +2449,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
     const double v = valid ? to_global(m.vs)[c] : 0.0;
     const uint32_t pc = valid ? to_global(m.perm)[c] : 0u;
     const bool fp64 = (rb & 1ull) != 0;
+    // an item whose entries were taken in groups holds one run per group for
+    // a cell: its lanes then gather their records from the whole chunk
+    const bool multi = (rb & 2ull) != 0;
     const unsigned char *rbase = W.rec + (rb & ~15ull);
     double S0 = 0.0, S1 = 0.0, S2 = 0.0;
     bool any = false;
@@ -2388,6 +2483,22 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         sh.cc[1][j] = -q1;
         sh.cc[2][j] = -q2;
         cl = meta & 63u;
+      }
+      if (multi) {
+        // every record of the chunk whose cell is this lane's, in record order
+        // (group after group, beam order inside a group: beam order)
+        if (j < nch) sh.cl[j] = (uint8_t)cl;
+        __syncthreads();
+        for (uint32_t q = 0; q < nch; ++q) {
+          if (sh.cl[q] == (uint32_t)lane) {
+            S0 += sh.cc[0][q];
+            S1 += sh.cc[1][q];
+            S2 += sh.cc[2][q];
+            any = true;
+          }
+        }
+        __syncthreads();
+        continue;
       }
       // run boundaries of each cell (records are sorted by cell): the
       // neighbouring records' cells come from the neighbouring lanes

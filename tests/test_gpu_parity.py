@@ -555,12 +555,11 @@ def test_integrated_bitwise_across_binnings(gu, ctx):
             assert d[k] == dref[k], (tb, bs, k)
 
 
-def crowded_column(n_b, seed=3):
-    """n_b straight vertical beams of 5 points, all inside one column of
+def crowded_column(n_b, seed=3, n=5):
+    """n_b straight vertical beams of n points, all inside one column of
     4-bin tiles (h = 1 cm), so every tile they reach holds n_b windows."""
     C, V = W.uniform_mesh(16, 16, 16, 0.01)
     rng = np.random.default_rng(seed)
-    n = 5
     pts = []
     for _ in range(n_b):
         x0, y0 = 0.05 + 0.02 * rng.random(2)
@@ -573,23 +572,35 @@ def crowded_column(n_b, seed=3):
             "box": None, "beams": beams, "params": {"rho": 1000.0, "tau": 1e-6}}
 
 
-@pytest.mark.parametrize("n_b", [40, 100])
+@pytest.mark.parametrize("n_b", [40, 100, 200, 400])
 @pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
 def test_crowded_tiles_both_merge_paths(gu, ctx, n_b, prec):
     """A tile reached by at most 64 windows is merged in registers, a fuller
-    one by a sort in LDS (100 beams in one tile column), and the weights pass
-    screens its windows 65-100 in a second batch of frames: both match the
-    oracle."""
+    one by a sort in LDS (100 and 200 beams in one tile column), and one with
+    more than 256 by the second merge kernel's larger sort (400); the weights
+    pass screens windows 65-128 in a second batch of frames, and takes the
+    entries of a tile with more than 128 in groups (200, 400), so that a cell
+    has one run of records per group: all match the oracle, batched and
+    unbatched."""
     run_and_compare(gu, ctx, crowded_column(n_b), prec, tile_bins=4, bin_size=0.01)
+    if n_b >= 200:
+        run_and_compare(gu, ctx, crowded_column(n_b, seed=4), prec, batched=False, tile_bins=4, bin_size=0.01)
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_crowded_tiles_integrated_rule(gu, ctx, prec):
+    """The segment-integrated rule on a tile column crowded by 200 beams: its
+    entries are taken in groups too."""
+    run_and_compare(gu, ctx, integrated(crowded_column(200)), prec, tile_bins=4, bin_size=0.01)
 
 
 def test_per_tile_limit_is_reported(gu, ctx):
-    """More than 128 beams reaching one tile exceeds the documented per-tile
-    limit: the step returns ALP_ERR_CAPACITY without computing that tile, and
-    the context keeps working afterwards."""
-    wl = crowded_column(140)
+    """More than 4096 windows in one tile exceeds the documented per-tile
+    limit of the merge: the step returns ALP_ERR_CAPACITY without computing
+    that tile, and the context keeps working afterwards."""
+    wl = crowded_column(4200, n=2)
     case = gu.GpuCase(ctx, wl, alp.PREC_FP64, tile_bins=4, bin_size=0.01)
-    gu.log("[parity] crowded tile: 140 beams in one tile column")
+    gu.log("[parity] crowded tile: 4200 beams in one tile column")
     with pytest.raises(alp.AlpError) as err:
         gu.step_batched(ctx, [case])
     assert err.value.status == -6 and "per-tile" in str(err.value)
