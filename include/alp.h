@@ -244,6 +244,22 @@ typedef struct {
 
 #define ALP_USE_GRAPH 1u /* capture the step on the first call, replay it afterwards */
 #define ALP_CHECKED 2u   /* synchronise at the end and grow the work lists on overflow */
+#define ALP_AUTOTUNE 4u  /* before the first step of a new set of cases, choose the launch
+                            shape (alp_tuning) by timing graph replays of the step */
+
+/* Launch shape of a step's kernels.  Every output is bitwise independent of
+   it (decisions are exact and every sum is exact or in a fixed order), so it
+   only changes the time a step takes. */
+typedef struct {
+  int32_t sample_lanes;  /* lanes per actuator point in the sampler: 2, 4 or 8, i.e. 32, 16
+                            or 8 points per 64-lane workgroup */
+  int32_t sample_waves;  /* sampler workgroups per CU beside the segment binning (1..32), or
+                            0 = chosen from the point count */
+  int32_t weights_grab;  /* work items (up to 64 cells of one tile each) a weights workgroup
+                            takes from its queue at once: 1..16 */
+  int32_t weights_waves; /* weights workgroups (one wave each) per CU: 1..32 */
+  int32_t spread_waves;  /* spread workgroups per CU (1..32), or 0 = every resident slot */
+} alp_tuning;
 
 /* A whole coupling step (sample -> drag -> project) for n_cases independent
    cases in one set of launches: every stage runs once over the concatenated
@@ -272,6 +288,12 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
    threads) race.  alp_get_diag reads this step's diagnostics from it, so it
    must come before another call on the same device. */
 alp_status alp_step_noalloc(alp_context *ctx, int32_t n_cases, const alp_case *cases);
+
+/* The context's launch shape (the defaults, the last ALP_AUTOTUNE choice or
+   the last alp_set_tuning), and setting it.  alp_set_tuning rejects values out
+   of range (ALP_ERR_INVALID_ARG) and drops captured graphs.  HOST structs. */
+alp_status alp_get_tuning(alp_context *ctx, alp_tuning *out);
+alp_status alp_set_tuning(alp_context *ctx, const alp_tuning *t);
 
 /* Diagnostics of case `case_index` of the last step (or of the last
    alp_sample / alp_spread pair, index 0).  Synchronous. */
@@ -309,6 +331,27 @@ alp_status alp_autotune(alp_context *ctx, int64_t n_cells, const double *C, cons
                         const double *domain_box, int32_t n_cases, const alp_case *cases,
                         int32_t tuned_case, uint32_t flags, int32_t reps, double *out_bin_size,
                         int32_t *out_tile_bins, double *out_ms);
+
+/* Autotuner of the cell binning of every case of a batch at once: each
+   candidate bins every case's cells with bin size = scale x that case's
+   default bin size (scale 0.75, 1 or 1.5) and tile edge T (2..5 bins), runs
+   the batch with those meshes (flags as given, plus one sizing run), times
+   `reps` steps (<= 0: 3) and keeps the fastest.  A candidate whose step
+   overflows a per-tile limit (ALP_ERR_CAPACITY) is skipped.
+     cases        HOST [n_cases], as for alp_step_batched; on return
+                  cases[i].mesh is the best candidate's mesh for case i, a new
+                  mesh the caller destroys with alp_mesh_destroy (the meshes
+                  passed in are left as they were)
+     C, V         HOST arrays [n_cases] of DEVICE pointers: each case's cell
+                  centres [n][3] and volumes [n] (n = that mesh's cell count)
+     boxes        HOST array [n_cases] of HOST domain boxes (each nullable), or NULL
+     out_scale, out_tile_bins, out_ms   HOST out (out_ms nullable)
+   The cases' outputs are overwritten by the trial steps.  Captured graphs are
+   dropped.  Synchronous; not allowed under capture. */
+alp_status alp_autotune_binning(alp_context *ctx, int32_t n_cases, alp_case *cases,
+                                const double *const *C, const double *const *V,
+                                const double *const *boxes, uint32_t flags, int32_t reps,
+                                double *out_scale, int32_t *out_tile_bins, double *out_ms);
 
 /* Beam state for the point-wise helpers (Sec. 3.2.2): one actuator point per
    beam control volume, beams as a CSR over points as in alp_beams.  DEVICE

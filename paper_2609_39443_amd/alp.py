@@ -21,13 +21,14 @@ PREC_FP64, PREC_FP32_SPLIT = 0, 1
 DRAG_FULLMAG, DRAG_COMPONENTWISE = 0, 1
 SAMPLE_CELL, SAMPLE_KERNEL = 0, 1
 PROJ_NEAREST, PROJ_INTEGRATED = 0, 1
-USE_GRAPH, CHECKED = 1, 2
+USE_GRAPH, CHECKED, AUTOTUNE = 1, 2, 4
 
 # every symbol include/alp.h declares
 EXPORTS = ("alp_create", "alp_destroy", "alp_last_error", "alp_bin_cells", "alp_mesh_destroy",
            "alp_sample", "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag",
            "alp_invalidate", "alp_version", "alp_step_profile", "alp_stage_name", "alp_autotune",
-           "alp_beam_geometry", "alp_step_noalloc")
+           "alp_beam_geometry", "alp_step_noalloc", "alp_get_tuning", "alp_set_tuning",
+           "alp_autotune_binning")
 
 
 class AlpError(RuntimeError):
@@ -73,6 +74,14 @@ class alp_case(ct.Structure):
                 ("cell_a", ct.c_void_p), ("cell_s", ct.c_void_p), ("dUdt", ct.c_void_p)]
 
 
+class alp_tuning(ct.Structure):
+    _fields_ = [("sample_lanes", ct.c_int32), ("sample_waves", ct.c_int32), ("weights_grab", ct.c_int32),
+                ("weights_waves", ct.c_int32), ("spread_waves", ct.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class alp_beam_state(ct.Structure):
     _fields_ = [("n_beams", ct.c_int32), ("reserved0", ct.c_int32), ("n_points", ct.c_int64),
                 ("offsets", ct.c_void_p), ("Cb", ct.c_void_p), ("Wref", ct.c_void_p), ("W", ct.c_void_p),
@@ -112,13 +121,18 @@ def load():
     lib.alp_autotune.argtypes = [vp, i64, vp, vp, vp, i32, ct.POINTER(alp_case), i32, u32, i32,
                                  ct.POINTER(ct.c_double), ct.POINTER(i32), ct.POINTER(ct.c_double)]
     lib.alp_autotune.restype = ct.c_int
+    lib.alp_get_tuning.argtypes = [vp, ct.POINTER(alp_tuning)]
+    lib.alp_set_tuning.argtypes = [vp, ct.POINTER(alp_tuning)]
+    lib.alp_autotune_binning.argtypes = [vp, i32, ct.POINTER(alp_case), ct.POINTER(vp), ct.POINTER(vp),
+                                         ct.POINTER(vp), u32, i32, ct.POINTER(ct.c_double), ct.POINTER(i32),
+                                         ct.POINTER(ct.c_double)]
     lib.alp_beam_geometry.argtypes = [vp, vp, ct.POINTER(alp_beam_state), vp, vp, vp, vp]
     lib.alp_beam_geometry.restype = ct.c_int
     lib.alp_stage_name.argtypes = [i32]
     lib.alp_stage_name.restype = ct.c_char_p
     for name in ("alp_create", "alp_destroy", "alp_bin_cells", "alp_mesh_destroy", "alp_sample",
                  "alp_drag", "alp_spread", "alp_step_batched", "alp_get_diag", "alp_invalidate",
-                 "alp_step_noalloc"):
+                 "alp_step_noalloc", "alp_get_tuning", "alp_set_tuning", "alp_autotune_binning"):
         getattr(lib, name).restype = ct.c_int
     _lib = lib
     return lib
@@ -225,6 +239,46 @@ def alp_autotune(ctx, C, V, cases, tuned_case=0, flags=USE_GRAPH, reps=3, domain
                                     int(tuned_case), int(flags), int(reps), ct.byref(bs), ct.byref(tb),
                                     ct.byref(ms)))
     return {"bin_size": bs.value, "tile_bins": tb.value, "ms": ms.value}
+
+
+def alp_get_tuning(ctx):
+    t = alp_tuning()
+    _check(ctx, load().alp_get_tuning(ctx, ct.byref(t)))
+    return t.as_dict()
+
+
+def alp_set_tuning(ctx, sample_lanes=4, sample_waves=0, weights_grab=4, weights_waves=16, spread_waves=0):
+    t = alp_tuning(sample_lanes, sample_waves, weights_grab, weights_waves, spread_waves)
+    _check(ctx, load().alp_set_tuning(ctx, ct.byref(t)))
+
+
+def alp_autotune_binning(ctx, cases, C, V, boxes=None, flags=USE_GRAPH, reps=3):
+    """Rebin every case's cells with each candidate (scale of its default bin
+    size, tile edge) and keep the fastest; returns {"scale", "tile_bins", "ms",
+    "meshes"}: the new meshes (handles the caller destroys with
+    alp_mesh_destroy), one per case, in case order."""
+    n = len(cases)
+    arr = (alp_case * n)(*cases)
+    cp = (ct.c_void_p * n)(*[_ptr(c) for c in C])
+    vp_ = (ct.c_void_p * n)(*[_ptr(v) for v in V])
+    keep = []
+    if boxes is None:
+        bp = None
+    else:
+        bx = []
+        for b in boxes:
+            if b is None:
+                bx.append(None)
+            else:
+                a = (ct.c_double * 6)(*[float(x) for x in b])
+                keep.append(a)
+                bx.append(ct.cast(a, ct.c_void_p).value)
+        bp = (ct.c_void_p * n)(*bx)
+    sc, tb, ms = ct.c_double(), ct.c_int32(), ct.c_double()
+    _check(ctx, load().alp_autotune_binning(ctx, n, arr, cp, vp_, bp, int(flags), int(reps), ct.byref(sc),
+                                            ct.byref(tb), ct.byref(ms)))
+    return {"scale": sc.value, "tile_bins": tb.value, "ms": ms.value,
+            "meshes": [ct.c_void_p(arr[i].mesh) for i in range(n)]}
 
 
 def alp_beam_geometry(ctx, mesh, state, P=None, e_t=None, eps=None, counts=None):

@@ -69,6 +69,9 @@ struct alp_context {
   unsigned char *scratch = nullptr;  // this device's scratch array (device address)
   int any_kernel_sample = 0;  // some case of the uploaded batch samples with the kernel
   int any_proj[4] = {0, 0, 0, 0};  // the uploaded batch has cases of each (rule, precision)
+  // launch shape of the step's kernels, and the cases ALP_AUTOTUNE chose it for
+  alp_tuning tun{4, 0, 4, 16, 0};
+  std::vector<alp_case> tkey;
 };
 
 // Workspace of alp_step_noalloc: every per-step list, the case table and
@@ -454,11 +457,10 @@ alp_status upload_cases(alp_context *ctx, const std::vector<CaseDev> &cs, const 
 
 // Sampler waves per CU while it runs beside the segment binning: four, which
 // leaves the binning's small kernels the most room, unless the sampler would
-// then need more than 16 passes over the CUs (a wave takes 64 / kSampleLanes
-// points per pass), in which case eight, so that it still ends near the
-// binning.
-int sample_waves_beside(int64_t n_points, int n_cu) {
-  const int64_t pass4 = (int64_t)n_cu * 4 * (64 / kSampleLanes);  // points per pass at four waves per CU
+// then need more than 16 passes over the CUs (a wave takes 64 / lanes points
+// per pass), in which case eight, so that it still ends near the binning.
+int sample_waves_beside(int64_t n_points, int n_cu, int lanes) {
+  const int64_t pass4 = (int64_t)n_cu * 4 * (64 / lanes);  // points per pass at four waves per CU
   return n_points <= 16 * pass4 ? 4 : 8;
 }
 
@@ -472,7 +474,12 @@ StepLaunch make_launch_from(alp_context *ctx, const Work &w, const CaseDev *d_ca
   L.w = w;
   L.n_cases = n_cases;
   L.grid_persistent = ctx->n_cu * 8;
-  L.grid_spread = ctx->n_cu * ctx->spread_per_cu;
+  const alp_tuning &t = ctx->tun;
+  const int spw = t.spread_waves > 0 ? std::min(t.spread_waves, ctx->spread_per_cu) : ctx->spread_per_cu;
+  L.grid_spread = ctx->n_cu * spw;
+  L.grid_weights = ctx->n_cu * t.weights_waves;
+  L.weights_grab = t.weights_grab;
+  L.sample_lanes = t.sample_lanes;
   L.sample_waves = 0;
   L.kernel_sample = ctx->any_kernel_sample;
   L.near_split = ctx->any_proj[0];
@@ -520,7 +527,9 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
     // beside the segment binning the sampler keeps to a few waves per CU,
     // which leaves the binning's small kernels room on every CU
     StepLaunch Ls = L;
-    Ls.sample_waves = fork ? sample_waves_beside(L.w.n_points, ctx->n_cu) : 0;
+    Ls.sample_waves = !fork ? 0
+                      : (ctx->tun.sample_waves > 0 ? ctx->tun.sample_waves
+                                                   : sample_waves_beside(L.w.n_points, ctx->n_cu, L.sample_lanes));
     launch_sample(Ls, sd);
     launch_sample_kernel(L, sd);
   }
@@ -736,6 +745,84 @@ bool carve_fixed(Carver &cv, Work &w, const StepShape &sh, CaseDev **d_cases, in
   w.n_pblocks = PB;
   return cv.ok;
 }
+
+// ALP_AUTOTUNE: the launch shape of a batch by coordinate descent over the
+// sampler (lanes per point, waves per CU), the weights pass (queue grab,
+// waves per CU) and the spread (waves per CU), each candidate timed over
+// graph replays of the step (the caller's outputs are overwritten).  A
+// candidate is kept only if it is faster by more than 1%.
+alp_status tune_launch(alp_context *ctx, int32_t n, const alp_case *cases, uint32_t flags) {
+  flags = (flags & ~(ALP_AUTOTUNE | ALP_CHECKED)) | ALP_USE_GRAPH;
+  constexpr int kReps = 5;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIPCHK(ctx, hipEventCreate(&ea));
+  HIPCHK(ctx, hipEventCreate(&eb));
+  auto timed = [&](const alp_tuning &t, double &ms) -> alp_status {
+    ctx->tun = t;
+    drop_graph(ctx);
+    alp_status rc = alp_step_batched(ctx, n, cases, flags);  // sizes, runs and captures
+    for (int r = 0; r < 1 && rc == ALP_OK; ++r) rc = alp_step_batched(ctx, n, cases, flags);
+    if (rc != ALP_OK) return rc;
+    if (hipEventRecord(ea, ctx->user) != hipSuccess) return fail(ctx, ALP_ERR_HIP, "event record failed");
+    for (int r = 0; r < kReps && rc == ALP_OK; ++r) rc = alp_step_batched(ctx, n, cases, flags);
+    if (rc != ALP_OK) return rc;
+    float e = 0.f;
+    if (hipEventRecord(eb, ctx->user) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+        hipEventElapsedTime(&e, ea, eb) != hipSuccess)
+      return fail(ctx, ALP_ERR_HIP, "timing the candidate failed");
+    ms = e / kReps;
+    return ALP_OK;
+  };
+  alp_tuning best = ctx->tun;
+  double best_ms = INFINITY;
+  alp_status rc = timed(best, best_ms);
+  const int samp[][2] = {{4, 0}, {4, 4}, {4, 8}, {4, 16}, {2, 4}, {2, 8}, {8, 4}, {8, 8}};
+  const int grab[] = {2, 4, 8};
+  const int wwav[] = {8, 12, 16, 24};
+  const int swav[] = {0, 4, 6};
+  auto consider = [&](const alp_tuning &t) {
+    if (rc != ALP_OK) return;
+    double ms = INFINITY;
+    rc = timed(t, ms);
+    if (rc == ALP_OK && ms < 0.99 * best_ms) {
+      best = t;
+      best_ms = ms;
+    }
+  };
+  for (const auto &c : samp) {
+    alp_tuning t = best;
+    t.sample_lanes = c[0];
+    t.sample_waves = c[1];
+    if (t.sample_lanes != best.sample_lanes || t.sample_waves != best.sample_waves) consider(t);
+  }
+  for (int g : grab) {
+    alp_tuning t = best;
+    t.weights_grab = g;
+    if (g != best.weights_grab) consider(t);
+  }
+  for (int w : wwav) {
+    alp_tuning t = best;
+    t.weights_waves = w;
+    if (w != best.weights_waves) consider(t);
+  }
+  for (int w : swav) {
+    alp_tuning t = best;
+    t.spread_waves = w;
+    if (w != best.spread_waves) consider(t);
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  ctx->tun = best;
+  drop_graph(ctx);
+  return rc;
+}
+
+bool tuning_valid(const alp_tuning &t) {
+  return (t.sample_lanes == 2 || t.sample_lanes == 4 || t.sample_lanes == 8) && t.sample_waves >= 0 &&
+         t.sample_waves <= 32 && t.weights_grab >= 1 && t.weights_grab <= 16 && t.weights_waves >= 1 &&
+         t.weights_waves <= 32 && t.spread_waves >= 0 && t.spread_waves <= 32;
+}
+
 }  // namespace
 
 // ================================================================= C ABI ==
@@ -1037,8 +1124,17 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
   ctx->err.clear();
   if (n_cases < 1 || !cases) return fail(ctx, ALP_ERR_INVALID_ARG, "need n_cases >= 1 and cases");
   if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "the stream is capturing");
-  bool use_graph = (flags & ALP_USE_GRAPH) != 0;
   alp_status rc;
+  if (flags & ALP_AUTOTUNE) {
+    // choose the launch shape once per set of case descriptors
+    flags &= ~ALP_AUTOTUNE;
+    if (!((int)ctx->tkey.size() == n_cases &&
+          std::memcmp(ctx->tkey.data(), cases, sizeof(alp_case) * (size_t)n_cases) == 0)) {
+      if ((rc = tune_launch(ctx, n_cases, cases, flags)) != ALP_OK) return rc;
+      ctx->tkey.assign(cases, cases + n_cases);
+    }
+  }
+  bool use_graph = (flags & ALP_USE_GRAPH) != 0;
   // replay an existing graph for identical case descriptors
   if (use_graph && ctx->gexec && (int)ctx->gkey.size() == n_cases && ctx->gflags == flags &&
       std::memcmp(ctx->gkey.data(), cases, sizeof(alp_case) * (size_t)n_cases) == 0) {
@@ -1270,6 +1366,7 @@ alp_status alp_autotune(alp_context *ctx, int64_t n_cells, const double *C, cons
       }
       (void)alp_invalidate(ctx);
       alp_mesh_destroy(m);
+      if (rc == ALP_ERR_CAPACITY) continue;  // this binning exceeds a per-tile limit: skip it
       if (rc != ALP_OK) return rc;
       if (ms < best_ms) {
         best_ms = ms;
@@ -1280,6 +1377,86 @@ alp_status alp_autotune(alp_context *ctx, int64_t n_cells, const double *C, cons
   }
   if (!(best_ms < INFINITY)) return fail(ctx, ALP_ERR_INVALID_ARG, "no binning setting could be built");
   *out_bin_size = best_bin;
+  *out_tile_bins = best_t;
+  if (out_ms) *out_ms = best_ms;
+  return ALP_OK;
+}
+
+alp_status alp_autotune_binning(alp_context *ctx, int32_t n_cases, alp_case *cases, const double *const *C,
+                                const double *const *V, const double *const *boxes, uint32_t flags, int32_t reps,
+                                double *out_scale, int32_t *out_tile_bins, double *out_ms) {
+  if (!ctx) return ALP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!cases || n_cases < 1 || !C || !V || !out_scale || !out_tile_bins)
+    return fail(ctx, ALP_ERR_INVALID_ARG, "need cases, C, V and outputs");
+  if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "alp_autotune_binning cannot run under capture");
+  if (reps <= 0) reps = 3;
+  flags &= ~ALP_AUTOTUNE;
+  alp_status rc;
+  // each case's default bin size is the reference of its candidates
+  std::vector<double> base((size_t)n_cases);
+  std::vector<int64_t> ncell((size_t)n_cases);
+  for (int i = 0; i < n_cases; ++i) {
+    if (!cases[i].mesh || !C[i] || !V[i]) return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: mesh, C or V is NULL", i);
+    ncell[i] = cases[i].mesh->d.n_cells;
+    alp_mesh *m0 = nullptr;
+    if ((rc = alp_bin_cells(ctx, ncell[i], C[i], V[i], boxes ? boxes[i] : nullptr, 0.0, 4, &m0)) != ALP_OK)
+      return rc;
+    base[i] = m0->d.bin;
+    alp_mesh_destroy(m0);
+  }
+  const double scales[] = {0.75, 1.0, 1.5};
+  const int32_t tiles[] = {2, 3, 4, 5};
+  std::vector<alp_case> cs(cases, cases + n_cases);
+  std::vector<alp_mesh *> best_m, cur((size_t)n_cases, nullptr);
+  double best_ms = INFINITY, best_sc = 1.0;
+  int32_t best_t = 4;
+  auto drop = [](std::vector<alp_mesh *> &v) {
+    for (alp_mesh *m : v)
+      if (m) alp_mesh_destroy(m);
+    v.clear();
+  };
+  for (int32_t T : tiles) {
+    for (double sc : scales) {
+      rc = ALP_OK;
+      cur.assign((size_t)n_cases, nullptr);
+      for (int i = 0; i < n_cases && rc == ALP_OK; ++i) {
+        rc = alp_bin_cells(ctx, ncell[i], C[i], V[i], boxes ? boxes[i] : nullptr, base[i] * sc, T, &cur[i]);
+        cs[i].mesh = cur[i];
+      }
+      double ms = INFINITY;
+      if (rc == ALP_OK) {
+        (void)alp_invalidate(ctx);
+        rc = alp_step_batched(ctx, n_cases, cs.data(), flags | ALP_CHECKED);
+        if (rc == ALP_OK) rc = alp_step_batched(ctx, n_cases, cs.data(), flags);
+        if (rc == ALP_OK && hipStreamSynchronize(ctx->user) != hipSuccess) rc = ALP_ERR_HIP;
+        if (rc == ALP_OK) {
+          const auto t0 = std::chrono::steady_clock::now();
+          for (int r = 0; r < reps && rc == ALP_OK; ++r) rc = alp_step_batched(ctx, n_cases, cs.data(), flags);
+          if (rc == ALP_OK && hipStreamSynchronize(ctx->user) != hipSuccess) rc = ALP_ERR_HIP;
+          ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+        }
+        (void)alp_invalidate(ctx);
+      }
+      if (rc == ALP_OK && ms < best_ms) {
+        drop(best_m);
+        best_m = cur;
+        best_ms = ms;
+        best_sc = sc;
+        best_t = T;
+      } else {
+        drop(cur);
+      }
+      if (rc == ALP_ERR_CAPACITY) continue;  // a per-tile limit: skip this candidate
+      if (rc != ALP_OK) {
+        drop(best_m);
+        return rc;
+      }
+    }
+  }
+  if (!(best_ms < INFINITY)) return fail(ctx, ALP_ERR_INVALID_ARG, "no binning setting could be built");
+  for (int i = 0; i < n_cases; ++i) cases[i].mesh = best_m[i];
+  *out_scale = best_sc;
   *out_tile_bins = best_t;
   if (out_ms) *out_ms = best_ms;
   return ALP_OK;
@@ -1352,6 +1529,25 @@ alp_status alp_invalidate(alp_context *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->st);
   drop_graph(ctx);
+  ctx->tkey.clear();  // the next ALP_AUTOTUNE call chooses again (the shape stays until then)
+  return ALP_OK;
+}
+
+alp_status alp_get_tuning(alp_context *ctx, alp_tuning *out) {
+  if (!ctx || !out) return fail(ctx, ALP_ERR_INVALID_ARG, "NULL argument");
+  *out = ctx->tun;
+  return ALP_OK;
+}
+
+alp_status alp_set_tuning(alp_context *ctx, const alp_tuning *t) {
+  if (!ctx || !t) return fail(ctx, ALP_ERR_INVALID_ARG, "NULL argument");
+  if (!tuning_valid(*t))
+    return fail(ctx, ALP_ERR_INVALID_ARG, "tuning out of range (lanes 2/4/8, waves 0..32, grab 1..16)");
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->st);
+  drop_graph(ctx);
+  ctx->tun = *t;
+  ctx->tkey.clear();
   return ALP_OK;
 }
 

@@ -453,7 +453,10 @@ struct StepLaunch {
   int grid_persistent;     // blocks for persistent wave kernels
   int grid_spread;         // blocks of the spread pass: one per resident wave slot
   int kernel_sample;       // some case uses ALP_SAMPLE_KERNEL
-  int sample_waves;        // sampler waves per CU (0: one wave per 4 points, no cap)
+  int sample_waves;        // sampler waves per CU (0: one wave per 64 / lanes points, no cap)
+  int sample_lanes;        // lanes per point in the sampler (2, 4 or 8)
+  int weights_grab;        // work items a weights wave takes from its queue at once
+  int grid_weights;        // blocks (one wave each) of the weights kernels
   int near_split, near_fp64;  // some case projects with ALP_PROJ_NEAREST in that precision
   int int_split, int_fp64;    // some case projects with ALP_PROJ_INTEGRATED in that precision
 };

@@ -824,6 +824,7 @@ __device__ __forceinline__ double4 loc_record(const MeshDev &m, int64_t j) {
 // Returns the sorted index (the same on every lane of the group) and, in
 // *caller, the caller's index of that cell; -1 for both when x is outside the
 // domain box.
+template <int kLanes = kSampleLanes>
 __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, int sub, int32_t *caller) {
   *caller = -1;
   if (!(x >= m.box[0] && x <= m.box[3] && y >= m.box[1] && y <= m.box[4] && z >= m.box[2] &&
@@ -843,7 +844,7 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
   // kFirstBins bins, in batches of kFirstBatch whose loads are issued
   // together (bin ranges, then the first cell of each).  Later passes add one
   // Chebyshev shell each.
-  constexpr int kFirstBins = (27 + kSampleLanes - 1) / kSampleLanes;
+  constexpr int kFirstBins = (27 + kLanes - 1) / kLanes;
   constexpr int kFirstBatch = 4;
   for (int r = 1;; ++r) {
     if (r == 1) {
@@ -853,7 +854,7 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
 #pragma unroll
         for (int hh = 0; hh < kFirstBatch; ++hh) {
           const int h = h0 + hh;
-          const int c = sub + h * kSampleLanes;
+          const int c = sub + h * kLanes;
           const int ix = qi[0] - 1 + c % 3, iy = qi[1] - 1 + (c / 3) % 3, iz = qi[2] - 1 + c / 9;
           ok[hh] = h < kFirstBins && c < 27 && ix >= 0 && iy >= 0 && iz >= 0 && ix < m.nb[0] && iy < m.nb[1] &&
                    iz < m.nb[2];
@@ -880,7 +881,7 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
     } else {
       const int side = 2 * r + 1;
       const int ncube = side * side * side;
-      for (int c = sub; c < ncube; c += kSampleLanes) {
+      for (int c = sub; c < ncube; c += kLanes) {
         int dz = c / (side * side), dy = (c / side) % side, dx = c % side;
         int ix = qi[0] - r + dx, iy = qi[1] - r + dy, iz = qi[2] - r + dz;
         int ch = max(abs(dx - r), max(abs(dy - r), abs(dz - r)));
@@ -893,7 +894,7 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
     }
     // group reduction (all lanes of the group end with the same best)
 #pragma unroll
-    for (int o = kSampleLanes / 2; o > 0; o >>= 1) {
+    for (int o = kLanes / 2; o > 0; o >>= 1) {
       const double oD = __shfl_xor(nr.bD, o, 64);
       const long long ob = __shfl_xor((long long)nr.best, o, 64);
       const int oc = __shfl_xor(nr.caller, o, 64);
@@ -925,13 +926,14 @@ __device__ int64_t locate_group(const MeshDev &m, double x, double y, double z, 
 
 // Eq. (16)-(18) per actuator point, in the paper's order.  Every lane of a
 // group computes the same values; lane 0 of the group writes them.
+template <int kLanes>
 __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
 #pragma clang fp contract(off)
   Work W = L.w;
-  const int sub = threadIdx.x % kSampleLanes;
-  constexpr int kPts = 64 / kSampleLanes;  // points per wave and pass
+  const int sub = threadIdx.x % kLanes;
+  constexpr int kPts = 64 / kLanes;  // points per wave and pass
   for (int64_t g0 = (int64_t)blockIdx.x * kPts; g0 < W.n_points; g0 += (int64_t)gridDim.x * kPts) {
-  const int64_t g = g0 + threadIdx.x / kSampleLanes;
+  const int64_t g = g0 + threadIdx.x / kLanes;
   const bool act = g < W.n_points;
   bool out = false, fb = false, dg = false;
   int c = 0;
@@ -946,7 +948,7 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
     double e[3] = {et[0] / nrm, et[1] / nrm, et[2] / nrm};
     double ps[3] = {Pa[0], Pa[1], Pa[2]}, us[3] = {0.0, 0.0, 0.0}, as[3] = {0.0, 0.0, 0.0};
     int32_t ca_c = -1, cs_c = -1;  // caller indices of the two cells
-    int64_t ca = locate_group(m, Pa[0], Pa[1], Pa[2], sub, &ca_c), cs_ = -1;
+    int64_t ca = locate_group<kLanes>(m, Pa[0], Pa[1], Pa[2], sub, &ca_c), cs_ = -1;
     if (ca < 0) {
       out = true;
     } else {
@@ -979,7 +981,7 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
       double dn = dot3_exact(np[0], np[1], np[2], es[0], es[1], es[2]);
       double ls = to_global(cs.ls)[b];
       for (int a = 0; a < 3; ++a) ps[a] = Pa[a] + ls * (es[a] - dn * np[a]);
-      cs_ = locate_group(m, ps[0], ps[1], ps[2], sub, &cs_c);
+      cs_ = locate_group<kLanes>(m, ps[0], ps[1], ps[2], sub, &cs_c);
       if (cs_ < 0) {
         out = true;
       } else {
@@ -1032,14 +1034,18 @@ __global__ __launch_bounds__(64) void k_sample(StepLaunch L) {
   }
 }
 
-// One wave per 64 / kSampleLanes points, or (sample_waves > 0) at most that
-// many waves per CU walking the points with a stride.
+// One wave per 64 / lanes points, or (sample_waves > 0) at most that many
+// waves per CU walking the points with a stride.  2, 4 or 8 lanes per point
+// (the tuning chooses; 4 otherwise).
 void launch_sample(const StepLaunch &L, hipStream_t st) {
   if (L.w.n_points == 0) return;
-  int64_t blocks = (L.w.n_points * kSampleLanes + 63) / 64;
+  const int lanes = L.sample_lanes == 2 || L.sample_lanes == 8 ? L.sample_lanes : 4;
+  int64_t blocks = (L.w.n_points * lanes + 63) / 64;
   const int64_t cap = (int64_t)(L.grid_persistent / 8) * L.sample_waves;
   if (cap > 0 && blocks > cap) blocks = cap;
-  hipLaunchKernelGGL(k_sample, dim3((unsigned)blocks), dim3(64), 0, st, L);
+  if (lanes == 2) hipLaunchKernelGGL(k_sample<2>, dim3((unsigned)blocks), dim3(64), 0, st, L);
+  else if (lanes == 8) hipLaunchKernelGGL(k_sample<8>, dim3((unsigned)blocks), dim3(64), 0, st, L);
+  else hipLaunchKernelGGL(k_sample<4>, dim3((unsigned)blocks), dim3(64), 0, st, L);
 }
 
 // ---------------------------------------------------------- kernel sample --
@@ -1502,7 +1508,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   int acc_case = -1;
   unsigned long long acc_pairs = 0, acc_guard = 0;
   WorkQueue wq = work_queue(W.counters + queue_words(kInt ? (kSplit ? 1 : 2) : (kSplit ? 0 : 3)),
-                            (uint32_t)min((int64_t)n_items, W.cap_item), 4u);
+                            (uint32_t)min((int64_t)n_items, W.cap_item), (uint32_t)L.weights_grab);
   const uint32_t n_multi = kMulti ? min(W.counters[kMultiItemCounter], (uint32_t)min((int64_t)n_items, W.cap_item)) : 0u;
   uint32_t mi = blockIdx.x;
   for (;;) {
@@ -2204,10 +2210,11 @@ void k_weights_int64(StepLaunch L) {
 }
 
 void launch_weights(const StepLaunch &L, hipStream_t st) {
-  if (L.near_split) hipLaunchKernelGGL(k_weights, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
-  if (L.near_fp64) hipLaunchKernelGGL(k_weights64, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
-  if (L.int_split) hipLaunchKernelGGL(k_weights_int, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
-  if (L.int_fp64) hipLaunchKernelGGL(k_weights_int64, dim3(L.grid_persistent * 2), dim3(64), 0, st, L);
+  const dim3 g((unsigned)L.grid_weights);
+  if (L.near_split) hipLaunchKernelGGL(k_weights, g, dim3(64), 0, st, L);
+  if (L.near_fp64) hipLaunchKernelGGL(k_weights64, g, dim3(64), 0, st, L);
+  if (L.int_split) hipLaunchKernelGGL(k_weights_int, g, dim3(64), 0, st, L);
+  if (L.int_fp64) hipLaunchKernelGGL(k_weights_int64, g, dim3(64), 0, st, L);
   const int flags[4] = {L.near_split, L.near_fp64, L.int_split, L.int_fp64};
   for (int q = 0; q < 4; ++q)
     if (flags[q]) hipLaunchKernelGGL(k_weights_multi, dim3(kMultiBlocks), dim3(64), 0, st, L, q);

@@ -40,16 +40,17 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2609_39443_amd import alp
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "alp.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(alp_beams), '
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(alp_beams), '
                     'sizeof(alp_params), sizeof(alp_diag), sizeof(alp_case), offsetof(alp_case, beams), '
                     'offsetof(alp_case, params), offsetof(alp_diag, F_beam), sizeof(alp_beam_state), '
-                    'offsetof(alp_beam_state, eps_factor));return 0;}\n')
+                    'offsetof(alp_beam_state, eps_factor), sizeof(alp_tuning));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ct.sizeof(alp.alp_beams), ct.sizeof(alp.alp_params), ct.sizeof(alp.alp_diag),
             ct.sizeof(alp.alp_case), alp.alp_case.beams.offset, alp.alp_case.params.offset,
-            alp.alp_diag.F_beam.offset, ct.sizeof(alp.alp_beam_state), alp.alp_beam_state.eps_factor.offset]
+            alp.alp_diag.F_beam.offset, ct.sizeof(alp.alp_beam_state), alp.alp_beam_state.eps_factor.offset,
+            ct.sizeof(alp.alp_tuning)]
     assert got == want
 
 

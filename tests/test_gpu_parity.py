@@ -555,17 +555,18 @@ def test_integrated_bitwise_across_binnings(gu, ctx):
             assert d[k] == dref[k], (tb, bs, k)
 
 
-def crowded_column(n_b, seed=3, n=5):
+def crowded_column(n_b, seed=3, n=5, span=0.02, eps=0.01):
     """n_b straight vertical beams of n points, all inside one column of
-    4-bin tiles (h = 1 cm), so every tile they reach holds n_b windows."""
+    4-bin tiles (h = 1 cm, roots within span of x = y = 5 cm), so every tile
+    they reach holds n_b windows."""
     C, V = W.uniform_mesh(16, 16, 16, 0.01)
     rng = np.random.default_rng(seed)
     pts = []
     for _ in range(n_b):
-        x0, y0 = 0.05 + 0.02 * rng.random(2)
+        x0, y0 = 0.05 + span * rng.random(2)
         pts.append(np.stack([np.full(n, x0), np.full(n, y0), 0.03 + 0.02 * np.arange(n)], axis=1))
     beams = W._beamset(pts, [np.tile([0, 0, 1.0], (n, 1))] * n_b, [np.zeros((n, 3))] * n_b,
-                       [np.full(n, 0.002)] * n_b, [np.full(n, 0.02)] * n_b, [np.full(n, 0.01)] * n_b,
+                       [np.full(n, 0.002)] * n_b, [np.full(n, 0.02)] * n_b, [np.full(n, eps)] * n_b,
                        np.full(n_b, 1.2), np.full(n_b, 0.0), np.full(n_b, 0.03), np.zeros((n_b, 3)),
                        np.tile([-1.0, 0, 0], (n_b, 1)))
     return {"name": f"crowded-column-{n_b}", "C": C, "V": V, "U": np.tile([0.3, 0.0, 0.0], (C.shape[0], 1)),
@@ -650,3 +651,90 @@ def test_replay_overflow_is_reported(gu):
     gu.compare(case.results(), ref, ctx.diag(0), ref["diag"], 1e-12, 1e-12)
     del case
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+def test_launch_shapes_leave_outputs_bitwise_unchanged(gu, ctx, prec):
+    """Every decision is exact and every sum exact or in a fixed order, so the
+    launch shape (sampler lanes per point and waves, weights queue grab and
+    waves, spread waves) changes no output bit; shapes out of range are
+    rejected."""
+    wls = [W.canopy(n=40, n_stems=30, cv_range=(5, 30), inset=0.04), random_scene(12, outside=True)]
+    cases = [gu.GpuCase(ctx, wl, prec) for wl in wls]
+    alp.alp_set_tuning(ctx.h)
+    gu.step_batched(ctx, cases, alp.USE_GRAPH)
+    ref = [c.results() for c in cases]
+    dref = [ctx.diag(i) for i in range(2)]
+    for shape in ((2, 0, 4, 16, 0), (8, 4, 2, 8, 4), (4, 16, 8, 24, 6), (4, 2, 1, 1, 1), (2, 8, 16, 32, 32)):
+        gu.log(f"[parity] launch shape {shape}")
+        alp.alp_set_tuning(ctx.h, *shape)
+        assert tuple(alp.alp_get_tuning(ctx.h).values()) == shape
+        gu.step_batched(ctx, cases, alp.USE_GRAPH)
+        gu.step_batched(ctx, cases, alp.USE_GRAPH)
+        for i, c in enumerate(cases):
+            r = c.results()
+            for k in r:
+                assert np.array_equal(r[k], ref[i][k]), (shape, i, k)
+            d = ctx.diag(i)
+            for k in ("n_pairs", "n_band_cells", "n_zero_weight", "n_outside", "F_beam"):
+                assert d[k] == dref[i][k], (shape, k)
+    for bad in ((3, 0, 4, 16, 0), (4, -1, 4, 16, 0), (4, 0, 0, 16, 0), (4, 0, 4, 33, 0), (4, 0, 4, 16, 40)):
+        with pytest.raises(alp.AlpError):
+            alp.alp_set_tuning(ctx.h, *bad)
+    alp.alp_set_tuning(ctx.h)
+    alp.alp_invalidate(ctx.h)
+
+
+def test_autotune_flag_chooses_a_shape_and_keeps_outputs(gu, ctx):
+    """ALP_AUTOTUNE times graph replays over the launch shapes before the first
+    step of a new set of cases; the chosen shape is in range and the outputs
+    equal the default shape's bitwise and match the oracle."""
+    wl = W.canopy(n=48, n_stems=40, cv_range=(5, 40), inset=0.05)
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP32_SPLIT)
+    alp.alp_set_tuning(ctx.h)
+    gu.step_batched(ctx, [case], alp.USE_GRAPH)
+    ref = case.results()
+    alp.alp_invalidate(ctx.h)
+    gu.step_batched(ctx, [case], alp.USE_GRAPH | alp.AUTOTUNE)
+    t = alp.alp_get_tuning(ctx.h)
+    gu.log(f"[parity] ALP_AUTOTUNE chose {t}")
+    assert t["sample_lanes"] in (2, 4, 8) and 1 <= t["weights_grab"] <= 16 and 1 <= t["weights_waves"] <= 32
+    gu.step_batched(ctx, [case], alp.USE_GRAPH | alp.AUTOTUNE)  # same cases: no new search
+    res = case.results()
+    for k in res:
+        assert np.array_equal(res[k], ref[k]), k
+    oref = gu.oracle_step(wl)
+    gu.compare(res, oref, ctx.diag(0), oref["diag"], 1e-5, 1e-5)
+    alp.alp_set_tuning(ctx.h)
+    alp.alp_invalidate(ctx.h)
+
+
+def test_binning_autotuners_skip_candidates_over_the_tile_limit(gu, ctx):
+    """4200 two-point beams over a 6 cm square: tiles of 6 cm and more hold
+    all 4200 windows, beyond the merge limit of 4096, so those candidates
+    return ALP_ERR_CAPACITY; both autotuners skip them and return a setting
+    whose step matches the oracle.  The batch autotuner rebins every case."""
+    wl = crowded_column(4200, n=2, span=0.06, eps=0.001)
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP64)
+    gu.log("[parity] alp_autotune with candidates over the tile limit")
+    res = alp.alp_autotune(ctx.h, case.C, case.V, [case.case_struct()], 0, alp.USE_GRAPH, reps=1)
+    gu.log(f"[parity]   chose {res}")
+    run_and_compare(gu, ctx, wl, alp.PREC_FP64, tile_bins=res["tile_bins"], bin_size=res["bin_size"])
+    other = random_scene(15, n_beams=4)
+    c2 = gu.GpuCase(ctx, other, alp.PREC_FP32_SPLIT)
+    case = gu.GpuCase(ctx, wl, alp.PREC_FP64)
+    gu.log("[parity] alp_autotune_binning over a two-case batch")
+    out = alp.alp_autotune_binning(ctx.h, [case.case_struct(), c2.case_struct()], [case.C, c2.C],
+                                   [case.V, c2.V], reps=1)
+    gu.log(f"[parity]   chose scale {out['scale']} tile {out['tile_bins']}")
+    try:
+        case.mesh, c2.mesh = out["meshes"]
+        gu.step_batched(ctx, [case, c2])
+        for i, (c, w_, p) in enumerate(((case, wl, alp.PREC_FP64), (c2, other, alp.PREC_FP32_SPLIT))):
+            ref = gu.oracle_step(w_)
+            tS, tw = TOL[p]
+            gu.compare(c.results(), ref, ctx.diag(i), ref["diag"], tS, tw)
+    finally:
+        alp.alp_invalidate(ctx.h)
+        for m in out["meshes"]:
+            alp.alp_mesh_destroy(m)
