@@ -88,12 +88,14 @@ def counters_from_profiles(kernel, n_cells, n_stems):
     return t.get("kernels", {}).get(kernel) or {}
 
 
-def measure_graph(alp, torch, np, wls, prec, steps, warmup):
+def measure_graph(alp, torch, np, wls, prec, steps, warmup, autotune=False):
     """Device copies of `wls`, one batched graph-captured step over all of
-    them: ms per step and the diagnostics of every case."""
+    them: ms per step and the diagnostics of every case.  With autotune, every
+    case's cells are first rebinned with the batch binning autotuner and the
+    launch shape is chosen by ALP_AUTOTUNE; the choices are returned."""
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     ctx = alp.Context(0)
-    keep, cases = [], []
+    keep, cases, info = [], [], {}
     try:
         for wl in wls:
             C, V, U = dev(wl["C"]), dev(wl["V"]), dev(wl["U"])
@@ -104,20 +106,35 @@ def measure_graph(alp, torch, np, wls, prec, steps, warmup):
             keep.append((C, V, U, beams, f, S))
             cases.append(alp.alp_case(mesh, U.data_ptr(), beams.struct, alp.make_params(wl["params"], prec),
                                       None, f.data_ptr(), S.data_ptr(), None, None, None, None, None))
-        alp.alp_step_batched(ctx.h, cases, alp.USE_GRAPH)
+        flags = alp.USE_GRAPH
+        alp.alp_set_tuning(ctx.h)
+        if autotune:
+            t0 = time.perf_counter()
+            out = alp.alp_autotune_binning(ctx.h, cases, [k[0] for k in keep], [k[1] for k in keep],
+                                           [wl.get("box") for wl in wls], reps=2)
+            ctx.meshes.extend(out["meshes"])
+            for c, m in zip(cases, out["meshes"]):
+                c.mesh = m
+            info["binning"] = {"bin_scale": out["scale"], "tile_bins": out["tile_bins"]}
+            flags |= alp.AUTOTUNE
+            alp.alp_step_batched(ctx.h, cases, flags)
+            info["tuning"] = alp.alp_get_tuning(ctx.h)
+            info["autotune_s"] = time.perf_counter() - t0
+            flags = alp.USE_GRAPH
+        alp.alp_step_batched(ctx.h, cases, flags)
         for _ in range(warmup):
-            alp.alp_step_batched(ctx.h, cases, alp.USE_GRAPH)
+            alp.alp_step_batched(ctx.h, cases, flags)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            alp.alp_step_batched(ctx.h, cases, alp.USE_GRAPH)
+            alp.alp_step_batched(ctx.h, cases, flags)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
         alp.alp_invalidate(ctx.h)
         diags = [ctx.diag(i) for i in range(len(cases))]
     finally:
         ctx.close()
-    return dt, diags
+    return dt, diags, info
 
 
 def host_description():
@@ -262,6 +279,7 @@ def secondary(alp, W, torch, np, steps):
          "the headline canopy (256^3 cells, 2000 stems) under the segment-integrated projection "
          "(a Gaussian integrated along every segment within the cutoff); pairs are (cell, segment)"),
     ]
+    tuned = {"jittered_net", "batched_scenarios"}
     for name, make, desc in specs:
         t0 = time.time()
         wls = make()
@@ -269,8 +287,14 @@ def secondary(alp, W, torch, np, steps):
         ncell = sum(wl["C"].shape[0] for wl in wls)
         log(f"{name}: {len(wls)} case(s), {ncell} cells, {npnt} points ({time.time() - t0:.1f} s to generate)")
         r = {"workload": desc, "n_cases": len(wls), "n_cells": ncell, "n_points": npnt}
-        for tag, prec in (("split", alp.PREC_FP32_SPLIT), ("fp64", alp.PREC_FP64)):
-            dt, diags = measure_graph(alp, torch, np, wls, prec, steps, 2)
+        # the batched scenarios are timed over 100 replays, the others over `steps`
+        nsteps = 100 if name == "batched_scenarios" else steps
+        r["replays"] = nsteps
+        legs = [("split", alp.PREC_FP32_SPLIT, False), ("fp64", alp.PREC_FP64, False)]
+        if name in tuned:
+            legs += [("split_autotuned", alp.PREC_FP32_SPLIT, True), ("fp64_autotuned", alp.PREC_FP64, True)]
+        for tag, prec, auto in legs:
+            dt, diags, info = measure_graph(alp, torch, np, wls, prec, nsteps, 2, autotune=auto)
             pairs = sum(int(d["n_pairs"]) for d in diags)
             r[f"{tag}_ms_per_step"] = dt * 1e3
             r[f"{tag}_points_per_s"] = npnt / dt
@@ -278,11 +302,16 @@ def secondary(alp, W, torch, np, steps):
             r[f"{tag}_max_cons_rel_err"] = max(float(d["cons_rel_err"]) for d in diags
                                                if int(d["n_zero_weight"]) == 0) if any(
                 int(d["n_zero_weight"]) == 0 for d in diags) else None
+            if info:
+                r[f"{tag}_choice"] = info
             r["n_pairs"] = pairs
             r["n_band_cells"] = sum(int(d["n_band_cells"]) for d in diags)
             r["n_overflow"] = sum(int(d["n_overflow"]) for d in diags)
-            log(f"{name} {tag}: {dt * 1e3:.3f} ms/step")
+            r["n_guard_fp64"] = sum(int(d.get("n_guard_fp64", 0)) for d in diags)
+            log(f"{name} {tag}: {dt * 1e3:.3f} ms/step {info if info else ''}")
         r["speedup_split_vs_fp64"] = r["fp64_ms_per_step"] / r["split_ms_per_step"]
+        if name in tuned:
+            r["speedup_autotuned_split"] = r["split_ms_per_step"] / r["split_autotuned_ms_per_step"]
         out[name] = r
         del wls
         torch.cuda.empty_cache()
@@ -337,12 +366,16 @@ def main():
                             out["f"].data_ptr(), S.data_ptr(), out["U_s"].data_ptr(),
                             out["w"].data_ptr(), out["P_s"].data_ptr(), None, None)
 
-    def timed_graph(prec, steps, warmup, stat_reps=STAT_REPLAYS):
+    def timed_graph(prec, steps, warmup, stat_reps=STAT_REPLAYS, autotune=False):
         """K replays timed by the host clock between two synchronisations, then
         `stat_reps` replays timed one by one with events on the caller's
-        stream (each replay is ordered on it): median, p10, p90."""
+        stream (each replay is ordered on it): median, p10, p90.  With
+        autotune the first call chooses the launch shape (ALP_AUTOTUNE);
+        otherwise the default shape is used."""
         cs = [case(prec)]
-        alp.alp_step_batched(ctx.h, cs, alp.USE_GRAPH)   # sizes, runs and captures
+        alp.alp_set_tuning(ctx.h)
+        first = alp.USE_GRAPH | (alp.AUTOTUNE if autotune else 0)
+        alp.alp_step_batched(ctx.h, cs, first)   # (tunes,) sizes, runs and captures
         for _ in range(warmup):
             alp.alp_step_batched(ctx.h, cs, alp.USE_GRAPH)
         torch.cuda.synchronize()
@@ -360,6 +393,7 @@ def main():
         per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(stat_reps)])
         stats = {"replays": stat_reps, "median_ms": float(np.median(per)),
                  "p10_ms": float(np.percentile(per, 10)), "p90_ms": float(np.percentile(per, 90))}
+        stats["tuning"] = alp.alp_get_tuning(ctx.h)
         alp.alp_invalidate(ctx.h)
         return dt, ctx.diag(0), stats
 
@@ -383,27 +417,34 @@ def main():
         torch.cuda.synchronize()
         return {"S": S.cpu().numpy(), "w": out["w"].cpu().numpy(), "f": out["f"].cpu().numpy()}
 
-    # headline: FP32-split, batched persistent launches, graph replay
-    log("timing the FP32-split graph step")
-    t_split, diag, st_split = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup)
+    # the default launch shape first, then the headline: FP32-split, batched
+    # persistent launches, launch shape chosen by ALP_AUTOTUNE, graph replay
+    log("timing the FP32-split graph step, default launch shape")
+    t_def, _, st_def = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup)
+    log(f"default shape: {t_def * 1e3:.3f} ms/step")
+    log("timing the FP32-split graph step, autotuned launch shape")
+    t_split, diag, st_split = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup, autotune=True)
     got = {"split": host_outputs()}
     log(f"split: {t_split * 1e3:.3f} ms/step (median {st_split['median_ms']:.3f}, "
         f"p10 {st_split['p10_ms']:.3f}, p90 {st_split['p90_ms']:.3f}), diag {diag}")
     # live per-stage timings (HIP events on the stream the kernels run on)
+    alp.alp_set_tuning(ctx.h, **st_split["tuning"])  # the stage timings use the chosen shape
     stage_runs = [alp.alp_step_profile(ctx.h, [case(alp.PREC_FP32_SPLIT)]) for _ in range(5)]
     stages = {k: float(np.median([r[k] for r in stage_runs])) for k in stage_runs[0]}
     log(f"stages (ms): {stages}")
     res = {}
     stages64 = None
     if not args.no_fp64:
-        t64, d64, st64 = timed_graph(alp.PREC_FP64, max(3, args.steps // 2), 1)
+        t64, d64, st64 = timed_graph(alp.PREC_FP64, max(3, args.steps // 2), 1, autotune=True)
         got["fp64"] = host_outputs()
         res["fp64_graph_ms_per_step"] = t64 * 1e3
         res["fp64_step_stats"] = st64
         res["fp64_cons_rel_err"] = d64["cons_rel_err"]
+        alp.alp_set_tuning(ctx.h, **st64["tuning"])
         stage64 = [alp.alp_step_profile(ctx.h, [case(alp.PREC_FP64)]) for _ in range(3)]
         stages64 = {k: float(np.median([r[k] for r in stage64])) for k in stage64[0]}
         res["fp64_stages_ms"] = stages64
+        alp.alp_set_tuning(ctx.h)  # the plain path: unbatched, uncaptured, default shape
         tp = timed_plain(alp.PREC_FP64, max(3, args.steps // 4), 1)
         res["plain_fp64_unbatched_ms_per_step"] = tp * 1e3
         res["speedup_split_vs_fp64_graph"] = t64 / t_split
@@ -458,10 +499,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"canopy: {args.n}^3 uniform cells (h = 4 mm), {args.stems} stems of "
                                f"20-200 CVs, FP32-split, all stems in one persistent launch per stage, "
-                               f"hipGraph replay", "n_cells": n_cells, "n_points": npnt,
+                               f"launch shape chosen by ALP_AUTOTUNE, hipGraph replay", "n_cells": n_cells,
+                   "n_points": npnt,
                    "n_band_cells": n_band, "n_pairs": n_pairs, "parallelism": "single GPU"},
         "cell_updates_per_s": n_pairs / t_split, "band_cells_per_s": n_band / t_split,
         "mesh_cells_per_s": n_cells / t_split, "step_stats": st_split,
+        "default_shape_ms_per_step": t_def * 1e3, "default_shape_step_stats": st_def,
         "alg_bytes_per_band_cell": BYTES_PER_BAND_CELL["split"], "alg_bytes_per_point": BYTES_PER_POINT,
         "alg_bytes_per_step": bytes_step, "alg_hbm_gbps": gbps, "alg_hbm_frac": gbps / HBM_PEAK_GBPS,
         "cons_rel_err": diag["cons_rel_err"], "accuracy": accuracy, "stages_ms": stages, "roofline": roofline,
