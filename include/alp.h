@@ -243,7 +243,10 @@ typedef struct {
 } alp_case;
 
 #define ALP_USE_GRAPH 1u /* capture the step on the first call, replay it afterwards */
-#define ALP_CHECKED 2u   /* synchronise at the end and grow the work lists on overflow */
+#define ALP_CHECKED 2u   /* synchronise at the end, grow the work lists on overflow, and check
+                            the pair-record layout on the host (every item's records inside the
+                            allocated record area, no two items' records overlapping):
+                            ALP_ERR_HIP if violated */
 #define ALP_AUTOTUNE 4u  /* before the first step of a new set of cases, choose the launch
                             shape (alp_tuning) by timing graph replays of the step */
 

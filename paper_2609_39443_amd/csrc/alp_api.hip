@@ -599,8 +599,49 @@ alp_status read_needs(alp_context *ctx, uint32_t &ovf, int64_t &need_emit, int64
   return ALP_OK;
 }
 
+// ALP_CHECKED: the record layout the weights pass left, checked on the host
+// (synchronises).  Every item's records must lie inside the record area the
+// wave allocator handed out, item ranges must not overlap, and a base may
+// carry only its flag bits (record size, grouped item) below 16 bytes.  The
+// spread reads records j < count of each item from its base and nothing else,
+// so these invariants bound every record read of the step.
+alp_status verify_records(alp_context *ctx) {
+  const Work &w = ctx->w;
+  uint32_t n_items = 0;
+  unsigned long long used = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&n_items, w.tile_itoff + w.n_tiles, sizeof(n_items), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(&used, w.rec_alloc, sizeof(used), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  const size_t n = (size_t)std::min<int64_t>(n_items, w.cap_item);
+  std::vector<uint32_t> cnt(n);
+  std::vector<unsigned long long> base(n);
+  if (n > 0) {
+    HIPCHK(ctx, hipMemcpyAsync(cnt.data(), w.rec_cnt, n * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(ctx, hipMemcpyAsync(base.data(), w.rec_base, n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               ctx->st));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  }
+  const unsigned long long limit = std::min<unsigned long long>(used, (unsigned long long)w.cap_rec);
+  std::vector<std::pair<unsigned long long, unsigned long long>> r;
+  r.reserve(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (cnt[i] == 0) continue;
+    if (base[i] & 12ull) return fail(ctx, ALP_ERR_HIP, "record invariant: item %zu base 0x%llx", i, base[i]);
+    const unsigned long long a = base[i] & ~15ull, e = a + (unsigned long long)cnt[i] * ((base[i] & 1ull) ? 24 : 16);
+    if (e > limit)
+      return fail(ctx, ALP_ERR_HIP, "record invariant: item %zu records end at %llu beyond %llu", i, e, limit);
+    r.emplace_back(a, e);
+  }
+  std::sort(r.begin(), r.end());
+  for (size_t i = 1; i < r.size(); ++i)
+    if (r[i].first < r[i - 1].second)
+      return fail(ctx, ALP_ERR_HIP, "record invariant: overlapping item records at %llu", r[i].first);
+  return ALP_OK;
+}
+
 alp_status run_checked(alp_context *ctx, std::vector<CaseDev> &cs, int stages,
-                       const std::vector<alp_mesh *> &meshes, const std::vector<double *> &S) {
+                       const std::vector<alp_mesh *> &meshes, const std::vector<double *> &S,
+                       bool verify = false) {
   StepShape sh = shape_cases(ctx, cs);
   int64_t want_emit = std::max<int64_t>(ctx->have_emit, 16 * sh.n_points + 4096);
   int64_t want_rec = std::max<int64_t>(ctx->have_rec, 24 * (3 * sh.n_cells + (1 << 16)) +
@@ -617,7 +658,7 @@ alp_status run_checked(alp_context *ctx, std::vector<CaseDev> &cs, int stages,
     uint32_t ovf;
     int64_t ne, nr;
     if ((rc = read_needs(ctx, ovf, ne, nr)) != ALP_OK) return rc;
-    if (ovf == 0) return ALP_OK;
+    if (ovf == 0) return verify ? verify_records(ctx) : ALP_OK;
     if (ovf & (4u | 8u | 16u))
       return fail(ctx, ALP_ERR_CAPACITY,
                   "per-tile limits exceeded (flags 0x%x): more than %d segment windows in one tile",
@@ -1161,6 +1202,7 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
       int64_t ne, nr;
       if ((rc = read_needs(ctx, ovf, ne, nr)) != ALP_OK) return rc;
       if (ovf) return fail(ctx, ALP_ERR_CAPACITY, "work list overflow in graph replay (0x%x); call alp_invalidate", ovf);
+      if ((rc = verify_records(ctx)) != ALP_OK) return rc;
     }
     ctx->last_cases = n_cases;
     ctx->dg_cnt = nullptr;
@@ -1174,7 +1216,7 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
   if ((rc = build_batch(ctx, n_cases, cases, cs, meshes, S)) != ALP_OK) return rc;
   if ((rc = enter(ctx)) != ALP_OK) return rc;
   // size the work lists with a checked run (this also produces this step's result)
-  if ((rc = run_checked(ctx, cs, ST_ALL, meshes, S)) != ALP_OK) return rc;
+  if ((rc = run_checked(ctx, cs, ST_ALL, meshes, S, (flags & ALP_CHECKED) != 0)) != ALP_OK) return rc;
   ctx->last_cases = n_cases;
   ctx->dg_cnt = nullptr;
   ctx->dg_out = nullptr;

@@ -13,6 +13,7 @@
 // balance are accumulated as exact fixed-point integers, and every source
 // value is summed by one lane in beam order.
 #include "alp_internal.h"
+#include "alp_reccursor.h"
 
 namespace alp {
 
@@ -2325,7 +2326,13 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // records of a work item are sorted by cell, so each cell owns one contiguous
 // run; its lane sums the run in record order.  Every cell of an active tile
 // is written.
-constexpr int kSpreadChunk = 64;  // records summed per pass, one per lane
+// The record counts and bases of the work items, for the record cursor.
+struct ItemRecs {
+  const uint32_t *c;
+  const unsigned long long *b;
+  __device__ __forceinline__ uint32_t cnt(uint32_t i) const { return c[i]; }
+  __device__ __forceinline__ uint64_t base(uint32_t i) const { return b[i]; }
+};
 
 struct SpreadScratch {
   double cc[3][kSpreadChunk];
@@ -2333,57 +2340,21 @@ struct SpreadScratch {
   uint8_t cl[kSpreadChunk];      // cell lane of each record (items with several runs per cell)
 };
 
-// The records of a wave's items, taken as one stream of 64-record chunks.  A
-// cursor runs two chunks ahead of the summation, so the records of the next
-// two chunks are in flight while one is summed; it holds the descriptor of
-// the item after its own, read ahead as well.  An item's record base carries
-// the record size in bit 0 (bases are 16-byte aligned): set for the 24-byte
-// FP64 records, whose a1 is read when the chunk is summed.
-struct RecCursor {
-  uint32_t item, p0, rn;     // item, first record of the chunk to fetch, item's record count
-  unsigned long long rb;     // item's record base (with the size bit)
-  uint32_t gitem, grn;       // the item after it
-  unsigned long long grb;
-  bool done;
-};
-
-// skip to the next chunk that has records
-__device__ __forceinline__ void rec_settle(const Work &W, RecCursor &c, uint32_t n_items, uint32_t stride) {
-  while (!c.done && c.p0 >= c.rn) {
-    if (c.gitem >= n_items) {
-      c.done = true;
-      break;
-    }
-    c.item = c.gitem;
-    c.rn = c.grn;
-    c.rb = c.grb;
-    c.p0 = 0;
-    c.gitem += stride;
-    if (c.gitem < n_items) {
-      c.grn = W.rec_cnt[c.gitem];
-      c.grb = W.rec_base[c.gitem];
-    }
-  }
-}
-
 // this lane's record of the cursor's chunk (meta, node, a0 as FP32 or the
 // two words of the FP64 a0), then the cursor moves on
-__device__ __forceinline__ uint4 rec_take(const Work &W, RecCursor &c, uint32_t n_items, uint32_t stride,
-                                          int lane) {
+__device__ __forceinline__ uint4 rec_take(const Work &W, const ItemRecs &src, RecCursor &c, uint32_t n_items,
+                                          uint32_t stride, int lane) {
   uint4 r = make_uint4(0u, 0u, 0u, 0u);
-  if (!c.done) {
-    const uint32_t j = c.p0 + (uint32_t)lane;
-    if (j < c.rn) {
-      const unsigned char *p = W.rec + (c.rb & ~15ull) + (size_t)j * ((c.rb & 1ull) ? 24 : 16);
-      if (c.rb & 1ull) {
-        const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 8);
-        r = make_uint4(lo.x, lo.y, hi.x, hi.y);
-      } else {
-        r = *(const uint4 *)p;
-      }
+  uint32_t bytes;
+  const uint64_t at = rec_next(src, c, n_items, stride, lane, &bytes);
+  if (at != kRecNone) {
+    const unsigned char *p = W.rec + at;
+    if (bytes == 24u) {
+      const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 8);
+      r = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    } else {
+      r = *(const uint4 *)p;
     }
-    c.p0 += kSpreadChunk;
-    rec_settle(W, c, n_items, stride);
   }
   return r;
 }
@@ -2416,22 +2387,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
     nrb = W.rec_base[item + stride];
   }
   // the record stream, two chunks ahead
-  RecCursor cur;
-  cur.item = item;
-  cur.p0 = 0;
-  cur.rn = rn;
-  cur.rb = rb;
-  cur.gitem = item + stride;
-  cur.grn = 0;
-  cur.grb = 0;
-  cur.done = false;
-  if (cur.gitem < n_items) {
-    cur.grn = W.rec_cnt[cur.gitem];
-    cur.grb = W.rec_base[cur.gitem];
-  }
-  rec_settle(W, cur, n_items, stride);
-  uint4 R1 = rec_take(W, cur, n_items, stride, lane);
-  uint4 R2 = rec_take(W, cur, n_items, stride, lane);
+  const ItemRecs src{W.rec_cnt, W.rec_base};
+  RecCursor cur = rec_start(src, item, rn, rb, n_items, stride);
+  uint4 R1 = rec_take(W, src, cur, n_items, stride, lane);
+  uint4 R2 = rec_take(W, src, cur, n_items, stride, lane);
   __syncthreads();
   for (;;) {
     if (it.cs != acc_case) {
@@ -2466,7 +2425,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
       const uint32_t nch = min(rn - p0, (uint32_t)kSpreadChunk);
       const uint4 C = R1;
       R1 = R2;
-      R2 = rec_take(W, cur, n_items, stride, lane);
+      R2 = rec_take(W, src, cur, n_items, stride, lane);
       const uint32_t j = (uint32_t)lane;
       uint32_t cl = ~0u;
       if (j < nch) {

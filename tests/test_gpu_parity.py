@@ -738,3 +738,22 @@ def test_binning_autotuners_skip_candidates_over_the_tile_limit(gu, ctx):
         alp.alp_invalidate(ctx.h)
         for m in out["meshes"]:
             alp.alp_mesh_destroy(m)
+
+
+def test_checked_steps_verify_the_record_layout(gu, ctx):
+    """ALP_CHECKED checks on the host, after the step, that every work item's
+    pair records lie inside the allocated record area and that no two items'
+    records overlap, for 16- and 24-byte records and grouped items (a tile
+    column crowded by 200 beams), uncaptured and in graph replay."""
+    wls = [W.canopy(n=40, n_stems=30, cv_range=(5, 30), inset=0.04), crowded_column(200), random_scene(16)]
+    precs = [alp.PREC_FP32_SPLIT, alp.PREC_FP64, alp.PREC_FP32_SPLIT]
+    cases = [gu.GpuCase(ctx, wl, p, **({"tile_bins": 4, "bin_size": 0.01} if i == 1 else {}))
+             for i, (wl, p) in enumerate(zip(wls, precs))]
+    gu.step_batched(ctx, cases, alp.CHECKED)
+    for flags in (alp.USE_GRAPH | alp.CHECKED, alp.USE_GRAPH | alp.CHECKED):
+        gu.step_batched(ctx, cases, flags)
+    for i, (c, wl, p) in enumerate(zip(cases, wls, precs)):
+        ref = gu.oracle_step(wl)
+        tS, tw = TOL[p]
+        gu.compare(c.results(), ref, ctx.diag(i), ref["diag"], tS, tw)
+    alp.alp_invalidate(ctx.h)
