@@ -189,6 +189,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
               sh.cap_item > ctx->have_item || want_rec > ctx->have_rec ||
               sh.cap_chunk > ctx->have_chunk;
   if (!grow) {
+    w.rec_compact = sh.n_points < kRecCompactPoints ? 1 : 0;
     w.n_points = sh.n_points;
     w.n_beams = sh.n_beams;
     w.n_tiles = sh.n_tiles;
@@ -282,6 +283,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   w.n_tiles = sh.n_tiles;
   w.n_cases = sh.n_cases;
   w.n_pblocks = sh.n_pblocks;
+  w.rec_compact = sh.n_points < kRecCompactPoints ? 1 : 0;
   return ALP_OK;
 }
 
@@ -626,8 +628,10 @@ alp_status verify_records(alp_context *ctx) {
   r.reserve(n);
   for (size_t i = 0; i < n; ++i) {
     if (cnt[i] == 0) continue;
-    if (base[i] & 12ull) return fail(ctx, ALP_ERR_HIP, "record invariant: item %zu base 0x%llx", i, base[i]);
-    const unsigned long long a = base[i] & ~15ull, e = a + (unsigned long long)cnt[i] * ((base[i] & 1ull) ? 24 : 16);
+    if ((base[i] & 8ull) || (base[i] & 5ull) == 5ull)
+      return fail(ctx, ALP_ERR_HIP, "record invariant: item %zu base 0x%llx", i, base[i]);
+    const unsigned long long a = base[i] & ~15ull,
+                             e = a + (unsigned long long)cnt[i] * ((base[i] & 1ull) ? 24 : ((base[i] & 4ull) ? 12 : 16));
     if (e > limit)
       return fail(ctx, ALP_ERR_HIP, "record invariant: item %zu records end at %llu beyond %llu", i, e, limit);
     r.emplace_back(a, e);
@@ -784,6 +788,7 @@ bool carve_fixed(Carver &cv, Work &w, const StepShape &sh, CaseDev **d_cases, in
   w.n_tiles = T;
   w.n_cases = (int32_t)NC;
   w.n_pblocks = PB;
+  w.rec_compact = P < kRecCompactPoints ? 1 : 0;
   return cv.ok;
 }
 

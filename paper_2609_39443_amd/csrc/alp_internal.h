@@ -81,12 +81,20 @@ struct Emit {
   int32_t tile;   // global tile index
 };
 
-// Pair record written by the weights pass and read by the spread pass:
-// meta = cell lane in the work item (bits 0-5) | 0x80 for a single-point beam,
-// node = global index of the first node, then a0, a1 as float (split) or
-// double (FP64).  16 or 24 bytes.
+// Pair record written by the weights pass and read by the spread pass.  Split
+// precision: one word holding the cell lane in the work item (bits 0-5), 1 in
+// bit 6 for a single-point beam and the global index of the first node above
+// bit 6, then a0 and a1 as float: 12 bytes, while a batch has fewer than 2^25
+// points; else the 16-byte form below with a0, a1 as float.  FP64: meta = cell
+// lane | 0x80 for a single-point beam, node = the global index of the first
+// node, then a0, a1 as double: 24 bytes.  The spread reads every form into
+// the 16-byte layout (meta, node, a0 bits, a1 bits or the FP64 a0).
 constexpr uint32_t kRecSingle = 0x80u;
-__host__ __device__ inline int rec_size(int prec) { return prec == ALP_PREC_FP32_SPLIT ? 16 : 24; }
+constexpr int kRecNodeShift = 7;                    // node above the lane and single bit (12-byte form)
+constexpr int64_t kRecCompactPoints = 1ll << 25;    // the 12-byte form holds node indices below this
+__host__ __device__ inline int rec_size(int prec, bool compact) {
+  return prec == ALP_PREC_FP32_SPLIT ? (compact ? 12 : 16) : 24;
+}
 
 // A window grouped by tile: the tile is implied by the position; k0 is the
 // beam's first point (case-local) and hi < 0 marks a single-point beam.
@@ -168,6 +176,7 @@ struct Work {
   uint32_t *scan_tmp;   // scan block totals (host-side launch use only)
   int64_t cap_emit, cap_item, cap_rec, cap_chunk;
   int64_t n_points, n_beams, n_tiles;
+  int32_t rec_compact;  // split-precision pair records in the 12-byte form (n_points < 2^25)
   int32_t n_cases, n_pblocks;
 };
 

@@ -17,10 +17,11 @@ constexpr int kSpreadChunk = 64;          // records summed per pass, one per la
 constexpr uint64_t kRecNone = ~0ull;      // no record for this lane
 
 // An item's record base carries flags in its low bits (bases are 16-byte
-// aligned): bit 0 for 24-byte records (FP64 weights), else 16 bytes; bit 1
-// for an item whose cells have one run of records per entry group.
+// aligned): bit 0 for 24-byte records (FP64 weights), bit 2 for 12-byte
+// records (FP32 weights, packed node index), else 16 bytes; bit 1 for an item
+// whose cells have one run of records per entry group.
 ALP_HD uint64_t rec_addr(uint64_t rb) { return rb & ~15ull; }
-ALP_HD uint32_t rec_bytes(uint64_t rb) { return (rb & 1ull) ? 24u : 16u; }
+ALP_HD uint32_t rec_bytes(uint64_t rb) { return (rb & 1ull) ? 24u : ((rb & 4ull) ? 12u : 16u); }
 
 // The records of a wave's items (item, item + stride, ...), taken as one
 // stream of 64-record chunks.  The cursor runs ahead of the summation; it

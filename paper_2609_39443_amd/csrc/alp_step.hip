@@ -1476,7 +1476,14 @@ __device__ __forceinline__ uint32_t int_count(const CaseDev &cs, int k0, int i0,
 
 __device__ __forceinline__ void write_record(unsigned char *r, int rsz, uint32_t meta, uint32_t node, double a0,
                                              double a1) {
-  if (rsz == 16) {
+  if (rsz == 12) {
+    // lane and single bit below the node index
+    const uint32_t w0 = (meta & 63u) | ((meta & kRecSingle) ? 64u : 0u) | (node << kRecNodeShift);
+    uint32_t *q = (uint32_t *)r;
+    q[0] = w0;
+    q[1] = __float_as_uint((float)a0);
+    q[2] = __float_as_uint((float)a1);
+  } else if (rsz == 16) {
     uint4 q;
     q.x = meta;
     q.y = node;
@@ -1546,7 +1553,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     const gptr<double> Eps = to_global(cs.eps);
     const int64_t pbase = cs.point_base;
     const int64_t tl = it.tile - cs.tile_base;
-    const int rsz = rec_size(cs.prec);
+    const int rsz = rec_size(cs.prec, W.rec_compact != 0);
     // the tile's entries, in beam order; more than kMaxEntries are taken in
     // groups of kMaxEntries, one after another
     const uint32_t ne_all = it.nent;
@@ -2119,21 +2126,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
         if (act && in && rec_ok) {
           const unsigned long long at = rbase + (unsigned long long)(nreal + lanemask_lt_popc(bal)) * rsz;
           unsigned char *r = W.rec + at;
-          const uint32_t meta = (uint32_t)Lc | (single ? kRecSingle : 0u);
-          if (rsz == 16) {
-            uint4 q;
-            q.x = meta;
-            q.y = (uint32_t)bi;
-            q.z = __float_as_uint((float)a0);
-            q.w = __float_as_uint((float)a1);
-            *(uint4 *)r = q;
-          } else {
-            uint2 q;
-            q.x = meta;
-            q.y = (uint32_t)bi;
-            *(uint2 *)r = q;
-            *(double2 *)(r + 8) = make_double2(a0, a1);
-          }
+          write_record(r, rsz, (uint32_t)Lc | (single ? kRecSingle : 0u), (uint32_t)bi, a0, a1);
         }
         nreal += (uint32_t)__popcll(bal);
         acc_guard += (unsigned long long)__popcll(ballot64(act && guard));
@@ -2159,10 +2152,10 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     }  // entry groups
     if (multi) blk_cur = rbase + (((unsigned long long)nreal * rsz + 15ull) & ~15ull);
     if (lane == 0) {
-      // bases are 16-byte aligned: bit 0 carries the record size (set for 24
-      // bytes), bit 1 marks an item whose cells have records in several runs
-      // (one per entry group)
-      W.rec_base[item] = rbase | (rsz == 24 ? 1ull : 0ull) | (multi ? 2ull : 0ull);
+      // bases are 16-byte aligned: bits 0 and 2 carry the record size (24
+      // and 12 bytes), bit 1 marks an item whose cells have records in
+      // several runs (one per entry group)
+      W.rec_base[item] = rbase | (rsz == 24 ? 1ull : 0ull) | (rsz == 12 ? 4ull : 0ull) | (multi ? 2ull : 0ull);
       W.rec_cnt[item] = rec_ok ? nreal : 0u;
     }
     acc_pairs += nreal;
@@ -2352,6 +2345,10 @@ __device__ __forceinline__ uint4 rec_take(const Work &W, const ItemRecs &src, Re
     if (bytes == 24u) {
       const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 8);
       r = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    } else if (bytes == 12u) {
+      const uint32_t *q = (const uint32_t *)p;
+      const uint32_t w0 = q[0], a0 = q[1], a1 = q[2];
+      r = make_uint4((w0 & 63u) | ((w0 & 64u) ? kRecSingle : 0u), w0 >> kRecNodeShift, a0, a1);
     } else {
       r = *(const uint4 *)p;
     }

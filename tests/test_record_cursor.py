@@ -5,7 +5,7 @@ stride, ...) as one stream of 64-record chunks, with the cursor two chunks
 ahead of the summation and the next item's count and base read one item
 ahead.  A C++ program compiled on the host from the same header replays that
 walk for every wave of a grid over random record layouts (items without
-records, 16- and 24-byte records, grouped items, gaps between reservations,
+records, 12-, 16- and 24-byte records, grouped items, gaps between reservations,
 grids larger than the item count) and checks that every record read lies
 inside its own item's records and inside the record area, that no item's
 count or base is read past the item count, and that the chunk each lane sums
@@ -59,10 +59,11 @@ int main() {
       if (mode == 0) c = (rng() % 3 == 0) ? 0 : (uint32_t)(rng() % 200);
       else if (mode == 2) c = (uint32_t)(rng() % 1000);
       else if (mode == 3) c = (rng() % 10 == 0) ? 1 + (uint32_t)(rng() % 70) : 0;
-      const bool fp64 = rng() % 2, grouped = rng() % 5 == 0;
-      const uint32_t size = fp64 ? 24 : 16;
+      const int kind = (int)(rng() % 3);  // 24-, 16- or 12-byte records
+      const bool grouped = rng() % 5 == 0;
+      const uint32_t size = kind == 0 ? 24 : (kind == 1 ? 16 : 12);
       top += 16 * (rng() % 4);  // a gap
-      base[i] = top | (fp64 ? 1ull : 0ull) | (grouped ? 2ull : 0ull);
+      base[i] = top | (kind == 0 ? 1ull : 0ull) | (kind == 2 ? 4ull : 0ull) | (grouped ? 2ull : 0ull);
       top += ((uint64_t)c * size + 15) & ~15ull;
       cnt[i] = c;
     }
