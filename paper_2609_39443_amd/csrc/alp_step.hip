@@ -2062,8 +2062,44 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
                 // the one or two segments in the band are evaluated exactly;
                 // their node widths are loaded with their end points, not
                 // after the choice
-                const int j1 = (int)(k1 & kSegIdxMask);
-                const bool two = k2 != ~0u && __uint_as_float(k2 & ~kSegIdxMask) <= band;
+                int j1 = (int)(k1 & kSegIdxMask);
+                bool two = k2 != ~0u && __uint_as_float(k2 & ~kSegIdxMask) <= band;
+                if (two) {
+                  const int j2 = (int)(k2 & kSegIdxMask);
+                  if (j2 == j1 + 1 || j2 + 1 == j1) {
+                    // Neighbouring segments a (A -> V) and b (V -> B) meet at V.
+                    // If the cell's projection falls before V on a's line
+                    // (t_a < 1) and not after V on b's (t_b <= 0), a's closest
+                    // point lies strictly closer than V, which is b's closest
+                    // point: a wins; mirrored for b.  The FP32 parameters are
+                    // trusted only beyond 2^-19 ((R/|e|)^2 + R/|e|) + 2^-20 of
+                    // the thresholds, R the largest coordinate of the window:
+                    // a bound, with a margin of 16 and more, on their error from
+                    // rounding and on the zone where the exact squared
+                    // distances differ by less than their FP64 rounding.
+                    const int ja = min(j1, j2);
+                    const float4 Aa = sh.sa[pt0 + ja], Vv = sh.sa[pt0 + ja + 1], Bb = sh.sa[pt0 + ja + 2];
+                    if (Aa.w > 0.f && Vv.w > 0.f) {
+                      const float qx = (float)(pcx - ctx), qy = (float)(pcy - cty), qz = (float)(pcz - ctz);
+                      const float R2 = sh.e_dabs[e] * 0x1p14f;  // R^2 of the window (the allowance is 2^-14 R^2)
+                      const float ax = Vv.x - Aa.x, ay = Vv.y - Aa.y, az = Vv.z - Aa.z;
+                      const float bx = Bb.x - Vv.x, by = Bb.y - Vv.y, bz = Bb.z - Vv.z;
+                      // t_a - 1 and t_b times |e|^2 (1/|e|^2 is each segment's staged w)
+                      const float ga = (qx - Aa.x) * ax + (qy - Aa.y) * ay + (qz - Aa.z) * az - 1.0f / Aa.w;
+                      const float gb = (qx - Vv.x) * bx + (qy - Vv.y) * by + (qz - Vv.z) * bz;
+                      const float ra = R2 * Aa.w, rb = R2 * Vv.w;  // (R/|e|)^2
+                      const float da = (0x1p-19f * (ra + __builtin_amdgcn_sqrtf(ra)) + 0x1p-20f) / Aa.w;
+                      const float db = (0x1p-19f * (rb + __builtin_amdgcn_sqrtf(rb)) + 0x1p-20f) / Vv.w;
+                      if (ga < -da && gb < -db) {
+                        j1 = ja;
+                        two = false;
+                      } else if (ga > da && gb > db) {
+                        j1 = ja + 1;
+                        two = false;
+                      }
+                    }
+                  }
+                }
                 guard = two;
                 const gptr<double> E = Eps + (int64_t)k0 + i0;
                 double e0 = E[j1], e1 = E[j1 + 1];
