@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "alp_internal.h"
+#include "alp_reccursor.h"
 
 using namespace alp;
 
@@ -219,7 +220,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(wexp, P);
   WALLOC(w_hi, P);
   WALLOC(w_lo, P);
-  WALLOC(fhat, 3 * P);
+  WALLOC(fhat, 3 * (P + 2));  // two nodes of slack: the spread reads both nodes of every record
   WALLOC(Us, 3 * P);
   WALLOC(Ps, 3 * P);
   WALLOC(As, 3 * P);
@@ -246,7 +247,7 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
   WALLOC(multi_items, IT);
   WALLOC(rec_base, IT);
   WALLOC(rec_cnt, IT);
-  WALLOC(rec, RC);
+  WALLOC(rec, RC + (int64_t)kRecSlack);  // the spread reads 24 bytes from every record's start
   WALLOC(rec_alloc, 1);
   WALLOC(F_hi, 3 * NC);
   WALLOC(F_lo, 3 * NC);
@@ -634,6 +635,9 @@ alp_status verify_records(alp_context *ctx) {
                              e = a + (unsigned long long)cnt[i] * ((base[i] & 1ull) ? 24 : ((base[i] & 4ull) ? 12 : 16));
     if (e > limit)
       return fail(ctx, ALP_ERR_HIP, "record invariant: item %zu records end at %llu beyond %llu", i, e, limit);
+    // the spread reads kRecReadBytes from the start of every record
+    if (e - (e - a) / cnt[i] + kRecReadBytes > (unsigned long long)w.cap_rec + kRecSlack)
+      return fail(ctx, ALP_ERR_HIP, "record invariant: item %zu: a record read passes the record area", i);
     r.emplace_back(a, e);
   }
   std::sort(r.begin(), r.end());
@@ -747,7 +751,7 @@ bool carve_fixed(Carver &cv, Work &w, const StepShape &sh, CaseDev **d_cases, in
   w.wexp = cv.take<int32_t>(P);
   w.w_hi = cv.take<long long>(P);
   w.w_lo = cv.take<unsigned long long>(P);
-  w.fhat = cv.take<double>(3 * P);
+  w.fhat = cv.take<double>(3 * (P + 2));
   w.Us = cv.take<double>(3 * P);
   w.Ps = cv.take<double>(3 * P);
   w.As = cv.take<double>(3 * P);
@@ -1280,11 +1284,11 @@ alp_status alp_step_noalloc(alp_context *ctx, int32_t n_cases, const alp_case *c
   const size_t rec_off = (cv.off + 255) & ~(size_t)255;
   const int64_t rc_bytes = cv.ok && rec_off < cv.size ? (int64_t)((cv.size - rec_off) & ~(size_t)255) : 0;
   w.rec = cv.take<unsigned char>(rc_bytes);
-  if (!cv.ok || em <= 0 || rc_bytes <= 0)
+  if (!cv.ok || em <= 0 || rc_bytes <= (int64_t)kRecSlack)
     return fail(ctx, ALP_ERR_CAPACITY, "no room left for the window and pair lists in %zu bytes",
                 (size_t)kScratchBytes);
   w.cap_emit = em;
-  w.cap_rec = rc_bytes;
+  w.cap_rec = rc_bytes - (int64_t)kRecSlack;
   if ((rc = enter(ctx)) != ALP_OK) return rc;
   // case table, bases and point blocks (from host arrays the context keeps);
   // the transfers complete before the host arrays can change

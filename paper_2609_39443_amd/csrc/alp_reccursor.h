@@ -1,9 +1,9 @@
 // alp_reccursor.h -- the spread pass's walk over the pair records of a wave's
-// work items, as index arithmetic only: which byte offset of the record area
-// each lane reads for each 64-record chunk.  The spread kernel loads through
-// it; a host program compiled from the same source replays it over record
-// layouts with bounds checks (no HIP header here, so a host compiler can
-// include it with ALP_HD defined empty).
+// work items, as index arithmetic only: which chunk of which item comes next,
+// and which byte offset of the record area each lane reads for it.  The
+// spread kernel loads through it; a host program compiled from the same
+// source replays it over record layouts with bounds checks (no HIP header
+// here, so a host compiler can include it with ALP_HD defined empty).
 #pragma once
 #include <stdint.h>
 
@@ -15,6 +15,8 @@ namespace alp {
 
 constexpr int kSpreadChunk = 64;          // records summed per pass, one per lane
 constexpr uint64_t kRecNone = ~0ull;      // no record for this lane
+constexpr uint32_t kRecReadBytes = 24;    // bytes a lane loads from a record's start, whatever its size
+constexpr uint64_t kRecSlack = 256;       // readable bytes the record area has beyond its capacity
 
 // An item's record base carries flags in its low bits (bases are 16-byte
 // aligned): bit 0 for 24-byte records (FP64 weights), bit 2 for 12-byte
@@ -23,77 +25,77 @@ constexpr uint64_t kRecNone = ~0ull;      // no record for this lane
 ALP_HD uint64_t rec_addr(uint64_t rb) { return rb & ~15ull; }
 ALP_HD uint32_t rec_bytes(uint64_t rb) { return (rb & 1ull) ? 24u : ((rb & 4ull) ? 12u : 16u); }
 
-// The records of a wave's items (item, item + stride, ...), taken as one
-// stream of 64-record chunks.  The cursor runs ahead of the summation; it
-// holds the count and base of the item after its own, read ahead as well.
+// One chunk of the stream: records p0 .. p0 + 63 (those below rn) of `item`,
+// whose record count and base are rn and rb.  item >= n_items: past the end.
+struct RecChunk {
+  uint32_t item, p0, rn;
+  uint64_t rb;
+};
+
+// The chunks of a wave's items (item, item + stride, ...) in order.  Every
+// item gives ceil(rn / 64) chunks and at least one, since the cells of an
+// item without records are written too.  The cursor holds the chunk it hands
+// out next and the count and base of the item after that chunk's item, read
+// one item ahead.
 struct RecCursor {
-  uint32_t item, p0, rn;  // item, first record of the chunk to fetch, item's record count
-  uint64_t rb;            // item's record base (with the flag bits)
-  uint32_t gitem, grn;    // the item after it
+  RecChunk c;
+  uint32_t gitem, grn;
   uint64_t grb;
-  bool done;
 };
 
 // Src provides cnt(i) and base(i) for items i < n_items.
 template <class Src>
-ALP_HD void rec_settle(const Src &src, RecCursor &c, uint32_t n_items, uint32_t stride) {
-  while (!c.done && c.p0 >= c.rn) {  // skip to the next chunk that has records
-    if (c.gitem >= n_items) {
-      c.done = true;
-      break;
-    }
-    c.item = c.gitem;
-    c.rn = c.grn;
-    c.rb = c.grb;
-    c.p0 = 0;
-    c.gitem += stride;
-    if (c.gitem < n_items) {
-      c.grn = src.cnt(c.gitem);
-      c.grb = src.base(c.gitem);
-    }
+ALP_HD RecCursor rec_start(const Src &src, uint32_t item, uint32_t n_items, uint32_t stride) {
+  RecCursor k;
+  k.c.item = item;
+  k.c.p0 = 0;
+  k.c.rn = 0;
+  k.c.rb = 0;
+  if (item < n_items) {
+    k.c.rn = src.cnt(item);
+    k.c.rb = src.base(item);
   }
+  k.gitem = item + stride;
+  k.grn = 0;
+  k.grb = 0;
+  if (item < n_items && k.gitem < n_items) {
+    k.grn = src.cnt(k.gitem);
+    k.grb = src.base(k.gitem);
+  }
+  return k;
 }
 
-// A cursor at the first chunk with records of the wave's items, the first
-// being `item` (< n_items) with count rn and base rb.
+// The next chunk; the cursor moves past it.
 template <class Src>
-ALP_HD RecCursor rec_start(const Src &src, uint32_t item, uint32_t rn, uint64_t rb, uint32_t n_items,
-                           uint32_t stride) {
-  RecCursor c;
-  c.item = item;
-  c.p0 = 0;
-  c.rn = rn;
-  c.rb = rb;
-  c.gitem = item + stride;
-  c.grn = 0;
-  c.grb = 0;
-  c.done = false;
-  if (c.gitem < n_items) {
-    c.grn = src.cnt(c.gitem);
-    c.grb = src.base(c.gitem);
+ALP_HD RecChunk rec_take(const Src &src, RecCursor &k, uint32_t n_items, uint32_t stride) {
+  const RecChunk out = k.c;
+  if (out.item < n_items) {
+    k.c.p0 += kSpreadChunk;
+    if (k.c.p0 >= (k.c.rn > 0u ? k.c.rn : 1u)) {
+      k.c.item = k.gitem;
+      k.c.p0 = 0;
+      k.c.rn = k.grn;
+      k.c.rb = k.grb;
+      k.grn = 0;
+      k.grb = 0;
+      if (k.gitem < n_items) {
+        k.gitem += stride;
+        if (k.gitem < n_items) {
+          k.grn = src.cnt(k.gitem);
+          k.grb = src.base(k.gitem);
+        }
+      }
+    }
   }
-  rec_settle(src, c, n_items, stride);
-  return c;
+  return out;
 }
 
-// Byte offset (into the record area) of this lane's record of the cursor's
-// chunk, or kRecNone, with the record size in *bytes; then the cursor moves
-// to its next chunk.  A lane reads only records j < rn of the cursor's item.
-template <class Src>
-ALP_HD uint64_t rec_next(const Src &src, RecCursor &c, uint32_t n_items, uint32_t stride, int lane,
-                         uint32_t *bytes) {
-  uint64_t at = kRecNone;
-  *bytes = 16u;
-  if (!c.done) {
-    const uint32_t j = c.p0 + (uint32_t)lane;
-    if (j < c.rn) {
-      *bytes = rec_bytes(c.rb);
-      at = rec_addr(c.rb) + (uint64_t)j * *bytes;
-    }
-    c.p0 += kSpreadChunk;
-    rec_settle(src, c, n_items, stride);
-  }
-  return at;
+// Byte offset (into the record area) of this lane's record of chunk c, or
+// kRecNone: a lane reads only records j < rn of the chunk's item.
+ALP_HD uint64_t rec_lane(const RecChunk &c, uint32_t n_items, int lane) {
+  const uint32_t j = c.p0 + (uint32_t)lane;
+  if (c.item >= n_items || j >= c.rn) return kRecNone;
+  return rec_addr(c.rb) + (uint64_t)j * rec_bytes(c.rb);
 }
 
 }  // namespace alp

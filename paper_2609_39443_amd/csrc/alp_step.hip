@@ -2355,12 +2355,21 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // records of a work item are sorted by cell, so each cell owns one contiguous
 // run; its lane sums the run in record order.  Every cell of an active tile
 // is written.
+// Loads of values that no kernel of the pass writes (work-item tables, the
+// case table) through the scalar unit: a wave-uniform address then costs no
+// vector-memory slot, and the wait for it does not also wait for the
+// record and force loads in flight.
+template <class T>
+__device__ __forceinline__ T sload(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)(p);
+}
+
 // The record counts and bases of the work items, for the record cursor.
 struct ItemRecs {
   const uint32_t *c;
   const unsigned long long *b;
-  __device__ __forceinline__ uint32_t cnt(uint32_t i) const { return c[i]; }
-  __device__ __forceinline__ uint64_t base(uint32_t i) const { return b[i]; }
+  __device__ __forceinline__ uint32_t cnt(uint32_t i) const { return sload(c + i); }
+  __device__ __forceinline__ uint64_t base(uint32_t i) const { return sload(b + i); }
 };
 
 struct SpreadScratch {
@@ -2369,27 +2378,30 @@ struct SpreadScratch {
   uint8_t cl[kSpreadChunk];      // cell lane of each record (items with several runs per cell)
 };
 
-// this lane's record of the cursor's chunk (meta, node, a0 as FP32 or the
-// two words of the FP64 a0), then the cursor moves on
-__device__ __forceinline__ uint4 rec_take(const Work &W, const ItemRecs &src, RecCursor &c, uint32_t n_items,
-                                          uint32_t stride, int lane) {
-  uint4 r = make_uint4(0u, 0u, 0u, 0u);
-  uint32_t bytes;
-  const uint64_t at = rec_next(src, c, n_items, stride, lane, &bytes);
-  if (at != kRecNone) {
-    const unsigned char *p = W.rec + at;
-    if (bytes == 24u) {
-      const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 8);
-      r = make_uint4(lo.x, lo.y, hi.x, hi.y);
-    } else if (bytes == 12u) {
-      const uint32_t *q = (const uint32_t *)p;
-      const uint32_t w0 = q[0], a0 = q[1], a1 = q[2];
-      r = make_uint4((w0 & 63u) | ((w0 & 64u) ? kRecSingle : 0u), w0 >> kRecNodeShift, a0, a1);
-    } else {
-      r = *(const uint4 *)p;
-    }
+// A chunk in flight: its place in the stream, its item's descriptor and the
+// first 24 bytes of this lane's record (every record size is read the same
+// way, so every pass issues the same loads and the waits for one chunk leave
+// the next chunk's loads in flight; a shorter record's tail words belong to
+// the next record or to the slack of the record area, and are not used).
+struct SpreadChunk {
+  RecChunk k;
+  Item it;
+  uint32_t d[6];
+};
+
+__device__ __forceinline__ void spread_issue(const Work &W, const ItemRecs &src, RecCursor &cur, uint32_t n_items,
+                                             uint32_t stride, int lane, SpreadChunk &o) {
+  o.k = rec_take(src, cur, n_items, stride);
+  if (o.k.item < n_items) {
+    const Item *ip = W.item + o.k.item;
+    o.it.c0 = sload(&ip->c0);
+    o.it.c1 = sload(&ip->c1);
+    o.it.cs = sload(&ip->cs);
   }
-  return r;
+  const uint64_t at = rec_lane(o.k, n_items, lane);
+  const uint32_t *p = (const uint32_t *)(W.rec + (at == kRecNone ? 0ull : at));
+#pragma unroll
+  for (int q = 0; q < 6; ++q) o.d[q] = to_global(p)[q];
 }
 
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(8))) void k_spread(StepLaunch L) {
@@ -2398,112 +2410,131 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
   const int lane = threadIdx.x;
   const uint32_t n_items = (uint32_t)min((int64_t)W.tile_itoff[W.n_tiles], W.cap_item);
   const uint32_t stride = gridDim.x;
-  uint32_t item = blockIdx.x;
-  if (item >= n_items) return;
+  if (blockIdx.x >= n_items) return;
   // per-wave accumulation (exact fixed point, flushed when the case changes)
   int acc_case = -1;
   unsigned long long acc_band = 0;
   long long fh = 0;  // lanes 0..2 hold x, y, z
   unsigned long long fl = 0;
+  auto flush = [&]() {
+    if (acc_case < 0) return;
+    if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 4), acc_band);
+    if (lane < 3 && (fh || fl)) {
+      fh += (long long)(fl >> kLoBits);
+      fl &= (1ull << kLoBits) - 1ull;
+      atomicAdd((unsigned long long *)&W.F_hi[3 * acc_case + lane], (unsigned long long)fh);
+      atomicAdd(&W.F_lo[3 * acc_case + lane], fl);
+    }
+  };
   sh.first[lane] = 0;
   sh.last[lane] = 0;
-  // the current item, and the next one's descriptor and record range
-  Item it = W.item[item];
-  uint32_t rn = W.rec_cnt[item];
-  unsigned long long rb = W.rec_base[item];
-  Item nxt = it;
-  uint32_t nrn = 0;
-  unsigned long long nrb = 0;
-  if (item + stride < n_items) {
-    nxt = W.item[item + stride];
-    nrn = W.rec_cnt[item + stride];
-    nrb = W.rec_base[item + stride];
-  }
-  // the record stream, two chunks ahead
+  // the chunk stream, one chunk ahead of the one being summed: A and B
+  // alternate, so a chunk's registers are filled by its loads and read in
+  // place, never copied while its loads are in flight
   const ItemRecs src{W.rec_cnt, W.rec_base};
-  RecCursor cur = rec_start(src, item, rn, rb, n_items, stride);
-  uint4 R1 = rec_take(W, src, cur, n_items, stride, lane);
-  uint4 R2 = rec_take(W, src, cur, n_items, stride, lane);
+  RecCursor cur = rec_start(src, blockIdx.x, n_items, stride);
+  SpreadChunk A, B;
+  spread_issue(W, src, cur, n_items, stride, lane, A);
+  spread_issue(W, src, cur, n_items, stride, lane, B);
   __syncthreads();
-  for (;;) {
-    if (it.cs != acc_case) {
-      if (acc_case >= 0) {
-        if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 4), acc_band);
-        if (lane < 3 && (fh || fl)) {
-          fh += (long long)(fl >> kLoBits);
-          fl &= (1ull << kLoBits) - 1ull;
-          atomicAdd((unsigned long long *)&W.F_hi[3 * acc_case + lane], (unsigned long long)fh);
-          atomicAdd(&W.F_lo[3 * acc_case + lane], fl);
-        }
-      }
+  double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the lane's cell, over the item's chunks so far
+  bool any = false;
+  // sum chunk X, then refill X with the chunk after the one in flight
+  auto pass = [&](SpreadChunk &X) -> bool {
+    if (X.k.item >= n_items) return false;
+    const Item it = X.it;
+    const uint32_t p0 = X.k.p0, rn = X.k.rn;
+    const uint64_t rb = X.k.rb;
+    if (p0 == 0 && it.cs != acc_case) {
+      flush();
       acc_case = it.cs;
       acc_band = 0;
       fh = 0;
       fl = 0;
     }
-    const CaseDev &cs = L.cases[it.cs];
-    const MeshDev &m = cs.m;
+    const uint32_t nch = rn > p0 ? min(rn - p0, (uint32_t)kSpreadChunk) : 0u;
+    const bool last = p0 + (uint32_t)kSpreadChunk >= rn;
+    const CaseDev *cp = L.cases + it.cs;
+    const double *vs = sload(&cp->m.vs);
+    const uint32_t *perm = sload(&cp->m.perm);
+    // this lane's record
+    const uint32_t j = (uint32_t)lane;
+    const bool has = j < nch;
+    const uint32_t bytes = rec_bytes(rb);
+    uint32_t cl = X.d[0] & 63u, node;
+    bool single;
+    double a0, a1;
+    if (bytes == 12u) {
+      single = (X.d[0] & 64u) != 0u;
+      node = X.d[0] >> kRecNodeShift;
+      a0 = (double)__uint_as_float(X.d[1]);
+      a1 = (double)__uint_as_float(X.d[2]);
+    } else {
+      single = (X.d[0] & kRecSingle) != 0u;
+      node = X.d[1];
+      if (bytes == 24u) {
+        a0 = __hiloint2double((int)X.d[3], (int)X.d[2]);
+        a1 = __hiloint2double((int)X.d[5], (int)X.d[4]);
+      } else {
+        a0 = (double)__uint_as_float(X.d[2]);
+        a1 = (double)__uint_as_float(X.d[3]);
+      }
+    }
+    if (!has) {
+      cl = ~0u;
+      node = 0;
+      single = true;
+    }
+    // the record is decoded before X is refilled: nothing reads X's words
+    // after their next loads are issued, so those loads can land in the same
+    // registers (a copy of a register with a load in flight waits for it)
+    uint32_t sgl = single ? 1u : 0u;
+    asm volatile("" : "+v"(cl), "+v"(node), "+v"(sgl), "+v"(a0), "+v"(a1));
+    single = sgl != 0u;
+    // f_hat of the record's nodes (the force array has one node of slack, so
+    // the second node's address is valid for single-CV records as well), and
+    // the volume and caller index of the lane's cell
+    const gptr<double> fp = to_global(W.fhat) + 3 * (int64_t)node;
+    const double f0 = fp[0], f1 = fp[1], f2 = fp[2], f3 = fp[3], f4 = fp[4], f5 = fp[5];
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
-    const double v = valid ? to_global(m.vs)[c] : 0.0;
-    const uint32_t pc = valid ? to_global(m.perm)[c] : 0u;
-    const bool fp64 = (rb & 1ull) != 0;
-    // an item whose entries were taken in groups holds one run per group for
-    // a cell: its lanes then gather their records from the whole chunk
-    const bool multi = (rb & 2ull) != 0;
-    const unsigned char *rbase = W.rec + (rb & ~15ull);
-    double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-    bool any = false;
-    for (uint32_t p0 = 0; p0 < rn; p0 += kSpreadChunk) {
-      const uint32_t nch = min(rn - p0, (uint32_t)kSpreadChunk);
-      const uint4 C = R1;
-      R1 = R2;
-      R2 = rec_take(W, src, cur, n_items, stride, lane);
-      const uint32_t j = (uint32_t)lane;
-      uint32_t cl = ~0u;
-      if (j < nch) {
-        const uint32_t meta = C.x, node = C.y;
-        double a0, a1;
-        if (fp64) {
-          a0 = __hiloint2double((int)C.w, (int)C.z);
-          a1 = *(const double *)(rbase + (size_t)(p0 + j) * 24 + 16);
-        } else {
-          a0 = (double)__uint_as_float(C.z);
-          a1 = (double)__uint_as_float(C.w);
-        }
-        const gptr<double> fp = to_global(W.fhat) + 3 * (int64_t)node;
-        double q0 = a0 * fp[0], q1 = a0 * fp[1], q2 = a0 * fp[2];
-        if (!(meta & kRecSingle)) {
-          q0 += a1 * fp[3];
-          q1 += a1 * fp[4];
-          q2 += a1 * fp[5];
-        }
-        sh.cc[0][j] = -q0;
-        sh.cc[1][j] = -q1;
-        sh.cc[2][j] = -q2;
-        cl = meta & 63u;
+    const int cr = valid ? c : it.c0;
+    const double v = to_global(vs)[cr];
+    const uint32_t pc = to_global(perm)[cr];
+    // the next chunk's loads go out before this chunk's forces are used
+    spread_issue(W, src, cur, n_items, stride, lane, X);
+    if (has) {
+      double q0 = a0 * f0, q1 = a0 * f1, q2 = a0 * f2;
+      if (!single) {
+        q0 += a1 * f3;
+        q1 += a1 * f4;
+        q2 += a1 * f5;
       }
-      if (multi) {
-        // every record of the chunk whose cell is this lane's, in record order
-        // (group after group, beam order inside a group: beam order)
-        if (j < nch) sh.cl[j] = (uint8_t)cl;
-        __syncthreads();
-        for (uint32_t q = 0; q < nch; ++q) {
-          if (sh.cl[q] == (uint32_t)lane) {
-            S0 += sh.cc[0][q];
-            S1 += sh.cc[1][q];
-            S2 += sh.cc[2][q];
-            any = true;
-          }
+      sh.cc[0][j] = -q0;
+      sh.cc[1][j] = -q1;
+      sh.cc[2][j] = -q2;
+    }
+    if ((rb & 2ull) != 0ull) {
+      // an item whose entries were taken in groups holds one run per group
+      // for a cell: every record of the chunk whose cell is this lane's, in
+      // record order (group after group, beam order inside a group)
+      sh.cl[j] = (uint8_t)(has ? cl : 255u);
+      __syncthreads();
+      for (uint32_t q = 0; q < nch; ++q) {
+        if (sh.cl[q] == (uint32_t)lane) {
+          S0 += sh.cc[0][q];
+          S1 += sh.cc[1][q];
+          S2 += sh.cc[2][q];
+          any = true;
         }
-        __syncthreads();
-        continue;
       }
+      __syncthreads();
+    } else {
       // run boundaries of each cell (records are sorted by cell): the
       // neighbouring records' cells come from the neighbouring lanes
       const uint32_t up = (uint32_t)__shfl((int)cl, lane - 1, 64);
       const uint32_t dn = (uint32_t)__shfl((int)cl, lane + 1, 64);
-      if (j < nch) {
+      if (has) {
         if (j == 0 || up != cl) sh.first[cl] = (uint16_t)j;
         if (j + 1 == nch || dn != cl) sh.last[cl] = (uint16_t)(j + 1);
       }
@@ -2519,45 +2550,41 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
       }
       __syncthreads();
     }
-    if (valid && cs.write_S) {
-      double *S = cs.S + 3 * (int64_t)pc;
-      S[0] = S0;
-      S[1] = S1;
-      S[2] = S2;
-    }
-    acc_band += (unsigned long long)__popcll(ballot64(valid && any));
-    // force on the fluid: deterministic wave sum, then exact accumulation
-    const double fx = wave_sum_f64(S0 * v), fy = wave_sum_f64(S1 * v), fz = wave_sum_f64(S2 * v);
-    if (lane < 3) {
-      const double val = lane == 0 ? fx : (lane == 1 ? fy : fz);
-      if (val != 0.0) {
-        long long h;
-        unsigned long long l;
-        fx_encode(val, W.F_exp[it.cs], h, l);
-        fh += h;
-        fl += l;
+    if (last) {
+      // the item's cells are complete: write them, count the band cells and
+      // add the force on the fluid (deterministic wave sum, then exact
+      // accumulation)
+      if (valid && sload(&cp->write_S)) {
+        double *S = sload(&cp->S) + 3 * (int64_t)pc;
+        S[0] = S0;
+        S[1] = S1;
+        S[2] = S2;
       }
+      acc_band += (unsigned long long)__popcll(ballot64(valid && any));
+      const double fx = wave_sum_f64(S0 * v), fy = wave_sum_f64(S1 * v), fz = wave_sum_f64(S2 * v);
+      const int fe = sload(W.F_exp + it.cs);
+      if (lane < 3) {
+        const double val = lane == 0 ? fx : (lane == 1 ? fy : fz);
+        if (val != 0.0) {
+          long long h;
+          unsigned long long l;
+          fx_encode(val, fe, h, l);
+          fh += h;
+          fl += l;
+        }
+      }
+      S0 = 0.0;
+      S1 = 0.0;
+      S2 = 0.0;
+      any = false;
     }
-    item += stride;
-    if (item >= n_items) break;
-    it = nxt;
-    rn = nrn;
-    rb = nrb;
-    if (item + stride < n_items) {
-      nxt = W.item[item + stride];
-      nrn = W.rec_cnt[item + stride];
-      nrb = W.rec_base[item + stride];
-    }
+    return true;
+  };
+  for (;;) {
+    if (!pass(A)) break;
+    if (!pass(B)) break;
   }
-  if (acc_case >= 0) {
-    if (lane == 0 && acc_band) atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 4), acc_band);
-    if (lane < 3 && (fh || fl)) {
-      fh += (long long)(fl >> kLoBits);
-      fl &= (1ull << kLoBits) - 1ull;
-      atomicAdd((unsigned long long *)&W.F_hi[3 * acc_case + lane], (unsigned long long)fh);
-      atomicAdd(&W.F_lo[3 * acc_case + lane], fl);
-    }
-  }
+  flush();
 }
 
 // The spread walks its items with a static stride, so its grid is exactly

@@ -743,7 +743,7 @@ def test_binning_autotuners_skip_candidates_over_the_tile_limit(gu, ctx):
 def test_checked_steps_verify_the_record_layout(gu, ctx):
     """ALP_CHECKED checks on the host, after the step, that every work item's
     pair records lie inside the allocated record area and that no two items'
-    records overlap, for 16- and 24-byte records and grouped items (a tile
+    records overlap, for 12- and 24-byte records and grouped items (a tile
     column crowded by 200 beams), uncaptured and in graph replay."""
     wls = [W.canopy(n=40, n_stems=30, cv_range=(5, 30), inset=0.04), crowded_column(200), random_scene(16)]
     precs = [alp.PREC_FP32_SPLIT, alp.PREC_FP64, alp.PREC_FP32_SPLIT]

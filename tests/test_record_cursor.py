@@ -1,15 +1,18 @@
 """Host replay of the spread pass's record cursor (csrc/alp_reccursor.h).
 
 The spread kernel walks the pair records of its work items (item, item +
-stride, ...) as one stream of 64-record chunks, with the cursor two chunks
-ahead of the summation and the next item's count and base read one item
-ahead.  A C++ program compiled on the host from the same header replays that
-walk for every wave of a grid over random record layouts (items without
-records, 12-, 16- and 24-byte records, grouped items, gaps between reservations,
-grids larger than the item count) and checks that every record read lies
-inside its own item's records and inside the record area, that no item's
-count or base is read past the item count, and that the chunk each lane sums
-is the record the summation expects.
+stride, ...) as one stream of chunks of up to 64 records, every item giving at
+least one chunk (the cells of an item without records are written too), with
+two chunks in flight: a chunk's loads are issued two passes before it is
+summed, and the next item's count and base are read one item ahead.  A C++
+program compiled on the host from the same header replays that walk for every
+wave of a grid over random record layouts (items without records, 12-, 16-
+and 24-byte records, grouped items, gaps between reservations, grids larger
+than the item count) and checks that every chunk comes in item order with the
+right first record, that every lane's read of kRecReadBytes from its record
+lies inside its own item's records or, for its tail, inside the record area
+and its slack, that lanes past an item's records read nothing, and that no
+item's count or base is read past the item count.
 """
 import os
 import subprocess
@@ -69,56 +72,46 @@ int main() {
     }
     const uint64_t cap = top;
     Src src{&cnt, &base};
-    // one wave per block: each call of rec_next by the 64 lanes starts from the
-    // same (wave-uniform) cursor; the cursor after a chunk is any lane's
-    auto chunk = [&](RecCursor &cur, uint64_t (*out)[2]) {
-      RecCursor after = cur;
-      for (int l = 0; l < 64; ++l) {
-        RecCursor t = cur;
-        uint32_t bytes;
-        out[l][0] = rec_next(src, t, n, grid, l, &bytes);
-        out[l][1] = bytes;
-        after = t;
-      }
-      cur = after;
-    };
     for (uint32_t b = 0; b < grid; ++b) {
-      uint32_t item = b;
-      if (item >= n) continue;
-      uint32_t rn = src.cnt(item);
-      uint64_t rb = src.base(item);
-      RecCursor cur = rec_start(src, item, rn, rb, n, grid);
-      uint64_t R1[64][2], R2[64][2];
-      chunk(cur, R1);  // the cursor runs two chunks ahead of the summation
-      chunk(cur, R2);
-      for (;;) {
-        for (uint32_t p0 = 0; p0 < rn; p0 += kSpreadChunk) {
-          // the chunk summed now must be records p0 .. p0 + 63 of this item
-          for (int l = 0; l < 64; ++l) {
-            const uint32_t j = p0 + (uint32_t)l;
-            if (j < rn) {
-              const uint64_t want = rec_addr(rb) + (uint64_t)j * rec_bytes(rb);
-              CHECK(R1[l][0] == want && R1[l][1] == rec_bytes(rb),
-                    "trial %d wave %u item %u record %u: read %llu, want %llu", trial, b, item, j,
-                    (unsigned long long)R1[l][0], (unsigned long long)want);
-              CHECK(R1[l][0] + R1[l][1] <= cap, "record outside the record area");
-              ++checked;
-            } else {
-              CHECK(R1[l][0] == kRecNone, "trial %d wave %u item %u: lane %d past the item's records reads %llu",
-                    trial, b, item, l, (unsigned long long)R1[l][0]);
-            }
+      if (b >= n) continue;
+      RecCursor cur = rec_start(src, b, n, grid);
+      RecChunk A = rec_take(src, cur, n, grid), B = rec_take(src, cur, n, grid);
+      // the chunks the summation must see, in order
+      uint32_t item = b, p0 = 0;
+      auto pass = [&](RecChunk &X) -> int {
+        if (X.item >= n) return 0;
+        if (X.item != item || X.p0 != p0) return -1;
+        const uint32_t rn = cnt[item];
+        if (X.rn != rn || X.rb != base[item]) return -1;
+        for (int l = 0; l < 64; ++l) {
+          const uint64_t at = rec_lane(X, n, l);
+          const uint32_t j = p0 + (uint32_t)l;
+          if (j < rn) {
+            const uint64_t a0 = rec_addr(base[item]), sz = rec_bytes(base[item]);
+            if (at != a0 + (uint64_t)j * sz) return -2;
+            if (at + sz > a0 + (uint64_t)rn * sz) return -3;       // the record is the item's
+            if (at + kRecReadBytes > cap + kRecSlack) return -4;   // the read stays in the area
+            ++checked;
+          } else if (at != kRecNone) {
+            return -5;
           }
-          std::memcpy(R1, R2, sizeof(R1));
-          chunk(cur, R2);
-          for (int l = 0; l < 64; ++l)
-            if (R2[l][0] != kRecNone) CHECK(R2[l][0] + R2[l][1] <= cap, "prefetch outside the record area");
         }
-        item += grid;
-        if (item >= n) break;
-        rn = src.cnt(item);
-        rb = src.base(item);
+        p0 += kSpreadChunk;
+        if (p0 >= (rn > 0 ? rn : 1u)) {
+          item += grid;
+          p0 = 0;
+        }
+        X = rec_take(src, cur, n, grid);
+        return 1;
+      };
+      for (;;) {
+        int r = pass(A);
+        if (r == 1) r = pass(B);
+        CHECK(r >= 0, "trial %d wave %u item %u p0 %u: chunk check %d", trial, b, item, p0, r);
+        if (r == 0) break;
       }
-      CHECK(cur.done, "trial %d wave %u: the cursor still has records after the last item", trial, b);
+      CHECK(item >= n, "trial %d wave %u: the stream ended before item %u", trial, b, item);
+      CHECK(A.item >= n && B.item >= n, "trial %d wave %u: chunks after the last item", trial, b);
     }
     CHECK(src.bad == 0, "trial %d: %ld count/base reads past the item count", trial, src.bad);
   }
