@@ -239,7 +239,7 @@ __device__ __forceinline__ void pair_weights(int prec, double s, double r2, doub
                                              double &a1) {
   if (prec == ALP_PREC_FP32_SPLIT) {
     const float e2 = (float)(ej * ej);
-    const float ie2 = 1.0f / e2;  // one division serves both quotients
+    const float ie2 = __builtin_amdgcn_rcpf(e2);  // one reciprocal (1 ulp) serves both quotients
     const float x = (float)r2 * ie2;
     const float eta = expf(-x) * (ie2 * 0.318309886183790671538f);  // 1/pi
     float sf = (float)s;

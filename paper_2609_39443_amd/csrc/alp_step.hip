@@ -2084,12 +2084,15 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
                       const float R2 = sh.e_dabs[e] * 0x1p14f;  // R^2 of the window (the allowance is 2^-14 R^2)
                       const float ax = Vv.x - Aa.x, ay = Vv.y - Aa.y, az = Vv.z - Aa.z;
                       const float bx = Bb.x - Vv.x, by = Bb.y - Vv.y, bz = Bb.z - Vv.z;
-                      // t_a - 1 and t_b times |e|^2 (1/|e|^2 is each segment's staged w)
-                      const float ga = (qx - Aa.x) * ax + (qy - Aa.y) * ay + (qz - Aa.z) * az - 1.0f / Aa.w;
+                      // t_a - 1 and t_b times |e|^2 (1/|e|^2 is each segment's staged
+                      // w; its hardware reciprocal is within 1 ulp, far inside the
+                      // 2^-20 |e|^2 term of the margins)
+                      const float la = __builtin_amdgcn_rcpf(Aa.w), lb = __builtin_amdgcn_rcpf(Vv.w);
+                      const float ga = (qx - Aa.x) * ax + (qy - Aa.y) * ay + (qz - Aa.z) * az - la;
                       const float gb = (qx - Vv.x) * bx + (qy - Vv.y) * by + (qz - Vv.z) * bz;
                       const float ra = R2 * Aa.w, rb = R2 * Vv.w;  // (R/|e|)^2
-                      const float da = (0x1p-19f * (ra + __builtin_amdgcn_sqrtf(ra)) + 0x1p-20f) / Aa.w;
-                      const float db = (0x1p-19f * (rb + __builtin_amdgcn_sqrtf(rb)) + 0x1p-20f) / Vv.w;
+                      const float da = (0x1p-19f * (ra + __builtin_amdgcn_sqrtf(ra)) + 0x1p-20f) * la;
+                      const float db = (0x1p-19f * (rb + __builtin_amdgcn_sqrtf(rb)) + 0x1p-20f) * lb;
                       if (ga < -da && gb < -db) {
                         j1 = ja;
                         two = false;
