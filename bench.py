@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison runs")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary measurements (wave flume, batched scenarios, jittered net)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the headline at the default launch shape only (no ALP_AUTOTUNE search: "
+                         "for profiler runs, whose per-kernel averages would otherwise mix candidate shapes)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -420,10 +423,13 @@ def main():
     # the default launch shape first, then the headline: FP32-split, batched
     # persistent launches, launch shape chosen by ALP_AUTOTUNE, graph replay
     log("timing the FP32-split graph step, default launch shape")
-    t_def, _, st_def = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup)
+    t_def, d_def, st_def = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup)
     log(f"default shape: {t_def * 1e3:.3f} ms/step")
-    log("timing the FP32-split graph step, autotuned launch shape")
-    t_split, diag, st_split = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup, autotune=True)
+    if args.no_autotune:
+        t_split, diag, st_split = t_def, d_def, st_def
+    else:
+        log("timing the FP32-split graph step, autotuned launch shape")
+        t_split, diag, st_split = timed_graph(alp.PREC_FP32_SPLIT, args.steps, args.warmup, autotune=True)
     got = {"split": host_outputs()}
     log(f"split: {t_split * 1e3:.3f} ms/step (median {st_split['median_ms']:.3f}, "
         f"p10 {st_split['p10_ms']:.3f}, p90 {st_split['p90_ms']:.3f}), diag {diag}")
@@ -499,7 +505,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"canopy: {args.n}^3 uniform cells (h = 4 mm), {args.stems} stems of "
                                f"20-200 CVs, FP32-split, all stems in one persistent launch per stage, "
-                               f"launch shape chosen by ALP_AUTOTUNE, hipGraph replay", "n_cells": n_cells,
+                               + ("default launch shape" if args.no_autotune else "launch shape chosen by ALP_AUTOTUNE")
+                               + ", hipGraph replay", "n_cells": n_cells,
                    "n_points": npnt,
                    "n_band_cells": n_band, "n_pairs": n_pairs, "parallelism": "single GPU"},
         "cell_updates_per_s": n_pairs / t_split, "band_cells_per_s": n_band / t_split,

@@ -31,8 +31,8 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-BENCH = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-fp64 --no-extra"
-BENCH_PMC = "python3 bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-fp64 --no-extra"
+BENCH = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-fp64 --no-extra --no-autotune"
+BENCH_PMC = "python3 bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-fp64 --no-extra --no-autotune"
 SQ = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_INSTS_SMEM SQ_WAIT_INST_ANY "
       "SQ_BUSY_CYCLES SQ_WAVE_CYCLES")
 LDS = ("SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT SQ_LDS_IDX_ACTIVE SQ_INSTS_LDS SQ_ACTIVE_INST_LDS "
@@ -42,7 +42,8 @@ LDS = ("SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT SQ_LDS_IDX_ACTIVE SQ_INSTS_LDS
 def commands(out: str) -> dict:
     """The rocprofv3 runs whose output (under `out`) the summaries read."""
     return {
-        "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d {out}/prof -o canopy -- {BENCH}",
+        "trace": (f"timeout -s KILL 300 rocprofv3 --kernel-trace --stats --output-format csv -d {out}/prof "
+                  f"-o canopy -- {BENCH}"),
         "sq": f"timeout -s KILL 240 rocprofv3 --pmc {SQ} --output-format csv -d {out}/pmc -o sq -- {BENCH_PMC}",
         "fetch": (f"timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/pmc -o fetch -- "
                   f"{BENCH_PMC} --copy-probe-mb 1024"),
