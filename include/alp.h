@@ -269,8 +269,14 @@ typedef struct {
    work of all cases.  cases is a HOST array.  With ALP_USE_GRAPH the first call
    for a given set of cases captures the launch sequence in a hipGraph and later
    calls with identical case descriptors replay it; the arrays in the cases may
-   be updated in place between replays.  A mesh may appear in at most one case
-   of a batch. */
+   be updated in place between replays.  If updated arrays need longer work
+   lists than the captured ones (beams that moved so that more cells or tiles
+   lie within reach), the replay drops what does not fit (it accesses nothing
+   beyond its lists), alp_get_diag reports n_overflow, and the next call with
+   the same cases returns ALP_ERR_CAPACITY once that replay has completed and
+   drops the graph; the call after it sizes the lists again.  With
+   ALP_CHECKED a replay reports its own overflow.  A mesh may appear in at
+   most one case of a batch. */
 alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *cases,
                             uint32_t flags);
 
