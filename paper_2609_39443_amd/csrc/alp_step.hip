@@ -2362,6 +2362,10 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // case table) through the scalar unit: a wave-uniform address then costs no
 // vector-memory slot, and the wait for it does not also wait for the
 // record and force loads in flight.
+// s_waitcnt operand waiting for vmcnt 0 only (expcnt 7 and lgkmcnt 15 are
+// the fields' maxima, i.e. no wait on them)
+constexpr unsigned kWaitVmcnt0 = 0x0F70u;
+
 template <class T>
 __device__ __forceinline__ T sload(const T *p) {
   return *(const __attribute__((address_space(4))) T *)(p);
@@ -2407,6 +2411,56 @@ __device__ __forceinline__ void spread_issue(const Work &W, const ItemRecs &src,
   for (int q = 0; q < 6; ++q) o.d[q] = to_global(p)[q];
 }
 
+// A chunk's records decoded: what the pass that sums it needs (a lane
+// without a record has cl = ~0 and node 0).
+struct SpreadDec {
+  RecChunk k;
+  Item it;
+  uint32_t nch, cl, node, sgl;
+  double a0, a1;
+};
+
+__device__ __forceinline__ void spread_decode(SpreadChunk &X, int lane, SpreadDec &D) {
+  // every word is taken, whatever the record size, so that no register of X
+  // is left with its load counted as in flight
+  asm volatile("" : "+v"(X.d[0]), "+v"(X.d[1]), "+v"(X.d[2]), "+v"(X.d[3]), "+v"(X.d[4]), "+v"(X.d[5]));
+  D.k = X.k;
+  D.it = X.it;
+  const uint32_t p0 = X.k.p0, rn = X.k.rn;
+  D.nch = rn > p0 ? min(rn - p0, (uint32_t)kSpreadChunk) : 0u;
+  const uint32_t bytes = rec_bytes(X.k.rb);
+  uint32_t cl = X.d[0] & 63u, node, sgl;
+  double a0, a1;
+  if (bytes == 12u) {
+    sgl = (X.d[0] & 64u) ? 1u : 0u;
+    node = X.d[0] >> kRecNodeShift;
+    a0 = (double)__uint_as_float(X.d[1]);
+    a1 = (double)__uint_as_float(X.d[2]);
+  } else {
+    sgl = (X.d[0] & kRecSingle) ? 1u : 0u;
+    node = X.d[1];
+    if (bytes == 24u) {
+      a0 = __hiloint2double((int)X.d[3], (int)X.d[2]);
+      a1 = __hiloint2double((int)X.d[5], (int)X.d[4]);
+    } else {
+      a0 = (double)__uint_as_float(X.d[2]);
+      a1 = (double)__uint_as_float(X.d[3]);
+    }
+  }
+  if ((uint32_t)lane >= D.nch) {
+    cl = ~0u;
+    node = 0;
+    sgl = 1u;
+    a0 = 0.0;
+    a1 = 0.0;
+  }
+  D.cl = cl;
+  D.node = node;
+  D.sgl = sgl;
+  D.a0 = a0;
+  D.a1 = a1;
+}
+
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(8))) void k_spread(StepLaunch L) {
   Work W = L.w;
   __shared__ SpreadScratch sh;
@@ -2431,31 +2485,40 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
   };
   sh.first[lane] = 0;
   sh.last[lane] = 0;
-  // the chunk stream, one chunk ahead of the one being summed: A and B
-  // alternate, so a chunk's registers are filled by its loads and read in
-  // place, never copied while its loads are in flight
+  // the chunk stream, one chunk ahead of the one being summed.  The record
+  // registers A and B alternate: a chunk's loads fill its registers, which
+  // are decoded at the end of the pass before the one that sums it (after
+  // that pass has waited for its own force loads, issued after these) and
+  // refilled by the pass that sums it.  So no record register is read or
+  // copied while its load is in flight.
   const ItemRecs src{W.rec_cnt, W.rec_base};
   RecCursor cur = rec_start(src, blockIdx.x, n_items, stride);
   SpreadChunk A, B;
   spread_issue(W, src, cur, n_items, stride, lane, A);
   spread_issue(W, src, cur, n_items, stride, lane, B);
+  SpreadDec D;
+  spread_decode(A, lane, D);
   __syncthreads();
   double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the lane's cell, over the item's chunks so far
   bool any = false;
-  // sum chunk X, then refill X with the chunk after the one in flight
-  auto pass = [&](SpreadChunk &X) -> bool {
-    if (X.k.item >= n_items) return false;
-    const Item it = X.it;
-    const uint32_t p0 = X.k.p0, rn = X.k.rn;
-    const uint64_t rb = X.k.rb;
+  // sum the chunk decoded in D (it came from X), refill X with the chunk
+  // after Y's, then decode Y
+  auto pass = [&](SpreadChunk &X, SpreadChunk &Y) -> bool {
+    if (D.k.item >= n_items) return false;
+    const Item it = D.it;
+    const uint32_t p0 = D.k.p0, rn = D.k.rn;
+    const uint64_t rb = D.k.rb;
     if (p0 == 0 && it.cs != acc_case) {
       flush();
+      // (the compiler cannot wait for one load while atomics of unknown
+      // order are in flight: the rare path that issues them waits for them)
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       acc_case = it.cs;
       acc_band = 0;
       fh = 0;
       fl = 0;
     }
-    const uint32_t nch = rn > p0 ? min(rn - p0, (uint32_t)kSpreadChunk) : 0u;
+    const uint32_t nch = D.nch;
     const bool last = p0 + (uint32_t)kSpreadChunk >= rn;
     const CaseDev *cp = L.cases + it.cs;
     const double *vs = sload(&cp->m.vs);
@@ -2463,50 +2526,36 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
     // this lane's record
     const uint32_t j = (uint32_t)lane;
     const bool has = j < nch;
-    const uint32_t bytes = rec_bytes(rb);
-    uint32_t cl = X.d[0] & 63u, node;
-    bool single;
-    double a0, a1;
-    if (bytes == 12u) {
-      single = (X.d[0] & 64u) != 0u;
-      node = X.d[0] >> kRecNodeShift;
-      a0 = (double)__uint_as_float(X.d[1]);
-      a1 = (double)__uint_as_float(X.d[2]);
-    } else {
-      single = (X.d[0] & kRecSingle) != 0u;
-      node = X.d[1];
-      if (bytes == 24u) {
-        a0 = __hiloint2double((int)X.d[3], (int)X.d[2]);
-        a1 = __hiloint2double((int)X.d[5], (int)X.d[4]);
-      } else {
-        a0 = (double)__uint_as_float(X.d[2]);
-        a1 = (double)__uint_as_float(X.d[3]);
-      }
-    }
-    if (!has) {
-      cl = ~0u;
-      node = 0;
-      single = true;
-    }
-    // the record is decoded before X is refilled: nothing reads X's words
-    // after their next loads are issued, so those loads can land in the same
-    // registers (a copy of a register with a load in flight waits for it)
-    uint32_t sgl = single ? 1u : 0u;
-    asm volatile("" : "+v"(cl), "+v"(node), "+v"(sgl), "+v"(a0), "+v"(a1));
-    single = sgl != 0u;
-    // f_hat of the record's nodes (the force array has one node of slack, so
-    // the second node's address is valid for single-CV records as well), and
-    // the volume and caller index of the lane's cell
-    const gptr<double> fp = to_global(W.fhat) + 3 * (int64_t)node;
-    const double f0 = fp[0], f1 = fp[1], f2 = fp[2], f3 = fp[3], f4 = fp[4], f5 = fp[5];
+    const uint32_t cl = D.cl;
+    const bool single = D.sgl != 0u;
+    const double a0 = D.a0, a1 = D.a1;
+    // f_hat of the record's nodes (the force array has two nodes of slack,
+    // so the second node's address is valid for single-CV records as well),
+    // and, in the item's last pass, the volume and caller index of the
+    // lane's cell.  Every load of a pass is used in that pass: a register
+    // with a load in flight is never left for the compiler to wait on later.
+    const gptr<double> fp = to_global(W.fhat) + 3 * (int64_t)D.node;
+    double fq[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) fq[q] = fp[q];
     const int c = it.c0 + lane;
     const bool valid = c < it.c1;
-    const int cr = valid ? c : it.c0;
-    const double v = to_global(vs)[cr];
-    const uint32_t pc = to_global(perm)[cr];
+    double v = 0.0;
+    uint32_t pc = 0;
+    if (last) {
+      const int cr = valid ? c : it.c0;
+      v = to_global(vs)[cr];
+      pc = to_global(perm)[cr];
+    }
     // the next chunk's loads go out before this chunk's forces are used
+    // (the empty statement keeps every use of the forces, the volume and
+    // the index after them)
     spread_issue(W, src, cur, n_items, stride, lane, X);
-    if (has) {
+    double f0 = fq[0], f1 = fq[1], f2 = fq[2], f3 = fq[3], f4 = fq[4], f5 = fq[5];
+    asm volatile("" : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3), "+v"(f4), "+v"(f5), "+v"(v), "+v"(pc));
+    {
+      // (a lane without a record has a0 = a1 = 0 and node 0: it writes a
+      // zero that no run reads)
       double q0 = a0 * f0, q1 = a0 * f1, q2 = a0 * f2;
       if (!single) {
         q0 += a1 * f3;
@@ -2581,11 +2630,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
       S2 = 0.0;
       any = false;
     }
+    spread_decode(Y, lane, D);
     return true;
   };
   for (;;) {
-    if (!pass(A)) break;
-    if (!pass(B)) break;
+    if (!pass(A, B)) break;
+    if (!pass(B, A)) break;
   }
   flush();
 }
