@@ -63,3 +63,13 @@ def test_documented_full_sizes():
     assert net["beams"]["P"].shape[0] == 1400 * 357
     # jittered volumes renormalised to the box volume (Sigma V = 2 x 2 x 0.25 m^3 at full size)
     assert np.isclose(net["V"].sum(), (40 * 0.005) * (40 * 0.005) * (10 * 0.005), rtol=1e-12)
+
+
+def test_flume_stem_uses_the_paper_sampling_distance():
+    """The wave-flume stem samples the flow 0.375 m upstream, the offset of the
+    paper's flume set-up (tests/golden/paper_constants.json, Sec. 7.4)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+    wl = W.wave_flume(snapshot=0, nx=60, ny=20, nz=30, n_cv=30)
+    assert np.all(wl["beams"]["ls"] == gold["flume_sampling_distance_m"]["value"])
