@@ -276,8 +276,14 @@ def near_tie_scene():
 def test_near_tie_segments_and_long_windows(gu, ctx, prec):
     """The closest-segment search ranks segments in FP32 and re-evaluates the
     near-best ones exactly; ties between distant segments of one beam, and
-    windows too long to stage, must still give the FP64 scan's choice."""
-    run_and_compare(gu, ctx, near_tie_scene(), prec)
+    windows too long to stage, must still give the FP64 scan's choice.  The
+    scene's ties leave several segments for the FP64 evaluation
+    (n_guard_fp64 > 0), while in a small canopy of leaning stems fewer than
+    one candidate in fifty needs more than one FP64 evaluation."""
+    _, _, _, diag = run_and_compare(gu, ctx, near_tie_scene(), prec)
+    assert diag["n_guard_fp64"] > 0
+    _, _, _, diag = run_and_compare(gu, ctx, W.canopy(n=40, n_stems=30, cv_range=(5, 30), inset=0.04), prec)
+    assert diag["n_guard_fp64"] * 50 < diag["n_pairs"]
 
 
 def test_batch_equals_single_cases(gu, ctx):
