@@ -172,6 +172,14 @@ alp_status leave(alp_context *ctx) {
   HIPCHK(ctx, hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
   return ALP_OK;
 }
+// wait for everything enqueued so far on the caller's stream (graph replays
+// run there) and on the internal stream
+alp_status settle(alp_context *ctx) {
+  alp_status rc = enter(ctx);
+  if (rc != ALP_OK) return rc;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return ALP_OK;
+}
 
 
 // Work-list capacities and per-case sizes for one step.
@@ -198,8 +206,8 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
     w.n_pblocks = sh.n_pblocks;
     return ALP_OK;
   }
-  drop_graph(ctx);
   (void)hipStreamSynchronize(ctx->st);
+  drop_graph(ctx);
   // keep every dimension at least as large as before
   int64_t P = std::max(sh.n_points, ctx->have_points), B = std::max(sh.n_beams, ctx->have_beams);
   int64_t T = std::max(sh.n_tiles, ctx->have_tiles);
@@ -290,8 +298,8 @@ alp_status ensure_work(alp_context *ctx, const StepShape &sh, int64_t want_emit,
 
 alp_status ensure_cases(alp_context *ctx, int n) {
   if (n <= ctx->cap_cases) return ALP_OK;
-  drop_graph(ctx);
   (void)hipStreamSynchronize(ctx->st);
+  drop_graph(ctx);
   if (ctx->d_cases) (void)hipFree(ctx->d_cases);
   if (ctx->d_bases) (void)hipFree(ctx->d_bases);
   ctx->d_cases = nullptr;
@@ -919,7 +927,7 @@ alp_status alp_create(int device, void *hip_stream, alp_context **out) {
 alp_status alp_destroy(alp_context *ctx) {
   if (!ctx) return ALP_ERR_INVALID_ARG;
   (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->st);
+  (void)settle(ctx);
   drop_graph(ctx);
   free_work(ctx);
   if (ctx->d_cases) (void)hipFree(ctx->d_cases);
@@ -1202,22 +1210,26 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
                     ovf);
       }
     }
-    if ((rc = enter(ctx)) != ALP_OK) return rc;
-    HIPCHK(ctx, hipGraphLaunch(ctx->gexec, ctx->st));
-    HIPCHK(ctx, hipEventRecord(ctx->ev_replay, ctx->st));
+    // the replay runs on the caller's stream itself: it is ordered after the
+    // caller's earlier work and before its later work with no event hand-over
+    // (every other call orders the internal stream after the caller's first)
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipGraphLaunch(ctx->gexec, ctx->user));
+    HIPCHK(ctx, hipEventRecord(ctx->ev_replay, ctx->user));
     ctx->replay_pending = true;
-    if (flags & ALP_CHECKED) {
-      uint32_t ovf;
-      int64_t ne, nr;
-      if ((rc = read_needs(ctx, ovf, ne, nr)) != ALP_OK) return rc;
-      if (ovf) return fail(ctx, ALP_ERR_CAPACITY, "work list overflow in graph replay (0x%x); call alp_invalidate", ovf);
-      if ((rc = verify_records(ctx)) != ALP_OK) return rc;
-    }
     ctx->last_cases = n_cases;
     ctx->dg_cnt = nullptr;
     ctx->dg_out = nullptr;
     ctx->dg_counters = nullptr;
-    return leave(ctx);
+    if (flags & ALP_CHECKED) {
+      uint32_t ovf;
+      int64_t ne, nr;
+      if ((rc = enter(ctx)) != ALP_OK) return rc;
+      if ((rc = read_needs(ctx, ovf, ne, nr)) != ALP_OK) return rc;
+      if (ovf) return fail(ctx, ALP_ERR_CAPACITY, "work list overflow in graph replay (0x%x); call alp_invalidate", ovf);
+      if ((rc = verify_records(ctx)) != ALP_OK) return rc;
+    }
+    return ALP_OK;
   }
   std::vector<CaseDev> cs;
   std::vector<alp_mesh *> meshes;
@@ -1545,7 +1557,8 @@ alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out) {
   if (!ctx || !out) return fail(ctx, ALP_ERR_INVALID_ARG, "NULL argument");
   if (case_index < 0 || case_index >= ctx->last_cases || (!ctx->w.cnt && !ctx->dg_cnt))
     return fail(ctx, ALP_ERR_INVALID_ARG, "no diagnostics for case %d", case_index);
-  HIPCHK(ctx, hipSetDevice(ctx->device));
+  alp_status rc = enter(ctx);  // after a replay on the caller's stream
+  if (rc != ALP_OK) return rc;
   long long cnt[kCnt];
   double d[16];
   uint32_t counters[16];
@@ -1577,8 +1590,7 @@ alp_status alp_get_diag(alp_context *ctx, int32_t case_index, alp_diag *out) {
 
 alp_status alp_invalidate(alp_context *ctx) {
   if (!ctx) return ALP_ERR_INVALID_ARG;
-  (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->st);
+  (void)settle(ctx);
   drop_graph(ctx);
   ctx->tkey.clear();  // the next ALP_AUTOTUNE call chooses again (the shape stays until then)
   return ALP_OK;
@@ -1594,8 +1606,7 @@ alp_status alp_set_tuning(alp_context *ctx, const alp_tuning *t) {
   if (!ctx || !t) return fail(ctx, ALP_ERR_INVALID_ARG, "NULL argument");
   if (!tuning_valid(*t))
     return fail(ctx, ALP_ERR_INVALID_ARG, "tuning out of range (lanes 2/4/8, waves 0..32, grab 1..16)");
-  (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->st);
+  (void)settle(ctx);
   drop_graph(ctx);
   ctx->tun = *t;
   ctx->tkey.clear();
