@@ -512,7 +512,8 @@ constexpr int kNumStages = 8;
 
 // the launch sequence of one step (no host synchronisation inside); when ev is
 // given, ev[i+1] is recorded after stage i (ev[0] before the first)
-void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent_t *ev = nullptr) {
+void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent_t *ev = nullptr,
+                     uint32_t *ovf_dst = nullptr) {
   hipStream_t st = ctx->st;
   const Work &w = L.w;
   auto mark = [&](int i) {
@@ -571,8 +572,7 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   mark(6);
   launch_spread(L, st);
   mark(7);
-  launch_zero_dirty(L, st);
-  launch_finalize(L, st);
+  launch_step_end(L, ovf_dst, st);
   mark(8);
 }
 
@@ -1248,8 +1248,7 @@ alp_status alp_step_batched(alp_context *ctx, int32_t n_cases, const alp_case *c
     StepLaunch L = make_launch(ctx, n_cases);
     hipGraph_t g = nullptr;
     HIPCHK(ctx, hipStreamBeginCapture(ctx->st, hipStreamCaptureModeThreadLocal));
-    launch_sequence(ctx, L, ST_ALL);
-    launch_export_overflow(L, ctx->d_ovf, ctx->st);
+    launch_sequence(ctx, L, ST_ALL, nullptr, ctx->d_ovf);
     hipError_t e = hipStreamEndCapture(ctx->st, &g);
     if (e != hipSuccess) return fail(ctx, ALP_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);

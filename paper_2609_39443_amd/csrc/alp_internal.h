@@ -501,9 +501,7 @@ void launch_norm(const StepLaunch &L, hipStream_t st);
 void launch_beam_sums(const StepLaunch &L, hipStream_t st);
 void launch_spread(const StepLaunch &L, hipStream_t st);
 int spread_blocks_per_cu();  // resident k_spread blocks per CU (0 if the query fails)
-void launch_zero_dirty(const StepLaunch &L, hipStream_t st);
-void launch_finalize(const StepLaunch &L, hipStream_t st);
+void launch_step_end(const StepLaunch &L, uint32_t *ovf_dst, hipStream_t st);
 // copy the step's overflow word to a device-visible host word
-void launch_export_overflow(const StepLaunch &L, uint32_t *dst, hipStream_t st);
 
 }  // namespace alp

@@ -2654,68 +2654,57 @@ void launch_spread(const StepLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL(k_spread, dim3(L.grid_spread), dim3(64), 0, st, L);
 }
 
-// ------------------------------------------------------------- zero dirty --
-// Cells of tiles written at the previous step but not now return to zero;
-// the tile activity becomes the new previous state.
-__global__ void k_zero_dirty(StepLaunch L) {
+// ---------------------------------------------------------------- step end --
+// One launch after the spread: the cells of tiles written at the previous
+// step but not now return to zero and the tile activity becomes the new
+// previous state (every block but the last, one thread per tile); the last
+// block decodes each case's fluid-side force and the balance check and, in a
+// captured step, writes the step's overflow word to mapped host memory, so
+// that a later call can see that a replay overflowed without synchronising.
+constexpr int kEndBlock = 256;
+__global__ __launch_bounds__(kEndBlock) void k_step_end(StepLaunch L, uint32_t *ovf_dst) {
   Work W = L.w;
-  int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tg >= W.n_tiles) return;
-  int c = case_of(L.tbase, L.n_cases, tg);
-  const CaseDev &cs = L.cases[c];
-  if (!cs.write_S || !cs.tile_prev) return;
-  int64_t tl = tg - cs.tile_base;
-  uint8_t now = W.tile_items[tg] > 0 ? 1 : 0;
-  if (cs.tile_prev[tl] && !now) {
-    uint32_t c0 = tile_cell_start(cs.m, tl), c1 = tile_cell_start(cs.m, tl + 1);
-    for (uint32_t j = c0; j < c1; ++j) {
-      double *S = cs.S + 3 * (int64_t)cs.m.perm[j];
-      S[0] = 0.0;
-      S[1] = 0.0;
-      S[2] = 0.0;
+  if (blockIdx.x + 1 < gridDim.x) {
+    const int64_t tg = (int64_t)blockIdx.x * kEndBlock + threadIdx.x;
+    if (tg >= W.n_tiles) return;
+    const int c = case_of(L.tbase, L.n_cases, tg);
+    const CaseDev &cs = L.cases[c];
+    if (!cs.write_S || !cs.tile_prev) return;
+    const int64_t tl = tg - cs.tile_base;
+    const uint8_t now = W.tile_items[tg] > 0 ? 1 : 0;
+    if (cs.tile_prev[tl] && !now) {
+      const uint32_t c0 = tile_cell_start(cs.m, tl), c1 = tile_cell_start(cs.m, tl + 1);
+      for (uint32_t j = c0; j < c1; ++j) {
+        double *S = cs.S + 3 * (int64_t)cs.m.perm[j];
+        S[0] = 0.0;
+        S[1] = 0.0;
+        S[2] = 0.0;
+      }
     }
+    cs.tile_prev[tl] = now;
+    return;
   }
-  cs.tile_prev[tl] = now;
-}
-
-void launch_zero_dirty(const StepLaunch &L, hipStream_t st) {
-  if (L.w.n_tiles == 0) return;
-  hipLaunchKernelGGL(k_zero_dirty, dim3((unsigned)((L.w.n_tiles + 255) / 256)), dim3(256), 0, st, L);
-}
-
-// --------------------------------------------------------------- finalize --
-__global__ void k_finalize(StepLaunch L) {
-  Work W = L.w;
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= L.n_cases) return;
-  double *d = W.diag_out + 16 * c;
-  int E = W.F_exp[c];
-  double F[3];
-  for (int a = 0; a < 3; ++a) F[a] = fx_decode(W.F_hi[3 * c + a], W.F_lo[3 * c + a], E);
-  d[4] = F[0];
-  d[5] = F[1];
-  d[6] = F[2];
-  double r0 = F[0] + d[0], r1 = F[1] + d[1], r2 = F[2] + d[2];
-  d[7] = d[3] > 0.0 ? sqrt(r0 * r0 + r1 * r1 + r2 * r2) / d[3] : 0.0;
-  d[8] = (double)W.counters[3];
-}
-
-// The overflow word of the step, written to mapped host memory at the end of
-// a captured step, so that a later call can see that a replay overflowed
-// without synchronising.
-__global__ void k_export_overflow(StepLaunch L, uint32_t *dst) {
-  if (threadIdx.x == 0) {
-    __atomic_store_n(dst, L.w.counters[3], __ATOMIC_RELEASE);
+  for (int c = threadIdx.x; c < L.n_cases; c += kEndBlock) {
+    double *d = W.diag_out + 16 * c;
+    const int E = W.F_exp[c];
+    double F[3];
+    for (int a = 0; a < 3; ++a) F[a] = fx_decode(W.F_hi[3 * c + a], W.F_lo[3 * c + a], E);
+    d[4] = F[0];
+    d[5] = F[1];
+    d[6] = F[2];
+    const double r0 = F[0] + d[0], r1 = F[1] + d[1], r2 = F[2] + d[2];
+    d[7] = d[3] > 0.0 ? sqrt(r0 * r0 + r1 * r1 + r2 * r2) / d[3] : 0.0;
+    d[8] = (double)W.counters[3];
+  }
+  if (ovf_dst && threadIdx.x == 0) {
+    __atomic_store_n(ovf_dst, W.counters[3], __ATOMIC_RELEASE);
     __threadfence_system();
   }
 }
 
-void launch_export_overflow(const StepLaunch &L, uint32_t *dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_export_overflow, dim3(1), dim3(64), 0, st, L, dst);
-}
-
-void launch_finalize(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3((L.n_cases + 63) / 64), dim3(64), 0, st, L);
+void launch_step_end(const StepLaunch &L, uint32_t *ovf_dst, hipStream_t st) {
+  const unsigned nz = (unsigned)((L.w.n_tiles + kEndBlock - 1) / kEndBlock);
+  hipLaunchKernelGGL(k_step_end, dim3(nz + 1), dim3(kEndBlock), 0, st, L, ovf_dst);
 }
 
 }  // namespace alp
