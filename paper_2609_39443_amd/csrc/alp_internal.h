@@ -390,6 +390,42 @@ __device__ __host__ inline double fx_decode(long long hi, unsigned long long lo,
   return ldexp((double)hi, E - kHiShift) + ldexp((double)lo, E - kHiShift - kLoBits);
 }
 
+// Loads of values that no kernel of the pass writes (work-item tables, the
+// case table) through the scalar unit: a wave-uniform address then costs no
+// vector-memory slot, and the wait for it does not also wait for vector
+// loads, stores or atomics in flight.
+template <class T>
+__device__ __forceinline__ T sload(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)(p);
+}
+__device__ __forceinline__ Item sload_item(const Item *p) {
+  Item it;
+  it.tile = sload(&p->tile);
+  it.c0 = sload(&p->c0);
+  it.c1 = sload(&p->c1);
+  it.cs = sload(&p->cs);
+  it.eoff = sload(&p->eoff);
+  it.nent = sload(&p->nent);
+  return it;
+}
+// the mesh fields of the tile geometry and the sorted cell arrays (the other
+// fields are left zero)
+__device__ __forceinline__ MeshDev sload_mesh_geometry(const MeshDev *p) {
+  MeshDev m = {};
+  m.T = sload(&p->T);
+  for (int a = 0; a < 3; ++a) {
+    m.nb[a] = sload(&p->nb[a]);
+    m.nt[a] = sload(&p->nt[a]);
+    m.lo[a] = sload(&p->lo[a]);
+  }
+  m.tile_len = sload(&p->tile_len);
+  m.cx = sload(&p->cx);
+  m.cy = sload(&p->cy);
+  m.cz = sload(&p->cz);
+  m.vs = sload(&p->vs);
+  return m;
+}
+
 // Centre of tile (tx, ty, tz): (lo + t tile_len) + tile_len / 2 per axis, in
 // this one evaluation order (no contraction), so that every kernel that
 // forms coordinates relative to it gets the same FP64 value.

@@ -1532,10 +1532,12 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     // the item index is wave-uniform: read it into a scalar register so that
     // the descriptor and the case fields are scalar loads
     item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
-    const Item it = W.item[item];
+    const Item it = sload_item(W.item + item);
     if (!kMulti && it.nent > (uint32_t)kMaxEntries) continue;
-    if ((L.cases[it.cs].proj_mode == ALP_PROJ_INTEGRATED) != kInt) continue;
-    if ((L.cases[it.cs].prec == ALP_PREC_FP32_SPLIT) != kSplit) continue;
+    const CaseDev *cp = L.cases + it.cs;
+    const int cprec = sload(&cp->prec);
+    if ((sload(&cp->proj_mode) == ALP_PROJ_INTEGRATED) != kInt) continue;
+    if ((cprec == ALP_PREC_FP32_SPLIT) != kSplit) continue;
     if (it.cs != acc_case) {
       if (lane == 0 && acc_case >= 0 && acc_pairs)
         atomicAdd((unsigned long long *)(W.cnt + kCnt * acc_case + 5), acc_pairs);
@@ -1545,15 +1547,16 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       acc_pairs = 0;
       acc_guard = 0;
     }
-    const CaseDev &cs = L.cases[it.cs];
-    const MeshDev &m = cs.m;
-    // case fields held in registers for the whole item: the loops below store
-    // and update atomically, after which the compiler would read them again
-    const gptr<double> Psp = to_global(cs.Psp);
-    const gptr<double> Eps = to_global(cs.eps);
-    const int64_t pbase = cs.point_base;
-    const int64_t tl = it.tile - cs.tile_base;
-    const int rsz = rec_size(cs.prec, W.rec_compact != 0);
+    // case fields held in registers for the whole item, read by scalar
+    // loads (the loops below store and update atomically, after which the
+    // compiler would read them again; and a vector load here would first
+    // wait for the previous item's node-sum atomics)
+    const MeshDev m = sload_mesh_geometry(&cp->m);
+    const gptr<double> Psp = to_global(sload(&cp->Psp));
+    const gptr<double> Eps = to_global(sload(&cp->eps));
+    const int64_t pbase = sload(&cp->point_base);
+    const int64_t tl = it.tile - sload(&cp->tile_base);
+    const int rsz = rec_size(cprec, W.rec_compact != 0);
     // the tile's entries, in beam order; more than kMaxEntries are taken in
     // groups of kMaxEntries, one after another
     const uint32_t ne_all = it.nent;
@@ -2358,18 +2361,9 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // records of a work item are sorted by cell, so each cell owns one contiguous
 // run; its lane sums the run in record order.  Every cell of an active tile
 // is written.
-// Loads of values that no kernel of the pass writes (work-item tables, the
-// case table) through the scalar unit: a wave-uniform address then costs no
-// vector-memory slot, and the wait for it does not also wait for the
-// record and force loads in flight.
 // s_waitcnt operand waiting for vmcnt 0 only (expcnt 7 and lgkmcnt 15 are
 // the fields' maxima, i.e. no wait on them)
 constexpr unsigned kWaitVmcnt0 = 0x0F70u;
-
-template <class T>
-__device__ __forceinline__ T sload(const T *p) {
-  return *(const __attribute__((address_space(4))) T *)(p);
-}
 
 // The record counts and bases of the work items, for the record cursor.
 struct ItemRecs {
