@@ -25,6 +25,42 @@ def test_actuator_points_eq15(oracle_mod):
     assert np.array_equal(oracle_mod.actuator_points(Cb, Wd), Cb + Wd)
 
 
+def test_actuator_points_follow_a_rigid_rotation(oracle_mod):
+    """W is a displacement from the initial centre, not a position: a stem
+    rotated rigidly about its base by W = R (C - b) + b - C puts every actuator
+    point on the rotated stem, at its initial distance from the base, with the
+    material offset W^ref rotated along when it is included in the body."""
+    rng = np.random.default_rng(4)
+    base = np.array([0.3, -0.2, 0.05])
+    s = np.sort(rng.uniform(0.0, 0.5, size=9))
+    Cb = base + s[:, None] * np.array([0.0, 0.0, 1.0])
+    th = 0.4
+    R = np.array([[math.cos(th), 0.0, math.sin(th)], [0.0, 1.0, 0.0], [-math.sin(th), 0.0, math.cos(th)]])
+    W = (Cb - base) @ R.T + base - Cb
+    P = oracle_mod.actuator_points(Cb, W)
+    axis = R @ np.array([0.0, 0.0, 1.0])
+    assert np.allclose(np.linalg.norm(P - base, axis=1), s, rtol=0, atol=1e-15)
+    assert np.allclose(P - base, s[:, None] * axis, rtol=0, atol=1e-15)
+    # an offset of 1 cm towards +x on the undeformed stem is carried as a
+    # constant vector (the paper's W^ref is fixed): the points shift by it
+    off = np.tile([0.01, 0.0, 0.0], (9, 1))
+    assert np.allclose(oracle_mod.actuator_points(Cb, W, off) - P, off, rtol=0, atol=1e-15)
+
+
+def test_actuator_points_sum_left_to_right(oracle_mod):
+    """Eq. (15) is summed in its written order, (C^b + W^ref) + W: with
+    1 + 2^-53 + 2^-53 the two half-ulp terms each round away, whereas a sum
+    that added them first would give 1 + 2^-52.  The GPU path sums in the same
+    order, which its bitwise comparisons rely on."""
+    h = 2.0 ** -53
+    Cb = np.array([[1.0, -1.0, 4.0]])
+    Wr = np.array([[h, -h, 4 * h]])
+    W = np.array([[h, -h, 4 * h]])
+    P = oracle_mod.actuator_points(Cb, W, Wr)
+    assert np.array_equal(P, Cb)
+    assert not np.array_equal(P, Cb + (Wr + W))
+
+
 def test_tangents_exact_on_straight_lines(oracle_mod):
     rng = np.random.default_rng(2)
     polys, dirs = [], []
