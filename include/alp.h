@@ -180,8 +180,11 @@ const char *alp_last_error(const alp_context *ctx);
 
 /* Bin a static mesh once (the paper builds its search structure once at the
    start of the run, Sec. 3.2.5): a uniform spatial hash of the cell centres,
-   the cells sorted by (tile, bin) with a counting sort, bin CSR, sorted FP64
-   centres and volumes, and the permutation back to the caller's order.
+   the cell ids sorted by (tile, bin) with a stable LDS radix sort (a bin's
+   cells in caller order), bin CSR, sorted FP64 centres and volumes, and the
+   permutation back to the caller's order.  The sorted layout is checked on
+   the device against the keys and the CSR; a failed check returns
+   ALP_ERR_HIP.
      n_cells     >= 1, < 2^31
      C           DEVICE [n_cells][3] cell centres
      V           DEVICE [n_cells] cell volumes (> 0)

@@ -1034,9 +1034,16 @@ alp_status alp_bin_cells(alp_context *ctx, int64_t n_cells, const double *C, con
   }
   d.n_bins = nbins;
   d.n_tiles = ntiles;
-  uint32_t *key = nullptr, *count = nullptr, *fillc = nullptr, *tmp = nullptr;
+  uint32_t *key = nullptr, *count = nullptr, *tmp = nullptr, *ks = nullptr, *k2 = nullptr, *v2 = nullptr,
+           *rcnt = nullptr, *bad = nullptr;
+  auto free_scratch = [&]() {
+    void *ps[] = {key, count, tmp, ks, k2, v2, rcnt, bad};
+    for (void *p : ps)
+      if (p) (void)hipFree(p);
+  };
 #define MALLOC_OR_FAIL(p, n)                      \
   if ((rc = dalloc(ctx, &(p), (n))) != ALP_OK) { \
+    free_scratch();                               \
     alp_mesh_destroy(m);                          \
     return rc;                                    \
   }
@@ -1049,26 +1056,35 @@ alp_status alp_bin_cells(alp_context *ctx, int64_t n_cells, const double *C, con
   MALLOC_OR_FAIL(m->perm, n_cells);
   MALLOC_OR_FAIL(m->tile_prev, ntiles);
   MALLOC_OR_FAIL(key, n_cells);
+  MALLOC_OR_FAIL(ks, n_cells);
+  MALLOC_OR_FAIL(k2, n_cells);
+  MALLOC_OR_FAIL(v2, n_cells);
   MALLOC_OR_FAIL(count, nbins + 1);
-  MALLOC_OR_FAIL(fillc, nbins + 1);
-  MALLOC_OR_FAIL(tmp, scan_tmp_words(nbins + 1));
+  MALLOC_OR_FAIL(rcnt, radix_scratch_words(n_cells));
+  MALLOC_OR_FAIL(tmp, scan_tmp_words(std::max(nbins + 1, radix_scratch_words(n_cells))));
+  MALLOC_OR_FAIL(bad, 1);
 #undef MALLOC_OR_FAIL
   launch_fill_u32(count, 0u, nbins + 1, st);
-  launch_fill_u32(fillc, 0u, nbins + 1, st);
+  launch_fill_u32(bad, 0u, 1, st);
   launch_fill_u8(m->tile_prev, 0, ntiles, st);
+  // bin keys and the bin CSR (exclusive scan of the histogram), then the
+  // cell ids radix-sorted by key, the layout checked against both
   launch_bin_keys(d, C, n_cells, key, count, st);
   launch_scan_u32(count, m->bin_start, nbins, tmp, st);
-  launch_bin_scatter(key, n_cells, m->bin_start, fillc, m->perm, st);
-  launch_bin_sort(m->bin_start, nbins, m->perm, st);
+  launch_radix_sort(key, n_cells, nbins, m->perm, ks, k2, v2, rcnt, tmp, st);
+  launch_bin_check(key, ks, m->perm, m->bin_start, n_cells, bad, st);
   launch_bin_reorder(C, V, m->perm, n_cells, m->cxyz, m->cx, m->cy, m->cz, m->vs, st);
-  hipError_t e = hipStreamSynchronize(st);
-  (void)hipFree(key);
-  (void)hipFree(count);
-  (void)hipFree(fillc);
-  (void)hipFree(tmp);
+  uint32_t hbad = 0;
+  hipError_t e = hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  free_scratch();
   if (e != hipSuccess) {
     alp_mesh_destroy(m);
     return fail(ctx, ALP_ERR_HIP, "binning failed: %s", hipGetErrorString(e));
+  }
+  if (hbad) {
+    alp_mesh_destroy(m);
+    return fail(ctx, ALP_ERR_HIP, "binned cell layout failed its check");
   }
   d.bin_start = m->bin_start;
   d.cxyz = m->cxyz;

@@ -481,9 +481,11 @@ void launch_mesh_bounds(const double *C, const double *V, int64_t n, double *par
 int mesh_bounds_blocks(int64_t n);
 void launch_bin_keys(const MeshDev &m, const double *C, int64_t n, uint32_t *key, uint32_t *count,
                      hipStream_t st);
-void launch_bin_scatter(const uint32_t *key, int64_t n, const uint32_t *start, uint32_t *fill,
-                        uint32_t *sorted, hipStream_t st);
-void launch_bin_sort(const uint32_t *start, int64_t n_bins, uint32_t *sorted, hipStream_t st);
+int64_t radix_scratch_words(int64_t n);
+void launch_radix_sort(const uint32_t *key, int64_t n, int64_t n_bins, uint32_t *perm, uint32_t *ksorted,
+                       uint32_t *k2, uint32_t *v2, uint32_t *cnt, uint32_t *tmp, hipStream_t st);
+void launch_bin_check(const uint32_t *key, const uint32_t *ksorted, const uint32_t *perm, const uint32_t *start,
+                      int64_t n, uint32_t *bad, hipStream_t st);
 void launch_bin_reorder(const double *C, const double *V, const uint32_t *sorted, int64_t n, double *cxyz,
                         double *cx, double *cy, double *cz, double *vs, hipStream_t st);
 

@@ -1,9 +1,9 @@
 // alp_mesh.hip -- scans, fills and the once-per-mesh binning of cell centres
 // (the static search structure the paper builds once at the start of a run,
-// Sec. 3.2.5): a uniform spatial hash whose bins are numbered tile-major, a
-// counting sort of the cells by bin (the histogram's exclusive scan is the
-// bin CSR), a per-bin sort by caller index for a deterministic layout, and
-// bin-sorted FP64 copies of the centres and volumes.
+// Sec. 3.2.5): a uniform spatial hash whose bins are numbered tile-major, the
+// bin CSR from the exclusive scan of the bin histogram, an LDS radix sort of
+// the cell ids by bin key (stable, so a bin's cells stay in caller order),
+// and bin-sorted FP64 copies of the centres and volumes.
 #include "alp_internal.h"
 
 namespace alp {
@@ -212,41 +212,144 @@ void launch_bin_keys(const MeshDev &m, const double *C, int64_t n, uint32_t *key
                      count);
 }
 
-__global__ void k_bin_scatter(const uint32_t *key, int64_t n, const uint32_t *start, uint32_t *fill,
-                              uint32_t *sorted) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t k = key[i];
-  uint32_t pos = start[k] + atomicAdd(&fill[k], 1u);
-  sorted[pos] = (uint32_t)i;
+// LSD radix sort of the cell ids by bin key, eight bits a pass.  The ids
+// start in caller order and every pass is stable, so the cells of a bin end
+// in caller order: the layout depends only on the centres and their
+// numbering, not on scheduling.  A pass: per-tile digit counts in LDS,
+// one exclusive scan of the counts laid out digit-major (which gives every
+// (digit, tile) its first output place), then a scatter in which each tile
+// ranks its keys in LDS, 256 at a time, and writes them in order.
+constexpr int kRadixBits = 8;
+constexpr int kRadixDigits = 1 << kRadixBits;
+constexpr int kRadixBlock = 256;  // one thread per digit in the LDS tables
+constexpr int kRadixPer = 16;     // keys per thread and tile
+constexpr int kRadixTile = kRadixBlock * kRadixPer;
+static_assert(kRadixBlock == kRadixDigits, "one thread per digit");
+
+int64_t radix_tiles(int64_t n) { return n > 0 ? (n + kRadixTile - 1) / kRadixTile : 1; }
+int radix_passes(int64_t n_bins) {
+  int bits = 0;
+  while (bits < 32 && ((uint64_t)(n_bins - 1) >> bits) != 0u) ++bits;
+  return (bits + kRadixBits - 1) / kRadixBits;
 }
 
-void launch_bin_scatter(const uint32_t *key, int64_t n, const uint32_t *start, uint32_t *fill,
-                        uint32_t *sorted, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, key, n,
-                     start, fill, sorted);
+__global__ __launch_bounds__(kRadixBlock) void k_radix_count(const uint32_t *key, int64_t n, int shift,
+                                                             uint32_t *cnt, int64_t n_tiles) {
+  __shared__ uint32_t h[kRadixDigits];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  for (int r = 0; r < kRadixPer; ++r) {
+    const int64_t i = base + (int64_t)r * kRadixBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & (kRadixDigits - 1)], 1u);
+  }
+  __syncthreads();
+  cnt[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// insertion sort of each bin's cells by caller index (bins hold a handful of
-// cells; the order only fixes a deterministic layout)
-__global__ void k_bin_sort(const uint32_t *start, int64_t n_bins, uint32_t *sorted) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_bins) return;
-  uint32_t s0 = start[b], s1 = start[b + 1];
-  for (uint32_t i = s0 + 1; i < s1; ++i) {
-    uint32_t v = sorted[i];
-    uint32_t j = i;
-    while (j > s0 && sorted[j - 1] > v) {
-      sorted[j] = sorted[j - 1];
-      --j;
+// vin == nullptr: the ids are the input positions (the first pass)
+__global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
+                                                               uint32_t *kout, uint32_t *vout, int64_t n,
+                                                               int shift, const uint32_t *off,
+                                                               int64_t n_tiles) {
+  __shared__ uint32_t run[kRadixDigits];                     // next place of each digit
+  __shared__ uint32_t wc[kRadixBlock / 64][kRadixDigits];    // this round's count per wave and digit
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  run[t] = off[(int64_t)t * n_tiles + blockIdx.x];
+  for (int w = 0; w < kRadixBlock / 64; ++w) wc[w][t] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int r = 0; r < kRadixPer; ++r) {
+    const int64_t i = base + (int64_t)r * kRadixBlock + t;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t v = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+    const uint32_t d = (k >> shift) & (kRadixDigits - 1);
+    // lanes of this wave holding the same digit: one ballot per digit bit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
     }
-    sorted[j] = v;
+    const uint32_t rank = (uint32_t)__popcll(peers & below);
+    if (valid && rank == 0u) wc[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wc[w][d];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0u;
+    for (int w = 0; w < kRadixBlock / 64; ++w) {
+      add += wc[w][t];
+      wc[w][t] = 0u;
+    }
+    run[t] += add;
+    __syncthreads();
   }
 }
 
-void launch_bin_sort(const uint32_t *start, int64_t n_bins, uint32_t *sorted, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((n_bins + 255) / 256)), dim3(256), 0, st, start,
-                     n_bins, sorted);
+__global__ void k_iota(uint32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (uint32_t)i;
+}
+
+int64_t radix_scratch_words(int64_t n) { return (int64_t)kRadixDigits * radix_tiles(n) + 1; }
+
+// Sorts the ids 0 .. n-1 by key (stable) into perm; ksorted receives the
+// sorted keys.  k2, v2: n words each; cnt: radix_scratch_words(n) words; tmp:
+// scan_tmp_words(radix_scratch_words(n)) words.  key is left unchanged.
+void launch_radix_sort(const uint32_t *key, int64_t n, int64_t n_bins, uint32_t *perm, uint32_t *ksorted,
+                       uint32_t *k2, uint32_t *v2, uint32_t *cnt, uint32_t *tmp, hipStream_t st) {
+  if (n <= 0) return;
+  const int passes = radix_passes(n_bins);
+  if (passes == 0) {
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, n);
+    (void)hipMemcpyAsync(ksorted, key, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    return;
+  }
+  const int64_t nt = radix_tiles(n);
+  const uint32_t *kin = key, *vin = nullptr;
+  for (int p = 0; p < passes; ++p) {
+    // the last pass writes perm and ksorted
+    const bool to_out = ((passes - 1 - p) & 1) == 0;
+    uint32_t *kout = to_out ? ksorted : k2, *vout = to_out ? perm : v2;
+    const int shift = p * kRadixBits;
+    hipLaunchKernelGGL(k_radix_count, dim3((unsigned)nt), dim3(kRadixBlock), 0, st, kin, n, shift, cnt, nt);
+    launch_scan_u32(cnt, cnt, (int64_t)kRadixDigits * nt, tmp, st);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kRadixBlock), 0, st, kin, vin, kout, vout, n,
+                       shift, cnt, nt);
+    kin = kout;
+    vin = vout;
+  }
+}
+
+// The binned layout checked against its definition: every sorted cell lies
+// in its own bin's range, carries its own key, and follows the one before it
+// in (key, caller index) order.  Any violation sets *bad.
+__global__ void k_bin_check(const uint32_t *key, const uint32_t *ksorted, const uint32_t *perm,
+                            const uint32_t *start, int64_t n, uint32_t *bad) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t k = ksorted[p], c = perm[p];
+  bool ok = c < (uint64_t)n && key[c] == k && start[k] <= (uint64_t)p && (uint64_t)p < start[k + 1];
+  if (p > 0) {
+    const uint32_t kp = ksorted[p - 1];
+    ok = ok && (kp < k || (kp == k && perm[p - 1] < c));
+  }
+  if (!ok) atomicOr(bad, 1u);
+}
+
+void launch_bin_check(const uint32_t *key, const uint32_t *ksorted, const uint32_t *perm, const uint32_t *start,
+                      int64_t n, uint32_t *bad, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_bin_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, key, ksorted, perm,
+                     start, n, bad);
 }
 
 __global__ void k_bin_reorder(const double *C, const double *V, const uint32_t *sorted, int64_t n,
