@@ -429,6 +429,24 @@ def test_bitwise_identical_across_binnings(gu, ctx, prec):
                 assert d[k] == dref[k], (tb, bs, k)
 
 
+@pytest.mark.parametrize("tb,bs,nx,passes", [(1, 1.0, 26, 0), (1, 0.05, 26, 1), (4, 0.0, 26, 2), (4, 0.0, 63, 3)])
+def test_cell_binning_radix_passes(gu, ctx, tb, bs, nx, passes):
+    """The cell ids are radix-sorted by bin key eight bits a pass: one bin (no
+    pass), under 256 bins (one), about one bin per cell (two), and a mesh of
+    161,280 cells (a ragged last sort tile) whose keys need three passes.
+    Every binning checks its sorted layout on the device; the step then
+    matches the oracle."""
+    wl = random_scene(41, nx=nx, ny=64 if nx > 26 else 22, nz=40 if nx > 26 else 18, n_beams=6)
+    C = wl["C"]
+    ext = C.max(axis=0) - C.min(axis=0)
+    if bs > 0:
+        nbins = int(np.prod(np.floor(ext / bs) + 1))
+        assert (nbins - 1).bit_length() <= 8 * passes and (passes == 0 or (nbins - 1).bit_length() > 8 * (passes - 1))
+    else:
+        assert 8 * (passes - 1) < (C.shape[0] - 1).bit_length() <= 8 * passes + 2
+    run_and_compare(gu, ctx, wl, alp.PREC_FP64, tile_bins=tb, bin_size=bs)
+
+
 def test_hundred_graph_replays_bitwise(gu, ctx):
     """Scheduling never changes a bit: 100 graph replays of a batch of two
     cases give the first replay's outputs and diagnostics exactly."""
