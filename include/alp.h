@@ -17,7 +17,9 @@
  * Conventions (all entry points)
  *   - Every array argument is DEVICE memory unless marked HOST, contiguous,
  *     row-major, little-endian, owned by the caller.  [n][3] means n rows of
- *     (x, y, z) doubles.  Indices are 0-based.
+ *     (x, y, z) doubles.  Indices are 0-based.  An array of zero rows may be
+ *     NULL (a case without beams needs no per-point array; its step writes a
+ *     zero source).
  *   - The library owns contexts, meshes and workspace.  It keeps no pointer to
  *     caller arrays beyond a call, except where a captured graph replays
  *     (alp_step_batched with ALP_USE_GRAPH): then the arrays named in the cases

@@ -698,8 +698,8 @@ alp_status build_batch(alp_context *ctx, int32_t n_cases, const alp_case *cases,
   S.assign((size_t)n_cases, nullptr);
   for (int i = 0; i < n_cases; ++i) {
     const alp_case &c = cases[i];
-    if (!c.mesh || !c.U || !c.f || !c.S)
-      return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: mesh, U, f and S are required", i);
+    if (!c.mesh || !c.U || !c.S || (!c.f && c.beams.n_points > 0))
+      return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: mesh, U, f and S are required (f only with points)", i);
     for (int j = 0; j < i; ++j)
       if (cases[j].mesh == c.mesh)
         return fail(ctx, ALP_ERR_INVALID_ARG, "case %d: a mesh may appear in one case per batch", i);
@@ -1113,9 +1113,10 @@ alp_status alp_sample(alp_context *ctx, const alp_mesh *mesh, const double *U,
                       int64_t *cell_a, int64_t *cell_s) {
   if (!ctx) return ALP_ERR_INVALID_ARG;
   ctx->err.clear();
-  if (!mesh || !U || !U_s) return fail(ctx, ALP_ERR_INVALID_ARG, "mesh, U or U_s is NULL");
+  if (!mesh || !U) return fail(ctx, ALP_ERR_INVALID_ARG, "mesh or U is NULL");
   alp_status rc;
   if ((rc = check_beams(ctx, beams, false, true, true)) != ALP_OK) return rc;
+  if (!U_s && beams->n_points > 0) return fail(ctx, ALP_ERR_INVALID_ARG, "U_s is NULL");
   if ((rc = check_params(ctx, params, false)) != ALP_OK) return rc;
   if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "use alp_step_batched under capture");
   if (beams->n_points == 0) return ALP_OK;
@@ -1140,9 +1141,9 @@ alp_status alp_drag(alp_context *ctx, const alp_beams *beams, const alp_params *
                     const double *U_s, const int64_t *cell_s, const double *f_prev, double *f) {
   if (!ctx) return ALP_ERR_INVALID_ARG;
   ctx->err.clear();
-  if (!U_s || !f) return fail(ctx, ALP_ERR_INVALID_ARG, "U_s or f is NULL");
   alp_status rc;
   if ((rc = check_beams(ctx, beams, false, true, true)) != ALP_OK) return rc;
+  if ((!U_s || !f) && beams->n_points > 0) return fail(ctx, ALP_ERR_INVALID_ARG, "U_s or f is NULL");
   if ((rc = check_params(ctx, params, f_prev != nullptr)) != ALP_OK) return rc;
   if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "use alp_step_batched under capture");
   if (beams->n_points == 0) return ALP_OK;
@@ -1170,9 +1171,10 @@ alp_status alp_spread(alp_context *ctx, const alp_mesh *mesh, const alp_beams *b
                       double *fhat) {
   if (!ctx) return ALP_ERR_INVALID_ARG;
   ctx->err.clear();
-  if (!mesh || !f || !S) return fail(ctx, ALP_ERR_INVALID_ARG, "mesh, f or S is NULL");
+  if (!mesh || !S) return fail(ctx, ALP_ERR_INVALID_ARG, "mesh or S is NULL");
   alp_status rc;
   if ((rc = check_beams(ctx, beams, true, false, true)) != ALP_OK) return rc;
+  if (!f && beams->n_points > 0) return fail(ctx, ALP_ERR_INVALID_ARG, "f is NULL");
   if ((rc = check_params(ctx, params, false)) != ALP_OK) return rc;
   if (is_capturing(ctx)) return fail(ctx, ALP_ERR_CAPTURE, "use alp_step_batched under capture");
   if ((rc = enter(ctx)) != ALP_OK) return rc;

@@ -244,6 +244,58 @@ def test_edge_cases(gu, ctx):
     run_and_compare(gu, ctx, wl, alp.PREC_FP64)
 
 
+def empty_scene(outside=False):
+    """A mesh with no beams, or (outside) with one beam whose every point lies
+    beyond the domain box: no point samples or loads the fluid."""
+    C, V = W.uniform_mesh(14, 12, 10, 0.01)
+    if outside:
+        n = 6
+        P = np.stack([np.full(n, 0.5), np.full(n, 0.05), 0.01 + 0.01 * np.arange(n)], axis=1)
+        beams = W._beamset([P], [np.tile([0, 0, 1.0], (n, 1))], [np.zeros((n, 3))], [np.full(n, 0.002)],
+                           [np.full(n, 0.01)], [np.full(n, 0.015)], [1.2], [0.0], [0.03], [[0, 0, 0]],
+                           [[-1.0, 0, 0]])
+    else:
+        beams = W._beamset([], [], [], [], [], [], [], [], [], np.zeros((0, 3)), np.zeros((0, 3)))
+    return {"name": "all-outside" if outside else "no-beams", "C": C, "V": V,
+            "U": np.tile([0.2, 0.0, 0.05], (C.shape[0], 1)), "box": None, "beams": beams,
+            "params": {"rho": 1000.0, "tau": 1e-6}}
+
+
+@pytest.mark.parametrize("prec", [alp.PREC_FP64, alp.PREC_FP32_SPLIT])
+@pytest.mark.parametrize("outside", [False, True])
+def test_empty_and_all_outside_cases(gu, ctx, prec, outside):
+    """A case with no beams, or whose points all lie outside the domain,
+    writes a zero source over its whole mesh (also over a source array that
+    held other values), batched, unbatched and between two loaded cases of
+    one batch, whose results it leaves bitwise unchanged."""
+    wl = empty_scene(outside)
+    for batched in (True, False):
+        case, res, ref, diag = run_and_compare(gu, ctx, wl, prec, batched=batched)
+        assert not np.any(res["S"]) and diag["n_band_cells"] == 0 and diag["n_pairs"] == 0
+        assert diag["n_outside"] == (6 if outside else 0)
+    # a source array holding other values is cleared on its first use
+    case = gu.GpuCase(ctx, wl, prec)
+    case.S.fill_(7.0)
+    gu.step_batched(ctx, [case], alp.USE_GRAPH)
+    assert not np.any(case.results()["S"])
+    alp.alp_invalidate(ctx.h)
+    # between two loaded cases
+    wa, wb = random_scene(51, n_beams=5), random_scene(52, n_beams=4)
+    singles = []
+    for w in (wa, wb):
+        c = gu.GpuCase(ctx, w, prec)
+        gu.step_batched(ctx, [c])
+        singles.append(c.results())
+    ca, ce, cb = gu.GpuCase(ctx, wa, prec), gu.GpuCase(ctx, wl, prec), gu.GpuCase(ctx, wb, prec)
+    gu.step_batched(ctx, [ca, ce, cb], alp.USE_GRAPH)
+    for c, ref1 in ((ca, singles[0]), (cb, singles[1])):
+        r = c.results()
+        for k in ref1:
+            assert np.array_equal(r[k], ref1[k]), k
+    assert not np.any(ce.results()["S"])
+    alp.alp_invalidate(ctx.h)
+
+
 def near_tie_scene():
     """Beams whose segments lie at (nearly) equal distances from many cells: a
     closed polygon around a cell centre, a beam folded back onto itself, and a
