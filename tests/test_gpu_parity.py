@@ -349,7 +349,7 @@ def test_batch_equals_single_cases(gu, ctx):
 
 def test_mixed_precision_batch_equals_single_cases(gu, ctx):
     """FP64 and FP32-split cases alternating in one batch (their 24- and
-    16-byte pair records interleave in the spread's record stream) give
+    12-byte pair records interleave in the spread's record stream) give
     bitwise the results of the same cases run alone, and match the oracle."""
     precs = [alp.PREC_FP64, alp.PREC_FP32_SPLIT, alp.PREC_FP64, alp.PREC_FP32_SPLIT]
     wls = [random_scene(40 + i, nx=18 + 2 * i, ny=16, nz=14, n_beams=3 + i) for i in range(4)]
@@ -366,6 +366,54 @@ def test_mixed_precision_batch_equals_single_cases(gu, ctx):
         res = alone.results()
         for k in ("S", "w", "f", "fhat"):
             assert np.array_equal(res[k], batched[i][k]), (i, k)
+
+
+def test_wide_split_records_beyond_2_25_points(gu, ctx):
+    """Split-precision pair records carry the node index packed beside the
+    cell lane (12 bytes) while a batch has fewer than 2^25 points, and take
+    16 bytes beyond.  A beam of 2^25 points outside the domain, ahead of a
+    loaded scene in the same case, puts the scene's nodes above 2^25: the
+    scene's source and node weights equal those of the scene alone, bitwise,
+    and match the oracle; every point of the long beams is counted outside."""
+    wl = random_scene(61, n_beams=5)
+    n_far, per = 1 << 25, 1 << 16  # 512 beams of 65,536 points
+    nb_far = n_far // per
+    b = wl["beams"]
+    far_P = np.zeros((n_far, 3))
+    far_P[:, 0] = 10.0 + 1e-6 * np.arange(n_far)
+    far_P[:, 1:] = 0.05
+    big = {"offsets": np.concatenate([np.arange(0, n_far, per), n_far + b["offsets"]]),
+           "P": np.concatenate([far_P, b["P"]]),
+           "e_t": np.concatenate([np.tile([1.0, 0.0, 0.0], (n_far, 1)), b["e_t"]]),
+           "Pdot": np.concatenate([np.zeros((n_far, 3)), b["Pdot"]])}
+    for k, v in (("d", 0.002), ("L", 1e-6), ("eps", 0.01)):
+        big[k] = np.concatenate([np.full(n_far, v), b[k]])
+    for k, v in (("Cdn", 1.2), ("Cdt", 0.0), ("ls", 0.03)):
+        big[k] = np.concatenate([np.full(nb_far, v), b[k]])
+    big["n_p"] = np.concatenate([np.zeros((nb_far, 3)), b["n_p"]])
+    big["e_up"] = np.concatenate([np.tile([0.0, 0.0, 1.0], (nb_far, 1)), b["e_up"]])
+    wide = dict(wl, beams=big, name="wide-records")
+    del far_P
+    case = gu.GpuCase(ctx, wide, alp.PREC_FP32_SPLIT)
+    gu.step_batched(ctx, [case], alp.USE_GRAPH)
+    res = case.results()
+    d = ctx.diag(0)
+    alp.alp_invalidate(ctx.h)
+    del case
+    torch.cuda.empty_cache()
+    alone = gu.GpuCase(ctx, wl, alp.PREC_FP32_SPLIT)
+    gu.step_batched(ctx, [alone], alp.USE_GRAPH)
+    ra = alone.results()
+    da = ctx.diag(0)
+    alp.alp_invalidate(ctx.h)
+    assert d["n_outside"] == n_far + da["n_outside"]
+    assert np.array_equal(res["S"], ra["S"])
+    assert np.array_equal(res["w"][n_far:], ra["w"]) and not np.any(res["w"][:n_far])
+    assert np.array_equal(res["f"][n_far:], ra["f"])
+    assert d["n_pairs"] == da["n_pairs"] and d["n_band_cells"] == da["n_band_cells"]
+    ref = gu.oracle_step(wl)
+    tS, tw = TOL[alp.PREC_FP32_SPLIT]
+    gu.compare(ra, ref, da, ref["diag"], tS, tw)
 
 
 def test_graph_replay_bitwise_and_updates(gu, ctx):
