@@ -2461,7 +2461,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
   const int lane = threadIdx.x;
   const uint32_t n_items = (uint32_t)min((int64_t)W.tile_itoff[W.n_tiles], W.cap_item);
   const uint32_t stride = gridDim.x;
-  if (blockIdx.x >= n_items) return;
+  const uint32_t first = rec_first_item(blockIdx.x, gridDim.x);
+  if (first >= n_items) return;
   // per-wave accumulation (exact fixed point, flushed when the case changes)
   int acc_case = -1;
   unsigned long long acc_band = 0;
@@ -2486,7 +2487,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
   // refilled by the pass that sums it.  So no record register is read or
   // copied while its load is in flight.
   const ItemRecs src{W.rec_cnt, W.rec_base};
-  RecCursor cur = rec_start(src, blockIdx.x, n_items, stride);
+  RecCursor cur = rec_start(src, first, n_items, stride);
   SpreadChunk A, B;
   spread_issue(W, src, cur, n_items, stride, lane, A);
   spread_issue(W, src, cur, n_items, stride, lane, B);

@@ -1,7 +1,9 @@
 """Host replay of the spread pass's record cursor (csrc/alp_reccursor.h).
 
 The spread kernel walks the pair records of its work items (item, item +
-stride, ...) as one stream of chunks of up to 64 records, every item giving at
+stride, ...; the first item of each wave is chosen so that the waves of one
+XCD start on neighbouring items) as one stream of chunks of up to 64 records,
+every item giving at
 least one chunk (the cells of an item without records are written too), with
 two chunks in flight: a chunk's loads are issued two passes before it is
 summed, and the next item's count and base are read one item ahead.  A C++
@@ -11,8 +13,9 @@ and 24-byte records, grouped items, gaps between reservations, grids larger
 than the item count) and checks that every chunk comes in item order with the
 right first record, that every lane's read of kRecReadBytes from its record
 lies inside its own item's records or, for its tail, inside the record area
-and its slack, that lanes past an item's records read nothing, and that no
-item's count or base is read past the item count.
+and its slack, that lanes past an item's records read nothing, that no
+item's count or base is read past the item count, that the waves' first items
+are a permutation of the grid, and that every item is summed exactly once.
 """
 import os
 import subprocess
@@ -47,7 +50,8 @@ int main() {
   long checked = 0;
   for (int trial = 0; trial < 400; ++trial) {
     const uint32_t n = (uint32_t)(rng() % 3000);
-    const uint32_t grid = 1 + (uint32_t)(rng() % 700);
+    // grids of any size, and multiples of 8 (whose waves start XCD-wise)
+    const uint32_t grid = trial % 2 ? 8 * (1 + (uint32_t)(rng() % 90)) : 1 + (uint32_t)(rng() % 700);
     std::vector<uint32_t> cnt(n);
     std::vector<uint64_t> base(n);
     // reservations in a random order, 16-byte aligned, with gaps
@@ -72,17 +76,22 @@ int main() {
     }
     const uint64_t cap = top;
     Src src{&cnt, &base};
+    std::vector<uint32_t> seen(n, 0u), firsts(grid, 0u);
     for (uint32_t b = 0; b < grid; ++b) {
-      if (b >= n) continue;
-      RecCursor cur = rec_start(src, b, n, grid);
+      const uint32_t first = rec_first_item(b, grid);
+      CHECK(first < grid, "trial %d wave %u: first item %u outside the grid", trial, b, first);
+      ++firsts[first];
+      if (first >= n) continue;
+      RecCursor cur = rec_start(src, first, n, grid);
       RecChunk A = rec_take(src, cur, n, grid), B = rec_take(src, cur, n, grid);
       // the chunks the summation must see, in order
-      uint32_t item = b, p0 = 0;
+      uint32_t item = first, p0 = 0;
       auto pass = [&](RecChunk &X) -> int {
         if (X.item >= n) return 0;
         if (X.item != item || X.p0 != p0) return -1;
         const uint32_t rn = cnt[item];
         if (X.rn != rn || X.rb != base[item]) return -1;
+        if (p0 == 0) ++seen[item];
         for (int l = 0; l < 64; ++l) {
           const uint64_t at = rec_lane(X, n, l);
           const uint32_t j = p0 + (uint32_t)l;
@@ -114,6 +123,8 @@ int main() {
       CHECK(A.item >= n && B.item >= n, "trial %d wave %u: chunks after the last item", trial, b);
     }
     CHECK(src.bad == 0, "trial %d: %ld count/base reads past the item count", trial, src.bad);
+    for (uint32_t b = 0; b < grid; ++b) CHECK(firsts[b] == 1, "trial %d: %u waves start at %u", trial, firsts[b], b);
+    for (uint32_t i = 0; i < n; ++i) CHECK(seen[i] == 1, "trial %d: item %u summed %u times", trial, i, seen[i]);
   }
   std::printf("ok %ld\n", checked);
   return 0;
