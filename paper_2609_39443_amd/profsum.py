@@ -57,7 +57,12 @@ COPY_KIB = 1024 * 1024  # the 1 GiB calibration copy, each way
 # kernels whose counters go into the traffic table (the per-step hot path)
 HOT = ("k_weights", "k_weights64", "k_weights_int", "k_weights_int64", "k_spread", "k_sample", "k_tile_merge",
        "k_chunk_tiles", "k_emit_scatter",
-       "k_chunk_boxes", "k_points_prep", "k_items", "k_drag", "k_normalise")
+       "k_chunk_boxes", "k_points_prep", "k_items", "k_drag", "k_norm")
+
+
+def hot(name: str) -> bool:
+    """A per-step kernel of the table (template arguments ignored)."""
+    return name.split("<")[0] in HOT
 
 
 def source_hash() -> str:
@@ -161,7 +166,7 @@ def main(argv):
                "kernels": {}}
     lines = [f"{'kernel':16s} {'disp':>5s} {'avg_us':>8s} {'waves':>7s} {'VALU':>12s} {'LDS':>10s} {'SALU':>11s} "
              f"{'fetchKiB':>10s} {'writeKiB':>10s} {'HBM_MB':>8s} {'GB/s':>8s}"]
-    for k in sorted((k for k in HOT if k in fe and k in wr), key=lambda k: -fe[k]["_dur_ns"]):
+    for k in sorted((k for k in fe if hot(k) and k in wr), key=lambda k: -fe[k]["_dur_ns"]):
         fk, wk = fe[k]["FETCH_SIZE"], wr[k]["WRITE_SIZE"]
         b = (fk * ff + wk * wf) * 1024.0
         dur = 0.5 * (fe[k]["_dur_ns"] + wr[k]["_dur_ns"])
@@ -191,7 +196,7 @@ def main(argv):
         tail += ("\nLDS counters per dispatch (the fourth pass above):\n"
                  f"{'kernel':16s} {'LDS_insts':>11s} {'LDS_active':>12s} {'bank_confl':>11s} {'addr_confl':>11s} "
                  f"{'confl/active':>12s}\n")
-        for k in sorted((k for k in HOT if k in ld and ld[k].get("SQ_INSTS_LDS", 0) > 0),
+        for k in sorted((k for k in ld if hot(k) and ld[k].get("SQ_INSTS_LDS", 0) > 0),
                         key=lambda k: -ld[k].get("SQ_LDS_IDX_ACTIVE", 0)):
             c = ld[k]
             act = c.get("SQ_LDS_IDX_ACTIVE", 0.0)
