@@ -309,8 +309,9 @@ void launch_radix_sort(const uint32_t *key, int64_t n, int64_t n_bins, uint32_t 
   if (n <= 0) return;
   const int passes = radix_passes(n_bins);
   if (passes == 0) {
+    // one bin: every key is 0 and the order is the caller's
     hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, n);
-    (void)hipMemcpyAsync(ksorted, key, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    launch_fill_u32(ksorted, 0u, n, st);
     return;
   }
   const int64_t nt = radix_tiles(n);

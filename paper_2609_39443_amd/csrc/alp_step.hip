@@ -2374,10 +2374,14 @@ struct ItemRecs {
 };
 
 struct SpreadScratch {
-  double cc[3][kSpreadChunk];
+  // per-record contributions; at an item's end, its cells' source rows in
+  // sorted order (64 rows of 24 bytes), read back in 16-byte pieces
+  alignas(16) double cc[3][kSpreadChunk];
   uint16_t first[64], last[64];  // run of each cell inside the chunk (last exclusive)
+  uint32_t pc[64];               // caller index of each cell of the item (at its end)
   uint8_t cl[kSpreadChunk];      // cell lane of each record (items with several runs per cell)
 };
+static_assert(sizeof(double) * 3 * kSpreadChunk == 24 * 64, "one 24-byte source row per cell");
 
 // A chunk in flight: its place in the stream, its item's descriptor and the
 // first 24 bytes of this lane's record (every record size is read the same
@@ -2601,11 +2605,37 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
       // the item's cells are complete: write them, count the band cells and
       // add the force on the fluid (deterministic wave sum, then exact
       // accumulation)
-      if (valid && sload(&cp->write_S)) {
-        double *S = sload(&cp->S) + 3 * (int64_t)pc;
-        S[0] = S0;
-        S[1] = S1;
-        S[2] = S2;
+      if (sload(&cp->write_S)) {
+        // The rows go out as 16-byte pieces of the item's rows in sorted
+        // order: cells that are consecutive in the caller's numbering (runs
+        // along the fastest mesh axis) then take whole pieces, and one store
+        // instruction covers whole runs instead of a part of every run.  A
+        // piece that spans two rows which are not neighbours in the caller's
+        // order is written as two words.
+        double *rows = &sh.cc[0][0];
+        rows[3 * lane] = S0;
+        rows[3 * lane + 1] = S1;
+        rows[3 * lane + 2] = S2;
+        sh.pc[lane] = pc;
+        __syncthreads();
+        double *S = sload(&cp->S);
+        const uint32_t nv = (uint32_t)(it.c1 - it.c0);
+        const uint32_t npiece = (24u * nv + 15u) / 16u;
+        for (uint32_t q = (uint32_t)lane; q < npiece; q += 64u) {
+          const uint32_t j = (16u * q) / 24u, word = (16u * q - 24u * j) / 8u;  // row, first word (0, 1, 2)
+          const double2 val = *reinterpret_cast<const double2 *>(rows + 2 * q);
+          const uint32_t pj = sh.pc[j];
+          const bool two_rows = word == 2u, has_next = two_rows && j + 1u < nv;
+          const uint32_t pn = has_next ? sh.pc[j + 1u] : 0u;
+          double *at = S + 3 * (int64_t)pj + word;
+          if (!two_rows || (has_next && pn == pj + 1u)) {
+            *reinterpret_cast<double2 *>(at) = val;
+          } else {
+            at[0] = val.x;
+            if (has_next) S[3 * (int64_t)pn] = val.y;
+          }
+        }
+        __syncthreads();
       }
       acc_band += (unsigned long long)__popcll(ballot64(valid && any));
       const double fx = wave_sum_f64(S0 * v), fy = wave_sum_f64(S1 * v), fz = wave_sum_f64(S2 * v);
