@@ -1507,6 +1507,10 @@ __device__ __forceinline__ void write_record(unsigned char *r, int rsz, uint32_t
 // otherwise cost the common kernels registers.
 template <bool kInt, bool kSplit, bool kMulti>
 __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
+  // The sampling stream's last waves can still be resident beside this pass,
+  // which is on the step's critical path: its waves take a higher issue
+  // priority, so the sampler's waves use the issue slots these leave free.
+  __builtin_amdgcn_s_setprio(3);
   Work W = L.w;
   __shared__ WeightsScratch sh;
   const int lane = threadIdx.x;
