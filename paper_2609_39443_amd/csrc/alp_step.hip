@@ -2623,17 +2623,20 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         sh.pc[lane] = pc;
         __syncthreads();
         double *S = sload(&cp->S);
+        // a row starts on an 8-byte boundary: the pieces are two doubles
+        // with that alignment
+        typedef double d2a8 __attribute__((ext_vector_type(2), aligned(8)));
         const uint32_t nv = (uint32_t)(it.c1 - it.c0);
         const uint32_t npiece = (24u * nv + 15u) / 16u;
         for (uint32_t q = (uint32_t)lane; q < npiece; q += 64u) {
           const uint32_t j = (16u * q) / 24u, word = (16u * q - 24u * j) / 8u;  // row, first word (0, 1, 2)
-          const double2 val = *reinterpret_cast<const double2 *>(rows + 2 * q);
+          const d2a8 val = *reinterpret_cast<const d2a8 *>(rows + 2 * q);
           const uint32_t pj = sh.pc[j];
           const bool two_rows = word == 2u, has_next = two_rows && j + 1u < nv;
           const uint32_t pn = has_next ? sh.pc[j + 1u] : 0u;
           double *at = S + 3 * (int64_t)pj + word;
           if (!two_rows || (has_next && pn == pj + 1u)) {
-            *reinterpret_cast<double2 *>(at) = val;
+            *reinterpret_cast<d2a8 *>(at) = val;
           } else {
             at[0] = val.x;
             if (has_next) S[3 * (int64_t)pn] = val.y;
