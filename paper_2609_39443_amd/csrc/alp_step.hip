@@ -2383,7 +2383,6 @@ struct SpreadScratch {
   alignas(16) double cc[3][kSpreadChunk];
   uint16_t first[64], last[64];  // run of each cell inside the chunk (last exclusive)
   uint32_t pc[64];               // caller index of each cell of the item (at its end)
-  uint8_t cl[kSpreadChunk];      // cell lane of each record (items with several runs per cell)
 };
 static_assert(sizeof(double) * 3 * kSpreadChunk == 24 * 64, "one 24-byte source row per cell");
 
@@ -2571,19 +2570,34 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
     }
     if ((rb & 2ull) != 0ull) {
       // an item whose entries were taken in groups holds one run per group
-      // for a cell: every record of the chunk whose cell is this lane's, in
-      // record order (group after group, beam order inside a group)
-      sh.cl[j] = (uint8_t)(has ? cl : 255u);
-      __syncthreads();
-      for (uint32_t q = 0; q < nch; ++q) {
-        if (sh.cl[q] == (uint32_t)lane) {
+      // for a cell.  The chunk splits into segments where the cell index
+      // falls (a group starts); inside a segment the records are sorted by
+      // cell, so each segment is summed like the chunk of a one-group item,
+      // one segment after the other: a cell still adds its records in record
+      // order (group after group, beam order inside a group).
+      const uint32_t up = (uint32_t)__shfl((int)cl, lane - 1, 64);
+      const uint32_t dn = (uint32_t)__shfl((int)cl, lane + 1, 64);
+      const bool head = has && (j == 0 || up > cl);
+      const uint64_t heads = ballot64(head);
+      const uint32_t nseg = (uint32_t)__popcll(heads);
+      const uint32_t seg = lanemask_lt_popc(heads) + (head ? 1u : 0u) - 1u;
+      for (uint32_t sg = 0; sg < nseg; ++sg) {
+        if (has && seg == sg) {
+          if (j == 0 || up != cl) sh.first[cl] = (uint16_t)j;
+          if (j + 1 == nch || dn != cl) sh.last[cl] = (uint16_t)(j + 1);
+        }
+        __syncthreads();
+        const uint32_t lo = sh.first[lane], hi = sh.last[lane];
+        sh.first[lane] = 0;
+        sh.last[lane] = 0;
+        any = any || hi > lo;
+        for (uint32_t q = lo; q < hi; ++q) {
           S0 += sh.cc[0][q];
           S1 += sh.cc[1][q];
           S2 += sh.cc[2][q];
-          any = true;
         }
+        __syncthreads();
       }
-      __syncthreads();
     } else {
       // run boundaries of each cell (records are sorted by cell): the
       // neighbouring records' cells come from the neighbouring lanes
