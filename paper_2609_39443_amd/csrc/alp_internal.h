@@ -13,7 +13,7 @@ constexpr int kChunkSegs = 16;      // segments per chunk in the segment binning
 constexpr int kMaxEmitTile = 256;   // (chunk, tile) windows of a tile merged by k_tile_merge
 constexpr int kMaxEmitBig = 4096;   // windows of a tile merged by k_tile_merge_big (the limit)
 constexpr int kBigTileCounter = 4;  // step counter word: tiles listed for k_tile_merge_big
-constexpr int kMultiItemCounter = 5;  // step counter word: items listed for k_weights_multi
+constexpr int kMultiItemCounter = 5;  // step counter word: items listed for the grouped weights kernels
 constexpr int kQueueStripes = 16;  // counters per work queue
 constexpr int kLineWords = 32;                    // uint32 words per 128-byte line
 // step counters: a line of flags, then four work queues whose counters each
@@ -23,6 +23,9 @@ __host__ __device__ constexpr int queue_words(int q) { return kLineWords + q * k
 constexpr int kMaxEntries = 128;    // merged (tile, beam) entries the weights pass takes at once
 constexpr int kMaskWords = kMaxEntries / 32;
 constexpr int kStagePts = 160;      // window points (and node accumulators) staged in LDS
+// flag on a tile's entry count: its entries' windows hold more points than
+// the staging area, so its items are taken in groups by the grouped kernels
+constexpr uint32_t kNentGrouped = 1u << 31;
 constexpr int kHiShift = 46;        // fixed-point: hi word holds v * 2^(46-E)
 constexpr int kLoBits = 40;         // lo word holds the next 40 bits
 constexpr int kSampleLanes = 4;  // lanes per actuator point in the sampler
@@ -154,7 +157,8 @@ struct Work {
   Win *emit;            // [cap_emit] windows grouped by tile
   Entry *entry;         // [cap_emit] merged windows, at the tile's window offset
   Item *item;           // [cap_item]
-  uint32_t *multi_items; // [cap_item] items of tiles with more than kMaxEntries entries
+  uint32_t *multi_items; // [cap_item] items taken in entry groups (more than kMaxEntries entries,
+                         // or more window points than the staging area)
   unsigned long long *rec_base;  // per item, byte offset into rec
   uint32_t *rec_cnt;    // per item
   unsigned char *rec;   // [cap_rec bytes] pair records

@@ -509,10 +509,22 @@ struct MergeScratch {
   int32_t k0[kCap];
 };
 
+// window points an entry stages (its segments' end points, or the point of a
+// single-CV beam)
+__device__ __forceinline__ uint32_t entry_points(const Entry &en) {
+  return en.single ? 1u : (uint32_t)(en.i1 - en.i0 + 2);
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += (uint32_t)__shfl_xor((int)v, d, 64);
+  return v;
+}
+
 // Tiles with more than 64 windows: sort the (beam, first segment) keys in
 // LDS (bitonic), then join each beam's run.  Returns the number of entries.
 template <int kCap>
-__device__ uint32_t tile_merge_lds(const Work &W, MergeScratch<kCap> &sh, int lane, uint32_t eoff, uint32_t n_emit) {
+__device__ uint32_t tile_merge_lds(const Work &W, MergeScratch<kCap> &sh, int lane, uint32_t eoff, uint32_t n_emit,
+                                   uint32_t &npts) {
   // the scratch may still be read for the wave's previous tile
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -558,7 +570,7 @@ __device__ uint32_t tile_merge_lds(const Work &W, MergeScratch<kCap> &sh, int la
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
-  uint32_t ne = 0;
+  uint32_t ne = 0, pts = 0;
   for (uint32_t r0 = 0; r0 < n_emit; r0 += 64) {
     const uint32_t i = r0 + lane;
     bool head = false;
@@ -579,9 +591,11 @@ __device__ uint32_t tile_merge_lds(const Work &W, MergeScratch<kCap> &sh, int la
       en.i1 = hi < 0 ? 0 : hi;
       en.single = hi < 0 ? 1 : 0;
       W.entry[eoff + idx] = en;  // idx < beams of the tile <= windows of the tile
+      pts += entry_points(en);
     }
     ne += (uint32_t)__popcll(bal);
   }
+  npts = wave_sum_u32(pts);
   return ne;
 }
 
@@ -589,7 +603,7 @@ __device__ uint32_t tile_merge_lds(const Work &W, MergeScratch<kCap> &sh, int la
 // its window with the smallest first segment, the entry's last segment the
 // largest over the beam's windows, and its place the number of smaller beams
 // in the tile.  Returns the number of entries.
-__device__ uint32_t tile_merge_regs(const Work &W, int lane, uint32_t eoff, uint32_t n_emit) {
+__device__ uint32_t tile_merge_regs(const Work &W, int lane, uint32_t eoff, uint32_t n_emit, uint32_t &npts) {
   uint32_t beam = ~0u, lo = 0;
   int32_t hi = 0, k0 = 0;
   if ((uint32_t)lane < n_emit) {
@@ -616,6 +630,7 @@ __device__ uint32_t tile_merge_regs(const Work &W, int lane, uint32_t eoff, uint
     const int j = __builtin_ctzll(mm);
     idx += (uint32_t)__builtin_amdgcn_readlane((int)beam, j) < beam ? 1u : 0u;
   }
+  uint32_t pts = 0;
   if (head) {
     Entry en;
     en.k0 = k0;
@@ -623,14 +638,18 @@ __device__ uint32_t tile_merge_regs(const Work &W, int lane, uint32_t eoff, uint
     en.i1 = mhi < 0 ? 0 : mhi;
     en.single = mhi < 0 ? 1 : 0;
     W.entry[eoff + idx] = en;
+    pts = entry_points(en);
   }
+  npts = wave_sum_u32(pts);
   return (uint32_t)__popcll(hb);
 }
 
-// The tile's item count and entry count, written once its merge is done.
-__device__ __forceinline__ void tile_done(Work &W, int64_t t, uint32_t ne, uint32_t ncell) {
+// The tile's item count and entry count, written once its merge is done;
+// the count carries kNentGrouped when the entries' windows hold more points
+// than the weights pass stages at once.
+__device__ __forceinline__ void tile_done(Work &W, int64_t t, uint32_t ne, uint32_t npts, uint32_t ncell) {
   const uint32_t ni = (ncell + 63u) / 64u;
-  W.tile_nent[t] = ni ? ne : 0u;
+  W.tile_nent[t] = ni ? (ne | (npts > (uint32_t)kStagePts ? kNentGrouped : 0u)) : 0u;
   W.tile_items[t] = ni;
 }
 
@@ -688,6 +707,7 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
     const uint32_t bj = (uint32_t)__shfl((int)beam, gbase | j, 64);
     idx += (((gheads >> j) & 1u) != 0u && bj < beam) ? 1u : 0u;
   }
+  uint32_t gpts = 0;
   if (head) {
     Entry en;
     en.k0 = k0;
@@ -695,10 +715,14 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
     en.i1 = mhi < 0 ? 0 : mhi;
     en.single = mhi < 0 ? 1 : 0;
     W.entry[eoff + idx] = en;
+    gpts = entry_points(en);
   }
+  // the group's staged points (xor steps below 16 stay inside the group)
+#pragma unroll
+  for (int d = kMergeGroup / 2; d > 0; d >>= 1) gpts += (uint32_t)__shfl_xor((int)gpts, d, 64);
   if (gl == 0 && have) {
     if (small) {
-      tile_done(W, tg, (uint32_t)__popc(gheads), ncell);
+      tile_done(W, tg, (uint32_t)__popc(gheads), gpts, ncell);
     } else if (n_emit == 0 || n_emit > (uint32_t)kMaxEmitBig) {
       if (n_emit) set_overflow(W, 4u);
       W.tile_nent[tg] = 0;
@@ -716,8 +740,9 @@ __global__ __launch_bounds__(64) void k_tile_merge(StepLaunch L) {
     const uint32_t te = (uint32_t)__builtin_amdgcn_readlane((int)eoff, l);
     const uint32_t tn = (uint32_t)__builtin_amdgcn_readlane((int)n_emit, l);
     const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)ncell, l);
-    const uint32_t ne = tn <= 64u ? tile_merge_regs(W, lane, te, tn) : tile_merge_lds(W, sh, lane, te, tn);
-    if (lane == 0) tile_done(W, t, ne, tc);
+    uint32_t npts = 0;
+    const uint32_t ne = tn <= 64u ? tile_merge_regs(W, lane, te, tn, npts) : tile_merge_lds(W, sh, lane, te, tn, npts);
+    if (lane == 0) tile_done(W, t, ne, npts, tc);
   }
 }
 
@@ -735,8 +760,9 @@ __global__ __launch_bounds__(64) void k_tile_merge_big(StepLaunch L) {
     const CaseDev &cs = L.cases[c];
     const int64_t tl = t - cs.tile_base;
     const uint32_t ncell = tile_cell_start(cs.m, tl + 1) - tile_cell_start(cs.m, tl);
-    const uint32_t ne = tile_merge_lds(W, sh, lane, eoff, n_emit);
-    if (lane == 0) tile_done(W, t, ne, ncell);
+    uint32_t npts = 0;
+    const uint32_t ne = tile_merge_lds(W, sh, lane, eoff, n_emit, npts);
+    if (lane == 0) tile_done(W, t, ne, npts, ncell);
   }
 }
 
@@ -1561,9 +1587,12 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     const int64_t pbase = sload(&cp->point_base);
     const int64_t tl = it.tile - sload(&cp->tile_base);
     const int rsz = rec_size(cprec, W.rec_compact != 0);
-    // the tile's entries, in beam order; more than kMaxEntries are taken in
-    // groups of kMaxEntries, one after another
-    const uint32_t ne_all = it.nent;
+    // the tile's entries, in beam order.  The grouped kernels take them in
+    // groups, one after another: each group is the run of entries whose
+    // windows fit the staging area together (at most kMaxEntries; a window
+    // that does not fit alone is a group of its own, read from global
+    // memory).  A cell then has one run of records per group.
+    const uint32_t ne_all = it.nent & ~kNentGrouped;
     constexpr bool multi = kMulti;
     // cells of the item, and their FP32 coordinates relative to the tile centre
     const int c = it.c0 + lane;
@@ -1618,15 +1647,15 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       reserve(per_cell * (uint64_t)(it.c1 - it.c0));
     }
     for (uint32_t g0 = 0;;) {
-    const uint32_t ne = kMulti ? min(ne_all - g0, (uint32_t)kMaxEntries) : ne_all;
+    const uint32_t ne_plan = kMulti ? min(ne_all - g0, (uint32_t)kMaxEntries) : ne_all;
     const uint32_t eoff = it.eoff + g0;
     // 1. entries and the staging plan: the leading entries whose windows fit
     uint32_t carry = 0;
     int nst = 0;
-    for (uint32_t e0 = 0; e0 < ne; e0 += 64) {
+    for (uint32_t e0 = 0; e0 < ne_plan; e0 += 64) {
       const uint32_t e = e0 + lane;
       uint32_t cntp = 0;
-      if (e < ne) {
+      if (e < ne_plan) {
         const Entry en = W.entry[eoff + e];
         sh.e_k0[e] = en.k0;
         sh.e_i0[e] = en.i0;
@@ -1636,13 +1665,16 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       }
       uint32_t tot;
       const uint32_t ex = wave_excl_scan_u32(cntp, tot) + carry;
-      const bool fits = e < ne && ex + cntp <= (uint32_t)kStagePts;
-      if (e < ne) sh.e_pt0[e] = fits ? (int32_t)ex : -1;
+      const bool fits = e < ne_plan && ex + cntp <= (uint32_t)kStagePts;
+      if (e < ne_plan) sh.e_pt0[e] = fits ? (int32_t)ex : -1;
       nst += __popcll(ballot64(fits));
       carry += tot;
     }
     __syncthreads();
     const int n_staged = nst;
+    // the entries of this group: all of them in the common kernels; in the
+    // grouped ones the staged prefix, or the first entry alone
+    const uint32_t ne = !kMulti ? ne_all : (n_staged > 0 ? (uint32_t)n_staged : 1u);
     int npts = 0;
     if (nst > 0) {
       const int last = nst - 1;
@@ -2192,7 +2224,7 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       atomicAdd(&W.w_lo[node], l);
     }
     if constexpr (!kMulti) break;
-    g0 += (uint32_t)kMaxEntries;
+    g0 += ne;
     if (g0 >= ne_all) break;
     __syncthreads();  // the previous group's scratch is done with
     }  // entry groups
@@ -2221,20 +2253,26 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
 void k_weights64(StepLaunch L) {
   weights_pass<false, false, false>(L);
 }
-// the items of tiles with more than kMaxEntries entries, every rule and
-// precision in one kernel (few items: registers do not matter here); a small
-// grid, so that a step without such items pays little for the launch
-constexpr int kMultiBlocks = 32;
-template <bool kInt, bool kSplit>
-__device__ __forceinline__ void weights_multi_one(const StepLaunch &L) {
-  weights_pass<kInt, kSplit, true>(L);
+// the items taken in entry groups (tiles with more than kMaxEntries entries,
+// or whose windows hold more points than the staging area), one kernel per
+// rule and precision with the register budgets of the common kernels; they
+// walk the list of such items with a static stride, so a step without any
+// launches waves that return at once
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
+void k_weights_grp(StepLaunch L) {
+  weights_pass<false, true, true>(L);
+}
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
+void k_weights_grp64(StepLaunch L) {
+  weights_pass<false, false, true>(L);
+}
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
+void k_weights_grp_int(StepLaunch L) {
+  weights_pass<true, true, true>(L);
 }
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(2)))
-void k_weights_multi(StepLaunch L, int which) {
-  if (which == 0) weights_multi_one<false, true>(L);
-  else if (which == 1) weights_multi_one<false, false>(L);
-  else if (which == 2) weights_multi_one<true, true>(L);
-  else weights_multi_one<true, false>(L);
+void k_weights_grp_int64(StepLaunch L) {
+  weights_pass<true, false, true>(L);
 }
 
 // the integrated rule, one kernel per precision: the split one (FP32
@@ -2255,9 +2293,10 @@ void launch_weights(const StepLaunch &L, hipStream_t st) {
   if (L.near_fp64) hipLaunchKernelGGL(k_weights64, g, dim3(64), 0, st, L);
   if (L.int_split) hipLaunchKernelGGL(k_weights_int, g, dim3(64), 0, st, L);
   if (L.int_fp64) hipLaunchKernelGGL(k_weights_int64, g, dim3(64), 0, st, L);
-  const int flags[4] = {L.near_split, L.near_fp64, L.int_split, L.int_fp64};
-  for (int q = 0; q < 4; ++q)
-    if (flags[q]) hipLaunchKernelGGL(k_weights_multi, dim3(kMultiBlocks), dim3(64), 0, st, L, q);
+  if (L.near_split) hipLaunchKernelGGL(k_weights_grp, g, dim3(64), 0, st, L);
+  if (L.near_fp64) hipLaunchKernelGGL(k_weights_grp64, g, dim3(64), 0, st, L);
+  if (L.int_split) hipLaunchKernelGGL(k_weights_grp_int, g, dim3(64), 0, st, L);
+  if (L.int_fp64) hipLaunchKernelGGL(k_weights_grp_int64, g, dim3(64), 0, st, L);
 }
 
 // ------------------------------------------------------------------- norm --
