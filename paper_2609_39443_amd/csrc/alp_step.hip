@@ -1378,6 +1378,14 @@ struct WeightsScratch {
     // screening frames of up to 64 entries (three float4 each), read by all
     // lanes at one address; live only during the screening
     float4 frm[3 * 64];
+    // while the frames are built: each staged window's unit chord axis and
+    // the extremes over its points (ordered keys of the smallest and largest
+    // axial coordinate, bits of the largest squared deviation from the chord
+    // line and of the largest squared distance from the tile centre)
+    struct {
+      float fax[3][kMaxEntries];
+      uint32_t fred[4][kMaxEntries];
+    };
     struct {
       // node accumulators of the staged points
       long long ahi[kStagePts];
@@ -1394,6 +1402,22 @@ struct WeightsScratch {
 };
 static_assert(sizeof(float4) * 3 * 64 <= 2 * 8 * kStagePts + 4 * 64 * kMaskWords,
               "screening frames overlay the accumulators and the candidate list");
+static_assert(7 * 4 * kMaxEntries <= 2 * 8 * kStagePts + 4 * 64 * kMaskWords,
+              "the frame reductions overlay the accumulators and the candidate list");
+
+// median of three (one v_med3_u32)
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
+// FP32 as an unsigned key that orders like the value (finite values)
+__device__ __forceinline__ uint32_t f32_key(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return (b & 0x80000000u) ? ~b : b | 0x80000000u;
+}
+__device__ __forceinline__ float f32_of_key(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? k & 0x7fffffffu : ~k);
+}
 
 // exact FP64 scan of window segments j0..j1 (local indices; points read from
 // the beam array at X), strict '<' so the lowest index wins a tie
@@ -1693,16 +1717,6 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
       if (ef > 0.f) atomicMax(&sh.e_em[e], __float_as_uint(ef));
     }
     __syncthreads();
-    for (int q = lane; q < npts; q += 64) {
-      const int e = staged_entry(sh.wx[q]);
-      const int np = sh.e_i1[e] < 0 ? 1 : sh.e_i1[e] - sh.e_i0[e] + 2;
-      if (q - sh.e_pt0[e] < np - 1) {
-        const float4 A = sh.sa[q], B = sh.sa[q + 1];
-        const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
-        const float ee = ex * ex + ey * ey + ez * ez;
-        sh.sa[q].w = ee > 0.f ? 1.0f / ee : 0.f;
-      }
-    }
     // Screening capsules, in registers (lane l holds entry 64 b + l).  Each
     // window gets a chord frame: origin P0 (its first point), unit axis u (to
     // its last point), the axial extent [amin, amax] of its points along u and
@@ -1712,7 +1726,33 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
     // rho from the line and axial gap g from [amin, amax],
     //   |c - x|^2 >= max(rho - dev, 0)^2 + g^2,
     // and a pair needs |c - x| <= 3 eps_j <= 3 eps_max of the window.
+    // The axis comes from one lane per entry; the extremes over a staged
+    // window's points from one lane per point (LDS min / max), those of a
+    // window read from the beam arrays from its entry's lane.
     float fr[2][10];
+    // the frame's extent, radius and error allowance from the extremes over
+    // its points (rr: largest squared distance of a point from the tile
+    // centre; em: the window's largest eps, rounded up)
+    auto frame_finish = [&](float *F, uint32_t e, float amin, float amax, float dev2, float rr, float em) {
+      // coordinates of points and cells lie within Rmax of the tile centre;
+      // rho and dev computed in FP32 are each within 2^-9 Rmax of their true
+      // values (|d| <= 2 Rmax), the axial gap within 2^-18 Rmax: the radius
+      // is widened by 2^-7 Rmax
+      const float r2max = fmaxf(rr, (float)(3.0 * hl * hl));
+      // (the square roots below and in the screening are the hardware's,
+      // within 1 ulp: far inside these allowances)
+      const float Rc = 3.0f * em * (1.0f + 1e-5f) + ldexpf(__builtin_amdgcn_sqrtf(r2max), -7);
+      F[6] = amin;
+      F[7] = amax;
+      F[8] = __builtin_amdgcn_sqrtf(fmaxf(dev2, 0.f));
+      F[9] = Rc * Rc;
+      // |FP32 distance^2 - exact distance^2| stays below ~80 u Rmax^2
+      // (u = 2^-24) for coordinates within Rmax of the tile centre: rounding
+      // of the inputs moves the distance by at most 2 sqrt(3) u Rmax, and the
+      // clamped projection adds at most ~64 u Rmax^2.  The allowance takes
+      // 2^-14 Rmax^2 (256 u Rmax^2).
+      sh.e_dabs[e] = ldexpf(r2max, -14) * (1.0f + 1e-5f);
+    };
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
       const uint32_t e = 64u * bb + lane;
@@ -1747,44 +1787,67 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
           uy = 0.f;
           uz = 0.f;
         }
-        float amin = INFINITY, amax = -INFINITY, dev2 = 0.f, rr = 0.f;
-        double dem = 0.0;
-        for (int p = 0; p < np; ++p) {
-          const float3 A = p == 0 ? P0 : point(p);
-          const float dx = A.x - P0.x, dy = A.y - P0.y, dz = A.z - P0.z;
-          const float a = dx * ux + dy * uy + dz * uz;
-          amin = fminf(amin, a);
-          amax = fmaxf(amax, a);
-          dev2 = fmaxf(dev2, dx * dx + dy * dy + dz * dz - a * a);
-          rr = fmaxf(rr, A.x * A.x + A.y * A.y + A.z * A.z);
-          if (pt0 < 0) dem = fmax(dem, Eps[k + p]);
-        }
-        const float em = pt0 >= 0 ? __uint_as_float(sh.e_em[e]) : (float)(dem * (1.0 + 1e-6));
-        // coordinates of points and cells lie within Rmax of the tile centre;
-        // rho and dev computed in FP32 are each within 2^-9 Rmax of their true
-        // values (|d| <= 2 Rmax), the axial gap within 2^-18 Rmax: the radius
-        // is widened by 2^-7 Rmax
-        const float r2max = fmaxf(rr, (float)(3.0 * hl * hl));
-        // (the square roots below and in the screening are the hardware's,
-        // within 1 ulp: far inside these allowances)
-        const float Rc = 3.0f * em * (1.0f + 1e-5f) + ldexpf(__builtin_amdgcn_sqrtf(r2max), -7);
         fr[bb][0] = P0.x;
         fr[bb][1] = P0.y;
         fr[bb][2] = P0.z;
         fr[bb][3] = ux;
         fr[bb][4] = uy;
         fr[bb][5] = uz;
-        fr[bb][6] = amin;
-        fr[bb][7] = amax;
-        fr[bb][8] = __builtin_amdgcn_sqrtf(fmaxf(dev2, 0.f));
-        fr[bb][9] = Rc * Rc;
-        // |FP32 distance^2 - exact distance^2| stays below ~80 u Rmax^2
-        // (u = 2^-24) for coordinates within Rmax of the tile centre: rounding
-        // of the inputs moves the distance by at most 2 sqrt(3) u Rmax, and the
-        // clamped projection adds at most ~64 u Rmax^2.  The allowance takes
-        // 2^-14 Rmax^2 (256 u Rmax^2).
-        sh.e_dabs[e] = ldexpf(r2max, -14) * (1.0f + 1e-5f);
+        if (pt0 >= 0) {
+          sh.fax[0][e] = ux;
+          sh.fax[1][e] = uy;
+          sh.fax[2][e] = uz;
+          sh.fred[0][e] = 0xffffffffu;  // no point yet: amin = +inf
+          sh.fred[1][e] = 0u;           // amax = -inf
+          sh.fred[2][e] = 0u;           // dev^2 = 0
+          sh.fred[3][e] = 0u;           // rr = 0
+        } else {
+          float amin = INFINITY, amax = -INFINITY, dev2 = 0.f, rr = 0.f;
+          double dem = 0.0;
+          for (int p = 0; p < np; ++p) {
+            const float3 A = p == 0 ? P0 : point(p);
+            const float dx = A.x - P0.x, dy = A.y - P0.y, dz = A.z - P0.z;
+            const float a = dx * ux + dy * uy + dz * uz;
+            amin = fminf(amin, a);
+            amax = fmaxf(amax, a);
+            dev2 = fmaxf(dev2, dx * dx + dy * dy + dz * dz - a * a);
+            rr = fmaxf(rr, A.x * A.x + A.y * A.y + A.z * A.z);
+            dem = fmax(dem, Eps[k + p]);
+          }
+          frame_finish(fr[bb], e, amin, amax, dev2, rr, (float)(dem * (1.0 + 1e-6)));
+        }
       }
+    }
+    __syncthreads();
+    // one lane per staged point: 1/|e|^2 of the segment it starts, and its
+    // window's extremes
+    for (int q = lane; q < npts; q += 64) {
+      const int e = staged_entry(sh.wx[q]);
+      const int np = sh.e_i1[e] < 0 ? 1 : sh.e_i1[e] - sh.e_i0[e] + 2;
+      const int pt0 = sh.e_pt0[e];
+      const float4 A = sh.sa[q], O = sh.sa[pt0];
+      if (q - pt0 < np - 1) {
+        const float4 B = sh.sa[q + 1];
+        const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
+        const float ee = ex * ex + ey * ey + ez * ez;
+        sh.sa[q].w = ee > 0.f ? 1.0f / ee : 0.f;
+      }
+      const float dx = A.x - O.x, dy = A.y - O.y, dz = A.z - O.z;
+      const float a = dx * sh.fax[0][e] + dy * sh.fax[1][e] + dz * sh.fax[2][e];
+      atomicMin(&sh.fred[0][e], f32_key(a));
+      atomicMax(&sh.fred[1][e], f32_key(a));
+      atomicMax(&sh.fred[2][e], __float_as_uint(fmaxf(dx * dx + dy * dy + dz * dz - a * a, 0.f)));
+      atomicMax(&sh.fred[3][e], __float_as_uint(A.x * A.x + A.y * A.y + A.z * A.z));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const uint32_t e = 64u * bb + lane;
+      if (bb == 1 && ne <= 64u) break;  // wave-uniform
+      if (e < ne && (int)e < n_staged && sh.e_pt0[e] >= 0)
+        frame_finish(fr[bb], e, f32_of_key(sh.fred[0][e]), f32_of_key(sh.fred[1][e]),
+                     __uint_as_float(sh.fred[2][e]), __uint_as_float(sh.fred[3][e]),
+                     __uint_as_float(sh.e_em[e]));
     }
     __syncthreads();
     // 2. screening
@@ -2071,9 +2134,10 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
               // FP32 ranking: the three smallest (distance, index) keys
               const float qx = (float)(pcx - ctx), qy = (float)(pcy - cty), qz = (float)(pcz - ctz);
               uint32_t k1 = ~0u, k2 = ~0u, k3 = ~0u;
-              float4 A = sh.sa[pt0];
               for (int j = 0; j < nseg; ++j) {
-                const float4 B = sh.sa[pt0 + j + 1];
+                // both end points from LDS (carrying B over as the next A
+                // costs register moves; LDS reads are not the binding resource)
+                const float4 A = sh.sa[pt0 + j], B = sh.sa[pt0 + j + 1];
                 const float ex = B.x - A.x, ey = B.y - A.y, ez = B.z - A.z;
                 float dx = qx - A.x, dy = qy - A.y, dz = qz - A.z;
                 const float t = dx * ex + dy * ey + dz * ez;
@@ -2082,13 +2146,14 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
                 dy -= sg * ey;
                 dz -= sg * ez;
                 const float d2 = dx * dx + dy * dy + dz * dz;
-                const uint32_t key = (__float_as_uint(d2) & ~kSegIdxMask) | (uint32_t)j;
-                const uint32_t m1 = max(k1, key);
+                // (the high three bytes of d2 and j as the low byte: one
+                // v_perm_b32, equal to (d2 & ~kSegIdxMask) | j)
+                const uint32_t key = __builtin_amdgcn_perm(__float_as_uint(d2), (uint32_t)j, 0x07060500u);
+                // insert into k1 <= k2 <= k3: the median of (k_i, k_i+1, key)
+                // is the new i+1-th smallest
+                k3 = umed3(k2, k3, key);
+                k2 = umed3(k1, k2, key);
                 k1 = min(k1, key);
-                const uint32_t m2 = max(k2, m1);
-                k2 = min(k2, m1);
-                k3 = min(k3, m2);
-                A = B;
               }
               // keys drop 8 mantissa bits (relative 2^-15): the band below holds
               // every segment whose exact distance can reach the best one
