@@ -13,6 +13,7 @@
 // balance are accumulated as exact fixed-point integers, and every source
 // value is summed by one lane in beam order.
 #include "alp_internal.h"
+#include "alp_keys.h"
 #include "alp_reccursor.h"
 
 namespace alp {
@@ -1410,14 +1411,6 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
   return max(min(a, b), min(max(a, b), c));
 }
 
-// FP32 as an unsigned key that orders like the value (finite values)
-__device__ __forceinline__ uint32_t f32_key(float x) {
-  const uint32_t b = __float_as_uint(x);
-  return (b & 0x80000000u) ? ~b : b | 0x80000000u;
-}
-__device__ __forceinline__ float f32_of_key(uint32_t k) {
-  return __uint_as_float((k & 0x80000000u) ? k & 0x7fffffffu : ~k);
-}
 
 // exact FP64 scan of window segments j0..j1 (local indices; points read from
 // the beam array at X), strict '<' so the lowest index wins a tie
