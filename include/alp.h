@@ -266,7 +266,8 @@ typedef struct {
   int32_t weights_grab;  /* work items (up to 64 cells of one tile each) a weights workgroup
                             takes from its queue at once: 1..16 */
   int32_t weights_waves; /* weights workgroups (one wave each) per CU: 1..32 */
-  int32_t spread_waves;  /* spread workgroups per CU (1..32), or 0 = every resident slot */
+  int32_t spread_waves;  /* spread workgroups (of 16 waves) per CU (1..32, capped at what a CU holds),
+                            or 0 = every resident slot */
 } alp_tuning;
 
 /* A whole coupling step (sample -> drag -> project) for n_cases independent

@@ -837,7 +837,7 @@ alp_status tune_launch(alp_context *ctx, int32_t n, const alp_case *cases, uint3
   const int samp[][2] = {{4, 0}, {4, 4}, {4, 8}, {4, 16}, {2, 4}, {2, 8}, {8, 4}, {8, 8}};
   const int grab[] = {2, 4, 8};
   const int wwav[] = {8, 12, 16, 24};
-  const int swav[] = {0, 4, 6};
+  const int swav[] = {0, 1};  // spread workgroups (16 waves each) per CU: all a CU holds, or one
   auto consider = [&](const alp_tuning &t) {
     if (rc != ALP_OK) return;
     double ms = INFINITY;

@@ -32,55 +32,74 @@ struct RecChunk {
   uint64_t rb;
 };
 
-// The chunks of a wave's items (item, item + stride, ...) in order.  Every
-// item gives ceil(rn / 64) chunks and at least one, since the cells of an
-// item without records are written too.  The cursor holds the chunk it hands
-// out next and the count and base of the item after that chunk's item, read
-// one item ahead.
+// The spread runs workgroups of kSpreadGroupWaves waves, and the items are
+// dealt in windows of g = (workgroups) x kSpreadGroupWaves consecutive items:
+// every workgroup owns kSpreadGroupWaves consecutive items of each window,
+// and its waves take the workgroup's items in window order from a counter in
+// its LDS, so a wave that finishes an item early takes the next one instead
+// of a fixed share, while all waves move through the windows together.
+// Workgroups are handed to the device's eight XCDs in turn (workgroup index
+// mod 8) and each XCD has its own L2: for a workgroup count that is a
+// multiple of 8, the workgroups of one XCD own one contiguous block of each
+// window, so the items an L2 serves at a time lie close together and share
+// more of the beams whose forces their records read.  Ticket t of a workgroup
+// whose first item is `base` is item (t / W) g + base + t mod W (W the waves
+// per workgroup).
+constexpr uint32_t kXcds = 8;
+constexpr uint32_t kSpreadGroupWaves = 16;
+ALP_HD uint32_t rec_group_base(uint32_t grp, uint32_t ngroups) {
+  const uint32_t nx = ngroups % kXcds == 0u ? kXcds : 1u;
+  const uint32_t per_xcd = ngroups / nx;  // workgroups per XCD
+  return (grp % nx) * per_xcd * kSpreadGroupWaves + (grp / nx) * kSpreadGroupWaves;
+}
+ALP_HD uint32_t rec_ticket_item(uint32_t t, uint32_t base, uint32_t g) {
+  const uint64_t it = (uint64_t)(t / kSpreadGroupWaves) * g + base + t % kSpreadGroupWaves;
+  return it > 0xffffffffull ? 0xffffffffu : (uint32_t)it;
+}
+
+// The chunks of a wave's items in order.  Every item gives ceil(rn / 64)
+// chunks and at least one, since the cells of an item without records are
+// written too.  The cursor holds the chunk it hands out next and the item
+// after that chunk's item, with its count and base (read one item ahead).  A
+// wave takes a ticket only while it holds a valid next item and uses every
+// ticket it takes; a workgroup's tickets come in increasing order and map to
+// increasing items, so each of its items is summed by exactly one wave.
 struct RecCursor {
   RecChunk c;
   uint32_t gitem, grn;
   uint64_t grb;
+  uint32_t base, g;  // the workgroup's first item and the window length
 };
 
-// The first item of wave b in a grid of g waves (the wave then takes every
-// g-th item).  Workgroups are handed to the device's eight XCDs in turn (b mod
-// 8) and each XCD has its own L2: for g a multiple of 8 the waves of one XCD
-// start on one contiguous eighth of every g consecutive items, rather than on
-// every eighth item, so the items an L2 serves at a time lie closer together
-// and share more of the beams whose forces their records read.  A permutation
-// of 0 .. g-1.
-constexpr uint32_t kXcds = 8;
-ALP_HD uint32_t rec_first_item(uint32_t b, uint32_t g) {
-  if (g % kXcds != 0u) return b;
-  return (b % kXcds) * (g / kXcds) + b / kXcds;
-}
-
-// Src provides cnt(i) and base(i) for items i < n_items.
+// Src provides cnt(i) and base(i) for items i < n_items and ticket(), the
+// workgroup counter's next value.
 template <class Src>
-ALP_HD RecCursor rec_start(const Src &src, uint32_t item, uint32_t n_items, uint32_t stride) {
+ALP_HD RecCursor rec_start(const Src &src, uint32_t base, uint32_t g, uint32_t n_items) {
   RecCursor k;
-  k.c.item = item;
+  k.base = base;
+  k.g = g;
+  k.c.item = rec_ticket_item(src.ticket(), base, g);
   k.c.p0 = 0;
   k.c.rn = 0;
   k.c.rb = 0;
-  if (item < n_items) {
-    k.c.rn = src.cnt(item);
-    k.c.rb = src.base(item);
-  }
-  k.gitem = item + stride;
+  k.gitem = n_items;
   k.grn = 0;
   k.grb = 0;
-  if (item < n_items && k.gitem < n_items) {
-    k.grn = src.cnt(k.gitem);
-    k.grb = src.base(k.gitem);
+  if (k.c.item < n_items) {
+    k.c.rn = src.cnt(k.c.item);
+    k.c.rb = src.base(k.c.item);
+    k.gitem = rec_ticket_item(src.ticket(), base, g);
+    if (k.gitem < n_items) {
+      k.grn = src.cnt(k.gitem);
+      k.grb = src.base(k.gitem);
+    }
   }
   return k;
 }
 
 // The next chunk; the cursor moves past it.
 template <class Src>
-ALP_HD RecChunk rec_take(const Src &src, RecCursor &k, uint32_t n_items, uint32_t stride) {
+ALP_HD RecChunk rec_take(const Src &src, RecCursor &k, uint32_t n_items) {
   const RecChunk out = k.c;
   if (out.item < n_items) {
     k.c.p0 += kSpreadChunk;
@@ -92,7 +111,7 @@ ALP_HD RecChunk rec_take(const Src &src, RecCursor &k, uint32_t n_items, uint32_
       k.grn = 0;
       k.grb = 0;
       if (k.gitem < n_items) {
-        k.gitem += stride;
+        k.gitem = rec_ticket_item(src.ticket(), k.base, k.g);
         if (k.gitem < n_items) {
           k.grn = src.cnt(k.gitem);
           k.grb = src.base(k.gitem);

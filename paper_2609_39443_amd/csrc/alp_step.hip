@@ -2466,13 +2466,30 @@ void launch_beam_sums(const StepLaunch &L, hipStream_t st) {
 // the fields' maxima, i.e. no wait on them)
 constexpr unsigned kWaitVmcnt0 = 0x0F70u;
 
-// The record counts and bases of the work items, for the record cursor.
+// The record counts and bases of the work items, and the workgroup's item
+// counter in LDS, for the record cursor (lane 0 takes the ticket; an LDS
+// atomic waits on the LDS counter only, not on the wave's global loads).
 struct ItemRecs {
   const uint32_t *c;
   const unsigned long long *b;
+  uint32_t *ctr;
+  int lane;
   __device__ __forceinline__ uint32_t cnt(uint32_t i) const { return sload(c + i); }
   __device__ __forceinline__ uint64_t base(uint32_t i) const { return sload(b + i); }
+  __device__ __forceinline__ uint32_t ticket() const {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(ctr, 1u);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+  }
 };
+
+// Order of one wave's own LDS accesses across lanes (each wave has its own
+// scratch; a workgroup barrier would hold waves that are at other items).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 struct SpreadScratch {
   // per-record contributions; at an item's end, its cells' source rows in
@@ -2495,8 +2512,8 @@ struct SpreadChunk {
 };
 
 __device__ __forceinline__ void spread_issue(const Work &W, const ItemRecs &src, RecCursor &cur, uint32_t n_items,
-                                             uint32_t stride, int lane, SpreadChunk &o) {
-  o.k = rec_take(src, cur, n_items, stride);
+                                             int lane, SpreadChunk &o) {
+  o.k = rec_take(src, cur, n_items);
   if (o.k.item < n_items) {
     const Item *ip = W.item + o.k.item;
     o.it.c0 = sload(&ip->c0);
@@ -2559,14 +2576,20 @@ __device__ __forceinline__ void spread_decode(SpreadChunk &X, int lane, SpreadDe
   D.a1 = a1;
 }
 
-__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(8))) void k_spread(StepLaunch L) {
+constexpr int kSpreadThreads = 64 * (int)kSpreadGroupWaves;
+__global__ __attribute__((amdgpu_flat_work_group_size(kSpreadThreads, kSpreadThreads), amdgpu_waves_per_eu(8)))
+void k_spread(StepLaunch L) {
   Work W = L.w;
-  __shared__ SpreadScratch sh;
-  const int lane = threadIdx.x;
+  __shared__ SpreadScratch shs[kSpreadGroupWaves];
+  __shared__ uint32_t group_ctr;
+  const int lane = threadIdx.x & 63;
+  SpreadScratch &sh = shs[threadIdx.x >> 6];
+  if (threadIdx.x == 0) group_ctr = 0u;
+  __syncthreads();  // the workgroup's only barrier: its waves then go their own ways
   const uint32_t n_items = (uint32_t)min((int64_t)W.tile_itoff[W.n_tiles], W.cap_item);
-  const uint32_t stride = gridDim.x;
-  const uint32_t first = rec_first_item(blockIdx.x, gridDim.x);
-  if (first >= n_items) return;
+  const ItemRecs src{W.rec_cnt, W.rec_base, &group_ctr, lane};
+  RecCursor cur = rec_start(src, rec_group_base(blockIdx.x, gridDim.x), gridDim.x * kSpreadGroupWaves, n_items);
+  if (cur.c.item >= n_items) return;
   // per-wave accumulation (exact fixed point, flushed when the case changes)
   int acc_case = -1;
   unsigned long long acc_band = 0;
@@ -2590,14 +2613,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
   // that pass has waited for its own force loads, issued after these) and
   // refilled by the pass that sums it.  So no record register is read or
   // copied while its load is in flight.
-  const ItemRecs src{W.rec_cnt, W.rec_base};
-  RecCursor cur = rec_start(src, first, n_items, stride);
   SpreadChunk A, B;
-  spread_issue(W, src, cur, n_items, stride, lane, A);
-  spread_issue(W, src, cur, n_items, stride, lane, B);
+  spread_issue(W, src, cur, n_items, lane, A);
+  spread_issue(W, src, cur, n_items, lane, B);
   SpreadDec D;
   spread_decode(A, lane, D);
-  __syncthreads();
+  wave_sync();
   double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the lane's cell, over the item's chunks so far
   bool any = false;
   // sum the chunk decoded in D (it came from X), refill X with the chunk
@@ -2649,7 +2670,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
     // the next chunk's loads go out before this chunk's forces are used
     // (the empty statement keeps every use of the forces, the volume and
     // the index after them)
-    spread_issue(W, src, cur, n_items, stride, lane, X);
+    spread_issue(W, src, cur, n_items, lane, X);
     double f0 = fq[0], f1 = fq[1], f2 = fq[2], f3 = fq[3], f4 = fq[4], f5 = fq[5];
     asm volatile("" : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3), "+v"(f4), "+v"(f5), "+v"(v), "+v"(pc));
     {
@@ -2683,7 +2704,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
           if (j == 0 || up != cl) sh.first[cl] = (uint16_t)j;
           if (j + 1 == nch || dn != cl) sh.last[cl] = (uint16_t)(j + 1);
         }
-        __syncthreads();
+        wave_sync();
         const uint32_t lo = sh.first[lane], hi = sh.last[lane];
         sh.first[lane] = 0;
         sh.last[lane] = 0;
@@ -2693,7 +2714,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
           S1 += sh.cc[1][q];
           S2 += sh.cc[2][q];
         }
-        __syncthreads();
+        wave_sync();
       }
     } else {
       // run boundaries of each cell (records are sorted by cell): the
@@ -2704,7 +2725,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         if (j == 0 || up != cl) sh.first[cl] = (uint16_t)j;
         if (j + 1 == nch || dn != cl) sh.last[cl] = (uint16_t)(j + 1);
       }
-      __syncthreads();
+      wave_sync();
       const uint32_t lo = sh.first[lane], hi = sh.last[lane];
       sh.first[lane] = 0;
       sh.last[lane] = 0;
@@ -2714,7 +2735,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         S1 += sh.cc[1][q];
         S2 += sh.cc[2][q];
       }
-      __syncthreads();
+      wave_sync();
     }
     if (last) {
       // the item's cells are complete: write them, count the band cells and
@@ -2732,7 +2753,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         rows[3 * lane + 1] = S1;
         rows[3 * lane + 2] = S2;
         sh.pc[lane] = pc;
-        __syncthreads();
+        wave_sync();
         double *S = sload(&cp->S);
         // a row starts on an 8-byte boundary: the pieces are two doubles
         // with that alignment
@@ -2753,7 +2774,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
             if (has_next) S[3 * (int64_t)pn] = val.y;
           }
         }
-        __syncthreads();
+        wave_sync();
       }
       acc_band += (unsigned long long)__popcll(ballot64(valid && any));
       const double fx = wave_sum_f64(S0 * v), fy = wave_sum_f64(S1 * v), fz = wave_sum_f64(S2 * v);
@@ -2783,18 +2804,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
   flush();
 }
 
-// The spread walks its items with a static stride, so its grid is exactly
-// the number of blocks the device holds at once: none waits for a slot.
+// The spread's waves take their items window by window, so its grid is
+// exactly the number of workgroups the device holds at once: none waits for
+// a slot.
 int spread_blocks_per_cu() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(k_spread), 64, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(k_spread), kSpreadThreads, 0) !=
       hipSuccess)
     return 0;
   return nb;
 }
 
 void launch_spread(const StepLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_spread, dim3(L.grid_spread), dim3(64), 0, st, L);
+  hipLaunchKernelGGL(k_spread, dim3(L.grid_spread), dim3(kSpreadThreads), 0, st, L);
 }
 
 // ---------------------------------------------------------------- step end --
