@@ -16,9 +16,10 @@ constexpr int kBigTileCounter = 4;  // step counter word: tiles listed for k_til
 constexpr int kMultiItemCounter = 5;  // step counter word: items listed for the grouped weights kernels
 constexpr int kQueueStripes = 16;  // counters per work queue
 constexpr int kLineWords = 32;                    // uint32 words per 128-byte line
-// step counters: a line of flags, then four work queues whose counters each
-// sit on a line of their own (atomics on one line serialise)
-constexpr int kCounters = kLineWords + 4 * kQueueStripes * kLineWords;
+// step counters: a line of flags, then eight work queues (the four common
+// weights kernels' and their grouped kernels') whose counters each sit on a
+// line of their own (atomics on one line serialise)
+constexpr int kCounters = kLineWords + 8 * kQueueStripes * kLineWords;
 __host__ __device__ constexpr int queue_words(int q) { return kLineWords + q * kQueueStripes * kLineWords; }
 constexpr int kMaxEntries = 128;    // merged (tile, beam) entries the weights pass takes at once
 constexpr int kMaskWords = kMaxEntries / 32;

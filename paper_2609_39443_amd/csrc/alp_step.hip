@@ -1562,16 +1562,17 @@ __device__ __forceinline__ void weights_pass(const StepLaunch &L) {
   unsigned long long blk_cur = 0, blk_end = 0;
   int acc_case = -1;
   unsigned long long acc_pairs = 0, acc_guard = 0;
-  WorkQueue wq = work_queue(W.counters + queue_words(kInt ? (kSplit ? 1 : 2) : (kSplit ? 0 : 3)),
-                            (uint32_t)min((int64_t)n_items, W.cap_item), (uint32_t)L.weights_grab);
+  // the grouped kernels take the list of grouped items from queues of their
+  // own, one item at a time (such items are long and vary widely)
   const uint32_t n_multi = kMulti ? min(W.counters[kMultiItemCounter], (uint32_t)min((int64_t)n_items, W.cap_item)) : 0u;
-  uint32_t mi = blockIdx.x;
+  WorkQueue wq = work_queue(W.counters + queue_words((kMulti ? 4 : 0) + (kInt ? (kSplit ? 1 : 2) : (kSplit ? 0 : 3))),
+                            kMulti ? n_multi : (uint32_t)min((int64_t)n_items, W.cap_item),
+                            kMulti ? 1u : (uint32_t)L.weights_grab);
   for (;;) {
     uint32_t item;
     if constexpr (kMulti) {
-      if (mi >= n_multi) break;
-      item = W.multi_items[mi];
-      mi += gridDim.x;
+      if (!wq.next(lane)) break;
+      item = W.multi_items[wq.item];
     } else {
       if (!wq.next(lane)) break;
       item = wq.item;
@@ -2314,8 +2315,8 @@ void k_weights64(StepLaunch L) {
 // the items taken in entry groups (tiles with more than kMaxEntries entries,
 // or whose windows hold more points than the staging area), one kernel per
 // rule and precision with the register budgets of the common kernels; they
-// walk the list of such items with a static stride, so a step without any
-// launches waves that return at once
+// take the list of such items from a work queue of their own, so a step
+// without any launches waves that return at once
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(4)))
 void k_weights_grp(StepLaunch L) {
   weights_pass<false, true, true>(L);
