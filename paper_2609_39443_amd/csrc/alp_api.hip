@@ -33,7 +33,7 @@ struct alp_context {
   hipStream_t user = nullptr;
   hipStream_t st = nullptr;
   hipStream_t st2 = nullptr;  // second stream: sampling and drag run beside the projection
-  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr, ev_items = nullptr;
   std::string err;
   int n_cu = 256;
   int spread_per_cu = 8;  // resident spread blocks per CU
@@ -528,7 +528,8 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   // Sampling and drag (eq. 16-20) do not depend on the segment binning or the
   // weights pass (eq. 21-22): in a full step they run on the second stream and
   // join before the normalisation, which needs f.  The profiled step keeps
-  // everything on one stream so that each stage is timed on its own.
+  // everything on one stream so that each stage is timed on its own.  (A fork
+  // happens only in a full step, so the join below is always reached.)
   const bool fork = (stages == ST_ALL) && !ev;
   hipStream_t sd = fork ? ctx->st2 : st;
   if (fork) {
@@ -550,7 +551,6 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   // the beam-side sums need only f: with the drag, they stay on its stream
   if ((stages & ST_DRAG) && (stages & ST_PROJECT)) launch_beam_sums(L, sd);
   mark(3);
-  if (fork) (void)hipEventRecord(ctx->ev_join, sd);
   if (!(stages & ST_PROJECT)) return;
   launch_beams_prep(L, st);
   launch_scan_u32(w.bchunks, w.bchunks, w.n_beams, w.scan_tmp, st);
@@ -564,7 +564,19 @@ void launch_sequence(alp_context *ctx, const StepLaunch &L, int stages, hipEvent
   launch_scan_u32(w.tile_items, w.tile_itoff, w.n_tiles, w.scan_tmp, st);
   launch_items(L, st);
   mark(4);
-  launch_weights(L, st);
+  // the grouped weights kernels need only the work items: in a full step they
+  // follow the drag on the second stream, beside the common weights kernels,
+  // and both streams join before the normalisation
+  if (fork) {
+    (void)hipEventRecord(ctx->ev_items, st);
+    (void)hipStreamWaitEvent(sd, ctx->ev_items, 0);
+    launch_weights_grouped(L, sd);
+    (void)hipEventRecord(ctx->ev_join, sd);
+    launch_weights_main(L, st);
+  } else {
+    launch_weights_main(L, st);
+    launch_weights_grouped(L, st);
+  }
   mark(5);
   if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
   launch_norm(L, st);
@@ -904,6 +916,7 @@ alp_status alp_create(int device, void *hip_stream, alp_context **out) {
       hipStreamCreateWithFlags(&ctx->st2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_items, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_replay, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void **)&ctx->h_ovf, sizeof(uint32_t), hipHostMallocMapped) != hipSuccess ||
       hipHostGetDevicePointer((void **)&ctx->d_ovf, ctx->h_ovf, 0) != hipSuccess) {
@@ -936,6 +949,7 @@ alp_status alp_destroy(alp_context *ctx) {
   (void)hipEventDestroy(ctx->ev_out);
   (void)hipEventDestroy(ctx->ev_fork);
   (void)hipEventDestroy(ctx->ev_join);
+  (void)hipEventDestroy(ctx->ev_items);
   (void)hipEventDestroy(ctx->ev_replay);
   if (ctx->h_ovf) (void)hipHostFree(ctx->h_ovf);
   (void)hipStreamDestroy(ctx->st2);

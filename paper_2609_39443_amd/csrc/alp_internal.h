@@ -543,7 +543,8 @@ struct GeomLaunch {
 void launch_beam_geometry(const GeomLaunch &G, hipStream_t st);
 void launch_sample_kernel(const StepLaunch &L, hipStream_t st);
 void launch_drag(const StepLaunch &L, hipStream_t st);
-void launch_weights(const StepLaunch &L, hipStream_t st);
+void launch_weights_main(const StepLaunch &L, hipStream_t st);
+void launch_weights_grouped(const StepLaunch &L, hipStream_t st);
 void launch_norm(const StepLaunch &L, hipStream_t st);
 void launch_beam_sums(const StepLaunch &L, hipStream_t st);
 void launch_spread(const StepLaunch &L, hipStream_t st);

@@ -2346,12 +2346,18 @@ void k_weights_int64(StepLaunch L) {
   weights_pass<true, false, false>(L);
 }
 
-void launch_weights(const StepLaunch &L, hipStream_t st) {
+// The common kernels and the grouped ones take disjoint items from their own
+// queues and share only the record allocator, the node sums and the
+// counters, all updated atomically, so the two sets may run on two streams.
+void launch_weights_main(const StepLaunch &L, hipStream_t st) {
   const dim3 g((unsigned)L.grid_weights);
   if (L.near_split) hipLaunchKernelGGL(k_weights, g, dim3(64), 0, st, L);
   if (L.near_fp64) hipLaunchKernelGGL(k_weights64, g, dim3(64), 0, st, L);
   if (L.int_split) hipLaunchKernelGGL(k_weights_int, g, dim3(64), 0, st, L);
   if (L.int_fp64) hipLaunchKernelGGL(k_weights_int64, g, dim3(64), 0, st, L);
+}
+void launch_weights_grouped(const StepLaunch &L, hipStream_t st) {
+  const dim3 g((unsigned)L.grid_weights);
   if (L.near_split) hipLaunchKernelGGL(k_weights_grp, g, dim3(64), 0, st, L);
   if (L.near_fp64) hipLaunchKernelGGL(k_weights_grp64, g, dim3(64), 0, st, L);
   if (L.int_split) hipLaunchKernelGGL(k_weights_grp_int, g, dim3(64), 0, st, L);
